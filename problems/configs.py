@@ -1,0 +1,129 @@
+"""The synthetic sequences A_j x_j = b_j used by the tests and the benchmark.
+
+Every constant lives here, so a run can record exactly what it solved.
+
+* Config 1 -- 2-D 5-point variable-coefficient diffusion, N = 32 (n = 1024).
+  k_j(x) = exp(0.5 g(x)) (1 + 0.01 j) with g a unit-variance field of
+  correlation length 0.2 (seed 1).  Because the factor (1 + 0.01 j) is
+  uniform, A_j = (1 + 0.01 j) A_0 exactly.  b_j(x) = f(c + R(theta_j)(x - c)),
+  f a second field (seed 2), c the centre of the square, theta_j = 0.05 j rad:
+  the load pattern rotates slowly about the centre.  Ten systems,
+  snapshot memory 5, POD rank 4, relative tolerance 1e-8.
+  Variant "r2": b_j = cos(theta_j) f_1 + sin(theta_j) f_2, so every x_j lies
+  in a fixed two-dimensional space (exact-recovery case).
+
+* Config 2 -- 3-D 7-point diffusion, N = 128 (n = 2,097,152), one implicit
+  time step per system: A_j = K(k_j) + (1/dt) I, dt = 1e-3.
+  k_j(x) = exp(g(x - j h e_1)): a lognormal field (sigma = 1, correlation
+  length 0.1) that drifts one cell along x per step.
+  b_j = x_{j-1} / dt + s with s = 1 and x_0 = 0.  Fifty systems, snapshot
+  memory 20, POD rank 10, relative tolerance 1e-10.
+  Smaller N gives the same problem family at test sizes.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .fv import FVDiffusion
+from .grf import FourierField
+
+
+@dataclass
+class Config1Diffusion2D:
+    N: int = 32
+    steps: int = 10
+    omega: int = 5
+    rank: int = 4
+    tol: float = 1e-8
+    corr_len: float = 0.2
+    sigma: float = 0.5
+    growth: float = 0.01
+    dtheta: float = 0.05
+    seed_kappa: int = 1
+    seed_rhs: int = 2
+    seed_rhs2: int = 3
+    variant: str = "rotate"          # "rotate" or "r2"
+    name: str = field(default="config1_diffusion2d")
+
+    def __post_init__(self):
+        self.fv = FVDiffusion(self.N, 2)
+        self.n, self.nnz = self.fv.n, self.fv.nnz
+        self.rowptr, self.colind = self.fv.rowptr, self.fv.colind
+        ax = self.fv.node_axis()
+        g = FourierField(2, self.corr_len, self.seed_kappa).on_grid(ax, ax)
+        self._vals0 = self.fv.values(np.exp(self.sigma * g))
+        self._pts = self.fv.interior_points()
+        self._f1 = FourierField(2, self.corr_len, self.seed_rhs)
+        self._f2 = FourierField(2, self.corr_len, self.seed_rhs2)
+
+    def matrix_values(self, j: int) -> np.ndarray:
+        return self._vals0 * (1.0 + self.growth * j)
+
+    def rhs(self, j: int, x_prev: np.ndarray | None = None) -> np.ndarray:
+        th = self.dtheta * j
+        if self.variant == "r2":
+            return np.cos(th) * self._f1.at_points(self._pts) + \
+                np.sin(th) * self._f2.at_points(self._pts)
+        c = np.array([0.5, 0.5])
+        rot = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        q = c + (self._pts - c) @ rot.T
+        return self._f1.at_points(q)
+
+    def describe(self) -> dict:
+        return {"workload": self.name, "N": self.N, "n": self.n, "nnz": self.nnz,
+                "steps": self.steps, "omega": self.omega, "rank": self.rank,
+                "tol": self.tol, "variant": self.variant}
+
+
+@dataclass
+class Config2Diffusion3D:
+    N: int = 128
+    steps: int = 50
+    omega: int = 20
+    rank: int = 10
+    tol: float = 1e-10
+    dt: float = 1e-3
+    corr_len: float = 0.1
+    sigma: float = 1.0
+    source: float = 1.0
+    seed_kappa: int = 4
+    name: str = field(default="config2_diffusion3d")
+
+    def __post_init__(self):
+        self.fv = FVDiffusion(self.N, 3)
+        self.n, self.nnz = self.fv.n, self.fv.nnz
+        self.rowptr, self.colind = self.fv.rowptr, self.fv.colind
+        h, J = self.fv.h, self.steps
+        ax = self.fv.node_axis()
+        ax_x = (np.arange(-J, self.N + 2, dtype=np.float64)) * h   # room for the drift
+        self._g = FourierField(3, self.corr_len, self.seed_kappa).on_grid(ax_x, ax, ax)
+
+    def matrix_values(self, j: int) -> np.ndarray:
+        J, N = self.steps, self.N
+        if not 0 <= j <= J:
+            raise ValueError("step out of range")
+        g = self._g[:, :, J - j: J - j + N + 2]          # g(x - j h e_1)
+        return self.fv.values(np.exp(self.sigma * g), shift=1.0 / self.dt)
+
+    def rhs(self, j: int, x_prev: np.ndarray | None) -> np.ndarray:
+        b = np.full(self.n, self.source)
+        if x_prev is not None:
+            b += x_prev / self.dt
+        return b
+
+    def describe(self) -> dict:
+        return {"workload": self.name, "N": self.N, "n": self.n, "nnz": self.nnz,
+                "steps": self.steps, "omega": self.omega, "rank": self.rank,
+                "tol": self.tol, "dt": self.dt, "corr_len": self.corr_len,
+                "sigma": self.sigma}
+
+
+def config1(**kw) -> Config1Diffusion2D:
+    return Config1Diffusion2D(**kw)
+
+
+def config2(**kw) -> Config2Diffusion3D:
+    return Config2Diffusion3D(**kw)
