@@ -1,0 +1,182 @@
+/*
+ * podcg.h -- C ABI of libpodcg, the GPU (MI355X, gfx950) hot path of the
+ * POD-augmented conjugate-gradient method for a sequence of SPD systems
+ *
+ *     A_j x_j = b_j,  j = 1, 2, ...           (Eq. (sequence), Section 2)
+ *
+ * solved to ||b_j - A_j x_j||_2 <= rtol * ||b_j||_2 (Eq. (sequenceInexact) with
+ * a relative forcing term).  Each solve runs Stage 1 (Alg. 2: Galerkin
+ * projection onto the augmenting basis W_j) followed by augmented PCG
+ * (Alg. 1 with Y = W_j and a Jacobi preconditioner M_j = diag(A_j)); this is
+ * Stage 3 of Section 4 with an empty Stage 2.  After a solve the caller
+ * pushes the centred solution x_j - xbar_j as a snapshot, and the next basis
+ * W_{j+1} is the POD of the last omega snapshots in the metric A_j with
+ * inverse-distance weights 2^{1-i} (Alg. pod_evd, Appendix A; weights of
+ * Section 3.3; metric choice Theta = A of Section 3.3).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" are HIP device pointers; "host" pointers are
+ *     ordinary host memory.  The library never keeps a caller pointer after
+ *     the call returns: what it needs later (matrix, snapshots) it copies.
+ *   - All device work is ordered on the HIP stream passed to podcg_create
+ *     (NULL = the legacy default stream).  Calls that must read a result back
+ *     (pattern ingest, status of a factorisation, convergence, statistics)
+ *     synchronise that stream before returning; no call synchronises the
+ *     whole device.
+ *   - Return value: 0 = success, > 0 = warning (result usable), < 0 = error.
+ *     No C++ exception crosses this boundary.  podcg_strerror() turns a code
+ *     into text; podcg_last_error() gives the context's last detailed message.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Sizes: n < 2^31, nnz < 2^31, basis and snapshot counts <= PODCG_MAX_BASIS.
+ */
+#ifndef PODCG_H
+#define PODCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PODCG_MAX_BASIS 32
+
+/* status codes */
+#define PODCG_OK                0
+#define PODCG_NOT_CONVERGED     1   /* iteration cap reached; x holds the last iterate       */
+#define PODCG_RANK_REDUCED      2   /* basis truncated at a small Cholesky pivot (still solved) */
+#define PODCG_ERR_INVALID_ARG  (-1)
+#define PODCG_ERR_HIP          (-2)
+#define PODCG_ERR_OOM          (-3)
+#define PODCG_ERR_NOT_SPD      (-4) /* non-positive diagonal or (A p, p) <= 0                 */
+#define PODCG_ERR_NONFINITE    (-5) /* NaN/Inf in b, xbar, the matrix or an iterate            */
+#define PODCG_ERR_NO_MATRIX    (-6)
+#define PODCG_ERR_SIZE         (-7)
+
+typedef struct podcg_ctx podcg_ctx;
+
+typedef struct {
+    int32_t omega;        /* snapshot memory: the last omega snapshots feed the POD (1..32)   */
+    int32_t rank_max;     /* largest POD dimension y (0..32); 0 turns recycling off          */
+    int32_t maxit;        /* iteration cap of one solve (>= 0)                                */
+    int32_t check_every;  /* the host reads the convergence flag every this many iterations  */
+    int32_t weights;      /* snapshot weights: 0 = inverse distance 2^{1-i}, 1 = all ones     */
+    int32_t timing;       /* > 0: time the three loop kernels with HIP events on every
+                             timing-th iteration (statistics only; 0 = off)                   */
+    double  rank_rtol;    /* POD keeps eigenvalues lam_i > rank_rtol * lam_1                  */
+    double  energy;       /* POD energy criterion in (0, 1); >= 1 disables it                 */
+} podcg_options;
+
+typedef struct {
+    int32_t iters;          /* search directions used = preconditioner applications in the loop */
+    int32_t matvecs;        /* products with A in this solve, setup included                    */
+    int32_t rank;           /* dimension of the augmenting basis used                            */
+    int32_t status;         /* the solve's return code                                           */
+    double  stage1_relres;  /* ||r|| / ||b|| after Stage 1                                       */
+    double  relres;         /* recursive ||r|| / ||b|| at exit                                   */
+    double  true_relres;    /* ||b - A x|| / ||b|| at exit                                      */
+    double  bnorm;          /* ||b||_2                                                           */
+    double  cond_G;         /* condition number of W^T A W (1 when there is no basis)            */
+    double  setup_ms;       /* A W, W^T A W, its factorisation (GPU time, 0 if reused)           */
+    double  solve_ms;       /* Stage 1 + loop + true residual (GPU time)                         */
+    int32_t timed_iters;    /* iterations whose kernels were timed (options.timing)              */
+    int32_t polls;          /* host reads of the convergence flag                                */
+    double  spmv_ms;        /* summed durations of the timed SpMV launches                       */
+    double  update_ms;      /* ... of the timed update/reduction launches                        */
+    double  dir_ms;         /* ... of the timed direction-update launches                        */
+} podcg_stats;
+
+/* Fill *opt with defaults: omega 20, rank_max 10, maxit 10000, check_every 16,
+ * inverse-distance weights, no timing, rank_rtol 1e-12, energy 1 (off). */
+void podcg_default_options(podcg_options* opt);
+
+/* Create a context for systems of size n.  opt may be NULL (defaults).
+ * hip_stream is a hipStream_t (NULL = default stream).  On success *out owns
+ * all device state; free it with podcg_destroy.
+ * Errors: INVALID_ARG (n < 1, options out of range), OOM, HIP. */
+int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip_stream);
+
+/* Release every resource of the context (NULL is accepted). */
+int podcg_destroy(podcg_ctx* ctx);
+
+/* Set the current matrix A_j (Section 2: sparse SPD, n x n) from CSR arrays
+ * in device memory: rowptr[n + 1] (int32, rowptr[0] = 0, rowptr[n] = nnz,
+ * non-decreasing), colind[nnz] (int32, 0 <= col < n), vals[nnz] (float64).
+ * The matrix is copied into the library's SELL-64 layout.  Passing rowptr
+ * and colind as NULL reuses the pattern of the previous call (values-only
+ * update, the usual case inside a sequence).  The Jacobi preconditioner
+ * diag(A_j)^{-1} is formed here.  Any stored basis stays but its products
+ * with the matrix are recomputed at the next solve.
+ * Errors: INVALID_ARG (bad pattern), NOT_SPD (missing or non-positive
+ * diagonal), NONFINITE (NaN/Inf value), NO_MATRIX (NULL pattern on first
+ * call), SIZE (nnz differs from the cached pattern), OOM, HIP. */
+int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr,
+                     const int32_t* colind, const double* vals);
+
+/* Append a snapshot s (device, n float64) to the memory of the last omega
+ * snapshots; the oldest is overwritten once omega are stored.  In a sequence
+ * s = x_j - xbar_j (the centred solution, Section 3.2).  Copied.
+ * Errors: INVALID_ARG, HIP. */
+int podcg_push_snapshot(podcg_ctx* ctx, const double* s);
+
+/* Forget all stored snapshots (the basis is kept). */
+int podcg_reset_snapshots(podcg_ctx* ctx);
+
+/* Build the next augmenting basis W = POD of the stored snapshots in the
+ * metric of the current matrix (Alg. pod_evd): Gram diag(w) S^T A S diag(w),
+ * symmetric eigen-decomposition, dimension y = #{lam_i > rank_rtol lam_1}
+ * capped by rank_max and the energy criterion, W = S diag(w) V_y Sigma_y^{-1}
+ * (so W^T A W = I for the current A).  *rank_out (host, may be NULL)
+ * receives y.  With no snapshots the basis becomes empty.
+ * Errors: NO_MATRIX, HIP. */
+int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out);
+
+/* Replace the augmenting basis with W (device, n x y, column-major with
+ * leading dimension n, y <= PODCG_MAX_BASIS; y = 0 clears it).  Copied.
+ * Lets a caller supply any basis to Alg. 1 (the paper's Y). */
+int podcg_set_basis(podcg_ctx* ctx, const double* W, int32_t y);
+
+/* Copy the current basis into W (device, n x y column-major, ld n, room for
+ * rank_max columns).  *rank (host) receives y. */
+int podcg_get_basis(podcg_ctx* ctx, double* W, int32_t* rank);
+
+/* Copy the reduced matrix G = W^T A W of the last setup and its inverse (both
+ * row-major y x y, host buffers of PODCG_MAX_BASIS^2 doubles, either may be
+ * NULL); *rank (host) receives y.  Runs the setup if it is stale. */
+int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank);
+
+/* Copy the eigenvalues of the last POD Gram matrix (decreasing) into lam
+ * (host, PODCG_MAX_BASIS doubles); *count (host) receives how many. */
+int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count);
+
+/* Solve A_j x = b (Stage 1 + augmented PCG, Alg. 2 then Alg. 1 with the
+ * current basis; plain Jacobi PCG when the basis is empty).
+ * b: device, n float64.  x: device, n float64, holds xbar_j on entry and x_j
+ * on return.  rtol >= 0.  st (host, may be NULL) receives statistics.
+ * Returns OK, NOT_CONVERGED (x = last iterate), RANK_REDUCED, or an error:
+ * NO_MATRIX, INVALID_ARG, NOT_SPD, NONFINITE, HIP. */
+int podcg_solve(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);
+
+/* Plain Jacobi PCG on the current matrix, ignoring the basis (the baseline
+ * of the comparison; Eq. (KrylovSolve)).  Same arguments and codes. */
+int podcg_solve_plain(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);
+
+/* y = A_j x for device vectors of length n (x and y must not overlap). */
+int podcg_matvec(podcg_ctx* ctx, const double* x, double* y);
+
+/* Bandwidth probe for the roofline: c[i] = a[i] + s * b[i] over n float64
+ * device elements, launched `reps` times on the context stream; *ms (host)
+ * receives the mean GPU time of one launch.  Not part of the method. */
+int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double* c,
+                       int64_t n, double s, int32_t reps, double* ms);
+
+/* Text of a status code (static storage). */
+const char* podcg_strerror(int code);
+
+/* Detailed message of the last error in this context (static until the next call). */
+const char* podcg_last_error(podcg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PODCG_H */

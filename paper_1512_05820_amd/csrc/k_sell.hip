@@ -1,0 +1,394 @@
+// Sparse kernels of libpodcg: CSR ingest into SELL-64 and the products with A.
+//
+// Layout (SELL-C-sigma with C = 64, sigma = 1, i.e. no row sorting): rows are
+// cut into slices of 64 consecutive rows, one row per lane of a wavefront.
+// Slice s stores its entries column-major: entry j of row 64 s + lane sits at
+// sptr[s] + 64 j + lane, for j < width(s) = the longest row of the slice.
+// Shorter rows are padded with value 0 and column = the row itself, so every
+// gather stays inside the vector.  One load instruction of a wave then reads
+// 64 consecutive values (512 B) and 64 consecutive column indices (256 B).
+#include "podcg_device.h"
+
+namespace podcg {
+
+// ---------------------------------------------------------------- ingest
+
+// flag |= 1: rowptr not a valid offset array; |= 2: column out of range.
+__global__ __launch_bounds__(kBlock) void k_validate_csr(int n, int64_t nnz,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         int* flag) {
+    int bad = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int64_t s = rowptr[i], e = rowptr[i + 1];
+        if (i == 0 && s != 0) bad |= 1;
+        if (i == n - 1 && e != nnz) bad |= 1;
+        if (s < 0 || e < s || e > nnz) { bad |= 1; continue; }
+        for (int64_t k = s; k < e; ++k) {
+            const int c = colind[k];
+            if (c < 0 || c >= n) bad |= 2;
+        }
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// sptr[s + 1] = 64 * (longest row of slice s); one wave per slice.
+__global__ __launch_bounds__(kBlock) void k_slice_widths(int n, int nslices,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         int64_t* __restrict__ sptr) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * kWavesPerBlock;
+    for (int s = wave; s < nslices; s += nwaves) {
+        const int row = s * kSlice + lane;
+        int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, kWave));
+        if (lane == 0) sptr[s + 1] = (int64_t)len * kSlice;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sptr[0] = 0;
+}
+
+// In-place inclusive scan of sptr[1..nslices] by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_slices(int nslices, int64_t* sptr) {
+    __shared__ int64_t sums[1024];
+    const int t = threadIdx.x;
+    const int chunk = (nslices + 1023) / 1024;
+    const int beg = 1 + t * chunk;
+    const int end = min(beg + chunk, nslices + 1);
+    int64_t acc = 0;
+    for (int i = beg; i < end; ++i) acc += sptr[i];
+    sums[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t > 0 ? sums[t - 1] : 0;
+    for (int i = beg; i < end; ++i) {
+        run += sptr[i];
+        sptr[i] = run;
+    }
+}
+
+// Column indices and the CSR position of every SELL slot (-1 for padding).
+__global__ __launch_bounds__(kBlock) void k_fill_pattern(int n, int nslices,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const int64_t* __restrict__ sptr,
+                                                         int* __restrict__ cols, int* __restrict__ map) {
+    const int total = nslices * kSlice;
+    for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock) {
+        const int s = row / kSlice, lane = row % kSlice;
+        const int64_t base = sptr[s];
+        const int w = (int)((sptr[s + 1] - base) / kSlice);
+        const int beg = row < n ? rowptr[row] : 0;
+        const int len = row < n ? rowptr[row + 1] - beg : 0;
+        const int pad_col = row < n ? row : 0;
+        for (int j = 0; j < w; ++j) {
+            const int64_t slot = base + (int64_t)j * kSlice + lane;
+            if (j < len) {
+                cols[slot] = colind[beg + j];
+                map[slot] = beg + j;
+            } else {
+                cols[slot] = pad_col;
+                map[slot] = -1;
+            }
+        }
+    }
+}
+
+// SELL values from CSR values, and dinv = 1 / (sum of the diagonal entries).
+// flag |= 4: a diagonal entry missing or not positive; |= 8: non-finite value.
+__global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
+                                                        const int64_t* __restrict__ sptr,
+                                                        const int* __restrict__ cols,
+                                                        const int* __restrict__ map,
+                                                        const double* __restrict__ csr_vals,
+                                                        double* __restrict__ vals,
+                                                        double* __restrict__ dinv, int* flag) {
+    const int total = nslices * kSlice;
+    int bad = 0;
+    for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock) {
+        const int s = row / kSlice, lane = row % kSlice;
+        const int64_t base = sptr[s];
+        const int w = (int)((sptr[s + 1] - base) / kSlice);
+        double d = 0.0;
+        for (int j = 0; j < w; ++j) {
+            const int64_t slot = base + (int64_t)j * kSlice + lane;
+            const int m = map[slot];
+            const double v = m >= 0 ? csr_vals[m] : 0.0;
+            vals[slot] = v;
+            if (!is_finite(v)) bad |= 8;
+            if (m >= 0 && cols[slot] == row) d += v;
+        }
+        if (row < n) {
+            if (!(d > 0.0)) bad |= 4;
+            dinv[row] = d > 0.0 ? 1.0 / d : 0.0;
+        } else {
+            dinv[row] = 0.0;
+        }
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// ---------------------------------------------------------------- products
+
+// Row `row` of A x for the slice handled by this wave.
+__device__ __forceinline__ double sell_row(const int* __restrict__ cols,
+                                           const double* __restrict__ vals, int64_t base, int w,
+                                           int lane, const double* __restrict__ x) {
+    const int* c = cols + base + lane;
+    const double* v = vals + base + lane;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < w; ++j) acc += __builtin_nontemporal_load(v + j * kSlice) *
+                                       x[__builtin_nontemporal_load(c + j * kSlice)];
+    return acc;
+}
+
+// Loop kernel 1 of augmented PCG (Alg. 1): q = A p and gamma = (A p, p);
+// the last workgroup forms alpha = (r, z) / gamma.
+__global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const double* __restrict__ p,
+                                                       double* __restrict__ q) {
+    __shared__ double lds[kWavesPerBlock * 1 + 1 + 1];
+    DevState* st = B.st;
+    const int done = st->done;
+    if (done != kRunning) {
+        if ((done == kConvergedPending || done == kCapPending) && blockIdx.x == 0 && threadIdx.x == 0)
+            st->done = kFinished;
+        return;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    double g[1] = {0.0};
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = L * kWavesPerBlock + wid;
+        if (s < B.nslices) {
+            const int64_t base = B.sptr[s];
+            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+            const double acc = sell_row(B.cols, B.vals, base, w, lane, p);
+            const int row = s * kSlice + lane;
+            if (row < B.n) {
+                q[row] = acc;
+                g[0] += acc * p[row];
+            }
+        }
+    }
+    if (grid_sum_last<1>(g, B.part, B.counter, lds) && threadIdx.x == 0) {
+        const double gamma = lds[0];
+        st->gamma = gamma;
+        if (!(gamma > 0.0) || !is_finite(gamma)) {
+            st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
+            st->done = kFailed;
+        } else {
+            st->alpha = st->rho / gamma;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_matvec(DevBufs B, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = L * kWavesPerBlock + wid;
+        if (s < B.nslices) {
+            const int64_t base = B.sptr[s];
+            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+            const double acc = sell_row(B.cols, B.vals, base, w, lane, x);
+            const int row = s * kSlice + lane;
+            if (row < B.n) y[row] = acc;
+        }
+    }
+}
+
+// r = b - A x with reductions.  STAGE1: partials (b, b), (r, r), W^T r; the
+// last workgroup sets ||b||^2, the absolute tolerance and the Stage-1
+// coefficients what = G^{-1} W^T r (Alg. 2).  Otherwise only (r, r) is kept
+// (the true residual at exit).  STORE writes r.
+template <int YB, bool STORE, bool STAGE1>
+__global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double* __restrict__ b,
+                                                  const double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ W) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    DevState* st = B.st;
+    if (STAGE1 && st->done != kRunning) return;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = L * kWavesPerBlock + wid;
+        if (s < B.nslices) {
+            const int64_t base = B.sptr[s];
+            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+            const double ax = sell_row(B.cols, B.vals, base, w, lane, x);
+            const int row = s * kSlice + lane;
+            if (row < B.n) {
+                const double bi = b[row];
+                const double ri = bi - ax;
+                if (STORE) r[row] = ri;
+                v[0] += bi * bi;
+                v[1] += ri * ri;
+#pragma unroll
+                for (int k = 0; k < YB; ++k)
+                    if (k < y) v[2 + k] += W[(size_t)k * B.ld + row] * ri;
+            }
+        }
+    }
+    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
+    if (STAGE1) {
+        if (threadIdx.x == 0) {
+            const double bb = lds[0];
+            st->bnorm2 = bb;
+            st->tol2 = st->tol2 * bb;
+            if (!is_finite(bb) || !is_finite(lds[1])) {
+                st->status = kStNonfinite;
+                st->done = kFailed;
+            }
+        }
+        if (threadIdx.x < y) {
+            double s = 0.0;
+            for (int j = 0; j < y; ++j) s += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+            st->what[threadIdx.x] = s;
+        }
+    } else if (threadIdx.x == 0) {
+        st->true_rr = lds[1];
+    }
+}
+
+// AX = A X for k <= KB columns (column-major, leading dimension B.ld).
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_spmm(DevBufs B, int k, const double* __restrict__ X,
+                                                 double* __restrict__ AX) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = L * kWavesPerBlock + wid;
+        if (s >= B.nslices) continue;
+        const int64_t base = B.sptr[s];
+        const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+        const int* c = B.cols + base + lane;
+        const double* vv = B.vals + base + lane;
+        double acc[KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) acc[kk] = 0.0;
+        for (int j = 0; j < w; ++j) {
+            const double a = vv[j * kSlice];
+            const int col = c[j * kSlice];
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk)
+                if (kk < k) acc[kk] += a * X[(size_t)kk * B.ld + col];
+        }
+        const int row = s * kSlice + lane;
+        if (row < B.n) {
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk)
+                if (kk < k) AX[(size_t)kk * B.ld + row] = acc[kk];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int grid_for_slices(int nslices) {
+    const int groups = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    return groups < kSpmvBlocksMax ? groups : kSpmvBlocksMax;
+}
+
+static int grid_for(int64_t items, int cap) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+hipError_t launch_validate_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                               int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_csr, dim3(grid_for(n, 4096)), dim3(kBlock), 0, s, n, nnz, rowptr,
+                       colind, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_widths(int n, int nslices, const int32_t* rowptr, int64_t* sptr, hipStream_t s) {
+    hipLaunchKernelGGL(k_slice_widths, dim3(grid_for_slices(nslices)), dim3(kBlock), 0, s, n, nslices,
+                       rowptr, sptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_slices(int nslices, int64_t* sptr, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_slices, dim3(1), dim3(1024), 0, s, nslices, sptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const int32_t* colind,
+                               const int64_t* sptr, int* cols, int* map, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_pattern, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
+                       0, s, n, nslices, rowptr, colind, sptr, cols, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
+                              const int* map, const double* csr_vals, double* vals, double* dinv,
+                              int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_values, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
+                       0, s, n, nslices, sptr, cols, map, csr_vals, vals, dinv, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmv_gamma, dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B, p, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_matvec, dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B, x, y);
+    return hipGetLastError();
+}
+
+template <int YB>
+static hipError_t resid_tier(const DevBufs& B, int y, const double* b, const double* x, double* r,
+                             const double* W, bool store, bool stage1, hipStream_t s) {
+    dim3 g(grid_for_slices(B.nslices)), t(kBlock);
+    if (stage1) {
+        if (store) hipLaunchKernelGGL((k_resid<YB, true, true>), g, t, 0, s, B, y, b, x, r, W);
+        else hipLaunchKernelGGL((k_resid<YB, false, true>), g, t, 0, s, B, y, b, x, r, W);
+    } else {
+        if (store) hipLaunchKernelGGL((k_resid<YB, true, false>), g, t, 0, s, B, y, b, x, r, W);
+        else hipLaunchKernelGGL((k_resid<YB, false, false>), g, t, 0, s, B, y, b, x, r, W);
+    }
+    return hipGetLastError();
+}
+
+
+hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x, double* r,
+                        const double* W, bool store, bool stage1, hipStream_t s) {
+    switch (yb) {
+#define CASE(T) case T: return resid_tier<T>(B, y, b, x, r, W, store, stage1, s);
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s) {
+    dim3 g(grid_for_slices(B.nslices)), t(kBlock);
+    if (k < 1) return hipSuccess;
+    switch (basis_tier(k)) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_spmm<T>), g, t, 0, s, B, k, X, AX); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace podcg

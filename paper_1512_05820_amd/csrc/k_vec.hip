@@ -1,0 +1,385 @@
+// Streaming kernels of libpodcg: the vector updates of augmented PCG with their
+// fused reductions, Stage 1, the tall-skinny Gram products and the POD basis
+// formation.  All column blocks (W, A W, S) are column-major with leading
+// dimension ld, so lane i of a wave touches row i of every column and each
+// load instruction reads 512 contiguous bytes.
+#include "podcg_device.h"
+
+namespace podcg {
+
+int basis_tier(int y) {
+    static const int tiers[] = {0, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+    for (int t : tiers)
+        if (y <= t) return t;
+    return -1;
+}
+
+// Loop kernel 2 of augmented PCG (Alg. 1): with alpha from kernel 1,
+//   r <- r - alpha q,  z <- M^{-1} r  (Jacobi),
+// and the sums (r, z), (r, r), c = (A W)^T z.  The last workgroup forms
+//   beta = (r', z') / (r, z),  mu = G^{-1} c  (the solve with W^T A W of
+// Alg. 1, with G^{-1} from the Cholesky factor of Stage 1),
+// counts the iteration and tests ||r|| <= tol ||b||.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __restrict__ r,
+                                                   double* __restrict__ z,
+                                                   const double* __restrict__ q,
+                                                   const double* __restrict__ AW) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    DevState* st = B.st;
+    if (st->done != kRunning) return;
+    const double alpha = st->alpha;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const double ri = r[i] - alpha * q[i];
+        const double zi = B.dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        v[0] += ri * zi;
+        v[1] += ri * ri;
+#pragma unroll
+        for (int k = 0; k < YB; ++k)
+            if (k < y) v[2 + k] += AW[(size_t)k * B.ld + i] * zi;
+    }
+    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rz = lds[0], rr = lds[1];
+        const int it = st->iter + 1;
+        st->iter = it;
+        st->rr = rr;
+        if (!is_finite(rr) || !is_finite(rz)) {
+            st->status = kStNonfinite;
+            st->done = kFailed;
+        } else {
+            st->beta = rz / st->rho;
+            st->rho = rz;
+            if (rr <= st->tol2) {
+                st->status = kStOk;
+                st->done = kConvergedPending;
+            } else if (it >= st->maxit) {
+                st->status = kStNotConverged;
+                st->done = kCapPending;
+            }
+        }
+    }
+    if (threadIdx.x < y) {
+        double s = 0.0;
+        for (int j = 0; j < y; ++j) s += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+        st->mu[threadIdx.x] = s;
+    }
+}
+
+// Loop kernel 3: x <- x + alpha p, then (while iterating) the new direction
+//   p <- z + beta p - W mu,
+// which keeps p A-orthogonal to range(W) (Alg. 1).  INIT forms the first
+// direction p = z - W mu and leaves x alone.
+template <int YB, bool INIT>
+__global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, double* __restrict__ p,
+                                                double* __restrict__ x, const double* __restrict__ z,
+                                                const double* __restrict__ W) {
+    const DevState* st = B.st;
+    const int done = st->done;
+    if (INIT) {
+        if (done != kRunning) return;
+    } else if (done != kRunning && done != kConvergedPending && done != kCapPending) {
+        return;
+    }
+    const bool new_dir = INIT || done == kRunning;
+    const double alpha = st->alpha, beta = st->beta;
+    double mu[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int k = 0; k < YB; ++k) mu[k] = k < y ? st->mu[k] : 0.0;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double s;
+        if (INIT) {
+            s = z[i];
+        } else {
+            const double pi = p[i];
+            x[i] += alpha * pi;
+            if (!new_dir) continue;
+            s = z[i] + beta * pi;
+        }
+#pragma unroll
+        for (int k = 0; k < YB; ++k)
+            if (k < y) s -= W[(size_t)k * B.ld + i] * mu[k];
+        p[i] = s;
+    }
+}
+
+// Stage 1 (Alg. 2 and the first steps of Alg. 1).  With what = G^{-1} W^T rbar
+// from the residual kernel and r = rbar:
+//   x <- xbar + W what,  r <- rbar - (A W) what,  z = M^{-1} r,
+// and the sums (r, z), (r, r), c = (A W)^T z; the last workgroup forms
+// mu = G^{-1} c and tests the Stage-1 residual against the tolerance.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         double* __restrict__ z,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ AW) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    DevState* st = B.st;
+    if (st->done != kRunning) return;
+    double what[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int k = 0; k < YB; ++k) what[k] = k < y ? st->what[k] : 0.0;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double ri = r[i];
+        if (YB > 0) {
+            double wx = 0.0, awx = 0.0;
+#pragma unroll
+            for (int k = 0; k < YB; ++k)
+                if (k < y) {
+                    wx += W[(size_t)k * B.ld + i] * what[k];
+                    awx += AW[(size_t)k * B.ld + i] * what[k];
+                }
+            x[i] += wx;
+            ri -= awx;
+            r[i] = ri;
+        }
+        const double zi = B.dinv[i] * ri;
+        z[i] = zi;
+        v[0] += ri * zi;
+        v[1] += ri * ri;
+#pragma unroll
+        for (int k = 0; k < YB; ++k)
+            if (k < y) v[2 + k] += AW[(size_t)k * B.ld + i] * zi;
+    }
+    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rz = lds[0], rr = lds[1];
+        st->rho = rz;
+        st->rr = rr;
+        st->rr0 = rr;
+        if (!is_finite(rr) || !is_finite(rz)) {
+            st->status = kStNonfinite;
+            st->done = kFailed;
+        } else if (rr <= st->tol2) {
+            st->status = kStOk;
+            st->done = kFinished;
+        } else if (st->maxit <= 0) {
+            st->status = kStNotConverged;
+            st->done = kFinished;
+        }
+    }
+    if (threadIdx.x < y) {
+        double s = 0.0;
+        for (int j = 0; j < y; ++j) s += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+        st->mu[threadIdx.x] = s;
+    }
+}
+
+// G = X^T Y for column blocks X (n x a) and Y (n x b), a, b <= 32, G row-major
+// a x b.  Rows are staged through LDS in tiles of kGramTile; each thread owns
+// up to four entries of G.  Per-workgroup partials are summed in a fixed order
+// by the last workgroup.
+__global__ __launch_bounds__(kBlock) void k_gram(int n, size_t ld, const double* __restrict__ X, int a,
+                                                 const double* __restrict__ Y, int b,
+                                                 double* __restrict__ G, double* part,
+                                                 unsigned* counter) {
+    __shared__ double tile[kGramTile * 2 * kYMax];
+    __shared__ int is_last;
+    const int cols = a + b;
+    const int nout = a * b;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int row0 = blockIdx.x * kGramTile; row0 < n; row0 += gridDim.x * kGramTile) {
+        for (int e = threadIdx.x; e < kGramTile * cols; e += kBlock) {
+            const int c = e / kGramTile, rr = e % kGramTile;
+            const int row = row0 + rr;
+            double v = 0.0;
+            if (row < n) v = c < a ? X[(size_t)c * ld + row] : Y[(size_t)(c - a) * ld + row];
+            tile[rr * cols + c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int o = threadIdx.x + m * kBlock;
+            if (o < nout) {
+                const int i = o / b, j = o % b;
+                double s = acc[m];
+                for (int rr = 0; rr < kGramTile; ++rr) s += tile[rr * cols + i] * tile[rr * cols + a + j];
+                acc[m] = s;
+            }
+        }
+        __syncthreads();
+    }
+    const int nb = gridDim.x;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int o = threadIdx.x + m * kBlock;
+        if (o < nout) part[(size_t)o * nb + blockIdx.x] = acc[m];
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int o = threadIdx.x + m * kBlock;
+        if (o < nout) {
+            const volatile double* po = part + (size_t)o * nb;
+            double s = 0.0;
+            for (int k = 0; k < nb; ++k) s += po[k];
+            G[o] = s;
+        }
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// W(:, i) = sum_k S(:, k) T(k, i) for i < y, k < count (Eq. (podAlgebraicDefinition)
+// with T = diag(w) V_y Sigma_y^{-1}).
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_pod_form(int n, size_t ld, const double* __restrict__ S,
+                                                     int count, const double* __restrict__ T, int y,
+                                                     double* __restrict__ W) {
+    __shared__ double t[kYMax * kYMax];
+    for (int e = threadIdx.x; e < count * y; e += kBlock) t[e] = T[e];
+    __syncthreads();
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double s[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) s[k] = k < count ? S[(size_t)k * ld + i] : 0.0;
+        for (int c = 0; c < y; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (k < count) acc += s[k] * t[k * y + c];
+            W[(size_t)c * ld + i] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ a, double* __restrict__ c,
+                                                 size_t n) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        c[i] = a[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ c, size_t n, double s) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        c[i] = a[i] + s * b[i];
+}
+
+__global__ void k_state_init(DevState* st, int maxit, double tol2, int y) {
+    if (threadIdx.x != 0) return;
+    st->iter = 0;
+    st->done = kRunning;
+    st->status = kStNotConverged;
+    st->y = y;
+    st->maxit = maxit;
+    st->rr = st->rr0 = st->bnorm2 = st->true_rr = 0.0;
+    st->tol2 = tol2;
+    st->rho = st->alpha = st->beta = st->gamma = 0.0;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int vec_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (int)(g < kVecBlocksMax ? g : kVecBlocksMax);
+}
+
+hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
+                         const double* AW, hipStream_t s) {
+    dim3 g(vec_grid(B.n)), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_update<T>), g, t, 0, s, B, y, r, z, q, AW); break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
+                      const double* W, bool init, hipStream_t s) {
+    dim3 g(vec_grid(B.n)), t(kBlock);
+    switch (yb) {
+#define CASE(T)                                                                                    \
+    case T:                                                                                        \
+        if (init) hipLaunchKernelGGL((k_dir<T, true>), g, t, 0, s, B, y, p, x, z, W);              \
+        else hipLaunchKernelGGL((k_dir<T, false>), g, t, 0, s, B, y, p, x, z, W);                  \
+        break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
+                               const double* W, const double* AW, hipStream_t s) {
+    dim3 g(vec_grid(B.n)), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_stage1_apply<T>), g, t, 0, s, B, y, x, r, z, W, AW); break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(int n, size_t ld, const double* X, int a, const double* Y, int b, double* G,
+                       double* part, unsigned* counter, hipStream_t s) {
+    if (a < 1 || b < 1 || a > kYMax || b > kYMax) return hipErrorInvalidValue;
+    int64_t tiles = (n + kGramTile - 1) / kGramTile;
+    int g = (int)(tiles < kGramBlocksMax ? tiles : kGramBlocksMax);
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_gram, dim3(g), dim3(kBlock), 0, s, n, ld, X, a, Y, b, G, part, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
+                           double* W, hipStream_t s) {
+    if (y < 1) return hipSuccess;
+    dim3 g(vec_grid(n)), t(kBlock);
+    switch (basis_tier(count)) {
+#define CASE(K) case K: hipLaunchKernelGGL((k_pod_form<K>), g, t, 0, s, n, ld, S, count, T, y, W); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) {
+    int64_t g = ((int64_t)n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_copy, dim3((int)g), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, double sc,
+                        hipStream_t s) {
+    int64_t g = ((int64_t)n + kBlock - 1) / kBlock;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_triad, dim3((int)g), dim3(kBlock), 0, s, a, b, c, n, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, tol2, y);
+    return hipGetLastError();
+}
+
+}  // namespace podcg

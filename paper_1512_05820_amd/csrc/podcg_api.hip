@@ -1,0 +1,619 @@
+// Host side of libpodcg: the C ABI declared in include/podcg.h.
+//
+// A context owns the SELL copy of the current matrix, the Jacobi inverse, the
+// augmenting basis W with A W and the factor of W^T A W, the snapshot ring,
+// the CG vectors and the device scalar state.  Every entry point validates its
+// arguments, enqueues kernels on the context stream and converts failures to
+// status codes; no C++ exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "podcg.h"
+#include "podcg_device.h"
+
+using namespace podcg;
+
+namespace {
+
+struct Fail {
+    int code;
+};
+
+}  // namespace
+
+struct podcg_ctx {
+    int64_t n = 0;
+    int nslices = 0;
+    size_t ld = 0;
+    podcg_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // matrix
+    bool has_pattern = false, has_values = false;
+    int64_t nnz = 0, nsell = 0, sell_cap = 0;
+    int64_t* d_sptr = nullptr;
+    int* d_cols = nullptr;
+    int* d_map = nullptr;
+    double* d_vals = nullptr;
+    double* d_dinv = nullptr;
+
+    // CG vectors (length ld)
+    double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
+
+    // basis
+    double *d_W = nullptr, *d_AW = nullptr;
+    int y = 0;                 // columns of W
+    int y_kept = 0;            // columns accepted by the last factorisation
+    bool setup_valid = false;
+    bool rank_reduced = false;
+    double cond_G = 1.0;
+    double *d_G = nullptr, *d_R = nullptr, *d_Ginv = nullptr, *d_lamG = nullptr;
+
+    // snapshots
+    double *d_S = nullptr, *d_AS = nullptr, *d_Gs = nullptr, *d_T = nullptr, *d_lamS = nullptr;
+    int head = 0, count = 0, pod_count = 0;
+    int* d_yout = nullptr;
+
+    // scalar state and scratch
+    DevState* d_st = nullptr;
+    double* d_part = nullptr;
+    unsigned* d_counter = nullptr;
+    int* d_flag = nullptr;
+    PollBlock* h_poll = nullptr;     // pinned
+    int* h_int = nullptr;            // pinned scratch ints
+    double* h_dbl = nullptr;         // pinned scratch doubles
+
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
+    std::vector<hipEvent_t> tev;     // per-iteration kernel timing events
+
+    std::string last_error;
+};
+
+namespace {
+
+#define HIPCHECK(expr)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            ctx->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
+            throw Fail{e_ == hipErrorOutOfMemory ? PODCG_ERR_OOM : PODCG_ERR_HIP};                  \
+        }                                                                                           \
+    } while (0)
+
+void fail(podcg_ctx* ctx, int code, const std::string& msg) {
+    ctx->last_error = msg;
+    throw Fail{code};
+}
+
+template <class T>
+void dalloc(podcg_ctx* ctx, T** p, size_t count) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    if (count == 0) count = 1;
+    HIPCHECK(hipMalloc((void**)p, count * sizeof(T)));
+}
+
+DevBufs bufs(podcg_ctx* ctx) {
+    DevBufs B;
+    B.n = (int)ctx->n;
+    B.nslices = ctx->nslices;
+    B.ld = ctx->ld;
+    B.sptr = ctx->d_sptr;
+    B.cols = ctx->d_cols;
+    B.vals = ctx->d_vals;
+    B.dinv = ctx->d_dinv;
+    B.st = ctx->d_st;
+    B.part = ctx->d_part;
+    B.counter = ctx->d_counter;
+    B.Ginv = ctx->d_Ginv;
+    return B;
+}
+
+void sync(podcg_ctx* ctx) { HIPCHECK(hipStreamSynchronize(ctx->stream)); }
+
+void poll(podcg_ctx* ctx) {
+    HIPCHECK(hipMemcpyAsync(ctx->h_poll, ctx->d_st, sizeof(PollBlock), hipMemcpyDeviceToHost,
+                            ctx->stream));
+    sync(ctx);
+}
+
+void check_opts(const podcg_options& o) {
+    if (o.omega < 1 || o.omega > PODCG_MAX_BASIS || o.rank_max < 0 || o.rank_max > PODCG_MAX_BASIS ||
+        o.maxit < 0 || o.check_every < 1 || (o.weights != 0 && o.weights != 1) || o.timing < 0 ||
+        !(o.rank_rtol >= 0.0) || !(o.energy > 0.0))
+        throw Fail{PODCG_ERR_INVALID_ARG};
+}
+
+// A W, G = W^T A W, factor and inverse; sync to read the kept rank.
+void setup_basis(podcg_ctx* ctx) {
+    if (ctx->y == 0) {
+        ctx->y_kept = 0;
+        ctx->setup_valid = true;
+        ctx->cond_G = 1.0;
+        ctx->rank_reduced = false;
+        return;
+    }
+    DevBufs B = bufs(ctx);
+    HIPCHECK(launch_spmm(B, ctx->y, ctx->d_W, ctx->d_AW, ctx->stream));
+    HIPCHECK(launch_gram((int)ctx->n, ctx->ld, ctx->d_W, ctx->y, ctx->d_AW, ctx->y, ctx->d_G,
+                         ctx->d_part, ctx->d_counter, ctx->stream));
+    HIPCHECK(launch_reduced_factor(ctx->d_G, ctx->y, ctx->d_R, ctx->d_Ginv, ctx->d_lamG, ctx->d_st,
+                                   ctx->stream));
+    poll(ctx);
+    const int kept = ctx->h_poll->y;
+    ctx->y_kept = kept;
+    ctx->rank_reduced = kept < ctx->y;
+    if (kept > 0) {
+        HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * kept, hipMemcpyDeviceToHost,
+                                ctx->stream));
+        sync(ctx);
+        const double lmax = ctx->h_dbl[0], lmin = ctx->h_dbl[kept - 1];
+        ctx->cond_G = lmin > 0.0 ? lmax / lmin : INFINITY;
+    } else {
+        ctx->cond_G = 1.0;
+    }
+    ctx->setup_valid = true;
+}
+
+void record(podcg_ctx* ctx, hipEvent_t e) { HIPCHECK(hipEventRecord(e, ctx->stream)); }
+
+int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st, bool plain) {
+    if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+    if (!b || !x || !(rtol >= 0.0)) fail(ctx, PODCG_ERR_INVALID_ARG, "bad solve arguments");
+    podcg_stats S{};
+    float ms = 0.f;
+
+    HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
+    bool did_setup = false;
+    if (!plain && ctx->y > 0 && !ctx->setup_valid) {
+        setup_basis(ctx);
+        did_setup = true;
+    }
+    HIPCHECK(hipEventRecord(ctx->ev_b, ctx->stream));
+    const int y = plain ? 0 : ctx->y_kept;
+    const int yb = basis_tier(y);
+    DevBufs B = bufs(ctx);
+    hipStream_t s = ctx->stream;
+
+    HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s));
+    // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
+    HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
+    // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r, mu = G^{-1} (A W)^T z
+    HIPCHECK(launch_stage1_apply(B, yb, y, x, ctx->d_r, ctx->d_z, ctx->d_W, ctx->d_AW, s));
+    // p = z - W mu
+    HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
+
+    const int timing = ctx->opt.timing;
+    std::vector<int> timed;   // iteration indices with events
+    int launched = 0;
+    int polls = 0;
+    ctx->h_poll->done = kRunning;   // the loop kernels are no-ops once Stage 1 has finished
+    while (ctx->h_poll->done == kRunning && launched < ctx->opt.maxit) {
+        const int batch = std::min(ctx->opt.check_every, ctx->opt.maxit - launched);
+        for (int k = 0; k < batch; ++k, ++launched) {
+            const bool t = timing > 0 && (launched % timing) == 0;
+            size_t base = 0;
+            if (t) {
+                base = timed.size() * 4;
+                while (ctx->tev.size() < base + 4) {
+                    hipEvent_t e;
+                    HIPCHECK(hipEventCreate(&e));
+                    ctx->tev.push_back(e);
+                }
+                timed.push_back(launched);
+                record(ctx, ctx->tev[base + 0]);
+            }
+            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s));
+            if (t) record(ctx, ctx->tev[base + 1]);
+            HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s));
+            if (t) record(ctx, ctx->tev[base + 2]);
+            HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s));
+            if (t) record(ctx, ctx->tev[base + 3]);
+        }
+        poll(ctx);
+        ++polls;
+    }
+    // true residual ||b - A x||
+    HIPCHECK(launch_resid(B, 0, 0, b, x, nullptr, nullptr, false, false, s));
+    HIPCHECK(hipEventRecord(ctx->ev_c, s));
+    poll(ctx);
+    const PollBlock P = *ctx->h_poll;
+
+    HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+    S.setup_ms = did_setup ? ms : 0.0;
+    HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_b, ctx->ev_c));
+    S.solve_ms = ms;
+    S.iters = P.iter;
+    S.rank = y;
+    const double bn = std::sqrt(P.bnorm2);
+    S.bnorm = bn;
+    S.stage1_relres = bn > 0 ? std::sqrt(P.rr0) / bn : std::sqrt(P.rr0);
+    S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
+    S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
+    S.cond_G = y > 0 ? ctx->cond_G : 1.0;
+    S.matvecs = P.iter + 2 + (did_setup ? ctx->y : 0);
+    S.polls = polls;
+    for (size_t k = 0; k < timed.size(); ++k) {
+        if (timed[k] >= P.iter) break;
+        float a = 0, b2 = 0, c = 0;
+        HIPCHECK(hipEventElapsedTime(&a, ctx->tev[4 * k + 0], ctx->tev[4 * k + 1]));
+        HIPCHECK(hipEventElapsedTime(&b2, ctx->tev[4 * k + 1], ctx->tev[4 * k + 2]));
+        HIPCHECK(hipEventElapsedTime(&c, ctx->tev[4 * k + 2], ctx->tev[4 * k + 3]));
+        S.spmv_ms += a;
+        S.update_ms += b2;
+        S.dir_ms += c;
+        S.timed_iters += 1;
+    }
+    int code = P.status;
+    if (P.done == kFailed) {
+        code = P.status;
+        ctx->last_error = code == PODCG_ERR_NOT_SPD ? "(A p, p) <= 0: matrix not SPD"
+                                                    : "non-finite value in the iteration";
+    } else if (code == PODCG_OK && !plain && ctx->rank_reduced) {
+        code = PODCG_RANK_REDUCED;
+    }
+    S.status = code;
+    if (st) *st = S;
+    return code;
+}
+
+template <class F>
+int guarded(podcg_ctx* ctx, F&& f) {
+    if (!ctx) return PODCG_ERR_INVALID_ARG;
+    try {
+        if (hipSetDevice(ctx->device) != hipSuccess) return PODCG_ERR_HIP;
+        return f();
+    } catch (const Fail& e) {
+        if (ctx->last_error.empty()) ctx->last_error = podcg_strerror(e.code);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        ctx->last_error = "host allocation failed";
+        return PODCG_ERR_OOM;
+    } catch (...) {
+        ctx->last_error = "unexpected exception";
+        return PODCG_ERR_HIP;
+    }
+}
+
+void release(podcg_ctx* ctx) {
+    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
+                   ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
+                   ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_AS, ctx->d_Gs, ctx->d_T,
+                   ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
+    if (ctx->h_int) (void)hipHostFree(ctx->h_int);
+    if (ctx->h_dbl) (void)hipHostFree(ctx->h_dbl);
+    hipEvent_t evs[] = {ctx->ev_a, ctx->ev_b, ctx->ev_c, ctx->ev_d};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void podcg_default_options(podcg_options* o) {
+    if (!o) return;
+    o->omega = 20;
+    o->rank_max = 10;
+    o->maxit = 10000;
+    o->check_every = 16;
+    o->weights = 0;
+    o->timing = 0;
+    o->rank_rtol = 1e-12;
+    o->energy = 1.0;
+}
+
+const char* podcg_strerror(int code) {
+    switch (code) {
+        case PODCG_OK: return "success";
+        case PODCG_NOT_CONVERGED: return "iteration cap reached before the tolerance";
+        case PODCG_RANK_REDUCED: return "augmenting basis truncated at a small Cholesky pivot";
+        case PODCG_ERR_INVALID_ARG: return "invalid argument";
+        case PODCG_ERR_HIP: return "HIP runtime error";
+        case PODCG_ERR_OOM: return "out of device memory";
+        case PODCG_ERR_NOT_SPD: return "matrix is not symmetric positive definite";
+        case PODCG_ERR_NONFINITE: return "non-finite value";
+        case PODCG_ERR_NO_MATRIX: return "no matrix has been set";
+        case PODCG_ERR_SIZE: return "size mismatch";
+        default: return "unknown status";
+    }
+}
+
+const char* podcg_last_error(podcg_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip_stream) {
+    if (!out) return PODCG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || n > (int64_t)0x7fffffff - 64) return PODCG_ERR_INVALID_ARG;
+    podcg_options o;
+    podcg_default_options(&o);
+    if (opt) o = *opt;
+    try {
+        check_opts(o);
+    } catch (const Fail& e) {
+        return e.code;
+    }
+    podcg_ctx* ctx = new (std::nothrow) podcg_ctx();
+    if (!ctx) return PODCG_ERR_OOM;
+    ctx->n = n;
+    ctx->opt = o;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return PODCG_ERR_HIP;
+    }
+    ctx->nslices = (int)((n + kSlice - 1) / kSlice);
+    ctx->ld = (size_t)ctx->nslices * kSlice;
+    int rc = guarded(ctx, [&]() {
+        const size_t ld = ctx->ld;
+        dalloc(ctx, &ctx->d_sptr, (size_t)ctx->nslices + 1);
+        dalloc(ctx, &ctx->d_dinv, ld);
+        dalloc(ctx, &ctx->d_r, ld);
+        dalloc(ctx, &ctx->d_z, ld);
+        dalloc(ctx, &ctx->d_p, ld);
+        dalloc(ctx, &ctx->d_q, ld);
+        dalloc(ctx, &ctx->d_W, ld * (size_t)std::max(1, o.rank_max));
+        dalloc(ctx, &ctx->d_AW, ld * (size_t)std::max(1, o.rank_max));
+        dalloc(ctx, &ctx->d_S, ld * (size_t)o.omega);
+        dalloc(ctx, &ctx->d_AS, ld * (size_t)o.omega);
+        dalloc(ctx, &ctx->d_G, kYMax * kYMax);
+        dalloc(ctx, &ctx->d_R, kYMax * kYMax);
+        dalloc(ctx, &ctx->d_Ginv, kYMax * kYMax);
+        dalloc(ctx, &ctx->d_lamG, kYMax);
+        dalloc(ctx, &ctx->d_Gs, kYMax * kYMax);
+        dalloc(ctx, &ctx->d_T, kYMax * kYMax);
+        dalloc(ctx, &ctx->d_lamS, kYMax);
+        dalloc(ctx, &ctx->d_yout, 4);
+        dalloc(ctx, &ctx->d_st, 1);
+        dalloc(ctx, &ctx->d_part, kPartials);
+        dalloc(ctx, &ctx->d_counter, 16);
+        dalloc(ctx, &ctx->d_flag, 4);
+        HIPCHECK(hipMemsetAsync(ctx->d_counter, 0, 16 * sizeof(unsigned), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_r, 0, ld * sizeof(double), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_z, 0, ld * sizeof(double), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_p, 0, ld * sizeof(double), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_q, 0, ld * sizeof(double), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_Ginv, 0, kYMax * kYMax * sizeof(double), ctx->stream));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_poll, sizeof(PollBlock), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_int, 64 * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_dbl, 64 * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipEventCreate(&ctx->ev_a));
+        HIPCHECK(hipEventCreate(&ctx->ev_b));
+        HIPCHECK(hipEventCreate(&ctx->ev_c));
+        HIPCHECK(hipEventCreate(&ctx->ev_d));
+        sync(ctx);
+        return PODCG_OK;
+    });
+    if (rc != PODCG_OK) {
+        release(ctx);
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return PODCG_OK;
+}
+
+int podcg_destroy(podcg_ctx* ctx) {
+    if (!ctx) return PODCG_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    delete ctx;
+    return PODCG_OK;
+}
+
+int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                     const double* vals) {
+    return guarded(ctx, [&]() {
+        if (!vals || nnz < 1 || nnz > (int64_t)0x7fffffff) fail(ctx, PODCG_ERR_INVALID_ARG, "bad nnz or vals");
+        if ((rowptr == nullptr) != (colind == nullptr))
+            fail(ctx, PODCG_ERR_INVALID_ARG, "rowptr and colind must both be given or both be NULL");
+        hipStream_t s = ctx->stream;
+        const int n = (int)ctx->n;
+        if (rowptr) {
+            HIPCHECK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s));
+            HIPCHECK(launch_validate_csr(n, nnz, rowptr, colind, ctx->d_flag, s));
+            HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            sync(ctx);
+            if (ctx->h_int[0]) {
+                ctx->has_pattern = ctx->has_values = false;
+                fail(ctx, PODCG_ERR_INVALID_ARG,
+                     (ctx->h_int[0] & 1) ? "rowptr is not a valid CSR offset array"
+                                         : "column index out of range");
+            }
+            HIPCHECK(launch_slice_widths(n, ctx->nslices, rowptr, ctx->d_sptr, s));
+            HIPCHECK(launch_scan_slices(ctx->nslices, ctx->d_sptr, s));
+            HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_sptr + ctx->nslices, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s));
+            sync(ctx);
+            int64_t nsell = 0;
+            std::memcpy(&nsell, ctx->h_dbl, sizeof(int64_t));
+            if (nsell > ctx->sell_cap) {
+                ctx->has_pattern = ctx->has_values = false;
+                dalloc(ctx, &ctx->d_cols, (size_t)nsell);
+                dalloc(ctx, &ctx->d_map, (size_t)nsell);
+                dalloc(ctx, &ctx->d_vals, (size_t)nsell);
+                ctx->sell_cap = nsell;
+            }
+            ctx->nsell = nsell;
+            HIPCHECK(launch_fill_pattern(n, ctx->nslices, rowptr, colind, ctx->d_sptr, ctx->d_cols,
+                                         ctx->d_map, s));
+            ctx->has_pattern = true;
+            ctx->nnz = nnz;
+        } else {
+            if (!ctx->has_pattern) fail(ctx, PODCG_ERR_NO_MATRIX, "values-only update before any pattern");
+            if (nnz != ctx->nnz) fail(ctx, PODCG_ERR_SIZE, "nnz differs from the cached pattern");
+        }
+        HIPCHECK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s));
+        HIPCHECK(launch_fill_values(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_map, vals,
+                                    ctx->d_vals, ctx->d_dinv, ctx->d_flag, s));
+        HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        ctx->setup_valid = false;
+        if (ctx->h_int[0] & 8) {
+            ctx->has_values = false;
+            fail(ctx, PODCG_ERR_NONFINITE, "non-finite matrix value");
+        }
+        if (ctx->h_int[0] & 4) {
+            ctx->has_values = false;
+            fail(ctx, PODCG_ERR_NOT_SPD, "missing or non-positive diagonal entry");
+        }
+        ctx->has_values = true;
+        return PODCG_OK;
+    });
+}
+
+int podcg_push_snapshot(podcg_ctx* ctx, const double* x) {
+    return guarded(ctx, [&]() {
+        if (!x) fail(ctx, PODCG_ERR_INVALID_ARG, "null snapshot");
+        HIPCHECK(launch_copy(x, ctx->d_S + (size_t)ctx->head * ctx->ld, (size_t)ctx->n, ctx->stream));
+        ctx->head = (ctx->head + 1) % ctx->opt.omega;
+        ctx->count = std::min(ctx->count + 1, ctx->opt.omega);
+        return PODCG_OK;
+    });
+}
+
+int podcg_reset_snapshots(podcg_ctx* ctx) {
+    return guarded(ctx, [&]() {
+        ctx->head = 0;
+        ctx->count = 0;
+        return PODCG_OK;
+    });
+}
+
+int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out) {
+    return guarded(ctx, [&]() {
+        if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+        const int count = ctx->count;
+        if (count == 0 || ctx->opt.rank_max == 0) {
+            ctx->y = 0;
+            ctx->pod_count = 0;
+            ctx->setup_valid = false;
+            if (rank_out) *rank_out = 0;
+            return PODCG_OK;
+        }
+        hipStream_t s = ctx->stream;
+        DevBufs B = bufs(ctx);
+        // the used snapshots are ring slots 0..count-1; weight by age
+        double w[kYMax];
+        for (int slot = 0; slot < count; ++slot) {
+            const int age = (ctx->head - 1 - slot + ctx->opt.omega) % ctx->opt.omega;   // 0 = newest
+            w[slot] = ctx->opt.weights == 0 ? std::ldexp(1.0, -age) : 1.0;
+        }
+        HIPCHECK(launch_spmm(B, count, ctx->d_S, ctx->d_AS, s));
+        HIPCHECK(launch_gram((int)ctx->n, ctx->ld, ctx->d_S, count, ctx->d_AS, count, ctx->d_Gs,
+                             ctx->d_part, ctx->d_counter, s));
+        HIPCHECK(launch_pod_coeffs(ctx->d_Gs, count, w, ctx->opt.rank_max, ctx->opt.rank_rtol,
+                                   ctx->opt.energy, ctx->d_T, ctx->d_lamS, ctx->d_yout, s));
+        HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_yout, sizeof(int), hipMemcpyDeviceToHost, s));
+        sync(ctx);
+        const int y = ctx->h_int[0];
+        HIPCHECK(launch_pod_form((int)ctx->n, ctx->ld, ctx->d_S, count, ctx->d_T, y, ctx->d_W, s));
+        ctx->y = y;
+        ctx->pod_count = count;
+        ctx->setup_valid = false;
+        if (rank_out) *rank_out = y;
+        return PODCG_OK;
+    });
+}
+
+int podcg_set_basis(podcg_ctx* ctx, const double* W, int32_t y) {
+    return guarded(ctx, [&]() {
+        if (y < 0 || y > ctx->opt.rank_max || (y > 0 && !W))
+            fail(ctx, PODCG_ERR_INVALID_ARG, "basis dimension out of range");
+        for (int k = 0; k < y; ++k)
+            HIPCHECK(launch_copy(W + (size_t)k * ctx->n, ctx->d_W + (size_t)k * ctx->ld, (size_t)ctx->n,
+                                 ctx->stream));
+        ctx->y = y;
+        ctx->setup_valid = false;
+        return PODCG_OK;
+    });
+}
+
+int podcg_get_basis(podcg_ctx* ctx, double* W, int32_t* rank) {
+    return guarded(ctx, [&]() {
+        if (rank) *rank = ctx->y;
+        if (ctx->y > 0 && !W) fail(ctx, PODCG_ERR_INVALID_ARG, "null output");
+        for (int k = 0; k < ctx->y; ++k)
+            HIPCHECK(launch_copy(ctx->d_W + (size_t)k * ctx->ld, W + (size_t)k * ctx->n, (size_t)ctx->n,
+                                 ctx->stream));
+        sync(ctx);
+        return PODCG_OK;
+    });
+}
+
+int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank) {
+    return guarded(ctx, [&]() {
+        if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+        if (!ctx->setup_valid) setup_basis(ctx);
+        const int y = ctx->y_kept;
+        if (rank) *rank = y;
+        std::vector<double> g((size_t)kYMax * kYMax);
+        if (G && ctx->y > 0) {
+            HIPCHECK(hipMemcpy(g.data(), ctx->d_G, sizeof(double) * ctx->y * ctx->y, hipMemcpyDeviceToHost));
+            for (int i = 0; i < y; ++i)
+                for (int j = 0; j < y; ++j) G[i * y + j] = g[(size_t)i * ctx->y + j];
+        }
+        if (Ginv && y > 0)
+            HIPCHECK(hipMemcpy(Ginv, ctx->d_Ginv, sizeof(double) * y * y, hipMemcpyDeviceToHost));
+        return PODCG_OK;
+    });
+}
+
+int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count) {
+    return guarded(ctx, [&]() {
+        if (count) *count = ctx->pod_count;
+        if (lam && ctx->pod_count > 0)
+            HIPCHECK(hipMemcpy(lam, ctx->d_lamS, sizeof(double) * ctx->pod_count, hipMemcpyDeviceToHost));
+        return PODCG_OK;
+    });
+}
+
+int podcg_solve(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st) {
+    return guarded(ctx, [&]() { return solve_impl(ctx, b, x, rtol, st, false); });
+}
+
+int podcg_solve_plain(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st) {
+    return guarded(ctx, [&]() { return solve_impl(ctx, b, x, rtol, st, true); });
+}
+
+int podcg_matvec(podcg_ctx* ctx, const double* x, double* y) {
+    return guarded(ctx, [&]() {
+        if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+        if (!x || !y || x == y) fail(ctx, PODCG_ERR_INVALID_ARG, "bad vectors");
+        HIPCHECK(launch_matvec(bufs(ctx), x, y, ctx->stream));
+        return PODCG_OK;
+    });
+}
+
+int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double* c, int64_t n,
+                       double s, int32_t reps, double* ms) {
+    return guarded(ctx, [&]() {
+        if (!a || !b || !c || n < 1 || reps < 1) fail(ctx, PODCG_ERR_INVALID_ARG, "bad triad arguments");
+        HIPCHECK(launch_triad(a, b, c, (size_t)n, s, ctx->stream));   // warm-up
+        HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
+        for (int r = 0; r < reps; ++r) HIPCHECK(launch_triad(a, b, c, (size_t)n, s, ctx->stream));
+        HIPCHECK(hipEventRecord(ctx->ev_b, ctx->stream));
+        sync(ctx);
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, ctx->ev_a, ctx->ev_b));
+        if (ms) *ms = t / reps;
+        return PODCG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Internal declarations of libpodcg: device-side state, reduction helpers and
+// the kernel launchers shared by the translation units.  Not a public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace podcg {
+
+constexpr int kWave = 64;                 // CDNA wavefront
+constexpr int kBlock = 256;               // threads per workgroup (4 waves)
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kSlice = 64;                // SELL slice height = one row per lane
+constexpr int kYMax = 32;                 // largest basis / snapshot count
+constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
+constexpr int kVecBlocksMax = 2048;       // grid cap of the streaming vector kernels
+constexpr int kSpmvBlocksMax = 8192;      // grid cap of the SELL kernels
+constexpr int kGramBlocksMax = 512;       // grid cap of the tall-skinny Gram kernel
+constexpr int kGramTile = 64;             // rows per LDS tile of the Gram kernel
+// doubles in the partials buffer: the larger of the loop kernels' need and the
+// Gram kernel's (one slot per output entry per workgroup)
+constexpr int kPartials = (kNVMax * kSpmvBlocksMax > kYMax * kYMax * kGramBlocksMax)
+                              ? kNVMax * kSpmvBlocksMax
+                              : kYMax * kYMax * kGramBlocksMax;
+
+// `done` values of the iteration state machine (see the loop kernels).
+constexpr int kRunning = 0;
+constexpr int kFinished = 1;
+constexpr int kConvergedPending = 2;      // x += alpha p still to apply in this iteration
+constexpr int kCapPending = 3;            // iteration cap reached, same pending update
+constexpr int kFailed = -1;
+
+// Scalar state of one solve, resident in device memory.  The first block is
+// what the host polls.
+struct DevState {
+    int iter, done, status, y;
+    int maxit, pad0, pad1, pad2;
+    double rr, rr0, bnorm2, true_rr;
+    double tol2, rho, alpha, beta, gamma;
+    double pad3[3];
+    double mu[kYMax];      // projection coefficients G^{-1} (A W)^T z
+    double what[kYMax];    // Stage-1 coefficients G^{-1} W^T rbar
+};
+
+struct PollBlock {         // host mirror of the first 48 bytes of DevState
+    int iter, done, status, y;
+    int maxit, pad0, pad1, pad2;
+    double rr, rr0, bnorm2, true_rr;
+};
+
+// Codes written by kernels into DevState::status (same values as the ABI).
+constexpr int kStOk = 0, kStNotConverged = 1, kStNotSpd = -4, kStNonfinite = -5;
+
+__device__ __forceinline__ bool is_finite(double v) { return v == v && fabs(v) <= 1.0e308; }
+
+// Butterfly sum over the 64 lanes of a wave; every lane gets the total, and
+// the order of additions is fixed.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Workgroup-wide reduction of NV values (fixed order).  `lds` needs
+// kWavesPerBlock * NV doubles.  The result is left in lds[0..NV) for all threads.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = lds[threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * NV + threadIdx.x];
+        lds[kWavesPerBlock * NV + threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) lds[threadIdx.x] = lds[kWavesPerBlock * NV + threadIdx.x];
+    __syncthreads();
+}
+
+// Deterministic grid reduction.  Every workgroup stores its NV partial sums
+// (part[k * gridDim.x + block]); the last workgroup to arrive sums all of them
+// in a fixed order and returns true with the totals in lds[0..NV).  The
+// counter is returned to zero by that workgroup.
+template <int NV>
+__device__ __forceinline__ bool grid_sum_last(double (&v)[NV], double* part, unsigned* counter,
+                                              double* lds) {
+    __shared__ int is_last;
+    block_sum<NV>(v, lds);
+    const int nb = gridDim.x;
+    if (threadIdx.x < NV) part[(size_t)threadIdx.x * nb + blockIdx.x] = lds[threadIdx.x];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == (unsigned)(nb - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        const volatile double* pk = part + (size_t)k * nb;
+        for (int b = threadIdx.x; b < nb; b += kBlock) s += pk[b];
+        acc[k] = s;
+    }
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// Workgroup index remapped so that each XCD (workgroups are dealt to the 8
+// XCDs round-robin) walks a contiguous range of the problem.  A bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7;
+    const int t = b >> 3;
+    return x * q + (x < r ? x : r) + t;
+}
+
+// ------------------------------------------------------------------ launchers
+// Device buffers of one context, passed to the launchers.
+struct DevBufs {
+    int n;
+    int nslices;
+    size_t ld;                 // leading dimension of column blocks (W, AW, S, AS)
+    const int64_t* sptr;       // slice offsets, nslices + 1
+    const int* cols;           // SELL column indices
+    const double* vals;        // SELL values
+    const double* dinv;        // 1 / diag(A)
+    DevState* st;
+    double* part;
+    unsigned* counter;
+    const double* Ginv;        // y x y row-major
+};
+
+// SELL kernels (k_sell.hip)
+hipError_t launch_validate_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                               int* flag, hipStream_t s);
+hipError_t launch_slice_widths(int n, int nslices, const int32_t* rowptr, int64_t* sptr, hipStream_t s);
+hipError_t launch_scan_slices(int nslices, int64_t* sptr, hipStream_t s);
+hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const int32_t* colind,
+                               const int64_t* sptr, int* cols, int* map, hipStream_t s);
+hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
+                              const int* map, const double* csr_vals, double* vals, double* dinv,
+                              int* flag, hipStream_t s);
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s);
+hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);
+hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x,
+                        double* r, const double* W, bool store, bool stage1, hipStream_t s);
+hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s);
+
+// Streaming vector kernels (k_vec.hip)
+int basis_tier(int y);   // smallest compiled register tier >= y
+hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
+                         const double* AW, hipStream_t s);
+hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
+                      const double* W, bool init, hipStream_t s);
+hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
+                               const double* W, const double* AW, hipStream_t s);
+hipError_t launch_gram(int n, size_t ld, const double* X, int a, const double* Y, int b,
+                       double* G, double* part, unsigned* counter, hipStream_t s);
+hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
+                           double* W, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
+hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, double sc,
+                        hipStream_t s);
+hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s);
+
+// Register tiers compiled for the basis dimension (runtime y <= tier).
+#define PODCG_POS_TIERS(X) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+#define PODCG_TIERS(X) X(0) PODCG_POS_TIERS(X)
+
+// Single-workgroup dense kernels (k_small.hip)
+// G (m x m row-major, symmetrised here) -> R, Ginv = G^{-1} on the accepted
+// leading block, kept rank written to st->y, eigenvalues of G to lam (cond).
+hipError_t launch_reduced_factor(double* G, int m, double* R, double* Ginv, double* lam,
+                                 DevState* st, hipStream_t s);
+// POD coefficients: Gram (count x count, unweighted S^T A S) -> weighted,
+// symmetrised, eigen-decomposed; writes T (count x y row-major) with
+// W = S T, lam (count), and y to *y_out.
+hipError_t launch_pod_coeffs(const double* Gs, int count, const double* w, int rank_max,
+                             double rank_rtol, double energy, double* T, double* lam, int* y_out,
+                             hipStream_t s);
+
+}  // namespace podcg

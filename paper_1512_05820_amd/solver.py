@@ -1,0 +1,145 @@
+"""Python face of libpodcg: one object per context, torch tensors in and out.
+
+Every method marshals arguments and calls the C ABI of the same name; all
+arithmetic runs in the library's HIP kernels.  Tensors must be contiguous
+float64 (int32 for CSR indices) on the GPU the context was created on.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class PodCGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"podcg error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t: torch.Tensor | None, dtype) -> C.c_void_p | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"tensor must be contiguous {dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+class PodCG:
+    """Context for a sequence of SPD systems of size n (include/podcg.h)."""
+
+    def __init__(self, n: int, omega: int = 20, rank_max: int = 10, maxit: int = 10000,
+                 check_every: int = 16, weights: str = "idw", timing: int = 0,
+                 rank_rtol: float = 1e-12, energy: float = 1.0, stream=None):
+        self._L = L.load()
+        opt = L.Options()
+        self._L.podcg_default_options(C.byref(opt))
+        opt.omega, opt.rank_max, opt.maxit = omega, rank_max, maxit
+        opt.check_every, opt.timing = check_every, timing
+        opt.weights = {"idw": 0, "unit": 1}[weights]
+        opt.rank_rtol, opt.energy = rank_rtol, energy
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.n = int(n)
+        self.omega, self.rank_max = omega, rank_max
+        h = C.c_void_p()
+        rc = self._L.podcg_create(C.byref(h), self.n, C.byref(opt), C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise PodCGError(rc, self._L.podcg_strerror(rc).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.podcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise PodCGError(rc, self._L.podcg_last_error(self._h).decode())
+        return rc
+
+    # ---------------------------------------------------------------- the four calls
+    def set_matrix(self, vals: torch.Tensor, rowptr: torch.Tensor | None = None,
+                   colind: torch.Tensor | None = None):
+        """A_j from CSR (rowptr/colind None: same pattern as before)."""
+        self._check(self._L.podcg_set_matrix(self._h, vals.numel(), _ptr(rowptr, torch.int32),
+                                             _ptr(colind, torch.int32), _ptr(vals, torch.float64)))
+
+    def push_snapshot(self, s: torch.Tensor):
+        self._check(self._L.podcg_push_snapshot(self._h, _ptr(s, torch.float64)))
+
+    def build_pod(self) -> int:
+        y = C.c_int32()
+        self._check(self._L.podcg_build_pod(self._h, C.byref(y)))
+        return y.value
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor, rtol: float) -> L.Stats:
+        """x holds xbar on entry and the solution on return."""
+        st = L.Stats()
+        self._check(self._L.podcg_solve(self._h, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                        float(rtol), C.byref(st)))
+        return st
+
+    # ---------------------------------------------------------------- the rest
+    def solve_plain(self, b: torch.Tensor, x: torch.Tensor, rtol: float) -> L.Stats:
+        st = L.Stats()
+        self._check(self._L.podcg_solve_plain(self._h, _ptr(b, torch.float64),
+                                              _ptr(x, torch.float64), float(rtol), C.byref(st)))
+        return st
+
+    def reset_snapshots(self):
+        self._check(self._L.podcg_reset_snapshots(self._h))
+
+    def set_basis(self, W: torch.Tensor | None):
+        """W: (n, y) tensor (stored column-major by the library) or None."""
+        if W is None or W.numel() == 0:
+            self._check(self._L.podcg_set_basis(self._h, None, 0))
+            return
+        Wc = W.t().contiguous()
+        self._check(self._L.podcg_set_basis(self._h, _ptr(Wc, torch.float64), Wc.shape[0]))
+
+    def get_basis(self) -> torch.Tensor:
+        out = torch.empty((max(self.rank_max, 1), self.n), dtype=torch.float64, device="cuda")
+        y = C.c_int32()
+        self._check(self._L.podcg_get_basis(self._h, _ptr(out, torch.float64), C.byref(y)))
+        return out[: y.value].t()
+
+    def get_reduced(self):
+        """(G, G^{-1}) of the current basis as NumPy arrays."""
+        G = np.zeros(L.MAX_BASIS * L.MAX_BASIS)
+        Gi = np.zeros(L.MAX_BASIS * L.MAX_BASIS)
+        y = C.c_int32()
+        self._check(self._L.podcg_get_reduced(self._h, G.ctypes.data_as(C.c_void_p),
+                                              Gi.ctypes.data_as(C.c_void_p), C.byref(y)))
+        k = y.value
+        return G[: k * k].reshape(k, k), Gi[: k * k].reshape(k, k)
+
+    def pod_spectrum(self) -> np.ndarray:
+        lam = np.zeros(L.MAX_BASIS)
+        c = C.c_int32()
+        self._check(self._L.podcg_get_pod_spectrum(self._h, lam.ctypes.data_as(C.c_void_p),
+                                                   C.byref(c)))
+        return lam[: c.value].copy()
+
+    def matvec(self, x: torch.Tensor, y: torch.Tensor):
+        self._check(self._L.podcg_matvec(self._h, _ptr(x, torch.float64), _ptr(y, torch.float64)))
+
+    def stream_triad(self, a, b, c, s: float = 3.0, reps: int = 20) -> float:
+        ms = C.c_double()
+        self._check(self._L.podcg_stream_triad(self._h, _ptr(a, torch.float64),
+                                               _ptr(b, torch.float64), _ptr(c, torch.float64),
+                                               a.numel(), float(s), int(reps), C.byref(ms)))
+        return ms.value

@@ -1,0 +1,385 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Protocol:
+  * kernels on identical inputs (SpMV, Stage 1, POD basis): relative error
+    <= 1e-12, far inside the 1e-10 the method's FP64 path must meet;
+  * lockstep: the GPU runs exactly the oracle's iteration count from the same
+    (A, b, xbar, W); solutions agree to 1e-10 relative;
+  * closed loop: each side runs its own sequence; every GPU solution meets
+    the tolerance by the oracle's own residual, and iteration counts agree
+    to within one.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from problems import config1, config2, tiny
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1512_05820_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.load()
+    return P
+
+
+def _ctx(P, n, **kw):
+    return P.PodCG(n, **kw)
+
+
+def _set(ctx, rowptr, colind, vals):
+    ctx.set_matrix(_dev(vals), _dev(rowptr, torch.int32), _dev(colind, torch.int32))
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ------------------------------------------------------------------- kernels
+
+@pytest.mark.parametrize("N,dim", [(32, 2), (23, 2), (3, 2), (21, 3), (41, 3)])
+def test_matvec_matches_oracle(P, N, dim):
+    cfg = config1(N=N) if dim == 2 else config2(N=N, steps=3)
+    vals = cfg.matrix_values(2)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    x = _rng(N).standard_normal(cfg.n)
+    ref = oracle.matvec(A, x)
+    ctx = _ctx(P, cfg.n)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    y = torch.empty(cfg.n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), ref) <= 1e-14
+    # values-only update keeps the pattern
+    ctx.set_matrix(_dev(vals * 2.0))
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), 2.0 * ref) <= 1e-14
+
+
+def test_matvec_general_sparsity_ragged_rows(P):
+    r = _rng(3)
+    n = 300
+    A = np.zeros((n, n))
+    for i in range(n):
+        k = r.integers(0, 40)
+        cols = r.choice(n, size=k, replace=False)
+        A[i, cols] = r.standard_normal(k)
+    A = A + A.T + np.diag(np.full(n, 50.0))
+    rowptr, colind, vals = tiny.dense_to_csr(A)
+    x = r.standard_normal(n)
+    ctx = _ctx(P, n)
+    _set(ctx, rowptr, colind, vals)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), A @ x) <= 1e-13
+
+
+def test_stage1_matches_closed_form_projection(P):
+    cfg = config2(N=19, steps=3)
+    vals = cfg.matrix_values(1)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    r = _rng(5)
+    W = r.standard_normal((cfg.n, 6))
+    b = r.standard_normal(cfg.n)
+    xbar = r.standard_normal(cfg.n)
+    xo, so = oracle.aug_pcg(A, b, xbar, W, tol=0.0, maxit=0)
+    ctx = _ctx(P, cfg.n, rank_max=6, maxit=0)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    ctx.set_basis(_dev(W))
+    x = _dev(xbar)
+    st = ctx.solve(_dev(b), x, 0.0)
+    assert st.iters == 0 and st.status == 1 and st.rank == 6
+    xg = _host(x)
+    assert _relerr(xg, xo) <= 1e-12
+    res = b - oracle.matvec(A, xg)
+    assert np.linalg.norm(W.T @ res) <= 1e-10 * np.linalg.norm(W) * np.linalg.norm(b)
+    assert abs(st.stage1_relres - so.stage1_relres) <= 1e-9 * so.stage1_relres
+
+
+def test_reduced_matrix_and_inverse(P):
+    cfg = config2(N=17, steps=3)
+    vals = cfg.matrix_values(1)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    W = _rng(6).standard_normal((cfg.n, 5))
+    _, G, R, kept = oracle.reduced_setup(A, W)
+    ctx = _ctx(P, cfg.n, rank_max=5)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    ctx.set_basis(_dev(W))
+    Gg, Gi = ctx.get_reduced()
+    assert kept == 5 and Gg.shape == (5, 5)
+    assert np.allclose(Gg, G, rtol=1e-13, atol=1e-13 * np.abs(G).max())
+    assert np.allclose(Gi @ G, np.eye(5), atol=1e-11)
+
+
+def test_pod_basis_matches_oracle_subspace(P):
+    cfg = config2(N=18, steps=4)
+    vals = cfg.matrix_values(2)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    r = _rng(7)
+    snaps = [r.standard_normal(cfg.n) for _ in range(7)]     # pushed oldest first
+    S_recent_first = np.stack(snaps[::-1], axis=1)
+    Wo, lam_o = oracle.pod_evd(A, S_recent_first, oracle.idw_weights(7), 5)
+    ctx = _ctx(P, cfg.n, omega=5, rank_max=5)                 # ring keeps the last 5
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    for s in snaps:
+        ctx.push_snapshot(_dev(s))
+    y = ctx.build_pod()
+    Wo5, lam5 = oracle.pod_evd(A, np.stack(snaps[::-1][:5], axis=1), oracle.idw_weights(5), 5)
+    assert y == Wo5.shape[1] == 5
+    lam_g = ctx.pod_spectrum()
+    assert np.allclose(lam_g, lam5, rtol=1e-11, atol=1e-13 * lam5[0])
+    Wg = _host(ctx.get_basis())
+    for i in range(y):     # columns agree up to the eigenvector sign convention
+        s = np.sign(Wg[:, i] @ Wo5[:, i])
+        assert _relerr(s * Wg[:, i], Wo5[:, i]) <= 1e-9
+    D = cfg.fv.dense(vals)
+    assert np.allclose(Wg.T @ D @ Wg, np.eye(y), atol=1e-10)
+
+
+def test_pod_rank_cut_on_duplicate_snapshots(P):
+    cfg = config1(N=16)
+    vals = cfg.matrix_values(1)
+    r = _rng(8)
+    a, b = r.standard_normal(cfg.n), r.standard_normal(cfg.n)
+    ctx = _ctx(P, cfg.n, omega=5, rank_max=4)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    for s in (a, b, a, 2 * b, a + b):
+        ctx.push_snapshot(_dev(s))
+    assert ctx.build_pod() == 2
+
+
+# ------------------------------------------------------------------- solves
+
+def _lockstep(P, cfg, vals, b, xbar, W, tol, maxit=20000):
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    xo, so = oracle.aug_pcg(A, b, xbar, W, tol=tol, maxit=maxit)
+    y = 0 if W is None else W.shape[1]
+    ctx = _ctx(P, cfg.n, rank_max=max(y, 1), maxit=so.iters)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    ctx.set_basis(None if W is None else _dev(W))
+    x = _dev(xbar)
+    st = ctx.solve(_dev(b), x, 0.0)
+    return xo, so, _host(x), st
+
+
+@pytest.mark.parametrize("use_basis", [False, True])
+def test_lockstep_config1(P, use_basis):
+    cfg = config1()
+    vals = cfg.matrix_values(3)
+    b = cfg.rhs(3)
+    W = _rng(9).standard_normal((cfg.n, 4)) if use_basis else None
+    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol)
+    assert so.status == 0 and st.iters == so.iters
+    assert _relerr(xg, xo) <= 1e-10
+
+
+@pytest.mark.parametrize("N", [24, 33])
+def test_lockstep_config2_small(P, N):
+    cfg = config2(N=N, steps=4)
+    vals = cfg.matrix_values(2)
+    r = _rng(N)
+    b = cfg.rhs(2, r.standard_normal(cfg.n) * 1e-3)
+    W = r.standard_normal((cfg.n, 10))
+    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol)
+    assert so.status == 0 and st.iters == so.iters
+    assert _relerr(xg, xo) <= 1e-10
+
+
+def _gpu_sequence(P, cfg, steps, method="aug", warm=False):
+    ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank)
+    rowptr, colind = _dev(cfg.rowptr, torch.int32), _dev(cfg.colind, torch.int32)
+    out = []
+    x_prev = None
+    for j in range(1, steps + 1):
+        vals = cfg.matrix_values(j)
+        if j == 1:
+            ctx.set_matrix(_dev(vals), rowptr, colind)
+        else:
+            ctx.set_matrix(_dev(vals))
+        b = cfg.rhs(j, None if x_prev is None else x_prev)
+        if method == "aug" or not warm or x_prev is None:
+            xbar = np.zeros(cfg.n)
+        else:
+            xbar = x_prev
+        x = _dev(xbar)
+        st = ctx.solve(_dev(b), x, cfg.tol) if method == "aug" else ctx.solve_plain(_dev(b), x, cfg.tol)
+        xh = _host(x)
+        if method == "aug":
+            ctx.push_snapshot(_dev(xh - xbar))
+            ctx.build_pod()
+        out.append((st.as_dict(), xh, b, vals))
+        x_prev = xh
+    return out
+
+
+@pytest.mark.parametrize("which", ["c1", "c1_r2", "c2_small"])
+def test_closed_loop_sequence(P, which):
+    if which == "c1":
+        cfg = config1()
+    elif which == "c1_r2":
+        cfg = config1(variant="r2", steps=6)
+    else:
+        cfg = config2(N=26, steps=8)
+    orc = oracle.run_sequence(cfg, "aug")
+    gpu = _gpu_sequence(P, cfg, cfg.steps)
+    for o, (st, x, b, vals) in zip(orc, gpu):
+        A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+        tr = np.linalg.norm(b - oracle.matvec(A, x)) / np.linalg.norm(b)
+        assert tr <= cfg.tol * 1.01, (o["j"], tr)
+        assert st["status"] in (0, 2)
+        assert abs(st["iters"] - o["iters"]) <= 1, (o["j"], st["iters"], o["iters"])
+        assert st["rank"] == o["rank"]
+
+
+def test_plain_pcg_warm_and_cold(P):
+    cfg = config2(N=20, steps=4)
+    for warm in (False, True):
+        orc = oracle.run_sequence(cfg, "plain", warm=warm)
+        gpu = _gpu_sequence(P, cfg, cfg.steps, method="plain", warm=warm)
+        for o, (st, x, b, vals) in zip(orc, gpu):
+            assert abs(st["iters"] - o["iters"]) <= 1
+            assert st["true_relres"] <= cfg.tol * 1.01
+
+
+def test_deterministic_bitwise(P):
+    cfg = config2(N=22, steps=3)
+    vals = cfg.matrix_values(1)
+    b = cfg.rhs(1, None)
+    W = _rng(10).standard_normal((cfg.n, 8))
+    xs = []
+    for _ in range(2):
+        ctx = _ctx(P, cfg.n, rank_max=8)
+        _set(ctx, cfg.rowptr, cfg.colind, vals)
+        ctx.set_basis(_dev(W))
+        x = _dev(np.zeros(cfg.n))
+        ctx.solve(_dev(b), x, 1e-10)
+        xs.append(_host(x))
+    assert np.array_equal(xs[0], xs[1])
+
+
+# ------------------------------------------------------------------- edge cases
+
+def test_error_paths(P):
+    cfg = config1(N=12)
+    n = cfg.n
+    vals = cfg.matrix_values(1)
+    ctx = _ctx(P, n, maxit=5)
+    x = _dev(np.zeros(n))
+    with pytest.raises(P.PodCGError) as e:
+        ctx.solve(_dev(np.ones(n)), x, 1e-8)
+    assert e.value.code == -6                     # no matrix
+    bad = cfg.colind.copy()
+    bad[5] = n + 3
+    with pytest.raises(P.PodCGError) as e:
+        _set(ctx, cfg.rowptr, bad, vals)
+    assert e.value.code == -1                     # column out of range, caught before use
+    neg = vals.copy()
+    neg[cfg.rowptr[4] + list(cfg.colind[cfg.rowptr[4]:cfg.rowptr[5]]).index(4)] = -1.0
+    with pytest.raises(P.PodCGError) as e:
+        _set(ctx, cfg.rowptr, cfg.colind, neg)
+    assert e.value.code == -4
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    bn = np.ones(n)
+    bn[7] = np.nan
+    with pytest.raises(P.PodCGError) as e:
+        ctx.solve(_dev(bn), x, 1e-8)
+    assert e.value.code == -5
+    x = _dev(np.zeros(n))
+    st = ctx.solve(_dev(np.ones(n)), x, 1e-14)    # cap of 5 iterations
+    assert st.status == 1 and st.iters == 5
+    x = _dev(np.zeros(n))
+    st = ctx.solve(_dev(np.zeros(n)), x, 1e-8)    # zero rhs, zero guess
+    assert st.status == 0 and st.iters == 0
+    assert not np.any(_host(x))
+    assert ctx.build_pod() == 0                   # no snapshots yet
+
+
+def test_indefinite_matrix_is_reported(P):
+    # symmetric, positive diagonal, but indefinite: (A p, p) <= 0 shows up
+    n = 64
+    A = np.eye(n) * 1.0
+    for i in range(n - 1):
+        A[i, i + 1] = A[i + 1, i] = 0.9
+    A[10, 11] = A[11, 10] = 5.0
+    rowptr, colind, vals = tiny.dense_to_csr(A)
+    orc = oracle.plain_pcg(oracle.CSR(rowptr, colind, vals), np.ones(n), np.zeros(n), 1e-12, 200)[1]
+    import paper_1512_05820_amd as P2
+    ctx = P2.PodCG(n, maxit=200)
+    ctx.set_matrix(_dev(vals), _dev(rowptr, torch.int32), _dev(colind, torch.int32))
+    if orc.status == oracle.ERR_NOT_SPD:
+        with pytest.raises(P2.PodCGError) as e:
+            ctx.solve(_dev(np.ones(n)), _dev(np.zeros(n)), 1e-12)
+        assert e.value.code == -4
+
+
+def test_exact_recovery_zero_iterations(P):
+    cfg = config2(N=15, steps=3)
+    vals = cfg.matrix_values(1)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    W = _rng(11).standard_normal((cfg.n, 4))
+    c = _rng(12).standard_normal(4)
+    b = oracle.matvec(A, W @ c)
+    ctx = _ctx(P, cfg.n, rank_max=4)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    ctx.set_basis(_dev(W))
+    x = _dev(np.zeros(cfg.n))
+    st = ctx.solve(_dev(b), x, 1e-10)
+    assert st.iters == 0 and st.status == 0
+    assert _relerr(_host(x), W @ c) <= 1e-12
+
+
+# ------------------------------------------------------------------- full size
+
+def test_full_size_config2_matvec_and_first_solves(P):
+    """128^3 (n = 2,097,152): every row of A p against the oracle, then two
+    systems of the sequence: the GPU answers meet 1e-10 by the oracle's own
+    residual, and the iteration counts agree with the oracle's."""
+    cfg = config2()
+    vals1 = cfg.matrix_values(1)
+    A1 = oracle.CSR(cfg.rowptr, cfg.colind, vals1)
+    x = _rng(13).standard_normal(cfg.n)
+    ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank)
+    _set(ctx, cfg.rowptr, cfg.colind, vals1)
+    y = torch.empty(cfg.n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), oracle.matvec(A1, x)) <= 1e-14
+
+    orc = oracle.run_sequence(cfg, "aug", steps=2)
+    b = cfg.rhs(1, None)
+    xg = _dev(np.zeros(cfg.n))
+    st = ctx.solve(_dev(b), xg, cfg.tol)
+    x1 = _host(xg)
+    assert abs(st.iters - orc[0]["iters"]) <= 1
+    assert np.linalg.norm(b - oracle.matvec(A1, x1)) <= cfg.tol * np.linalg.norm(b) * 1.01
+    ctx.push_snapshot(xg)
+    assert ctx.build_pod() == 1
+    vals2 = cfg.matrix_values(2)
+    ctx.set_matrix(_dev(vals2))
+    b2 = cfg.rhs(2, x1)
+    xg2 = _dev(np.zeros(cfg.n))
+    st2 = ctx.solve(_dev(b2), xg2, cfg.tol)
+    A2 = oracle.CSR(cfg.rowptr, cfg.colind, vals2)
+    x2 = _host(xg2)
+    assert st2.rank == 1 and abs(st2.iters - orc[1]["iters"]) <= 1
+    assert np.linalg.norm(b2 - oracle.matvec(A2, x2)) <= cfg.tol * np.linalg.norm(b2) * 1.01
