@@ -1,0 +1,223 @@
+"""Benchmark: POD-augmented PCG over a sequence of 3-D diffusion systems on one MI355X.
+
+One step = one whole sequence of config 2 (7-point variable-coefficient
+diffusion on a 128^3 grid, n = 2,097,152, 50 implicit time steps, snapshot
+memory 20, POD rank 10, relative tolerance 1e-10): for every system,
+set_matrix (values only), Stage 1 + augmented PCG, push_snapshot, build_pod.
+All 50 matrices are generated on the host and uploaded before timing, so the
+timed region starts with every input resident in HBM; the right-hand side
+b_j = x_{j-1} / dt + 1 is formed on the device inside the loop.
+
+The same sequence is then solved with plain Jacobi PCG from the library
+(warm start x_{j-1} and cold start 0) for the wall-time comparison.
+
+Prints one JSON line.  The value is milliseconds per sequence (lower is
+better).  The roofline object covers the loop kernel with the largest share
+of time, timed with HIP events on the library stream on every 8th iteration
+of the timed steps; bytes are algorithmic (true nnz, int32 indices, each
+vector counted once).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("sequence solve time vs plain GPU PCG at 1e-8 rel residual; SpMV+proj HBM GB/s")
+HBM_PEAK_GBPS = 8000.0
+TIMING_STRIDE = 8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(n: int, nnz: int, y: int) -> dict:
+    """Algorithmic bytes of one launch of each loop kernel (FP64 values, int32 columns)."""
+    return {
+        "spmv": 12 * nnz + 16 * n,            # A values + columns, read p, write q
+        "update": (5 + y) * 8 * n,             # read r, q, dinv, A W; write r, z
+        "dir": (5 + y) * 8 * n,                # read z, p, x, W; write p, x
+    }
+
+
+def run_sequence(torch, ctx, cfg, vals_dev, method: str, warm: bool = False):
+    """Solve the whole sequence on the GPU; returns per-system statistics."""
+    n = cfg.n
+    src = torch.full((n,), cfg.source, dtype=torch.float64, device="cuda")
+    x_prev = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.reset_snapshots()
+    ctx.set_basis(None)
+    out = []
+    for j in range(1, cfg.steps + 1):
+        ctx.set_matrix(vals_dev[j - 1])
+        b = torch.add(src, x_prev, alpha=1.0 / cfg.dt) if j > 1 else src.clone()
+        if method == "aug":
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            st = ctx.solve(b, x, cfg.tol)
+            ctx.push_snapshot(x)
+            ctx.build_pod()
+        else:
+            x = x_prev.clone() if warm else torch.zeros(n, dtype=torch.float64, device="cuda")
+            st = ctx.solve_plain(b, x, cfg.tol)
+        if st.status not in (0, 2):
+            raise RuntimeError(f"system {j}: status {st.status}")
+        out.append(st.as_dict())
+        x_prev = x
+    return out
+
+
+def cpu_baseline(cfg, systems: int) -> dict:
+    """The oracle as it stands on the first `systems` systems of the sequence."""
+    import oracle
+    res = oracle.run_sequence(cfg, "aug", steps=systems)
+    t = sum(r["solve_s"] + r["pod_s"] for r in res)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1e3 * t * cfg.steps / systems, "unit": "ms/sequence", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {systems} of {cfg.steps} systems (oracle solve + POD time, "
+                      f"generation excluded), scaled by {cfg.steps}/{systems}",
+            "iters": [r["iters"] for r in res]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=128, help="grid side (128 = the stated workload)")
+    ap.add_argument("--systems", type=int, default=50)
+    ap.add_argument("--cpu-systems", type=int, default=25)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1512_05820_amd as P
+    from problems import config2
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    cfg = config2(N=args.N, steps=args.systems)
+    vals_dev = [torch.from_numpy(cfg.matrix_values(j)).cuda() for j in range(1, cfg.steps + 1)]
+    rowptr = torch.from_numpy(cfg.rowptr).cuda()
+    colind = torch.from_numpy(cfg.colind).cuda()
+    log(f"generated and uploaded {cfg.steps} matrices n={cfg.n} nnz={cfg.nnz} "
+        f"in {time.perf_counter() - t0:.1f}s")
+
+    ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, timing=TIMING_STRIDE)
+    ctx.set_matrix(vals_dev[0], rowptr, colind)
+
+    # achievable bandwidth probe (not part of the method)
+    m = 1 << 27
+    a = torch.rand(m, dtype=torch.float64, device="cuda")
+    bb = torch.rand(m, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    triad_ms = ctx.stream_triad(a, bb, c, 3.0, 20)
+    triad_gbps = 3 * 8 * m / (triad_ms * 1e-3) / 1e9
+    del a, bb, c
+    log(f"stream triad {triad_gbps:.0f} GB/s")
+
+    for w in range(args.warmup):
+        st = run_sequence(torch, ctx, cfg, vals_dev, "aug")
+        log(f"warmup {w}: iters {[s['iters'] for s in st]}")
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    per_step = []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = run_sequence(torch, ctx, cfg, vals_dev, "aug")
+        torch.cuda.synchronize()
+        per_step.append((time.perf_counter() - t1, st))
+        log(f"step {k}: {1e3 * per_step[-1][0]:.1f} ms, iters {sum(s['iters'] for s in st)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    aug_stats = per_step[-1][1]
+
+    # loop-kernel roofline from the event-timed iterations of all timed steps
+    tot = {"spmv": [0.0, 0.0], "update": [0.0, 0.0], "dir": [0.0, 0.0]}
+    for _, sts in per_step:
+        for s in sts:
+            kb = kernel_bytes(cfg.n, cfg.nnz, s["rank"])
+            for key, ms_key in (("spmv", "spmv_ms"), ("update", "update_ms"), ("dir", "dir_ms")):
+                tot[key][0] += s["timed_iters"] * kb[key]
+                tot[key][1] += s[ms_key]
+    launches = sum(s["timed_iters"] for _, sts in per_step for s in sts)
+    dom = max(tot, key=lambda k: tot[k][1])
+    gbps = {k: (v[0] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else 0.0) for k, v in tot.items()}
+    loop_bytes = sum(v[0] for v in tot.values())
+    loop_ms = sum(v[1] for v in tot.values())
+    loop_gbps = loop_bytes / (loop_ms * 1e-3) / 1e9 if loop_ms > 0 else 0.0
+
+    plain = {}
+    if not args.no_plain:
+        for warm in (True, False):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sts = run_sequence(torch, ctx, cfg, vals_dev, "plain", warm=warm)
+            torch.cuda.synchronize()
+            key = "warm" if warm else "cold"
+            plain[key] = {"ms": 1e3 * (time.perf_counter() - t1),
+                          "iters": sum(s["iters"] for s in sts)}
+            log(f"plain {key}: {plain[key]['ms']:.1f} ms, iters {plain[key]['iters']}")
+
+    cpu = None
+    if not args.no_cpu:
+        t1 = time.perf_counter()
+        cpu = cpu_baseline(cfg, min(args.cpu_systems, cfg.steps))
+        log(f"cpu baseline {cpu['value']:.0f} ms/sequence ({time.perf_counter() - t1:.1f}s)")
+
+    aug_iters = sum(s["iters"] for s in aug_stats)
+    rec = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 3),
+        "unit": "ms/sequence",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "N": cfg.N, "n": cfg.n, "nnz": cfg.nnz,
+                   "systems": cfg.steps, "omega": cfg.omega, "rank_max": cfg.rank,
+                   "rel_tol": cfg.tol, "dt": cfg.dt, "preconditioner": "jacobi"},
+        "aug_iters_total": aug_iters,
+        "aug_iters_per_system": [s["iters"] for s in aug_stats],
+        "aug_rank_per_system": [s["rank"] for s in aug_stats],
+        "max_true_relres": max(s["true_relres"] for s in aug_stats),
+        "plain_gpu": plain,
+        "speedup_vs_plain_warm": (round(plain["warm"]["ms"] / ms_per_step, 3) if plain else None),
+        "iters_saved_vs_plain_warm": (1 - aug_iters / plain["warm"]["iters"]) if plain else None,
+        "loop_kernels_GBps": {k: round(v, 1) for k, v in gbps.items()},
+        "spmv_proj_GBps": round(loop_gbps, 1),
+        "stream_triad_GBps": round(triad_gbps, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbps[dom], 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(gbps[dom] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
+                     "timed_launches": launches},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,16 +136,37 @@ __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
 
 // ---------------------------------------------------------------- products
 
-// Row `row` of A x for the slice handled by this wave.
-__device__ __forceinline__ double sell_row(const int* __restrict__ cols,
-                                           const double* __restrict__ vals, int64_t base, int w,
-                                           int lane, const double* __restrict__ x) {
+// Row (64 s + lane) of A x for the slice s handled by this wave.  Slices of
+// width <= 8 (stencil matrices) take a branch-free path: all column indices
+// and values are loaded first (padding slots re-read the last valid slot and
+// are skipped with a select), then all gathers, then the sums in order j =
+// 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
+// slice bounds are scalar loads.
+__device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
+                                           const int* __restrict__ cols,
+                                           const double* __restrict__ vals, int s, int lane,
+                                           const double* __restrict__ x) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int64_t base = sptr[s];
+    const int w = (int)((sptr[s + 1] - base) / kSlice);
     const int* c = cols + base + lane;
     const double* v = vals + base + lane;
     double acc = 0.0;
-#pragma unroll 4
-    for (int j = 0; j < w; ++j) acc += __builtin_nontemporal_load(v + j * kSlice) *
-                                       x[__builtin_nontemporal_load(c + j * kSlice)];
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        int ci[8];
+        double vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u, w - 1);
+            ci[u] = __builtin_nontemporal_load(c + j * kSlice);
+            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
+        }
+        double xi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xi[u] = x[ci[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = (j0 + u < w) ? fma(vi[u], xi[u], acc) : acc;
+    }
     return acc;
 }
 
@@ -168,9 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const double* 
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const int64_t base = B.sptr[s];
-            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
-            const double acc = sell_row(B.cols, B.vals, base, w, lane, p);
+            const double acc = sell_row(B.sptr, B.cols, B.vals, s, lane, p);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 q[row] = acc;
@@ -198,9 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(DevBufs B, const double* __re
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const int64_t base = B.sptr[s];
-            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
-            const double acc = sell_row(B.cols, B.vals, base, w, lane, x);
+            const double acc = sell_row(B.sptr, B.cols, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) y[row] = acc;
         }
@@ -228,9 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const int64_t base = B.sptr[s];
-            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
-            const double ax = sell_row(B.cols, B.vals, base, w, lane, x);
+            const double ax = sell_row(B.sptr, B.cols, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 const double bi = b[row];
@@ -239,8 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
                 v[0] += bi * bi;
                 v[1] += ri * ri;
 #pragma unroll
-                for (int k = 0; k < YB; ++k)
-                    if (k < y) v[2 + k] += W[(size_t)k * B.ld + row] * ri;
+                for (int k = 0; k < YB; ++k) {
+                    const double wk = W[(size_t)tier_col<YB>(k, y) * B.ld + row];
+                    if (tier_live<YB>(k, y)) v[2 + k] += wk * ri;
+                }
             }
         }
     }
@@ -265,36 +282,140 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
     }
 }
 
-// AX = A X for k <= KB columns (column-major, leading dimension B.ld).
-template <int KB>
-__global__ __launch_bounds__(kBlock) void k_spmm(DevBufs B, int k, const double* __restrict__ X,
-                                                 double* __restrict__ AX) {
+// Fused AX = A X (optionally stored) and G = X^T (A X) for k <= KS columns,
+// the products of Alg. 2 (W^T A W) and of Alg. pod_evd (S^T A S).  Each wave
+// computes A X for one slice of 64 rows (lane = row), stages that block in
+// LDS, and accumulates the 64-row contraction X^T (A X) on the FP64 matrix
+// cores with v_mfma_f64_16x16x4f64: per instruction lane l supplies
+// X[row 4 s + l / 16][col l % 16] (loaded directly) and
+// (A X)[row 4 s + l / 16][col l % 16] (from LDS), and register r of lane l
+// accumulates G[4 r + l / 16][l % 16].  Columns are padded to KB = 16 or 32
+// (padding columns of A X are zero).  Per-workgroup partial Grams are summed
+// in a fixed two-level order.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const double* __restrict__ X,
+                                                      double* __restrict__ AX, int store,
+                                                      double* __restrict__ G, double* part,
+                                                      unsigned* counter) {
+    constexpr int KB = KS <= 16 ? 16 : 32;
+    constexpr int KT = KB / 16;
+    constexpr int LDSW = KS + 1;                               // padded row stride of a tile
+    constexpr int TILE = kSlice * LDSW;                        // doubles per wave tile
+    constexpr int RED = KT * KT * 4 * kWave;                   // doubles per wave accumulator
+    constexpr int SH = kWavesPerBlock * (TILE > RED ? TILE : RED);
+    __shared__ double shm[SH];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int nb = gridDim.x;
     const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    d4_t d[KT][KT];
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b) d[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+    double* tw = shm + wid * (SH / kWavesPerBlock);            // this wave's private tile
+    const int r4 = lane >> 4, cc = lane & 15;
+    // The trip count is uniform over the workgroup; each wave touches only its
+    // own tile, so the only ordering needed is within the wave (s_waitcnt).
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
-        const int s = L * kWavesPerBlock + wid;
-        if (s >= B.nslices) continue;
-        const int64_t base = B.sptr[s];
-        const int w = (int)((B.sptr[s + 1] - base) / kSlice);
-        const int* c = B.cols + base + lane;
-        const double* vv = B.vals + base + lane;
-        double acc[KB];
+        const int s = __builtin_amdgcn_readfirstlane(L * kWavesPerBlock + wid);
+        const bool sv = s < B.nslices;
+        double acc[KS];
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) acc[kk] = 0.0;
-        for (int j = 0; j < w; ++j) {
-            const double a = vv[j * kSlice];
-            const int col = c[j * kSlice];
-#pragma unroll
-            for (int kk = 0; kk < KB; ++kk)
-                if (kk < k) acc[kk] += a * X[(size_t)kk * B.ld + col];
-        }
+        for (int kk = 0; kk < KS; ++kk) acc[kk] = 0.0;
         const int row = s * kSlice + lane;
-        if (row < B.n) {
+        if (sv) {
+            const int64_t base = B.sptr[s];
+            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+            const int* c = B.cols + base + lane;
+            const double* vv = B.vals + base + lane;
+            for (int j = 0; j < w; ++j) {
+                const double a = vv[j * kSlice];
+                const int col = c[j * kSlice];
+                double xv[KS];
 #pragma unroll
-            for (int kk = 0; kk < KB; ++kk)
-                if (kk < k) AX[(size_t)kk * B.ld + row] = acc[kk];
+                for (int kk = 0; kk < KS; ++kk) xv[kk] = X[(size_t)(kk < k ? kk : k - 1) * B.ld + col];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) acc[kk] += a * xv[kk];
+            }
+            if (store && row < B.n) {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk)
+                    if (kk < k) AX[(size_t)kk * B.ld + row] = acc[kk];
+            }
         }
+        const bool live = sv && row < B.n;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) tw[lane * LDSW + kk] = (kk < k && live) ? acc[kk] : 0.0;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll 4
+        for (int st = 0; st < kSlice / 4; ++st) {
+            const int rr = 4 * st + r4;
+            const int grow = s * kSlice + rr;
+            double xa[KT], bb[KT];
+#pragma unroll
+            for (int a = 0; a < KT; ++a) {
+                const int colx = 16 * a + cc;
+                const int colc = colx < k ? colx : k - 1;
+                xa[a] = (sv && grow < B.n) ? X[(size_t)colc * B.ld + grow] : 0.0;
+                bb[a] = colx < KS ? tw[rr * LDSW + (colx < KS ? colx : 0)] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < KT; ++a)
+#pragma unroll
+                for (int b = 0; b < KT; ++b)
+                    d[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], bb[b], d[a][b], 0, 0, 0);
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+    // sum the four waves' accumulators (fixed order)
+    __syncthreads();
+    double* red = shm;
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wid * RED + ((a * KT + b) * 4 + r) * kWave + lane] = d[a][b][r];
+    __syncthreads();
+    // output entry o = i * k + j of this workgroup's partial, owned by one thread
+    const int nout = k * k;
+    const int ng = (nb + kGroup - 1) / kGroup;
+    const int g = blockIdx.x / kGroup;
+    const int gsize = min(kGroup, nb - g * kGroup);
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        const int i = o / k, j = o % k;
+        const int a = i / 16, b = j / 16, ii = i % 16, jj = j % 16;
+        const int r = ii / 4, ln = (ii % 4) * 16 + jj;
+        const int idx = ((a * KT + b) * 4 + r) * kWave + ln;
+        double v = red[idx];
+#pragma unroll
+        for (int wv = 1; wv < kWavesPerBlock; ++wv) v += red[wv * RED + idx];
+        store_shared(part + (size_t)o * nb + blockIdx.x, v);
+    }
+    if (!arrive_last(counter + 1 + g, gsize)) return;
+    double* part2 = part + (size_t)nout * nb;
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        double t[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) t[q] = q < gsize ? load_shared(part + (size_t)o * nb + g * kGroup + q) : 0.0;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) sum += t[q];
+        store_shared(part2 + (size_t)o * ng + g, sum);
+    }
+    if (!arrive_last(counter, ng)) return;
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        double sum = 0.0;
+        for (int q0 = 0; q0 < ng; q0 += kGroup) {
+            double t[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) t[q] = q0 + q < ng ? load_shared(part2 + (size_t)o * ng + q0 + q) : 0.0;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) sum += t[q];
+        }
+        G[o] = sum;
     }
 }
 
@@ -302,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(DevBufs B, int k, const double*
 
 static int grid_for_slices(int nslices) {
     const int groups = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
-    return groups < kSpmvBlocksMax ? groups : kSpmvBlocksMax;
+    return groups < kSpmvGrid ? groups : kSpmvGrid;
 }
 
 static int grid_for(int64_t items, int cap) {
@@ -354,41 +475,38 @@ hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream
     return hipGetLastError();
 }
 
-template <int YB>
-static hipError_t resid_tier(const DevBufs& B, int y, const double* b, const double* x, double* r,
-                             const double* W, bool store, bool stage1, hipStream_t s) {
-    dim3 g(grid_for_slices(B.nslices)), t(kBlock);
-    if (stage1) {
-        if (store) hipLaunchKernelGGL((k_resid<YB, true, true>), g, t, 0, s, B, y, b, x, r, W);
-        else hipLaunchKernelGGL((k_resid<YB, false, true>), g, t, 0, s, B, y, b, x, r, W);
-    } else {
-        if (store) hipLaunchKernelGGL((k_resid<YB, true, false>), g, t, 0, s, B, y, b, x, r, W);
-        else hipLaunchKernelGGL((k_resid<YB, false, false>), g, t, 0, s, B, y, b, x, r, W);
-    }
-    return hipGetLastError();
-}
-
-
 hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x, double* r,
                         const double* W, bool store, bool stage1, hipStream_t s) {
+    dim3 g(grid_for_slices(B.nslices)), t(kBlock);
+    if (!stage1) {   // true residual ||b - A x||^2 only
+        if (store || yb != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_resid<0, false, false>), g, t, 0, s, B, 0, b, x, r, W);
+        return hipGetLastError();
+    }
+    if (!store) return hipErrorInvalidValue;
     switch (yb) {
-#define CASE(T) case T: return resid_tier<T>(B, y, b, x, r, W, store, stage1, s);
+#define CASE(T) case T: hipLaunchKernelGGL((k_resid<T, true, true>), g, t, 0, s, B, y, b, x, r, W); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
-hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s) {
-    dim3 g(grid_for_slices(B.nslices)), t(kBlock);
-    if (k < 1) return hipSuccess;
+}  // namespace podcg
+
+namespace podcg {
+hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX, bool store, double* G,
+                            hipStream_t s) {
+    if (k < 1 || k > kYMax) return hipErrorInvalidValue;
+    const int groups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    dim3 g(groups < kGramBlocksMax ? groups : kGramBlocksMax), t(kBlock);
     switch (basis_tier(k)) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_spmm<T>), g, t, 0, s, B, k, X, AX); break;
+#define CASE(T) case T: hipLaunchKernelGGL((k_spmm_gram<T>), g, t, 0, s, B, k, X, AX, store ? 1 : 0, G, B.part, B.counter); break;
         PODCG_POS_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-
 }  // namespace podcg

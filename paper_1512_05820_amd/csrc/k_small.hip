@@ -8,14 +8,19 @@ namespace podcg {
 
 constexpr int kLd = kYMax + 1;   // padded LDS row stride
 
-// Cyclic Jacobi eigen-decomposition of the symmetric m x m matrix a (LDS,
-// stride kLd) by one wavefront; V (LDS) receives the eigenvectors as columns.
-// Rotations follow the symmetric Schur decomposition of each 2 x 2 block
-// (Golub & Van Loan); sweeps stop when the off-diagonal Frobenius norm drops
-// below 1e-15 of the full norm.  On exit lam[0..m) holds the eigenvalues in
-// decreasing order, V is permuted to match, and each eigenvector is signed so
-// that its entry of largest magnitude (first such index) is positive.
+// Jacobi eigen-decomposition of the symmetric m x m matrix a (LDS, stride
+// kLd) by one wavefront; V (LDS) receives the eigenvectors as columns.  Each
+// rotation is the symmetric Schur decomposition of a 2 x 2 block (Golub & Van
+// Loan).  The rotations of one sweep are grouped by the round-robin
+// (tournament) ordering: each step holds m/2 disjoint pairs, so all their row
+// rotations, then all their column rotations, run in parallel across the
+// lanes.  Sweeps stop when the off-diagonal Frobenius norm drops below 1e-15
+// of the full norm.  On exit lam[0..m) holds the eigenvalues in decreasing
+// order, V is permuted to match, and each eigenvector is signed so that its
+// entry of largest magnitude (first such index) is positive.
 __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
+    __shared__ double cs[2 * (kYMax / 2 + 1)];
+    __shared__ int pq[2 * (kYMax / 2 + 1)];
     const int lane = threadIdx.x;
     for (int e = lane; e < m * m; e += kWave) V[(e / m) * kLd + e % m] = (e / m == e % m) ? 1.0 : 0.0;
     double f = 0.0;
@@ -24,8 +29,10 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
         f += v * v;
     }
     const double fro = wave_sum(f);
+    const int me = m + (m & 1);          // players, with a bye when m is odd
+    const int npair = me / 2;
     __syncthreads();
-    for (int sweep = 0; sweep < 100; ++sweep) {
+    for (int sweep = 0; sweep < 100 && m > 1; ++sweep) {
         double o = 0.0;
         for (int e = lane; e < m * m; e += kWave) {
             const int i = e / m, j = e % m;
@@ -33,38 +40,64 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
         }
         const double off = wave_sum(o);
         if (off <= 1.0e-30 * fro) break;
-        for (int p = 0; p < m - 1; ++p) {
-            for (int q = p + 1; q < m; ++q) {
-                const double apq = a[p * kLd + q];
-                if (apq == 0.0) continue;
-                const double tau = (a[q * kLd + q] - a[p * kLd + p]) / (2.0 * apq);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double c = 1.0 / sqrt(1.0 + t * t);
-                const double s = t * c;
-                __syncthreads();
-                if (lane < m) {
-                    const double akp = a[lane * kLd + p], akq = a[lane * kLd + q];
-                    a[lane * kLd + p] = c * akp - s * akq;
-                    a[lane * kLd + q] = s * akp + c * akq;
+        for (int step = 0; step < me - 1; ++step) {
+            // pairs of this round: position 0 is fixed, the others rotate
+            if (lane < npair) {
+                const int i0 = lane, i1 = me - 1 - lane;
+                const int p0 = i0 == 0 ? 0 : 1 + (i0 - 1 + step) % (me - 1);
+                const int p1 = 1 + (i1 - 1 + step) % (me - 1);
+                int p = p0 < p1 ? p0 : p1, q = p0 < p1 ? p1 : p0;
+                double c = 1.0, sn = 0.0;
+                if (q < m) {
+                    const double apq = a[p * kLd + q];
+                    if (apq != 0.0) {
+                        const double tau = (a[q * kLd + q] - a[p * kLd + p]) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                    }
+                } else {
+                    p = q = -1;                  // bye
                 }
-                __syncthreads();
-                if (lane < m) {
-                    const double apk = a[p * kLd + lane], aqk = a[q * kLd + lane];
-                    a[p * kLd + lane] = c * apk - s * aqk;
-                    a[q * kLd + lane] = s * apk + c * aqk;
-                }
-                __syncthreads();
-                if (lane == 0) {
+                pq[2 * lane] = p;
+                pq[2 * lane + 1] = q;
+                cs[2 * lane] = c;
+                cs[2 * lane + 1] = sn;
+            }
+            __syncthreads();
+            // rows p, q of every pair:  A <- J^T A
+            for (int e = lane; e < npair * m; e += kWave) {
+                const int t = e / m, k = e % m;
+                const int p = pq[2 * t], q = pq[2 * t + 1];
+                if (p < 0) continue;
+                const double c = cs[2 * t], sn = cs[2 * t + 1];
+                const double apk = a[p * kLd + k], aqk = a[q * kLd + k];
+                a[p * kLd + k] = c * apk - sn * aqk;
+                a[q * kLd + k] = sn * apk + c * aqk;
+            }
+            __syncthreads();
+            // columns p, q of every pair:  A <- A J,  V <- V J
+            for (int e = lane; e < npair * m; e += kWave) {
+                const int t = e / m, k = e % m;
+                const int p = pq[2 * t], q = pq[2 * t + 1];
+                if (p < 0) continue;
+                const double c = cs[2 * t], sn = cs[2 * t + 1];
+                const double akp = a[k * kLd + p], akq = a[k * kLd + q];
+                a[k * kLd + p] = c * akp - sn * akq;
+                a[k * kLd + q] = sn * akp + c * akq;
+                const double vkp = V[k * kLd + p], vkq = V[k * kLd + q];
+                V[k * kLd + p] = c * vkp - sn * vkq;
+                V[k * kLd + q] = sn * vkp + c * vkq;
+            }
+            __syncthreads();
+            if (lane < npair) {
+                const int p = pq[2 * lane], q = pq[2 * lane + 1];
+                if (p >= 0 && cs[2 * lane + 1] != 0.0) {
                     a[p * kLd + q] = 0.0;
                     a[q * kLd + p] = 0.0;
                 }
-                if (lane < m) {
-                    const double vkp = V[lane * kLd + p], vkq = V[lane * kLd + q];
-                    V[lane * kLd + p] = c * vkp - s * vkq;
-                    V[lane * kLd + q] = s * vkp + c * vkq;
-                }
-                __syncthreads();
             }
+            __syncthreads();
         }
     }
     if (lane < m) lam[lane] = a[lane * kLd + lane];

@@ -8,8 +8,10 @@
 namespace podcg {
 
 int basis_tier(int y) {
-    static const int tiers[] = {0, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32};
-    for (int t : tiers)
+    if (y < 0) return -1;
+    if (y <= kExactTierMax) return y;
+    static const int wide[] = {20, 24, 28, 32};
+    for (int t : wide)
         if (y <= t) return t;
     return -1;
 }
@@ -20,7 +22,14 @@ int basis_tier(int y) {
 //   beta = (r', z') / (r, z),  mu = G^{-1} c  (the solve with W^T A W of
 // Alg. 1, with G^{-1} from the Cholesky factor of Stage 1),
 // counts the iteration and tests ||r|| <= tol ||b||.
-template <int YB>
+// Column of W or A W: read once per iteration, so loaded nontemporally when
+// NTB (keeps the smaller vectors resident in the caches).
+template <bool NTB>
+__device__ __forceinline__ double basis_load(const double* p) {
+    return NTB ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <int YB, bool NTB = false>
 __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __restrict__ r,
                                                    double* __restrict__ z,
                                                    const double* __restrict__ q,
@@ -43,8 +52,10 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __r
         v[0] += ri * zi;
         v[1] += ri * ri;
 #pragma unroll
-        for (int k = 0; k < YB; ++k)
-            if (k < y) v[2 + k] += AW[(size_t)k * B.ld + i] * zi;
+        for (int k = 0; k < YB; ++k) {
+            const double a = basis_load<NTB>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
+            if (tier_live<YB>(k, y)) v[2 + k] += a * zi;
+        }
     }
     if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
     if (threadIdx.x == 0) {
@@ -78,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __r
 //   p <- z + beta p - W mu,
 // which keeps p A-orthogonal to range(W) (Alg. 1).  INIT forms the first
 // direction p = z - W mu and leaves x alone.
-template <int YB, bool INIT>
+template <int YB, bool INIT, bool NTB = false>
 __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, double* __restrict__ p,
                                                 double* __restrict__ x, const double* __restrict__ z,
                                                 const double* __restrict__ W) {
@@ -107,8 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, double* __rest
             s = z[i] + beta * pi;
         }
 #pragma unroll
-        for (int k = 0; k < YB; ++k)
-            if (k < y) s -= W[(size_t)k * B.ld + i] * mu[k];
+        for (int k = 0; k < YB; ++k) s -= basis_load<NTB>(W + (size_t)tier_col<YB>(k, y) * B.ld + i) * mu[k];
         p[i] = s;
     }
 }
@@ -141,11 +151,11 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
         if (YB > 0) {
             double wx = 0.0, awx = 0.0;
 #pragma unroll
-            for (int k = 0; k < YB; ++k)
-                if (k < y) {
-                    wx += W[(size_t)k * B.ld + i] * what[k];
-                    awx += AW[(size_t)k * B.ld + i] * what[k];
-                }
+            for (int k = 0; k < YB; ++k) {
+                const int kc = tier_col<YB>(k, y);
+                wx += W[(size_t)kc * B.ld + i] * what[k];
+                awx += AW[(size_t)kc * B.ld + i] * what[k];
+            }
             x[i] += wx;
             ri -= awx;
             r[i] = ri;
@@ -155,8 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
         v[0] += ri * zi;
         v[1] += ri * ri;
 #pragma unroll
-        for (int k = 0; k < YB; ++k)
-            if (k < y) v[2 + k] += AW[(size_t)k * B.ld + i] * zi;
+        for (int k = 0; k < YB; ++k) {
+            const double a = AW[(size_t)tier_col<YB>(k, y) * B.ld + i];
+            if (tier_live<YB>(k, y)) v[2 + k] += a * zi;
+        }
     }
     if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
     if (threadIdx.x == 0) {
@@ -182,65 +194,6 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
     }
 }
 
-// G = X^T Y for column blocks X (n x a) and Y (n x b), a, b <= 32, G row-major
-// a x b.  Rows are staged through LDS in tiles of kGramTile; each thread owns
-// up to four entries of G.  Per-workgroup partials are summed in a fixed order
-// by the last workgroup.
-__global__ __launch_bounds__(kBlock) void k_gram(int n, size_t ld, const double* __restrict__ X, int a,
-                                                 const double* __restrict__ Y, int b,
-                                                 double* __restrict__ G, double* part,
-                                                 unsigned* counter) {
-    __shared__ double tile[kGramTile * 2 * kYMax];
-    __shared__ int is_last;
-    const int cols = a + b;
-    const int nout = a * b;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int row0 = blockIdx.x * kGramTile; row0 < n; row0 += gridDim.x * kGramTile) {
-        for (int e = threadIdx.x; e < kGramTile * cols; e += kBlock) {
-            const int c = e / kGramTile, rr = e % kGramTile;
-            const int row = row0 + rr;
-            double v = 0.0;
-            if (row < n) v = c < a ? X[(size_t)c * ld + row] : Y[(size_t)(c - a) * ld + row];
-            tile[rr * cols + c] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int o = threadIdx.x + m * kBlock;
-            if (o < nout) {
-                const int i = o / b, j = o % b;
-                double s = acc[m];
-                for (int rr = 0; rr < kGramTile; ++rr) s += tile[rr * cols + i] * tile[rr * cols + a + j];
-                acc[m] = s;
-            }
-        }
-        __syncthreads();
-    }
-    const int nb = gridDim.x;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int o = threadIdx.x + m * kBlock;
-        if (o < nout) part[(size_t)o * nb + blockIdx.x] = acc[m];
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int o = threadIdx.x + m * kBlock;
-        if (o < nout) {
-            const volatile double* po = part + (size_t)o * nb;
-            double s = 0.0;
-            for (int k = 0; k < nb; ++k) s += po[k];
-            G[o] = s;
-        }
-    }
-    if (threadIdx.x == 0) *counter = 0u;
-}
-
 // W(:, i) = sum_k S(:, k) T(k, i) for i < y, k < count (Eq. (podAlgebraicDefinition)
 // with T = diag(w) V_y Sigma_y^{-1}).
 template <int KB>
@@ -253,7 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_pod_form(int n, size_t ld, const dou
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         double s[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) s[k] = k < count ? S[(size_t)k * ld + i] : 0.0;
+        for (int k = 0; k < KB; ++k) {
+            const double v = S[(size_t)(k < count ? k : count - 1) * ld + i];
+            s[k] = k < count ? v : 0.0;
+        }
         for (int c = 0; c < y; ++c) {
             double acc = 0.0;
 #pragma unroll
@@ -291,17 +247,17 @@ __global__ void k_state_init(DevState* st, int maxit, double tol2, int y) {
 
 // ---------------------------------------------------------------- launchers
 
-static int vec_grid(int64_t n) {
+static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    return (int)(g < kVecBlocksMax ? g : kVecBlocksMax);
+    return (int)(g < cap ? g : cap);
 }
 
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
                          const double* AW, hipStream_t s) {
-    dim3 g(vec_grid(B.n)), t(kBlock);
+    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
     switch (yb) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_update<T>), g, t, 0, s, B, y, r, z, q, AW); break;
+#define CASE(T) case T: hipLaunchKernelGGL((k_update<T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -311,12 +267,12 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
 
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                       const double* W, bool init, hipStream_t s) {
-    dim3 g(vec_grid(B.n)), t(kBlock);
+    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<T, true>), g, t, 0, s, B, y, p, x, z, W);              \
-        else hipLaunchKernelGGL((k_dir<T, false>), g, t, 0, s, B, y, p, x, z, W);                  \
+        if (init) hipLaunchKernelGGL((k_dir<T, true, true>), g, t, 0, s, B, y, p, x, z, W);        \
+        else hipLaunchKernelGGL((k_dir<T, false, true>), g, t, 0, s, B, y, p, x, z, W);            \
         break;
         PODCG_TIERS(CASE)
 #undef CASE
@@ -327,23 +283,13 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
 
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s) {
-    dim3 g(vec_grid(B.n)), t(kBlock);
+    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_stage1_apply<T>), g, t, 0, s, B, y, x, r, z, W, AW); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_gram(int n, size_t ld, const double* X, int a, const double* Y, int b, double* G,
-                       double* part, unsigned* counter, hipStream_t s) {
-    if (a < 1 || b < 1 || a > kYMax || b > kYMax) return hipErrorInvalidValue;
-    int64_t tiles = (n + kGramTile - 1) / kGramTile;
-    int g = (int)(tiles < kGramBlocksMax ? tiles : kGramBlocksMax);
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_gram, dim3(g), dim3(kBlock), 0, s, n, ld, X, a, Y, b, G, part, counter);
     return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ struct podcg_ctx {
     double *d_G = nullptr, *d_R = nullptr, *d_Ginv = nullptr, *d_lamG = nullptr;
 
     // snapshots
-    double *d_S = nullptr, *d_AS = nullptr, *d_Gs = nullptr, *d_T = nullptr, *d_lamS = nullptr;
+    double *d_S = nullptr, *d_Gs = nullptr, *d_T = nullptr, *d_lamS = nullptr;
     int head = 0, count = 0, pod_count = 0;
     int* d_yout = nullptr;
 
@@ -73,6 +73,7 @@ struct podcg_ctx {
 
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
     std::vector<hipEvent_t> tev;     // per-iteration kernel timing events
+    int prev_iters[2] = {0, 0};      // iterations of the last augmented / plain solve
 
     std::string last_error;
 };
@@ -142,9 +143,7 @@ void setup_basis(podcg_ctx* ctx) {
         return;
     }
     DevBufs B = bufs(ctx);
-    HIPCHECK(launch_spmm(B, ctx->y, ctx->d_W, ctx->d_AW, ctx->stream));
-    HIPCHECK(launch_gram((int)ctx->n, ctx->ld, ctx->d_W, ctx->y, ctx->d_AW, ctx->y, ctx->d_G,
-                         ctx->d_part, ctx->d_counter, ctx->stream));
+    HIPCHECK(launch_spmm_gram(B, ctx->y, ctx->d_W, ctx->d_AW, true, ctx->d_G, ctx->stream));
     HIPCHECK(launch_reduced_factor(ctx->d_G, ctx->y, ctx->d_R, ctx->d_Ginv, ctx->d_lamG, ctx->d_st,
                                    ctx->stream));
     poll(ctx);
@@ -173,9 +172,9 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
 
     HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
     bool did_setup = false;
-    if (!plain && ctx->y > 0 && !ctx->setup_valid) {
+    if (!plain && !ctx->setup_valid) {   // also resets the kept rank when the basis is empty
         setup_basis(ctx);
-        did_setup = true;
+        did_setup = ctx->y > 0;
     }
     HIPCHECK(hipEventRecord(ctx->ev_b, ctx->stream));
     const int y = plain ? 0 : ctx->y_kept;
@@ -196,8 +195,14 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
     int launched = 0;
     int polls = 0;
     ctx->h_poll->done = kRunning;   // the loop kernels are no-ops once Stage 1 has finished
+    // The first convergence check comes after most of the previous solve's
+    // iteration count (kernels after convergence are no-ops), then every
+    // check_every iterations.
+    int first = (int)(0.85 * ctx->prev_iters[plain ? 1 : 0]);
+    first = std::max(first, ctx->opt.check_every);
     while (ctx->h_poll->done == kRunning && launched < ctx->opt.maxit) {
-        const int batch = std::min(ctx->opt.check_every, ctx->opt.maxit - launched);
+        const int want = launched == 0 ? first : ctx->opt.check_every;
+        const int batch = std::min(want, ctx->opt.maxit - launched);
         for (int k = 0; k < batch; ++k, ++launched) {
             const bool t = timing > 0 && (launched % timing) == 0;
             size_t base = 0;
@@ -232,6 +237,7 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
     HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_b, ctx->ev_c));
     S.solve_ms = ms;
     S.iters = P.iter;
+    ctx->prev_iters[plain ? 1 : 0] = P.iter;
     S.rank = y;
     const double bn = std::sqrt(P.bnorm2);
     S.bnorm = bn;
@@ -286,7 +292,7 @@ int guarded(podcg_ctx* ctx, F&& f) {
 void release(podcg_ctx* ctx) {
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
-                   ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_AS, ctx->d_Gs, ctx->d_T,
+                   ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
                    ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -369,7 +375,6 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_W, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_AW, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_S, ld * (size_t)o.omega);
-        dalloc(ctx, &ctx->d_AS, ld * (size_t)o.omega);
         dalloc(ctx, &ctx->d_G, kYMax * kYMax);
         dalloc(ctx, &ctx->d_R, kYMax * kYMax);
         dalloc(ctx, &ctx->d_Ginv, kYMax * kYMax);
@@ -380,9 +385,9 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_yout, 4);
         dalloc(ctx, &ctx->d_st, 1);
         dalloc(ctx, &ctx->d_part, kPartials);
-        dalloc(ctx, &ctx->d_counter, 16);
+        dalloc(ctx, &ctx->d_counter, kCounters);
         dalloc(ctx, &ctx->d_flag, 4);
-        HIPCHECK(hipMemsetAsync(ctx->d_counter, 0, 16 * sizeof(unsigned), ctx->stream));
+        HIPCHECK(hipMemsetAsync(ctx->d_counter, 0, kCounters * sizeof(unsigned), ctx->stream));
         HIPCHECK(hipMemsetAsync(ctx->d_r, 0, ld * sizeof(double), ctx->stream));
         HIPCHECK(hipMemsetAsync(ctx->d_z, 0, ld * sizeof(double), ctx->stream));
         HIPCHECK(hipMemsetAsync(ctx->d_p, 0, ld * sizeof(double), ctx->stream));
@@ -514,9 +519,7 @@ int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out) {
             const int age = (ctx->head - 1 - slot + ctx->opt.omega) % ctx->opt.omega;   // 0 = newest
             w[slot] = ctx->opt.weights == 0 ? std::ldexp(1.0, -age) : 1.0;
         }
-        HIPCHECK(launch_spmm(B, count, ctx->d_S, ctx->d_AS, s));
-        HIPCHECK(launch_gram((int)ctx->n, ctx->ld, ctx->d_S, count, ctx->d_AS, count, ctx->d_Gs,
-                             ctx->d_part, ctx->d_counter, s));
+        HIPCHECK(launch_spmm_gram(B, count, ctx->d_S, nullptr, false, ctx->d_Gs, s));
         HIPCHECK(launch_pod_coeffs(ctx->d_Gs, count, w, ctx->opt.rank_max, ctx->opt.rank_rtol,
                                    ctx->opt.energy, ctx->d_T, ctx->d_lamS, ctx->d_yout, s));
         HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_yout, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -14,15 +14,21 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlice = 64;                // SELL slice height = one row per lane
 constexpr int kYMax = 32;                 // largest basis / snapshot count
 constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
-constexpr int kVecBlocksMax = 2048;       // grid cap of the streaming vector kernels
-constexpr int kSpmvBlocksMax = 8192;      // grid cap of the SELL kernels
-constexpr int kGramBlocksMax = 512;       // grid cap of the tall-skinny Gram kernel
-constexpr int kGramTile = 64;             // rows per LDS tile of the Gram kernel
+constexpr int kVecBlocksMax = 2048;       // partial-sum capacity of the streaming kernels
+constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL kernels
+// Launch grids of the loop kernels (measured best on MI355X at 128^3 for the
+// three-kernel iteration: fewer, longer-lived workgroups shorten the
+// reduction tails without starving the memory system).
+constexpr int kSpmvGrid = 1024;
+constexpr int kUpdateGrid = 512;
+constexpr int kDirGrid = 1024;
+constexpr int kCounters = 1 + kSpmvBlocksMax;        // arrival counters (level 2 + groups)
+constexpr int kGramBlocksMax = 512;       // grid cap of the fused SpMM + Gram kernel
 // doubles in the partials buffer: the larger of the loop kernels' need and the
 // Gram kernel's (one slot per output entry per workgroup)
-constexpr int kPartials = (kNVMax * kSpmvBlocksMax > kYMax * kYMax * kGramBlocksMax)
-                              ? kNVMax * kSpmvBlocksMax
-                              : kYMax * kYMax * kGramBlocksMax;
+constexpr int kPartials = (2 * kNVMax * kSpmvBlocksMax > 2 * kYMax * kYMax * kGramBlocksMax)
+                              ? 2 * kNVMax * kSpmvBlocksMax
+                              : 2 * kYMax * kYMax * kGramBlocksMax;
 
 // `done` values of the iteration state machine (see the loop kernels).
 constexpr int kRunning = 0;
@@ -86,36 +92,70 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
-// Deterministic grid reduction.  Every workgroup stores its NV partial sums
-// (part[k * gridDim.x + block]); the last workgroup to arrive sums all of them
-// in a fixed order and returns true with the totals in lds[0..NV).  The
-// counter is returned to zero by that workgroup.
+// Stores and loads that are coherent across the XCDs (relaxed atomics at agent
+// scope: written through to, and read from, the level shared by all L2s).
+// They let one workgroup read the partials of all others without an
+// agent-scope fence, which on gfx950 writes back the whole L2 of the XCD.
+__device__ __forceinline__ void store_shared(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_shared(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wave's outstanding memory operations (the coherent stores
+// above) have completed; also a compiler barrier.
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Arrival counter: returns true in the last of `expected` workgroups to
+// arrive; that workgroup also returns the counter to zero.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, int expected) {
+    __shared__ int is_last;
+    wait_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == (unsigned)(expected - 1));
+        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return is_last != 0;
+}
+
+constexpr int kGroup = 16;   // workgroups per first-level reduction group
+
+// Deterministic two-level grid reduction of NV values.
+//   level 1: each workgroup stores its NV sums in part[k * nb + block]; the
+//            last workgroup of each group of kGroup consecutive workgroups
+//            sums the group's entries (in block order) into
+//            part[NV * nb + k * ng + group];
+//   level 2: the last group to finish sums the ng group entries.
+// Returns true in that final workgroup, with the totals in lds[0..NV).
+// Requires nb <= kGroup * kBlock.  counter[0] is the level-2 counter,
+// counter[1 + g] the counter of group g.  Each level issues all its loads
+// before it sums, so the tail costs two memory round trips.
 template <int NV>
 __device__ __forceinline__ bool grid_sum_last(double (&v)[NV], double* part, unsigned* counter,
                                               double* lds) {
-    __shared__ int is_last;
     block_sum<NV>(v, lds);
     const int nb = gridDim.x;
-    if (threadIdx.x < NV) part[(size_t)threadIdx.x * nb + blockIdx.x] = lds[threadIdx.x];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == (unsigned)(nb - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NV];
+    const int ng = (nb + kGroup - 1) / kGroup;
+    const int g = blockIdx.x / kGroup;
+    if (threadIdx.x < NV) store_shared(part + (size_t)threadIdx.x * nb + blockIdx.x, lds[threadIdx.x]);
+    const int gsize = min(kGroup, nb - g * kGroup);
+    if (!arrive_last(counter + 1 + g, gsize)) return false;
+    double a[NV];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        const volatile double* pk = part + (size_t)k * nb;
-        for (int b = threadIdx.x; b < nb; b += kBlock) s += pk[b];
-        acc[k] = s;
-    }
-    block_sum<NV>(acc, lds);
-    if (threadIdx.x == 0) *counter = 0u;
+    for (int k = 0; k < NV; ++k)
+        a[k] = t < gsize ? load_shared(part + (size_t)k * nb + g * kGroup + t) : 0.0;
+    block_sum<NV>(a, lds);
+    double* part2 = part + (size_t)NV * nb;
+    if (t < NV) store_shared(part2 + (size_t)t * ng + g, lds[t]);
+    if (!arrive_last(counter, ng)) return false;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = t < ng ? load_shared(part2 + (size_t)k * ng + t) : 0.0;
+    block_sum<NV>(a, lds);
     return true;
 }
 
@@ -159,7 +199,9 @@ hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipSt
 hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);
 hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x,
                         double* r, const double* W, bool store, bool stage1, hipStream_t s);
-hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s);
+// AX = A X (stored when `store`) and G = X^T A X (row-major k x k), FP64 MFMA.
+hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX, bool store, double* G,
+                            hipStream_t s);
 
 // Streaming vector kernels (k_vec.hip)
 int basis_tier(int y);   // smallest compiled register tier >= y
@@ -169,8 +211,6 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
                       const double* W, bool init, hipStream_t s);
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s);
-hipError_t launch_gram(int n, size_t ld, const double* X, int a, const double* Y, int b,
-                       double* G, double* part, unsigned* counter, hipStream_t s);
 hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
                            double* W, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
@@ -178,9 +218,27 @@ hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, d
                         hipStream_t s);
 hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s);
 
-// Register tiers compiled for the basis dimension (runtime y <= tier).
-#define PODCG_POS_TIERS(X) X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32)
+// Register tiers compiled for the basis dimension.  Up to 16 the kernels are
+// instantiated for the exact dimension (every column load is unconditional
+// and issued together); above 16 a tier serves all y <= tier, with clamped
+// column indices so loads stay unconditional and in bounds.
+#define PODCG_WIDE_TIERS(X) X(20) X(24) X(28) X(32)
+#define PODCG_POS_TIERS(X)                                                                         \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)        \
+        PODCG_WIDE_TIERS(X)
 #define PODCG_TIERS(X) X(0) PODCG_POS_TIERS(X)
+constexpr int kExactTierMax = 16;
+
+// Column index used for a load in tier YB with runtime dimension y: the
+// column itself for exact tiers, clamped into [0, y) otherwise.
+template <int YB>
+__device__ __forceinline__ int tier_col(int k, int y) {
+    return YB <= kExactTierMax ? k : (k < y ? k : y - 1);
+}
+template <int YB>
+__device__ __forceinline__ bool tier_live(int k, int y) {
+    return YB <= kExactTierMax ? true : k < y;
+}
 
 // Single-workgroup dense kernels (k_small.hip)
 // G (m x m row-major, symmetrised here) -> R, Ginv = G^{-1} on the accepted

@@ -278,6 +278,31 @@ def test_deterministic_bitwise(P):
     assert np.array_equal(xs[0], xs[1])
 
 
+def test_cleared_basis_after_a_sequence_is_plain_pcg(P):
+    """Clearing the basis after a sequence must give exactly a fresh plain solve."""
+    cfg = config2(N=16, steps=4)
+    seq = _gpu_sequence(P, cfg, 4)
+    assert seq[-1][0]["rank"] > 0
+    vals = cfg.matrix_values(1)
+    b = cfg.rhs(1, None)
+    fresh = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank)
+    _set(fresh, cfg.rowptr, cfg.colind, vals)
+    x0 = _dev(np.zeros(cfg.n))
+    st0 = fresh.solve(_dev(b), x0, cfg.tol)
+    ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank)
+    _set(ctx, cfg.rowptr, cfg.colind, cfg.matrix_values(3))
+    W = _rng(14).standard_normal((cfg.n, 3))
+    ctx.set_basis(_dev(W))
+    ctx.solve(_dev(b), _dev(np.zeros(cfg.n)), cfg.tol)
+    ctx.set_basis(None)
+    ctx.reset_snapshots()
+    ctx.set_matrix(_dev(vals))
+    x1 = _dev(np.zeros(cfg.n))
+    st1 = ctx.solve(_dev(b), x1, cfg.tol)
+    assert st1.rank == 0 and st1.iters == st0.iters
+    assert np.array_equal(_host(x1), _host(x0))
+
+
 # ------------------------------------------------------------------- edge cases
 
 def test_error_paths(P):
