@@ -13,7 +13,7 @@ The same sequence is then solved with plain Jacobi PCG from the library
 
 Prints one JSON line.  The value is milliseconds per sequence (lower is
 better).  The roofline object covers the loop kernel with the largest share
-of time, timed with HIP events on the library stream on every 8th iteration
+of time, timed with HIP events on the library stream on every 32nd iteration
 of the timed steps; bytes are algorithmic (true nnz, int32 indices, each
 vector counted once).
 """
@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("sequence solve time vs plain GPU PCG at 1e-8 rel residual; SpMV+proj HBM GB/s")
 HBM_PEAK_GBPS = 8000.0
-TIMING_STRIDE = 8
+TIMING_STRIDE = 32
 
 
 def log(*a):
@@ -47,6 +47,26 @@ def kernel_bytes(n: int, nnz: int, y: int) -> dict:
         "update": (5 + y) * 8 * n,             # read r, q, dinv, A W; write r, z
         "dir": (5 + y) * 8 * n,                # read z, p, x, W; write p, x
     }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_gamma_config2_128_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per SpMV launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and " " not in line.split(": ", 1)[0])
+    csrc = os.path.join(ROOT, "paper_1512_05820_amd", "csrc")
+    h1 = hashlib.sha256(open(os.path.join(csrc, "k_sell.hip"), "rb").read()).hexdigest()[:16]
+    h2 = hashlib.sha256(open(os.path.join(csrc, "podcg_device.h"), "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != h1 or fields.get("device_header_sha256_16") != h2:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def run_sequence(torch, ctx, cfg, vals_dev, method: str, warm: bool = False):
@@ -211,7 +231,10 @@ def main():
         "stream_triad_GBps": round(triad_gbps, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbps[dom], 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(gbps[dom] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(gbps[dom] / HBM_PEAK_GBPS, 4),
+                     "traffic": (measured_traffic() if dom == "spmv" and cfg.N == 128 else None),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+                     "algorithmic_bytes": kernel_bytes(cfg.n, cfg.nnz, 0)[dom] if dom == "spmv" else None,
                      "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
                      "timed_launches": launches},
         "cpu_baseline": cpu,
