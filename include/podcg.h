@@ -64,6 +64,12 @@ typedef struct {
                              timing-th iteration (statistics only; 0 = off)                   */
     double  rank_rtol;    /* POD keeps eigenvalues lam_i > rank_rtol * lam_1                  */
     double  energy;       /* POD energy criterion in (0, 1); >= 1 disables it                 */
+    int32_t precision;    /* 0: FP64 throughout.  1: the augmented PCG runs in FP32 (matrix,
+                             vectors and basis stored in FP32, sums in FP64) as the inner solve
+                             of FP64 iterative refinement; A W, W^T A W, its Cholesky factor,
+                             the POD and the refinement residuals b - A x stay FP64          */
+    int32_t max_refine;   /* refinement steps cap when precision = 1                         */
+    double  inner_rtol;   /* relative tolerance of each FP32 inner solve (precision = 1)      */
 } podcg_options;
 
 typedef struct {
@@ -83,10 +89,14 @@ typedef struct {
     double  spmv_ms;        /* summed durations of the timed SpMV launches                       */
     double  update_ms;      /* ... of the timed update/reduction launches                        */
     double  dir_ms;         /* ... of the timed direction-update launches                        */
+    int32_t refine_steps;   /* FP32 inner solves performed (precision = 1; 0 otherwise)          */
+    int32_t reserved;
+    double  first_inner_relres; /* ||b - A x|| / ||b|| in FP64 after the first FP32 inner solve */
 } podcg_stats;
 
 /* Fill *opt with defaults: omega 20, rank_max 10, maxit 10000, check_every 16,
- * inverse-distance weights, no timing, rank_rtol 1e-12, energy 1 (off). */
+ * inverse-distance weights, no timing, rank_rtol 1e-12, energy 1 (off),
+ * precision 0 (FP64), max_refine 20, inner_rtol 1e-6. */
 void podcg_default_options(podcg_options* opt);
 
 /* Create a context for systems of size n.  opt may be NULL (defaults).
@@ -152,6 +162,12 @@ int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count);
  * current basis; plain Jacobi PCG when the basis is empty).
  * b: device, n float64.  x: device, n float64, holds xbar_j on entry and x_j
  * on return.  rtol >= 0.  st (host, may be NULL) receives statistics.
+ * With precision = 1 the solve is FP64 iterative refinement: r = b - A x in
+ * FP64; Stage 1 on r in FP64; an FP32 augmented PCG for the correction to
+ * relative tolerance inner_rtol (but no further than half the outer target
+ * rtol ||b||), its steps added to x in FP64; repeated until the FP64
+ * residual meets rtol or max_refine steps were made; maxit caps each inner
+ * solve and iters counts all of them.
  * Returns OK, NOT_CONVERGED (x = last iterate), RANK_REDUCED, or an error:
  * NO_MATRIX, INVALID_ARG, NOT_SPD, NONFINITE, HIP. */
 int podcg_solve(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);

@@ -25,7 +25,8 @@ EXPORTED = [
 class Options(C.Structure):
     _fields_ = [("omega", C.c_int32), ("rank_max", C.c_int32), ("maxit", C.c_int32),
                 ("check_every", C.c_int32), ("weights", C.c_int32), ("timing", C.c_int32),
-                ("rank_rtol", C.c_double), ("energy", C.c_double)]
+                ("rank_rtol", C.c_double), ("energy", C.c_double), ("precision", C.c_int32),
+                ("max_refine", C.c_int32), ("inner_rtol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -34,7 +35,8 @@ class Stats(C.Structure):
                 ("true_relres", C.c_double), ("bnorm", C.c_double), ("cond_G", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("timed_iters", C.c_int32),
                 ("polls", C.c_int32), ("spmv_ms", C.c_double), ("update_ms", C.c_double),
-                ("dir_ms", C.c_double)]
+                ("dir_ms", C.c_double), ("refine_steps", C.c_int32), ("reserved", C.c_int32),
+                ("first_inner_relres", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -142,38 +142,43 @@ __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
 // are skipped with a select), then all gathers, then the sums in order j =
 // 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
 // slice bounds are scalar loads.
+template <typename T>
 __device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
                                            const int* __restrict__ cols,
-                                           const double* __restrict__ vals, int s, int lane,
-                                           const double* __restrict__ x) {
+                                           const T* __restrict__ vals, int s, int lane,
+                                           const T* __restrict__ x) {
     s = __builtin_amdgcn_readfirstlane(s);
     const int64_t base = sptr[s];
     const int w = (int)((sptr[s + 1] - base) / kSlice);
     const int* c = cols + base + lane;
-    const double* v = vals + base + lane;
-    double acc = 0.0;
+    const T* v = vals + base + lane;
+    double acc = 0.0;   // FP32 operands multiply exactly in FP64; the row sum is FP64
     for (int j0 = 0; j0 < w; j0 += 8) {
         int ci[8];
-        double vi[8];
+        T vi[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = min(j0 + u, w - 1);
             ci[u] = __builtin_nontemporal_load(c + j * kSlice);
             vi[u] = __builtin_nontemporal_load(v + j * kSlice);
         }
-        double xi[8];
+        T xi[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) xi[u] = x[ci[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = (j0 + u < w) ? fma(vi[u], xi[u], acc) : acc;
+        for (int u = 0; u < 8; ++u) acc = (j0 + u < w) ? fma((double)vi[u], (double)xi[u], acc) : acc;
     }
     return acc;
 }
 
 // Loop kernel 1 of augmented PCG (Alg. 1): q = A p and gamma = (A p, p);
-// the last workgroup forms alpha = (r, z) / gamma.
-__global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const double* __restrict__ p,
-                                                       double* __restrict__ q) {
+// the last workgroup forms alpha = (r, z) / gamma.  T is the storage type of
+// the matrix and vectors (FP64, or FP32 for the inner solve of mixed
+// precision); row sums and gamma are accumulated in FP64 and q is rounded to
+// T once.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __restrict__ p,
+                                                       T* __restrict__ q) {
     __shared__ double lds[kWavesPerBlock * 1 + 1 + 1];
     DevState* st = B.st;
     const int done = st->done;
@@ -189,11 +194,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const double* 
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double acc = sell_row(B.sptr, B.cols, B.vals, s, lane, p);
+            const double acc = sell_row<T>(B.sptr, B.cols, mat_vals<T>(B), s, lane, p);
             const int row = s * kSlice + lane;
             if (row < B.n) {
-                q[row] = acc;
-                g[0] += acc * p[row];
+                const T qv = (T)acc;
+                q[row] = qv;
+                g[0] += (double)qv * (double)p[row];
             }
         }
     }
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(DevBufs B, const double* __re
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double acc = sell_row(B.sptr, B.cols, B.vals, s, lane, x);
+            const double acc = sell_row<double>(B.sptr, B.cols, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) y[row] = acc;
         }
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double ax = sell_row(B.sptr, B.cols, B.vals, s, lane, x);
+            const double ax = sell_row<double>(B.sptr, B.cols, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 const double bi = b[row];
@@ -266,6 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
         if (threadIdx.x == 0) {
             const double bb = lds[0];
             st->bnorm2 = bb;
+            st->true_rr = lds[1];
             st->tol2 = st->tol2 * bb;
             if (!is_finite(bb) || !is_finite(lds[1])) {
                 st->status = kStNonfinite;
@@ -466,7 +473,14 @@ hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int
 }
 
 hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s) {
-    hipLaunchKernelGGL(k_spmv_gamma, dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B, p, q);
+    hipLaunchKernelGGL((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B,
+                       p, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s) {
+    hipLaunchKernelGGL((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B,
+                       p, q);
     return hipGetLastError();
 }
 

@@ -24,37 +24,39 @@ int basis_tier(int y) {
 // counts the iteration and tests ||r|| <= tol ||b||.
 // Column of W or A W: read once per iteration, so loaded nontemporally when
 // NTB (keeps the smaller vectors resident in the caches).
-template <bool NTB>
-__device__ __forceinline__ double basis_load(const double* p) {
+template <bool NTB, typename T>
+__device__ __forceinline__ T basis_load(const T* p) {
     return NTB ? __builtin_nontemporal_load(p) : *p;
 }
 
-template <int YB, bool NTB = false>
-__global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __restrict__ r,
-                                                   double* __restrict__ z,
-                                                   const double* __restrict__ q,
-                                                   const double* __restrict__ AW) {
+// T: storage and arithmetic type of the vectors and of A W (FP64, or FP32
+// for the inner solve of mixed precision); all sums are accumulated in FP64.
+template <typename T, int YB, bool NTB = false>
+__global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restrict__ r,
+                                                   T* __restrict__ z, const T* __restrict__ q,
+                                                   const T* __restrict__ AW) {
     constexpr int NV = 2 + YB;
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
     DevState* st = B.st;
     if (st->done != kRunning) return;
-    const double alpha = st->alpha;
+    const T alpha = (T)st->alpha;
+    const T* __restrict__ dinv = mat_dinv<T>(B);
     double v[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const double ri = r[i] - alpha * q[i];
-        const double zi = B.dinv[i] * ri;
+        const T ri = r[i] - alpha * q[i];
+        const T zi = dinv[i] * ri;
         r[i] = ri;
         z[i] = zi;
-        v[0] += ri * zi;
-        v[1] += ri * ri;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
 #pragma unroll
         for (int k = 0; k < YB; ++k) {
-            const double a = basis_load<NTB>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
-            if (tier_live<YB>(k, y)) v[2 + k] += a * zi;
+            const T a = basis_load<NTB>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
+            if (tier_live<YB>(k, y)) v[2 + k] += (double)a * (double)zi;
         }
     }
     if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
@@ -89,10 +91,13 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, double* __r
 //   p <- z + beta p - W mu,
 // which keeps p A-orthogonal to range(W) (Alg. 1).  INIT forms the first
 // direction p = z - W mu and leaves x alone.
-template <int YB, bool INIT, bool NTB = false>
-__global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, double* __restrict__ p,
-                                                double* __restrict__ x, const double* __restrict__ z,
-                                                const double* __restrict__ W) {
+// The solution x is always FP64: with FP32 vectors (mixed precision) the
+// update x += alpha p is carried out in FP64, so the correction of a
+// refinement step is accumulated without FP32 rounding.
+template <typename T, int YB, bool INIT, bool NTB = false>
+__global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict__ p,
+                                                double* __restrict__ x, const T* __restrict__ z,
+                                                const T* __restrict__ W) {
     const DevState* st = B.st;
     const int done = st->done;
     if (INIT) {
@@ -101,19 +106,20 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, double* __rest
         return;
     }
     const bool new_dir = INIT || done == kRunning;
-    const double alpha = st->alpha, beta = st->beta;
-    double mu[YB > 0 ? YB : 1];
+    const double alpha = st->alpha;
+    const T beta = (T)st->beta;
+    T mu[YB > 0 ? YB : 1];
 #pragma unroll
-    for (int k = 0; k < YB; ++k) mu[k] = k < y ? st->mu[k] : 0.0;
+    for (int k = 0; k < YB; ++k) mu[k] = k < y ? (T)st->mu[k] : (T)0;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        double s;
+        T s;
         if (INIT) {
             s = z[i];
         } else {
-            const double pi = p[i];
-            x[i] += alpha * pi;
+            const T pi = p[i];
+            x[i] += alpha * (double)pi;
             if (!new_dir) continue;
             s = z[i] + beta * pi;
         }
@@ -245,6 +251,89 @@ __global__ void k_state_init(DevState* st, int maxit, double tol2, int y) {
     st->rho = st->alpha = st->beta = st->gamma = 0.0;
 }
 
+// Stage 1 of one refinement step of the mixed-precision solve.  In FP64:
+// x64 += W what and r = r64 - (A W) what (what = G^{-1} W^T r64 from the
+// residual kernel); then the inner system starts in FP32: r32 = r,
+// z32 = M^{-1} r32, with the sums (r, z), (r, r) and (A W)^T z accumulated in
+// FP64.  The inner iterations add their steps to x64 directly.  The last workgroup sets mu = G^{-1} (A W)^T z and the
+// inner tolerance tol2 = inner_rtol2 (r, r).
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_stage1_mixed(DevBufs B, int y, double* __restrict__ x64,
+                                                         const double* __restrict__ r64,
+                                                         float* __restrict__ r32,
+                                                         float* __restrict__ z32,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ AW,
+                                                         const float* __restrict__ AW32,
+                                                         double inner_rtol2) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    DevState* st = B.st;
+    if (st->done != kRunning) return;
+    double what[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int k = 0; k < YB; ++k) what[k] = k < y ? st->what[k] : 0.0;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double ri = r64[i];
+        if (YB > 0) {
+            double wx = 0.0, awx = 0.0;
+#pragma unroll
+            for (int k = 0; k < YB; ++k) {
+                const int kc = tier_col<YB>(k, y);
+                wx += W[(size_t)kc * B.ld + i] * what[k];
+                awx += AW[(size_t)kc * B.ld + i] * what[k];
+            }
+            x64[i] += wx;
+            ri -= awx;
+        }
+        const float rf = (float)ri;
+        const float zf = B.dinv32[i] * rf;
+        r32[i] = rf;
+        z32[i] = zf;
+        v[0] += (double)rf * (double)zf;
+        v[1] += (double)rf * (double)rf;
+#pragma unroll
+        for (int k = 0; k < YB; ++k) {
+            const float a = AW32[(size_t)tier_col<YB>(k, y) * B.ld + i];
+            if (tier_live<YB>(k, y)) v[2 + k] += (double)a * (double)zf;
+        }
+    }
+    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rz = lds[0], rr = lds[1];
+        st->rho = rz;
+        st->rr = rr;
+        st->rr0 = rr;
+        // the inner solve aims at inner_rtol relative to its own right-hand
+        // side, but never below half of the outer target (st->tol2 holds
+        // rtol^2 ||b||^2 from the residual kernel)
+        st->tol2 = fmax(inner_rtol2 * rr, 0.25 * st->tol2);
+        if (!is_finite(rr) || !is_finite(rz)) {
+            st->status = kStNonfinite;
+            st->done = kFailed;
+        } else if (rr == 0.0 || st->maxit <= 0) {
+            st->status = rr == 0.0 ? kStOk : kStNotConverged;
+            st->done = kFinished;
+        }
+    }
+    if (threadIdx.x < y) {
+        double sum = 0.0;
+        for (int j = 0; j < y; ++j) sum += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+        st->mu[threadIdx.x] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ a, float* __restrict__ b,
+                                                     size_t n) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        b[i] = (float)a[i];
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
@@ -257,7 +346,7 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
                          const double* AW, hipStream_t s) {
     dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
     switch (yb) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_update<T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
+#define CASE(T) case T: hipLaunchKernelGGL((k_update<double, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -271,8 +360,8 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<T, true, true>), g, t, 0, s, B, y, p, x, z, W);        \
-        else hipLaunchKernelGGL((k_dir<T, false, true>), g, t, 0, s, B, y, p, x, z, W);            \
+        if (init) hipLaunchKernelGGL((k_dir<double, T, true, true>), g, t, 0, s, B, y, p, x, z, W); \
+        else hipLaunchKernelGGL((k_dir<double, T, false, true>), g, t, 0, s, B, y, p, x, z, W);     \
         break;
         PODCG_TIERS(CASE)
 #undef CASE
@@ -325,6 +414,60 @@ hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, d
 
 hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s) {
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, tol2, y);
+    return hipGetLastError();
+}
+
+}  // namespace podcg
+
+namespace podcg {
+
+hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
+                           const float* AW, hipStream_t s) {
+    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_update<float, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
+                        const float* W, bool init, hipStream_t s) {
+    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
+    switch (yb) {
+#define CASE(T)                                                                                    \
+    case T:                                                                                        \
+        if (init) hipLaunchKernelGGL((k_dir<float, T, true, true>), g, t, 0, s, B, y, p, x, z, W);  \
+        else hipLaunchKernelGGL((k_dir<float, T, false, true>), g, t, 0, s, B, y, p, x, z, W);      \
+        break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage1_mixed(const DevBufs& B, int yb, int y, double* x64, const double* r64,
+                               float* r32, float* z32, const double* W, const double* AW,
+                               const float* AW32, double inner_rtol, hipStream_t s) {
+    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    const double r2 = inner_rtol * inner_rtol;
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_stage1_mixed<T>), g, t, 0, s, B, y, x64, r64, r32, z32, W, AW, AW32, r2); break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double* src, float* dst, size_t n, hipStream_t s) {
+    int64_t g = ((int64_t)n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_to_float, dim3((int)g), dim3(kBlock), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

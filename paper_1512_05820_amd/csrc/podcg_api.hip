@@ -47,6 +47,10 @@ struct podcg_ctx {
 
     // CG vectors (length ld)
     double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
+    // mixed precision: FP32 copies of the matrix, Jacobi inverse, basis and
+    // the inner-solve vectors (the solution itself stays FP64)
+    float *d_vals32 = nullptr, *d_dinv32 = nullptr, *d_W32 = nullptr, *d_AW32 = nullptr;
+    float *d_r32 = nullptr, *d_z32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr;
 
     // basis
     double *d_W = nullptr, *d_AW = nullptr;
@@ -115,6 +119,8 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.part = ctx->d_part;
     B.counter = ctx->d_counter;
     B.Ginv = ctx->d_Ginv;
+    B.vals32 = ctx->d_vals32;
+    B.dinv32 = ctx->d_dinv32;
     return B;
 }
 
@@ -129,7 +135,8 @@ void poll(podcg_ctx* ctx) {
 void check_opts(const podcg_options& o) {
     if (o.omega < 1 || o.omega > PODCG_MAX_BASIS || o.rank_max < 0 || o.rank_max > PODCG_MAX_BASIS ||
         o.maxit < 0 || o.check_every < 1 || (o.weights != 0 && o.weights != 1) || o.timing < 0 ||
-        !(o.rank_rtol >= 0.0) || !(o.energy > 0.0))
+        !(o.rank_rtol >= 0.0) || !(o.energy > 0.0) || (o.precision != 0 && o.precision != 1) ||
+        o.max_refine < 1 || !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0))
         throw Fail{PODCG_ERR_INVALID_ARG};
 }
 
@@ -150,6 +157,10 @@ void setup_basis(podcg_ctx* ctx) {
     const int kept = ctx->h_poll->y;
     ctx->y_kept = kept;
     ctx->rank_reduced = kept < ctx->y;
+    if (ctx->opt.precision == 1 && kept > 0) {
+        HIPCHECK(launch_to_float(ctx->d_W, ctx->d_W32, ctx->ld * (size_t)kept, ctx->stream));
+        HIPCHECK(launch_to_float(ctx->d_AW, ctx->d_AW32, ctx->ld * (size_t)kept, ctx->stream));
+    }
     if (kept > 0) {
         HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * kept, hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -163,6 +174,126 @@ void setup_basis(podcg_ctx* ctx) {
 }
 
 void record(podcg_ctx* ctx, hipEvent_t e) { HIPCHECK(hipEventRecord(e, ctx->stream)); }
+
+// Launch loop iterations in batches until the device reports that the solve
+// finished, or maxit iterations were launched.  `iter3(t, ev)` enqueues one
+// iteration (SpMV, update, direction), recording ev[0..3] around the kernels
+// when t.  The first convergence check comes after most of the previous
+// solve's iteration count (kernels after convergence are no-ops), then every
+// check_every iterations.  Returns the iteration indices that were timed.
+template <class F>
+std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
+    const int timing = ctx->opt.timing;
+    std::vector<int> timed;
+    int launched = 0;
+    ctx->h_poll->done = kRunning;   // the loop kernels are no-ops once Stage 1 has finished
+    int first = (int)(0.85 * ctx->prev_iters[slot]);
+    first = std::max(first, ctx->opt.check_every);
+    while (ctx->h_poll->done == kRunning && launched < ctx->opt.maxit) {
+        const int want = launched == 0 ? first : ctx->opt.check_every;
+        const int batch = std::min(want, ctx->opt.maxit - launched);
+        for (int k = 0; k < batch; ++k, ++launched) {
+            const bool t = timing > 0 && (launched % timing) == 0;
+            hipEvent_t* ev = nullptr;
+            if (t) {
+                const size_t base = timed.size() * 4;
+                while (ctx->tev.size() < base + 4) {
+                    hipEvent_t e;
+                    HIPCHECK(hipEventCreate(&e));
+                    ctx->tev.push_back(e);
+                }
+                timed.push_back(launched);
+                ev = &ctx->tev[base];
+            }
+            iter3(t, ev);
+        }
+        poll(ctx);
+        ++*polls;
+    }
+    return timed;
+}
+
+// Add the event-timed kernel durations of the first `iters` iterations.
+void add_timing(podcg_ctx* ctx, const std::vector<int>& timed, int iters, podcg_stats& S) {
+    for (size_t k = 0; k < timed.size(); ++k) {
+        if (timed[k] >= iters) break;
+        float a = 0, b = 0, c = 0;
+        HIPCHECK(hipEventElapsedTime(&a, ctx->tev[4 * k + 0], ctx->tev[4 * k + 1]));
+        HIPCHECK(hipEventElapsedTime(&b, ctx->tev[4 * k + 1], ctx->tev[4 * k + 2]));
+        HIPCHECK(hipEventElapsedTime(&c, ctx->tev[4 * k + 2], ctx->tev[4 * k + 3]));
+        S.spmv_ms += a;
+        S.update_ms += b;
+        S.dir_ms += c;
+        S.timed_iters += 1;
+    }
+}
+
+int fail_code(podcg_ctx* ctx, const PollBlock& P) {
+    ctx->last_error = P.status == PODCG_ERR_NOT_SPD ? "(A p, p) <= 0: matrix not SPD"
+                                                    : "non-finite value in the iteration";
+    return P.status;
+}
+
+// FP64 iterative refinement around FP32 augmented PCG (precision = 1).
+int solve_mixed(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats& S, bool plain,
+                int y, bool did_setup) {
+    const int yb = basis_tier(y);
+    DevBufs B = bufs(ctx);
+    hipStream_t s = ctx->stream;
+    const int slot = plain ? 1 : 0;
+    int polls = 0, total = 0, steps = 0, code = PODCG_NOT_CONVERGED;
+    double bn2 = 0.0, rr64 = 0.0;
+    std::vector<int> timed_all;
+    for (int step = 0;; ++step) {
+        HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s));
+        // FP64 residual r = b - A x, with what = G^{-1} W^T r for Stage 1
+        HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
+        poll(ctx);
+        ++polls;
+        const PollBlock R = *ctx->h_poll;
+        if (R.done == kFailed) return fail_code(ctx, R);
+        bn2 = R.bnorm2;
+        rr64 = R.true_rr;
+        if (step == 1) S.first_inner_relres = bn2 > 0 ? std::sqrt(rr64 / bn2) : std::sqrt(rr64);
+        if (rr64 <= rtol * rtol * bn2) {
+            code = PODCG_OK;
+            break;
+        }
+        if (step >= ctx->opt.max_refine) break;
+        // Stage 1 in FP64, then the FP32 augmented PCG on the correction
+        HIPCHECK(launch_stage1_mixed(B, yb, y, x, ctx->d_r, ctx->d_r32, ctx->d_z32, ctx->d_W,
+                                     ctx->d_AW, ctx->d_AW32, ctx->opt.inner_rtol, s));
+        HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, true, s));
+        std::vector<int> timed = run_loop(ctx, slot, &polls, [&](bool t, hipEvent_t* ev) {
+            if (t) record(ctx, ev[0]);
+            HIPCHECK(launch_spmv_gamma32(B, ctx->d_p32, ctx->d_q32, s));
+            if (t) record(ctx, ev[1]);
+            HIPCHECK(launch_update32(B, yb, y, ctx->d_r32, ctx->d_z32, ctx->d_q32, ctx->d_AW32, s));
+            if (t) record(ctx, ev[2]);
+            HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, false, s));
+            if (t) record(ctx, ev[3]);
+        });
+        poll(ctx);
+        const PollBlock P = *ctx->h_poll;
+        if (P.done == kFailed) return fail_code(ctx, P);
+        if (step == 0) S.stage1_relres = bn2 > 0 ? std::sqrt(P.rr0 / bn2) : std::sqrt(P.rr0);
+        add_timing(ctx, timed, P.iter, S);
+        ctx->prev_iters[slot] = P.iter;
+        total += P.iter;
+        ++steps;
+    }
+    const double bn = std::sqrt(bn2);
+    S.bnorm = bn;
+    S.iters = total;
+    S.refine_steps = steps;
+    S.relres = S.true_relres = bn > 0 ? std::sqrt(rr64) / bn : std::sqrt(rr64);
+    if (steps == 0) S.stage1_relres = S.relres;
+    S.matvecs = total + steps + 1 + (did_setup ? ctx->y : 0);
+    S.polls = polls;
+    S.rank = y;
+    S.cond_G = y > 0 ? ctx->cond_G : 1.0;
+    return code;
+}
 
 int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st, bool plain) {
     if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
@@ -181,91 +312,54 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
     const int yb = basis_tier(y);
     DevBufs B = bufs(ctx);
     hipStream_t s = ctx->stream;
+    int code;
 
-    HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s));
-    // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
-    HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
-    // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r, mu = G^{-1} (A W)^T z
-    HIPCHECK(launch_stage1_apply(B, yb, y, x, ctx->d_r, ctx->d_z, ctx->d_W, ctx->d_AW, s));
-    // p = z - W mu
-    HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
-
-    const int timing = ctx->opt.timing;
-    std::vector<int> timed;   // iteration indices with events
-    int launched = 0;
-    int polls = 0;
-    ctx->h_poll->done = kRunning;   // the loop kernels are no-ops once Stage 1 has finished
-    // The first convergence check comes after most of the previous solve's
-    // iteration count (kernels after convergence are no-ops), then every
-    // check_every iterations.
-    int first = (int)(0.85 * ctx->prev_iters[plain ? 1 : 0]);
-    first = std::max(first, ctx->opt.check_every);
-    while (ctx->h_poll->done == kRunning && launched < ctx->opt.maxit) {
-        const int want = launched == 0 ? first : ctx->opt.check_every;
-        const int batch = std::min(want, ctx->opt.maxit - launched);
-        for (int k = 0; k < batch; ++k, ++launched) {
-            const bool t = timing > 0 && (launched % timing) == 0;
-            size_t base = 0;
-            if (t) {
-                base = timed.size() * 4;
-                while (ctx->tev.size() < base + 4) {
-                    hipEvent_t e;
-                    HIPCHECK(hipEventCreate(&e));
-                    ctx->tev.push_back(e);
-                }
-                timed.push_back(launched);
-                record(ctx, ctx->tev[base + 0]);
-            }
+    if (ctx->opt.precision == 1) {
+        code = solve_mixed(ctx, b, x, rtol, S, plain, y, did_setup);
+        HIPCHECK(hipEventRecord(ctx->ev_c, s));
+        sync(ctx);
+    } else {
+        HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s));
+        // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
+        HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
+        // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r, mu = G^{-1} (A W)^T z
+        HIPCHECK(launch_stage1_apply(B, yb, y, x, ctx->d_r, ctx->d_z, ctx->d_W, ctx->d_AW, s));
+        // p = z - W mu
+        HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
+        int polls = 0;
+        std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev) {
+            if (t) record(ctx, ev[0]);
             HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s));
-            if (t) record(ctx, ctx->tev[base + 1]);
+            if (t) record(ctx, ev[1]);
             HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s));
-            if (t) record(ctx, ctx->tev[base + 2]);
+            if (t) record(ctx, ev[2]);
             HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s));
-            if (t) record(ctx, ctx->tev[base + 3]);
-        }
+            if (t) record(ctx, ev[3]);
+        });
+        // true residual ||b - A x||
+        HIPCHECK(launch_resid(B, 0, 0, b, x, nullptr, nullptr, false, false, s));
+        HIPCHECK(hipEventRecord(ctx->ev_c, s));
         poll(ctx);
-        ++polls;
+        const PollBlock P = *ctx->h_poll;
+        S.iters = P.iter;
+        ctx->prev_iters[plain ? 1 : 0] = P.iter;
+        S.rank = y;
+        const double bn = std::sqrt(P.bnorm2);
+        S.bnorm = bn;
+        S.stage1_relres = bn > 0 ? std::sqrt(P.rr0) / bn : std::sqrt(P.rr0);
+        S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
+        S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
+        S.cond_G = y > 0 ? ctx->cond_G : 1.0;
+        S.matvecs = P.iter + 2 + (did_setup ? ctx->y : 0);
+        S.polls = polls;
+        add_timing(ctx, timed, P.iter, S);
+        code = P.done == kFailed ? fail_code(ctx, P) : P.status;
     }
-    // true residual ||b - A x||
-    HIPCHECK(launch_resid(B, 0, 0, b, x, nullptr, nullptr, false, false, s));
-    HIPCHECK(hipEventRecord(ctx->ev_c, s));
-    poll(ctx);
-    const PollBlock P = *ctx->h_poll;
-
     HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
     S.setup_ms = did_setup ? ms : 0.0;
     HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_b, ctx->ev_c));
     S.solve_ms = ms;
-    S.iters = P.iter;
-    ctx->prev_iters[plain ? 1 : 0] = P.iter;
-    S.rank = y;
-    const double bn = std::sqrt(P.bnorm2);
-    S.bnorm = bn;
-    S.stage1_relres = bn > 0 ? std::sqrt(P.rr0) / bn : std::sqrt(P.rr0);
-    S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
-    S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
-    S.cond_G = y > 0 ? ctx->cond_G : 1.0;
-    S.matvecs = P.iter + 2 + (did_setup ? ctx->y : 0);
-    S.polls = polls;
-    for (size_t k = 0; k < timed.size(); ++k) {
-        if (timed[k] >= P.iter) break;
-        float a = 0, b2 = 0, c = 0;
-        HIPCHECK(hipEventElapsedTime(&a, ctx->tev[4 * k + 0], ctx->tev[4 * k + 1]));
-        HIPCHECK(hipEventElapsedTime(&b2, ctx->tev[4 * k + 1], ctx->tev[4 * k + 2]));
-        HIPCHECK(hipEventElapsedTime(&c, ctx->tev[4 * k + 2], ctx->tev[4 * k + 3]));
-        S.spmv_ms += a;
-        S.update_ms += b2;
-        S.dir_ms += c;
-        S.timed_iters += 1;
-    }
-    int code = P.status;
-    if (P.done == kFailed) {
-        code = P.status;
-        ctx->last_error = code == PODCG_ERR_NOT_SPD ? "(A p, p) <= 0: matrix not SPD"
-                                                    : "non-finite value in the iteration";
-    } else if (code == PODCG_OK && !plain && ctx->rank_reduced) {
-        code = PODCG_RANK_REDUCED;
-    }
+    if (code == PODCG_OK && !plain && ctx->rank_reduced) code = PODCG_RANK_REDUCED;
     S.status = code;
     if (st) *st = S;
     return code;
@@ -293,7 +387,9 @@ void release(podcg_ctx* ctx) {
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
-                   ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag};
+                   ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag,
+                   ctx->d_vals32, ctx->d_dinv32, ctx->d_W32, ctx->d_AW32, ctx->d_r32, ctx->d_z32,
+                   ctx->d_p32, ctx->d_q32};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
@@ -321,6 +417,9 @@ void podcg_default_options(podcg_options* o) {
     o->timing = 0;
     o->rank_rtol = 1e-12;
     o->energy = 1.0;
+    o->precision = 0;
+    o->max_refine = 20;
+    o->inner_rtol = 1e-6;
 }
 
 const char* podcg_strerror(int code) {
@@ -375,6 +474,17 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_W, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_AW, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_S, ld * (size_t)o.omega);
+        if (o.precision == 1) {
+            dalloc(ctx, &ctx->d_dinv32, ld);
+            dalloc(ctx, &ctx->d_r32, ld);
+            dalloc(ctx, &ctx->d_z32, ld);
+            dalloc(ctx, &ctx->d_p32, ld);
+            dalloc(ctx, &ctx->d_q32, ld);
+            dalloc(ctx, &ctx->d_W32, ld * (size_t)std::max(1, o.rank_max));
+            dalloc(ctx, &ctx->d_AW32, ld * (size_t)std::max(1, o.rank_max));
+            HIPCHECK(hipMemsetAsync(ctx->d_p32, 0, ld * sizeof(float), ctx->stream));
+            HIPCHECK(hipMemsetAsync(ctx->d_q32, 0, ld * sizeof(float), ctx->stream));
+        }
         dalloc(ctx, &ctx->d_G, kYMax * kYMax);
         dalloc(ctx, &ctx->d_R, kYMax * kYMax);
         dalloc(ctx, &ctx->d_Ginv, kYMax * kYMax);
@@ -452,6 +562,7 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
                 dalloc(ctx, &ctx->d_cols, (size_t)nsell);
                 dalloc(ctx, &ctx->d_map, (size_t)nsell);
                 dalloc(ctx, &ctx->d_vals, (size_t)nsell);
+                if (ctx->opt.precision == 1) dalloc(ctx, &ctx->d_vals32, (size_t)nsell);
                 ctx->sell_cap = nsell;
             }
             ctx->nsell = nsell;
@@ -476,6 +587,10 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
         if (ctx->h_int[0] & 4) {
             ctx->has_values = false;
             fail(ctx, PODCG_ERR_NOT_SPD, "missing or non-positive diagonal entry");
+        }
+        if (ctx->opt.precision == 1) {
+            HIPCHECK(launch_to_float(ctx->d_vals, ctx->d_vals32, (size_t)ctx->nsell, s));
+            HIPCHECK(launch_to_float(ctx->d_dinv, ctx->d_dinv32, ctx->ld, s));
         }
         ctx->has_values = true;
         return PODCG_OK;

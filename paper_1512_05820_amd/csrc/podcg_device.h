@@ -183,7 +183,17 @@ struct DevBufs {
     double* part;
     unsigned* counter;
     const double* Ginv;        // y x y row-major
+    const float* vals32;       // FP32 copy of the SELL values (mixed precision)
+    const float* dinv32;       // FP32 copy of dinv
 };
+
+// Matrix values and Jacobi inverse in the storage type T of a kernel.
+template <typename T> __device__ __forceinline__ const T* mat_vals(const DevBufs& B);
+template <> __device__ __forceinline__ const double* mat_vals<double>(const DevBufs& B) { return B.vals; }
+template <> __device__ __forceinline__ const float* mat_vals<float>(const DevBufs& B) { return B.vals32; }
+template <typename T> __device__ __forceinline__ const T* mat_dinv(const DevBufs& B);
+template <> __device__ __forceinline__ const double* mat_dinv<double>(const DevBufs& B) { return B.dinv; }
+template <> __device__ __forceinline__ const float* mat_dinv<float>(const DevBufs& B) { return B.dinv32; }
 
 // SELL kernels (k_sell.hip)
 hipError_t launch_validate_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
@@ -196,6 +206,7 @@ hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int
                               const int* map, const double* csr_vals, double* vals, double* dinv,
                               int* flag, hipStream_t s);
 hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s);
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s);
 hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);
 hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x,
                         double* r, const double* W, bool store, bool stage1, hipStream_t s);
@@ -211,6 +222,19 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
                       const double* W, bool init, hipStream_t s);
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s);
+// FP32 loop kernels of the mixed-precision inner solve (same state machine).
+hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
+                           const float* AW, hipStream_t s);
+hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
+                        const float* W, bool init, hipStream_t s);
+// Mixed-precision Stage 1 of one refinement step: from the FP64 residual r64
+// (and what = G^{-1} W^T r64 in the state), x64 += W what, r = r64 - (A W) what
+// in FP64, then r32 = r, z32 = M^{-1} r32, sums (r, z), (r, r), (A W)^T z; the
+// inner tolerance is max(inner_rtol^2 (r, r), (rtol ||b|| / 2)^2).
+hipError_t launch_stage1_mixed(const DevBufs& B, int yb, int y, double* x64, const double* r64,
+                               float* r32, float* z32, const double* W, const double* AW,
+                               const float* AW32, double inner_rtol, hipStream_t s);
+hipError_t launch_to_float(const double* src, float* dst, size_t n, hipStream_t s);
 hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
                            double* W, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);

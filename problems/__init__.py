@@ -11,9 +11,12 @@ from .fv import FVDiffusion
 from .configs import (
     Config1Diffusion2D,
     Config2Diffusion3D,
+    Config3Elasticity,
     config1,
     config2,
+    config3,
 )
+from .elasticity import Q1Elasticity
 from . import tiny
 
 __all__ = [
@@ -23,5 +26,8 @@ __all__ = [
     "Config2Diffusion3D",
     "config1",
     "config2",
+    "config3",
+    "Config3Elasticity",
+    "Q1Elasticity",
     "tiny",
 ]
