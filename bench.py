@@ -108,6 +108,87 @@ def cpu_baseline(cfg, systems: int) -> dict:
             "iters": [r["iters"] for r in res]}
 
 
+def bench_config3(args):
+    """Mixed precision at the stated size: Q1 elasticity 64^3 x 3 dof, 30 systems.
+
+    Times whole sequences of augmented PCG (and plain PCG, warm start) in FP64
+    and in mixed precision (FP32 inner solve, FP64 refinement), for the stated
+    load (scaled, collinear) and for the moving-load variant, and states the
+    error of system 1 against the FP64 oracle."""
+    import torch
+    import paper_1512_05820_amd as P
+    import oracle
+    from problems import config3
+
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "unit": "ms/sequence", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f32 inner / f64 refinement", "vs_baseline": None}
+    results = {}
+    for variant in ("scale", "moving"):
+        cfg = config3(variant=variant, steps=args.systems if args.systems != 50 else 30)
+        vals = torch.from_numpy(cfg.matrix_values(1)).cuda()
+        rowptr, colind = torch.from_numpy(cfg.rowptr).cuda(), torch.from_numpy(cfg.colind).cuda()
+        rhs = [torch.from_numpy(cfg.rhs(j)).cuda() for j in range(1, cfg.steps + 1)]
+        for precision in ("mixed", "fp64"):
+            ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, precision=precision)
+            ctx.set_matrix(vals, rowptr, colind)
+            for method in ("aug", "plain"):
+                for rep in range(1 + args.warmup):
+                    ctx.reset_snapshots()
+                    ctx.set_basis(None)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    sts, x_prev, x1 = [], None, None
+                    for j in range(cfg.steps):
+                        if method == "aug" or x_prev is None:
+                            x = torch.zeros(cfg.n, dtype=torch.float64, device="cuda")
+                        else:
+                            x = x_prev.clone()
+                        st = (ctx.solve if method == "aug" else ctx.solve_plain)(rhs[j], x, cfg.tol)
+                        if method == "aug":
+                            ctx.push_snapshot(x)
+                            ctx.build_pod()
+                        if st.status not in (0, 2):
+                            raise RuntimeError(f"{variant}/{precision}/{method} system {j + 1}: {st.status}")
+                        sts.append(st.as_dict())
+                        x_prev = x
+                        if j == 0:
+                            x1 = x.clone()
+                    torch.cuda.synchronize()
+                    ms = 1e3 * (time.perf_counter() - t1)
+                key = f"{variant}/{precision}/{method}"
+                results[key] = {"ms": round(ms, 2), "iters": sum(s["iters"] for s in sts),
+                                "refine_steps": sum(s["refine_steps"] for s in sts),
+                                "first_inner_relres_sys1": sts[0]["first_inner_relres"],
+                                "max_true_relres": max(s["true_relres"] for s in sts)}
+                if variant == "scale" and method == "aug":
+                    results[key]["x1"] = x1.cpu().numpy()
+                log(key, {k: v for k, v in results[key].items() if k != "x1"})
+            ctx.close()
+    # error of system 1 against the FP64 oracle (solved to 1e-12)
+    cfg = config3()
+    A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(1))
+    t1 = time.perf_counter()
+    x_ref, so = oracle.plain_pcg(A, cfg.rhs(1), np.zeros(cfg.n), 1e-12, 100000)
+    cpu_s = time.perf_counter() - t1
+    errs = {}
+    for prec in ("mixed", "fp64"):
+        x1 = results[f"scale/{prec}/aug"].pop("x1")
+        errs[prec] = float(np.linalg.norm(x1 - x_ref) / np.linalg.norm(x_ref))
+    for k in results:
+        results[k].pop("x1", None)
+    out.update({"value": results["moving/mixed/aug"]["ms"], "ms_per_step": results["moving/mixed/aug"]["ms"],
+                "steps": 1, "warmup": args.warmup, "scaling": "weak",
+                "config": {"workload": cfg.name, "N": cfg.N, "n": cfg.n, "nnz": cfg.nnz,
+                           "systems": cfg.steps, "omega": cfg.omega, "rank_max": cfg.rank,
+                           "rel_tol": cfg.tol, "value_is": "moving-load variant, mixed precision"},
+                "runs": results,
+                "rel_error_vs_fp64_oracle_system1": errs,
+                "oracle_system1": {"iters": so.iters, "seconds": round(cpu_s, 2),
+                                   "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,11 +199,16 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3"],
+                    help="config2 (default, the headline) or config3 (mixed precision)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "config3":
+        bench_config3(args)
+        return
 
     import torch
     import paper_1512_05820_amd as P
