@@ -189,6 +189,71 @@ def bench_config3(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_config5(args):
+    """Differentiation at the stated size: 96^3 diffusion, 200 systems, outputs at
+    256 dofs, gradients of J = sum_j w_j . q_j with respect to log kappa and the
+    source, adjoint solves reusing the recycled bases, checkpoints every 20."""
+    import torch
+    import paper_1512_05820_amd as P
+    from paper_1512_05820_amd.adjoint import RecycledSequence, SequenceSpec
+    from problems import config5
+    from problems.fv_torch import FVDiffusionTorch
+
+    torch.cuda.set_device(0)
+    steps = args.systems if args.systems != 50 else 200
+    cfg = config5(steps=steps)
+    fvt = FVDiffusionTorch(cfg.fv, "cuda")
+    outs = torch.from_numpy(cfg.outputs).cuda()
+    theta = torch.from_numpy(cfg.theta).cuda()
+
+    def assemble(j, params):
+        return fvt.values(torch.exp(params[0][cfg.window(j)]), shift=1.0 / cfg.dt)
+
+    def rhs(j, x_prev, params):
+        return params[1].clone() if x_prev is None else params[1] + x_prev / cfg.dt
+
+    spec = SequenceSpec(cfg.steps, assemble, rhs, lambda j, x: x[outs], cfg.tol, cfg.checkpoint_every)
+    mk = lambda: P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=50000)
+    solver, adj = mk(), mk()
+    v0 = assemble(1, (theta, None)).contiguous()
+    rp, ci = torch.from_numpy(cfg.rowptr).cuda(), torch.from_numpy(cfg.colind).cuda()
+    solver.set_matrix(v0, rp, ci)
+    adj.set_matrix(v0, rp, ci)
+    w = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).standard_normal(
+        (cfg.steps, cfg.outputs.size))).cuda()
+    rec = {}
+    for rep in range(1 + args.warmup):
+        th = theta.clone().requires_grad_(True)
+        s = torch.full((cfg.n,), cfg.source, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q = RecycledSequence.apply(solver, adj, spec, th, s)
+        J = (q * w).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        node = q.grad_fn
+        rec = {"forward_ms": round(1e3 * (t1 - t0), 1), "backward_ms": round(1e3 * (t2 - t1), 1),
+               "J": float(J), "grad_theta_norm": float(th.grad.norm()),
+               "grad_s_norm": float(s.grad.norm())}
+        log(f"rep {rep}: {rec}")
+    fwd_it = adj_it = None
+    try:
+        fwd_it = sum(st["iters"] for st in node.forward_stats)
+        adj_it = sum(st["iters"] for st in node.adjoint_stats)
+    except AttributeError:
+        pass
+    total = rec["forward_ms"] + rec["backward_ms"]
+    out = {"metric": METRIC, "value": round(total, 1), "unit": "ms per forward+backward sequence",
+           "n_gpus": 1, "steps": 1, "warmup": args.warmup, "ms_per_step": round(total, 1),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": cfg.describe(), **rec,
+           "forward_iters": fwd_it, "adjoint_iters": adj_it}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,8 +264,9 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3"],
-                    help="config2 (default, the headline) or config3 (mixed precision)")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"],
+                    help="config2 (default, the headline), config3 (mixed precision) or "
+                         "config5 (adjoint gradients)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -208,6 +274,9 @@ def main():
         sys.exit(2)
     if args.workload == "config3":
         bench_config3(args)
+        return
+    if args.workload == "config5":
+        bench_config5(args)
         return
 
     import torch

@@ -179,6 +179,16 @@ int podcg_solve_plain(podcg_ctx* ctx, const double* b, double* x, double rtol, p
 /* y = A_j x for device vectors of length n (x and y must not overlap). */
 int podcg_matvec(podcg_ctx* ctx, const double* x, double* y);
 
+/* out_vals[e] = scale * u[row(e)] * v[col(e)] for every stored entry e of the
+ * current CSR pattern, in the caller's CSR order (device, nnz float64).
+ * u, v: device, n float64.  With u = lambda (the adjoint solution, Section 2's
+ * output functional q = C x differentiated through A x = b), v = x and
+ * scale = -1, this is the gradient of lambda^T (b - A x) with respect to the
+ * matrix values, i.e. the matrix part of the adjoint of a solve.
+ * Errors: NO_MATRIX, INVALID_ARG, HIP. */
+int podcg_pattern_outer(podcg_ctx* ctx, const double* u, const double* v, double scale,
+                        double* out_vals);
+
 /* Bandwidth probe for the roofline: c[i] = a[i] + s * b[i] over n float64
  * device elements, launched `reps` times on the context stream; *ms (host)
  * receives the mean GPU time of one launch.  Not part of the method. */

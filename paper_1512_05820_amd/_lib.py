@@ -17,8 +17,8 @@ EXPORTED = [
     "podcg_default_options", "podcg_create", "podcg_destroy", "podcg_set_matrix",
     "podcg_push_snapshot", "podcg_reset_snapshots", "podcg_build_pod", "podcg_set_basis",
     "podcg_get_basis", "podcg_get_reduced", "podcg_get_pod_spectrum", "podcg_solve",
-    "podcg_solve_plain", "podcg_matvec", "podcg_stream_triad", "podcg_strerror",
-    "podcg_last_error",
+    "podcg_solve_plain", "podcg_matvec", "podcg_pattern_outer", "podcg_stream_triad",
+    "podcg_strerror", "podcg_last_error",
 ]
 
 
@@ -69,6 +69,7 @@ def load(path: str = LIB_PATH):
         "podcg_solve": ([P, P, P, D, C.POINTER(Stats)], C.c_int),
         "podcg_solve_plain": ([P, P, P, D, C.POINTER(Stats)], C.c_int),
         "podcg_matvec": ([P, P, P], C.c_int),
+        "podcg_pattern_outer": ([P, P, P, D, P], C.c_int),
         "podcg_stream_triad": ([P, P, P, P, I64, D, I32, C.POINTER(D)], C.c_int),
         "podcg_strerror": ([C.c_int], C.c_char_p),
         "podcg_last_error": ([P], C.c_char_p),

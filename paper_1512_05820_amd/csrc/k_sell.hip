@@ -134,6 +134,32 @@ __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
     if (bad) atomicOr(flag, bad);
 }
 
+// out[e] = scale * u[row(e)] * v[col(e)] for every stored CSR entry e, in CSR
+// order (the slot -> CSR map of the ingest).  With u = lambda, v = x and
+// scale = -1 this is the derivative of lambda^T (b - A x) with respect to the
+// matrix values.
+__global__ __launch_bounds__(kBlock) void k_pattern_outer(int n, int nslices,
+                                                          const int64_t* __restrict__ sptr,
+                                                          const int* __restrict__ cols,
+                                                          const int* __restrict__ map,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ v, double scale,
+                                                          double* __restrict__ out) {
+    const int total = nslices * kSlice;
+    for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock) {
+        if (row >= n) continue;
+        const int s = row / kSlice, lane = row % kSlice;
+        const int64_t base = sptr[s];
+        const int w = (int)((sptr[s + 1] - base) / kSlice);
+        const double ur = scale * u[row];
+        for (int j = 0; j < w; ++j) {
+            const int64_t slot = base + (int64_t)j * kSlice + lane;
+            const int m = map[slot];
+            if (m >= 0) out[m] = ur * v[cols[slot]];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- products
 
 // Row (64 s + lane) of A x for the slice s handled by this wave.  Slices of
@@ -469,6 +495,14 @@ hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int
                               int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_values, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
                        0, s, n, nslices, sptr, cols, map, csr_vals, vals, dinv, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const int* cols, const int* map,
+                                const double* u, const double* v, double scale, double* out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_pattern_outer, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock), 0,
+                       s, n, nslices, sptr, cols, map, u, v, scale, out);
     return hipGetLastError();
 }
 

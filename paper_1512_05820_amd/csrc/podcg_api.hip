@@ -718,6 +718,17 @@ int podcg_matvec(podcg_ctx* ctx, const double* x, double* y) {
     });
 }
 
+int podcg_pattern_outer(podcg_ctx* ctx, const double* u, const double* v, double scale,
+                        double* out_vals) {
+    return guarded(ctx, [&]() {
+        if (!ctx->has_pattern) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix pattern set");
+        if (!u || !v || !out_vals) fail(ctx, PODCG_ERR_INVALID_ARG, "bad vectors");
+        HIPCHECK(launch_pattern_outer((int)ctx->n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_map, u,
+                                      v, scale, out_vals, ctx->stream));
+        return PODCG_OK;
+    });
+}
+
 int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double* c, int64_t n,
                        double s, int32_t reps, double* ms) {
     return guarded(ctx, [&]() {

@@ -205,6 +205,9 @@ hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const 
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
                               const int* map, const double* csr_vals, double* vals, double* dinv,
                               int* flag, hipStream_t s);
+hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const int* cols, const int* map,
+                                const double* u, const double* v, double scale, double* out,
+                                hipStream_t s);
 hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s);
 hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s);
 hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);

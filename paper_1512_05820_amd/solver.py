@@ -140,6 +140,14 @@ class PodCG:
     def matvec(self, x: torch.Tensor, y: torch.Tensor):
         self._check(self._L.podcg_matvec(self._h, _ptr(x, torch.float64), _ptr(y, torch.float64)))
 
+    def pattern_outer(self, u: torch.Tensor, v: torch.Tensor, scale: float,
+                      out: torch.Tensor) -> torch.Tensor:
+        """out[e] = scale * u[row(e)] * v[col(e)] on the stored CSR pattern."""
+        self._check(self._L.podcg_pattern_outer(self._h, _ptr(u, torch.float64),
+                                                _ptr(v, torch.float64), float(scale),
+                                                _ptr(out, torch.float64)))
+        return out
+
     def stream_triad(self, a, b, c, s: float = 3.0, reps: int = 20) -> float:
         ms = C.c_double()
         self._check(self._L.podcg_stream_triad(self._h, _ptr(a, torch.float64),

@@ -12,9 +12,11 @@ from .configs import (
     Config1Diffusion2D,
     Config2Diffusion3D,
     Config3Elasticity,
+    Config5Adjoint,
     config1,
     config2,
     config3,
+    config5,
 )
 from .elasticity import Q1Elasticity
 from . import tiny
@@ -27,7 +29,9 @@ __all__ = [
     "config1",
     "config2",
     "config3",
+    "config5",
     "Config3Elasticity",
+    "Config5Adjoint",
     "Q1Elasticity",
     "tiny",
 ]

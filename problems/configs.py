@@ -29,6 +29,14 @@ Every constant lives here, so a run can record exactly what it solved.
   exact.  Variant "moving": the load is additionally weighted by a Gaussian
   bump (width 0.15, amplitude 1) whose centre moves along x with j, which
   makes the solutions genuinely change.
+
+* Config 5 -- differentiation: the config-2 family at N = 96 (n = 884,736),
+  200 systems, snapshot memory 20, POD rank 10, relative tolerance 1e-10.
+  Outputs q_j = C x_j with C = 256 distinct seeded rows of the identity
+  (seed 6).  Parameters: the log-coefficient field theta on the extended
+  grid (kappa_j is the window of exp(theta) shifted by j cells) and the
+  source s (b_j = x_{j-1} / dt + s).  Adjoint gradients are checkpointed every
+  20 systems.
 """
 
 from __future__ import annotations
@@ -182,3 +190,57 @@ def config2(**kw) -> Config2Diffusion3D:
 
 def config3(**kw) -> Config3Elasticity:
     return Config3Elasticity(**kw)
+
+
+@dataclass
+class Config5Adjoint:
+    N: int = 96
+    steps: int = 200
+    omega: int = 20
+    rank: int = 10
+    tol: float = 1e-10
+    dt: float = 1e-3
+    corr_len: float = 0.1
+    sigma: float = 1.0
+    source: float = 1.0
+    seed_kappa: int = 4
+    seed_outputs: int = 6
+    n_outputs: int = 256
+    checkpoint_every: int = 20
+    name: str = field(default="config5_adjoint")
+
+    def __post_init__(self):
+        self.fv = FVDiffusion(self.N, 3)
+        self.n, self.nnz = self.fv.n, self.fv.nnz
+        self.rowptr, self.colind = self.fv.rowptr, self.fv.colind
+        h, J, N = self.fv.h, self.steps, self.N
+        ax = self.fv.node_axis()
+        ax_x = (np.arange(-J, N + 2, dtype=np.float64)) * h
+        g = FourierField(3, self.corr_len, self.seed_kappa).on_grid(ax_x, ax, ax)
+        self.theta = self.sigma * g                    # log kappa on the extended grid
+        r = np.random.Generator(np.random.PCG64(self.seed_outputs))
+        self.outputs = np.sort(r.choice(self.n, size=min(self.n_outputs, self.n), replace=False))
+
+    def window(self, j: int):
+        """Slice of theta giving log kappa_j on the (N+2)^3 node grid."""
+        J, N = self.steps, self.N
+        return (slice(None), slice(None), slice(J - j, J - j + N + 2))
+
+    def matrix_values(self, j: int, theta: np.ndarray | None = None) -> np.ndarray:
+        th = self.theta if theta is None else theta
+        return self.fv.values(np.exp(th[self.window(j)]), shift=1.0 / self.dt)
+
+    def rhs(self, j: int, x_prev: np.ndarray | None, s: np.ndarray | None = None) -> np.ndarray:
+        b = np.full(self.n, self.source) if s is None else np.array(s, dtype=np.float64)
+        if x_prev is not None:
+            b = b + x_prev / self.dt
+        return b
+
+    def describe(self) -> dict:
+        return {"workload": self.name, "N": self.N, "n": self.n, "nnz": self.nnz,
+                "steps": self.steps, "omega": self.omega, "rank": self.rank, "tol": self.tol,
+                "outputs": int(self.outputs.size), "checkpoint_every": self.checkpoint_every}
+
+
+def config5(**kw) -> Config5Adjoint:
+    return Config5Adjoint(**kw)
