@@ -33,6 +33,12 @@ class SequenceSpec:
     output: Callable[[int, torch.Tensor], torch.Tensor]                # j, x_j -> q_j
     rtol: float
     checkpoint_every: int = 20
+    # basis of the adjoint solves: "forward" = the forward sequence's W_j
+    # (replayed from checkpoints), "adjoint" = POD of the adjoint solutions
+    # lambda_{j+1}, lambda_{j+2}, ... themselves (the adjoint run is itself a
+    # sequence of SPD systems, recycled the same way; no replay needed),
+    # "none" = plain Jacobi PCG
+    adjoint_basis: str = "forward"
 
 
 class RecycledSequence(torch.autograd.Function):
@@ -79,25 +85,34 @@ class RecycledSequence(torch.autograd.Function):
         grads = [None] * len(params)
         carry = None                     # xbar_{j} contribution from b_{j+1}
         adj_stats = []
-        starts = list(range(1, m + 1, spec.checkpoint_every))
+        mode = spec.adjoint_basis
+        if mode not in ("forward", "adjoint", "none"):
+            raise ValueError(f"adjoint_basis must be forward, adjoint or none, not {mode!r}")
+        if mode != "forward":
+            adj.reset_snapshots()
+            adj.set_basis(None)
+        starts = list(range(1, m + 1, spec.checkpoint_every)) if mode == "forward" else [1]
         for k in reversed(starts):
-            end = min(k + spec.checkpoint_every, m + 1)
+            end = min(k + spec.checkpoint_every, m + 1) if mode == "forward" else m + 1
             # replay the POD builds of this segment: W_k .. W_{end-1}
             with torch.no_grad():
-                solver.reset_snapshots()
-                solver.set_basis(None)
-                if k > 1:
-                    solver.set_matrix(spec.assemble(k - 1, params).contiguous())
-                    for x in xs[max(0, k - 1 - omega):k - 1]:
-                        solver.push_snapshot(x)
-                    solver.build_pod()
-                Ws = {}
-                for j in range(k, end):
-                    Ws[j] = solver.get_basis().clone()
-                    if j + 1 < end:
-                        solver.set_matrix(spec.assemble(j, params).contiguous())
-                        solver.push_snapshot(xs[j - 1])
+                if mode != "forward":
+                    Ws = None
+                else:
+                    solver.reset_snapshots()
+                    solver.set_basis(None)
+                    if k > 1:
+                        solver.set_matrix(spec.assemble(k - 1, params).contiguous())
+                        for x in xs[max(0, k - 1 - omega):k - 1]:
+                            solver.push_snapshot(x)
                         solver.build_pod()
+                    Ws = {}
+                    for j in range(k, end):
+                        Ws[j] = solver.get_basis().clone()
+                        if j + 1 < end:
+                            solver.set_matrix(spec.assemble(j, params).contiguous())
+                            solver.push_snapshot(xs[j - 1])
+                            solver.build_pod()
             for j in range(end - 1, k - 1, -1):
                 xj = xs[j - 1]
                 with torch.enable_grad():
@@ -112,14 +127,19 @@ class RecycledSequence(torch.autograd.Function):
                 with torch.no_grad():
                     vals = spec.assemble(j, params).contiguous()
                     adj.set_matrix(vals)
-                    W = Ws[j]
-                    adj.set_basis(W if W.numel() else None)
+                    if mode == "forward":
+                        W = Ws[j]
+                        adj.set_basis(W if W.numel() else None)
                     lam = torch.zeros_like(xbar)
                     if torch.any(xbar != 0):
                         st = adj.solve(xbar, lam, spec.rtol)
                         if st.status not in (0, 2):
                             raise RuntimeError(f"adjoint solve {j} failed with status {st.status}")
                         adj_stats.append(st.as_dict())
+                        if mode == "adjoint":
+                            # metric A_j for the basis of system j-1
+                            adj.push_snapshot(lam)
+                            adj.build_pod()
                     vbar = adj.pattern_outer(lam, xj, -1.0, torch.empty_like(vals))
                 with torch.enable_grad():
                     p_req = [p for p in params if p.requires_grad]

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _setup(N, steps, ce, tol=1e-12, n_out=64):
+def _setup(N, steps, ce, tol=1e-12, n_out=64, basis="forward"):
     import paper_1512_05820_amd as P
     from paper_1512_05820_amd.adjoint import RecycledSequence, SequenceSpec
     cfg = config5(N=N, steps=steps, checkpoint_every=ce, n_outputs=n_out, omega=5, rank=4, tol=tol)
@@ -37,7 +37,7 @@ def _setup(N, steps, ce, tol=1e-12, n_out=64):
     def output(j, x):
         return x[outs]
 
-    spec = SequenceSpec(steps, assemble, rhs, output, tol, ce)
+    spec = SequenceSpec(steps, assemble, rhs, output, tol, ce, adjoint_basis=basis)
     mk = lambda: P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=50000)
     solver, adj = mk(), mk()
     v0 = torch.from_numpy(cfg.matrix_values(1)).cuda()
@@ -56,8 +56,9 @@ def _run(cfg, spec, solver, adj, RS, theta, s, w):
     return float(J), th.grad.cpu().numpy(), sv.grad.cpu().numpy()
 
 
-def test_gradient_matches_dense_adjoint_16cube():
-    cfg, spec, solver, adj, RS = _setup(16, 8, 3)
+@pytest.mark.parametrize("basis", ["forward", "adjoint", "none"])
+def test_gradient_matches_dense_adjoint_16cube(basis):
+    cfg, spec, solver, adj, RS = _setup(16, 8, 3, basis=basis)
     r = np.random.Generator(np.random.PCG64(21))
     w = r.standard_normal((cfg.steps, cfg.outputs.size))
     s = np.full(cfg.n, 1.0)
@@ -65,7 +66,7 @@ def test_gradient_matches_dense_adjoint_16cube():
     Jo, gth_o, gs_o, _ = sequence_gradient(cfg, cfg.theta, s, w, cfg.steps)
     e_t = np.linalg.norm(gth - gth_o) / np.linalg.norm(gth_o)
     e_s = np.linalg.norm(gs - gs_o) / np.linalg.norm(gs_o)
-    print(f"J {J:.12e} oracle {Jo:.12e}; dJ/dtheta rel err {e_t:.2e}; dJ/ds rel err {e_s:.2e}")
+    print(f"[{basis}] J {J:.12e} oracle {Jo:.12e}; dJ/dtheta rel err {e_t:.2e}; dJ/ds rel err {e_s:.2e}")
     assert abs(J - Jo) <= 1e-10 * abs(Jo)
     assert e_t <= 1e-8 and e_s <= 1e-8
 
