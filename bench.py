@@ -189,6 +189,115 @@ def bench_config3(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_config4(args):
+    """Batched: 64 independent 2-D diffusion sequences (sides 64..512), 20 systems
+    each, advanced together by the batched loop (podcg_batch_solve) after the
+    autotuner has picked work-item sizes and grid.  Compared with the same
+    batch solved by plain Jacobi PCG and with the 64 sequences solved one
+    context at a time (single-sequence path)."""
+    import torch
+    import paper_1512_05820_amd as P
+    from problems import config4
+
+    torch.cuda.set_device(0)
+    steps = args.systems if args.systems != 50 else 20
+    t0 = time.perf_counter()
+    cfg = config4(steps=steps)
+    mem = cfg.members
+    vals = [[torch.from_numpy(m.matrix_values(j)).cuda() for j in range(1, steps + 1)] for m in mem]
+    rhs = [[torch.from_numpy(m.rhs(j)).cuda() for j in range(1, steps + 1)] for m in mem]
+    pats = [(torch.from_numpy(m.rowptr).cuda(), torch.from_numpy(m.colind).cuda()) for m in mem]
+    log(f"config4: {len(mem)} sequences, n_total {cfg.n_total}, nnz_total {cfg.nnz_total}, "
+        f"inputs {time.perf_counter() - t0:.1f} s")
+    ctxs = [P.PodCG(m.n, omega=m.omega, rank_max=m.rank, maxit=20000) for m in mem]
+    for k, (rp, ci), v in zip(ctxs, pats, vals):
+        k.set_matrix(v[0], rp, ci)
+    batch = P.PodCGBatch(ctxs)
+    scratch = [torch.zeros(m.n, dtype=torch.float64, device="cuda") for m in mem]
+    tuned, tune_ms = batch.tune([r[0] for r in rhs], scratch, iters=32)
+    log(f"tuned {tuned}: {tune_ms:.2f} ms per 32 iterations")
+
+    def reset():
+        for k in ctxs:
+            k.reset_snapshots()
+            k.set_basis(None)
+
+    def batched(plain):
+        reset()
+        sts = []
+        for j in range(steps):
+            for k, v in zip(ctxs, vals):
+                k.set_matrix(v[j])
+            xs = [torch.zeros(m.n, dtype=torch.float64, device="cuda") for m in mem]
+            rc, st = batch.solve([r[j] for r in rhs], xs, [m.tol for m in mem], plain=plain)
+            if rc not in (0, 2):
+                raise RuntimeError(f"batched system {j + 1}: {rc}")
+            if not plain:
+                for k, x in zip(ctxs, xs):
+                    k.push_snapshot(x)
+                    k.build_pod()
+            sts.append([s.as_dict() for s in st])
+        return sts
+
+    def sequential():
+        reset()
+        sts = [[None] * len(mem) for _ in range(steps)]
+        for i, (k, m) in enumerate(zip(ctxs, mem)):
+            for j in range(steps):
+                k.set_matrix(vals[i][j])
+                x = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+                st = k.solve(rhs[i][j], x, m.tol)
+                if st.status not in (0, 2):
+                    raise RuntimeError(f"member {i} system {j + 1}: {st.status}")
+                k.push_snapshot(x)
+                k.build_pod()
+                sts[j][i] = st.as_dict()
+        return sts
+
+    def timed(fn, reps):
+        ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sts = fn()
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t1))
+        return min(ms), sts
+
+    for _ in range(args.warmup):
+        batched(False)
+    aug_ms, aug = timed(lambda: batched(False), max(1, args.steps))
+    log(f"batched augmented: {aug_ms:.1f} ms")
+    plain_ms, plain = timed(lambda: batched(True), 1)
+    log(f"batched plain: {plain_ms:.1f} ms")
+    seq_ms, seq = (None, None) if args.no_plain else timed(sequential, 1)
+    if seq_ms is not None:
+        log(f"one context at a time, augmented: {seq_ms:.1f} ms")
+
+    def iter_bytes(m, y):
+        return 12 * m.nnz + 4 * (m.n + 1) + 16 * m.n + 16 * y * m.n + 88 * m.n
+
+    loop_bytes = sum(iter_bytes(m, s["rank"]) * s["iters"] for sts in aug for m, s in zip(mem, sts))
+    solve_ms = sum(sts[0]["solve_ms"] for sts in aug)
+    worst = max(s["true_relres"] for sts in aug for s in sts)
+    out = {"metric": METRIC, "value": round(aug_ms, 1), "unit": "ms per batch of sequences",
+           "n_gpus": 1, "steps": max(1, args.steps), "warmup": args.warmup,
+           "ms_per_step": round(aug_ms, 1), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg.describe(),
+           "batched_plain_ms": round(plain_ms, 1),
+           "one_at_a_time_aug_ms": None if seq_ms is None else round(seq_ms, 1),
+           "speedup_vs_batched_plain": round(plain_ms / aug_ms, 3),
+           "speedup_vs_one_at_a_time": None if seq_ms is None else round(seq_ms / aug_ms, 3),
+           "iters_aug": sum(s["iters"] for sts in aug for s in sts),
+           "iters_plain": sum(s["iters"] for sts in plain for s in sts),
+           "iters_one_at_a_time": None if seq is None else sum(s["iters"] for sts in seq for s in sts),
+           "max_true_relres": worst,
+           "batched_solve_ms": round(solve_ms, 1),
+           "loop_GBps_lower_bound": round(loop_bytes / (solve_ms * 1e-3) / 1e9, 1),
+           "tuned_options": tuned, "tune_ms_per_32_iters": round(tune_ms, 3)}
+    print(json.dumps(out), flush=True)
+
+
 def bench_config5(args):
     """Differentiation at the stated size: 96^3 diffusion, 200 systems, outputs at
     256 dofs, gradients of J = sum_j w_j . q_j with respect to log kappa and the
@@ -268,9 +377,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--adjoint-basis", default="forward", choices=["forward", "adjoint", "none"],
                     help="config5: basis of the adjoint solves")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5"],
-                    help="config2 (default, the headline), config3 (mixed precision) or "
-                         "config5 (adjoint gradients)")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+                    help="config2 (default, the headline), config3 (mixed precision), "
+                         "config4 (batched sequences) or config5 (adjoint gradients)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -278,6 +387,9 @@ def main():
         sys.exit(2)
     if args.workload == "config3":
         bench_config3(args)
+        return
+    if args.workload == "config4":
+        bench_config4(args)
         return
     if args.workload == "config5":
         bench_config5(args)

@@ -195,6 +195,66 @@ int podcg_pattern_outer(podcg_ctx* ctx, const double* u, const double* v, double
 int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double* c,
                        int64_t n, double s, int32_t reps, double* ms);
 
+/* ------------------------------------------------------------- batches
+ * Many independent sequences advanced together.  A batch groups existing
+ * contexts (its members, each with its own matrix, snapshots and basis, all on
+ * one device, precision 0); every member still follows the sequence
+ * semantics above (set_matrix / solve / push_snapshot / build_pod on the
+ * member itself).  podcg_batch_solve replaces the members' podcg_solve calls
+ * for one system each: every member gets its basis setup and Stage 1
+ * (Alg. 2), then the loop of augmented PCG (Alg. 1) runs for all members at
+ * once -- per iteration one launch of each loop kernel over a work list of row
+ * ranges of the members still running, blocks of graph_iters iterations
+ * replayed from a HIP graph.  Per member the arithmetic is that of
+ * podcg_solve; only the grouping of partial sums differs (deterministic for
+ * fixed options).
+ *
+ * The batch uses its own HIP stream, ordered after each member's stream at
+ * the start of a call; podcg_batch_solve and podcg_batch_tune synchronise it
+ * before returning.  Members must outlive the batch and must not be used
+ * from another thread during a batch call. */
+typedef struct podcg_batch podcg_batch;
+
+typedef struct {
+    int32_t slices_per_item;  /* SELL slices (64 rows each) per SpMV work item (>= 1)           */
+    int32_t rows_per_item;    /* rows per work item of the vector kernels (>= 256, multiple of 64) */
+    int32_t grid;             /* workgroups per loop-kernel launch (1..65536)                  */
+    int32_t graph_iters;      /* iterations per captured HIP graph; 0 = direct launches          */
+    int32_t check_every;      /* iterations between polls when graph_iters = 0 (>= 1)           */
+} podcg_batch_options;
+
+/* Defaults: 8 slices, 2048 rows, grid 1024, graph_iters 16, check_every 16. */
+void podcg_batch_default_options(podcg_batch_options* opt);
+
+/* members: host array of `count` (1..1024) distinct contexts.  opt may be NULL.
+ * Errors: INVALID_ARG (count, duplicate member, mixed devices, a member with
+ * precision 1, options out of range), OOM, HIP. */
+int podcg_batch_create(podcg_batch** out, int32_t count, podcg_ctx* const* members,
+                       const podcg_batch_options* opt);
+int podcg_batch_destroy(podcg_batch* batch);
+int podcg_batch_set_options(podcg_batch* batch, const podcg_batch_options* opt);
+int podcg_batch_get_options(podcg_batch* batch, podcg_batch_options* opt);
+
+/* One system per member: b[m] (device, n_m float64) and x[m] (device, in:
+ * xbar, out: x) are host arrays of device pointers, rtol[m] host doubles;
+ * plain != 0 solves with plain Jacobi PCG (no basis).  stats (host, count
+ * entries, may be NULL) receives each member's statistics; its status field
+ * holds the member's code.  The return value is the most severe member
+ * code (an error, else NOT_CONVERGED, else RANK_REDUCED, else OK). */
+int podcg_batch_solve(podcg_batch* batch, const double* const* b, double* const* x,
+                      const double* rtol, int32_t plain, podcg_stats* stats);
+
+/* Autotuner: times `iters` loop iterations of all members (Stage 1 first,
+ * tolerance 0 so that no member stops early) for candidate work-item sizes and
+ * grids, by coordinate descent (SpMV item, vector item, grid), keeps the
+ * fastest options in the batch and returns them in *chosen (host, may be
+ * NULL) with the time of `iters` iterations in *best_ms.  x[m] is used as
+ * scratch and overwritten.  Errors as podcg_batch_solve. */
+int podcg_batch_tune(podcg_batch* batch, const double* const* b, double* const* x, int32_t iters,
+                     podcg_batch_options* chosen, double* best_ms);
+
+const char* podcg_batch_last_error(podcg_batch* batch);
+
 /* Text of a status code (static storage). */
 const char* podcg_strerror(int code);
 

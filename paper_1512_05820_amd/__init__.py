@@ -6,6 +6,6 @@ If the library has not been built, using it raises: there is no CPU fallback.
 """
 
 from ._lib import LIB_PATH, load
-from .solver import PodCG, PodCGError
+from .solver import PodCG, PodCGBatch, PodCGError
 
-__all__ = ["PodCG", "PodCGError", "LIB_PATH", "load"]
+__all__ = ["PodCG", "PodCGBatch", "PodCGError", "LIB_PATH", "load"]

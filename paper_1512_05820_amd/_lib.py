@@ -19,6 +19,9 @@ EXPORTED = [
     "podcg_get_basis", "podcg_get_reduced", "podcg_get_pod_spectrum", "podcg_solve",
     "podcg_solve_plain", "podcg_matvec", "podcg_pattern_outer", "podcg_stream_triad",
     "podcg_strerror", "podcg_last_error",
+    "podcg_batch_default_options", "podcg_batch_create", "podcg_batch_destroy",
+    "podcg_batch_set_options", "podcg_batch_get_options", "podcg_batch_solve", "podcg_batch_tune",
+    "podcg_batch_last_error",
 ]
 
 
@@ -27,6 +30,14 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("weights", C.c_int32), ("timing", C.c_int32),
                 ("rank_rtol", C.c_double), ("energy", C.c_double), ("precision", C.c_int32),
                 ("max_refine", C.c_int32), ("inner_rtol", C.c_double)]
+
+
+class BatchOptions(C.Structure):
+    _fields_ = [("slices_per_item", C.c_int32), ("rows_per_item", C.c_int32), ("grid", C.c_int32),
+                ("graph_iters", C.c_int32), ("check_every", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -73,6 +84,16 @@ def load(path: str = LIB_PATH):
         "podcg_stream_triad": ([P, P, P, P, I64, D, I32, C.POINTER(D)], C.c_int),
         "podcg_strerror": ([C.c_int], C.c_char_p),
         "podcg_last_error": ([P], C.c_char_p),
+        "podcg_batch_default_options": ([C.POINTER(BatchOptions)], None),
+        "podcg_batch_create": ([C.POINTER(P), I32, C.POINTER(P), C.POINTER(BatchOptions)], C.c_int),
+        "podcg_batch_destroy": ([P], C.c_int),
+        "podcg_batch_set_options": ([P, C.POINTER(BatchOptions)], C.c_int),
+        "podcg_batch_get_options": ([P, C.POINTER(BatchOptions)], C.c_int),
+        "podcg_batch_solve": ([P, C.POINTER(P), C.POINTER(P), C.POINTER(D), I32, C.POINTER(Stats)],
+                              C.c_int),
+        "podcg_batch_tune": ([P, C.POINTER(P), C.POINTER(P), I32, C.POINTER(BatchOptions),
+                             C.POINTER(D)], C.c_int),
+        "podcg_batch_last_error": ([P], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpodcg.so")
-SOURCES = ["podcg_api.hip", "k_sell.hip", "k_vec.hip", "k_small.hip"]
+SOURCES = ["podcg_api.hip", "podcg_batch.hip", "k_sell.hip", "k_vec.hip", "k_small.hip", "k_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,348 @@
+// Batched loop kernels: one launch per loop kernel advances augmented PCG
+// (Alg. 1) of many independent sequences at once.
+//
+// The work of an iteration is cut into items, contiguous ranges of one
+// member (SELL slices for the SpMV, rows for the vector kernels).  A fixed
+// grid walks the compacted item list in rounds; within a round, workgroup b
+// takes item xcd_block(b, m), so each XCD covers a contiguous range of items
+// and the neighbouring rows of a member share one L2.  Every item reduces its
+// partial sums and stores them in its member's slot; the last item of a
+// member to arrive (arrival counter per member) sums the member's slots in a
+// fixed order and forms that member's scalars, exactly as the last workgroup
+// of the single-sequence kernels does.  Results are deterministic for a given
+// item partition.  A member with a single item reduces inside its workgroup
+// and never touches global memory for the sums.
+//
+// Members that have finished (or failed) drop out of the lists at the start of
+// every block of iterations (k_batch_compact); within a block they exit on
+// their state flag.
+#include "podcg_device.h"
+
+namespace podcg {
+
+int batch_tier(int y) {
+    static const int tiers[] = {0, 1, 2, 4, 6, 8, 12, 16, 24, 32};
+    for (int t : tiers)
+        if (y <= t) return t;
+    return -1;
+}
+
+#define PODCG_BATCH_TIERS(X) X(0) X(1) X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32)
+
+namespace {
+
+// Column index of a batched basis load: clamped into [0, y) so every load of
+// the unrolled tier is unconditional and in bounds (y >= 1 is checked by the
+// caller).
+__device__ __forceinline__ int bcol(int k, int y) { return k < y ? k : y - 1; }
+
+// Sum of NV values over the items of one member.  Returns true in the last
+// item to arrive, with the member totals in lds[0..NV).
+template <int NV>
+__device__ __forceinline__ bool member_sum_last(double (&v)[NV], double* part, unsigned* counter,
+                                                int nitems, int local, double* lds) {
+    block_sum<NV>(v, lds);
+    if (nitems == 1) return true;
+    const int t = threadIdx.x;
+    if (t < NV) store_shared(part + (size_t)t * nitems + local, lds[t]);
+    if (!arrive_last(counter, nitems)) return false;
+    double a[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = 0.0;
+    for (int i = t; i < nitems; i += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a[k] += load_shared(part + (size_t)k * nitems + i);
+    }
+    block_sum<NV>(a, lds);
+    return true;
+}
+
+// Marks a member that leaves the running state inside a loop kernel.
+__device__ __forceinline__ void leave_running(int* active) {
+    __hip_atomic_fetch_add(active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+// q = A p, gamma = (A p, p), alpha = (r, z) / gamma per member.
+__global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __restrict__ mem,
+                                                       const BatchItem* __restrict__ items,
+                                                       const int* __restrict__ counts,
+                                                       int* __restrict__ active) {
+    __shared__ double lds[kWavesPerBlock + 2];
+    const int nitems = counts[0];
+    const int G = gridDim.x;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        DevState* st = M.B.st;
+        const int done = st->done;
+        __syncthreads();   // every thread has read the flag before anyone may change it
+        if (done != kRunning) {
+            if ((done == kConvergedPending || done == kCapPending) && it.local == 0 && threadIdx.x == 0)
+                st->done = kFinished;
+            continue;
+        }
+        const double* __restrict__ p = M.p;
+        double* __restrict__ q = M.q;
+        double g[1] = {0.0};
+        for (int s = it.begin + wid; s < it.end; s += kWavesPerBlock) {
+            const double acc = sell_row<double>(M.B.sptr, M.B.cols, M.B.vals, s, lane, p);
+            const int row = s * kSlice + lane;
+            if (row < M.B.n) {
+                q[row] = acc;
+                g[0] += acc * p[row];
+            }
+        }
+        if (member_sum_last<1>(g, M.B.part, M.B.counter, M.spmv_items, it.local, lds) &&
+            threadIdx.x == 0) {
+            const double gamma = lds[0];
+            st->gamma = gamma;
+            if (!(gamma > 0.0) || !is_finite(gamma)) {
+                st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
+                st->done = kFailed;
+                leave_running(active);
+            } else {
+                st->alpha = st->rho / gamma;
+            }
+        }
+        __syncthreads();   // lds is reused by the next item
+    }
+}
+
+// r -= alpha q, z = M^{-1} r, sums (r, z), (r, r), (A W)^T z; the last item of
+// a member forms beta, mu = G^{-1} (A W)^T z and tests convergence.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __restrict__ mem,
+                                                         const BatchItem* __restrict__ items,
+                                                         const int* __restrict__ counts,
+                                                         int* __restrict__ active) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    const int nitems = counts[1];
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        DevState* st = M.B.st;
+        if (st->done != kRunning) continue;   // only this kernel's last item changes it
+        const double alpha = st->alpha;
+        const int y = M.y;
+        double* __restrict__ r = M.r;
+        double* __restrict__ z = M.z;
+        const double* __restrict__ q = M.q;
+        const double* __restrict__ dinv = M.B.dinv;
+        const double* __restrict__ AW = M.AW;
+        const size_t ld = M.B.ld;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
+            const double ri = r[i] - alpha * q[i];
+            const double zi = dinv[i] * ri;
+            r[i] = ri;
+            z[i] = zi;
+            v[0] += ri * zi;
+            v[1] += ri * ri;
+            if (YB > 0 && y > 0) {
+#pragma unroll
+                for (int k = 0; k < YB; ++k) {
+                    const double a = __builtin_nontemporal_load(AW + (size_t)bcol(k, y) * ld + i);
+                    if (k < y) v[2 + k] += a * zi;
+                }
+            }
+        }
+        if (member_sum_last<NV>(v, M.B.part, M.B.counter, M.vec_items, it.local, lds)) {
+            if (threadIdx.x == 0) {
+                const double rz = lds[0], rr = lds[1];
+                const int iter = st->iter + 1;
+                st->iter = iter;
+                st->rr = rr;
+                if (!is_finite(rr) || !is_finite(rz)) {
+                    st->status = kStNonfinite;
+                    st->done = kFailed;
+                    leave_running(active);
+                } else {
+                    st->beta = rz / st->rho;
+                    st->rho = rz;
+                    if (rr <= st->tol2) {
+                        st->status = kStOk;
+                        st->done = kConvergedPending;
+                        leave_running(active);
+                    } else if (iter >= st->maxit) {
+                        st->status = kStNotConverged;
+                        st->done = kCapPending;
+                        leave_running(active);
+                    }
+                }
+            }
+            if ((int)threadIdx.x < y) {
+                double s = 0.0;
+                for (int j = 0; j < y; ++j) s += M.B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+                st->mu[threadIdx.x] = s;
+            }
+        }
+        __syncthreads();   // lds is reused by the next item
+    }
+}
+
+// x += alpha p; while iterating p = z + beta p - W mu.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_dir(const BatchMember* __restrict__ mem,
+                                                      const BatchItem* __restrict__ items,
+                                                      const int* __restrict__ counts) {
+    const int nitems = counts[1];
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        const DevState* st = M.B.st;
+        const int done = st->done;
+        if (done != kRunning && done != kConvergedPending && done != kCapPending) continue;
+        const bool new_dir = done == kRunning;
+        const double alpha = st->alpha, beta = st->beta;
+        const int y = M.y;
+        double mu[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int k = 0; k < YB; ++k) mu[k] = k < y ? st->mu[k] : 0.0;
+        double* __restrict__ p = M.p;
+        double* __restrict__ x = M.x;
+        const double* __restrict__ z = M.z;
+        const double* __restrict__ W = M.W;
+        const size_t ld = M.B.ld;
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
+            const double pi = p[i];
+            x[i] += alpha * pi;
+            if (!new_dir) continue;
+            double s = z[i] + beta * pi;
+            if (YB > 0 && y > 0) {
+#pragma unroll
+                for (int k = 0; k < YB; ++k)
+                    s -= __builtin_nontemporal_load(W + (size_t)bcol(k, y) * ld + i) * mu[k];
+            }
+            p[i] = s;
+        }
+    }
+}
+
+// Rebuilds the SpMV and vector lists from the members still running (or with
+// their last update x += alpha p pending) and counts the running members.
+// One workgroup.
+__global__ __launch_bounds__(kBlock) void k_batch_compact(const BatchMember* __restrict__ mem,
+                                                          int count,
+                                                          const BatchItem* __restrict__ spmv_full,
+                                                          const BatchItem* __restrict__ vec_full,
+                                                          BatchItem* __restrict__ spmv,
+                                                          BatchItem* __restrict__ vec,
+                                                          int* __restrict__ counts,
+                                                          int* __restrict__ active) {
+    __shared__ int keep[kBatchMaxMembers];
+    __shared__ int run[kBatchMaxMembers];
+    __shared__ int off_s[kBatchMaxMembers], off_v[kBatchMaxMembers];
+    const int t = threadIdx.x;
+    for (int m = t; m < count; m += kBlock) {
+        const int d = mem[m].B.st->done;
+        keep[m] = d == kRunning || d == kConvergedPending || d == kCapPending;
+        run[m] = d == kRunning;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int ns = 0, nv = 0, na = 0;
+        for (int m = 0; m < count; ++m) {
+            off_s[m] = ns;
+            off_v[m] = nv;
+            if (keep[m]) {
+                ns += mem[m].spmv_items;
+                nv += mem[m].vec_items;
+            }
+            na += run[m];
+        }
+        counts[0] = ns;
+        counts[1] = nv;
+        *active = na;
+    }
+    __syncthreads();
+    for (int m = 0; m < count; ++m) {
+        if (!keep[m]) continue;
+        const BatchMember& M = mem[m];
+        for (int i = t; i < M.spmv_items; i += kBlock) spmv[off_s[m] + i] = spmv_full[M.spmv_first + i];
+        for (int i = t; i < M.vec_items; i += kBlock) vec[off_v[m] + i] = vec_full[M.vec_first + i];
+    }
+}
+
+// Copies the polled block of every member's state into one array.
+__global__ void k_batch_gather(const BatchMember* __restrict__ mem, int count, PollBlock* out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    const DevState* st = mem[m].B.st;
+    PollBlock P;
+    P.iter = st->iter;
+    P.done = st->done;
+    P.status = st->status;
+    P.y = st->y;
+    P.maxit = st->maxit;
+    P.pad0 = P.pad1 = P.pad2 = 0;
+    P.rr = st->rr;
+    P.rr0 = st->rr0;
+    P.bnorm2 = st->bnorm2;
+    P.true_rr = st->true_rr;
+    out[m] = P;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_batch_compact(const BatchMember* mem, int count, const BatchItem* spmv_full,
+                                const BatchItem* vec_full, BatchItem* spmv, BatchItem* vec,
+                                int* counts, int* active, hipStream_t s) {
+    if (count < 1 || count > kBatchMaxMembers) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(kBlock), 0, s, mem, count, spmv_full, vec_full,
+                       spmv, vec, counts, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_spmv(const BatchMember* mem, const BatchItem* items, const int* counts,
+                             int* active, int grid, hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_spmv, dim3(grid), dim3(kBlock), 0, s, mem, items, counts, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_update(int yb, const BatchMember* mem, const BatchItem* items,
+                               const int* counts, int* active, int grid, hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_update<T>), dim3(grid), dim3(kBlock), 0, s, mem, items, counts, active); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_dir(int yb, const BatchMember* mem, const BatchItem* items, const int* counts,
+                            int grid, hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_dir<T>), dim3(grid), dim3(kBlock), 0, s, mem, items, counts); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const BatchMember* mem, int count, PollBlock* out, hipStream_t s) {
+    if (count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_gather, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, mem,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace podcg

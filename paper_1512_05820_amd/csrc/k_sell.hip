@@ -162,41 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_pattern_outer(int n, int nslices,
 
 // ---------------------------------------------------------------- products
 
-// Row (64 s + lane) of A x for the slice s handled by this wave.  Slices of
-// width <= 8 (stencil matrices) take a branch-free path: all column indices
-// and values are loaded first (padding slots re-read the last valid slot and
-// are skipped with a select), then all gathers, then the sums in order j =
-// 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
-// slice bounds are scalar loads.
-template <typename T>
-__device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
-                                           const int* __restrict__ cols,
-                                           const T* __restrict__ vals, int s, int lane,
-                                           const T* __restrict__ x) {
-    s = __builtin_amdgcn_readfirstlane(s);
-    const int64_t base = sptr[s];
-    const int w = (int)((sptr[s + 1] - base) / kSlice);
-    const int* c = cols + base + lane;
-    const T* v = vals + base + lane;
-    double acc = 0.0;   // FP32 operands multiply exactly in FP64; the row sum is FP64
-    for (int j0 = 0; j0 < w; j0 += 8) {
-        int ci[8];
-        T vi[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = min(j0 + u, w - 1);
-            ci[u] = __builtin_nontemporal_load(c + j * kSlice);
-            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
-        }
-        T xi[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) xi[u] = x[ci[u]];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = (j0 + u < w) ? fma((double)vi[u], (double)xi[u], acc) : acc;
-    }
-    return acc;
-}
-
 // Loop kernel 1 of augmented PCG (Alg. 1): q = A p and gamma = (A p, p);
 // the last workgroup forms alpha = (r, z) / gamma.  T is the storage type of
 // the matrix and vectors (FP64, or FP32 for the inner solve of mixed

@@ -17,94 +17,12 @@
 
 #include "podcg.h"
 #include "podcg_device.h"
+#include "podcg_host.h"
 
 using namespace podcg;
+using namespace podcg_host;
 
-namespace {
-
-struct Fail {
-    int code;
-};
-
-}  // namespace
-
-struct podcg_ctx {
-    int64_t n = 0;
-    int nslices = 0;
-    size_t ld = 0;
-    podcg_options opt{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-
-    // matrix
-    bool has_pattern = false, has_values = false;
-    int64_t nnz = 0, nsell = 0, sell_cap = 0;
-    int64_t* d_sptr = nullptr;
-    int* d_cols = nullptr;
-    int* d_map = nullptr;
-    double* d_vals = nullptr;
-    double* d_dinv = nullptr;
-
-    // CG vectors (length ld)
-    double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
-    // mixed precision: FP32 copies of the matrix, Jacobi inverse, basis and
-    // the inner-solve vectors (the solution itself stays FP64)
-    float *d_vals32 = nullptr, *d_dinv32 = nullptr, *d_W32 = nullptr, *d_AW32 = nullptr;
-    float *d_r32 = nullptr, *d_z32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr;
-
-    // basis
-    double *d_W = nullptr, *d_AW = nullptr;
-    int y = 0;                 // columns of W
-    int y_kept = 0;            // columns accepted by the last factorisation
-    bool setup_valid = false;
-    bool rank_reduced = false;
-    double cond_G = 1.0;
-    double *d_G = nullptr, *d_R = nullptr, *d_Ginv = nullptr, *d_lamG = nullptr;
-
-    // snapshots
-    double *d_S = nullptr, *d_Gs = nullptr, *d_T = nullptr, *d_lamS = nullptr;
-    int head = 0, count = 0, pod_count = 0;
-    int* d_yout = nullptr;
-
-    // scalar state and scratch
-    DevState* d_st = nullptr;
-    double* d_part = nullptr;
-    unsigned* d_counter = nullptr;
-    int* d_flag = nullptr;
-    PollBlock* h_poll = nullptr;     // pinned
-    int* h_int = nullptr;            // pinned scratch ints
-    double* h_dbl = nullptr;         // pinned scratch doubles
-
-    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
-    std::vector<hipEvent_t> tev;     // per-iteration kernel timing events
-    int prev_iters[2] = {0, 0};      // iterations of the last augmented / plain solve
-
-    std::string last_error;
-};
-
-namespace {
-
-#define HIPCHECK(expr)                                                                              \
-    do {                                                                                            \
-        hipError_t e_ = (expr);                                                                     \
-        if (e_ != hipSuccess) {                                                                     \
-            ctx->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
-            throw Fail{e_ == hipErrorOutOfMemory ? PODCG_ERR_OOM : PODCG_ERR_HIP};                  \
-        }                                                                                           \
-    } while (0)
-
-void fail(podcg_ctx* ctx, int code, const std::string& msg) {
-    ctx->last_error = msg;
-    throw Fail{code};
-}
-
-template <class T>
-void dalloc(podcg_ctx* ctx, T** p, size_t count) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    if (count == 0) count = 1;
-    HIPCHECK(hipMalloc((void**)p, count * sizeof(T)));
-}
+namespace podcg_host {
 
 DevBufs bufs(podcg_ctx* ctx) {
     DevBufs B;
@@ -365,23 +283,9 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
     return code;
 }
 
-template <class F>
-int guarded(podcg_ctx* ctx, F&& f) {
-    if (!ctx) return PODCG_ERR_INVALID_ARG;
-    try {
-        if (hipSetDevice(ctx->device) != hipSuccess) return PODCG_ERR_HIP;
-        return f();
-    } catch (const Fail& e) {
-        if (ctx->last_error.empty()) ctx->last_error = podcg_strerror(e.code);
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        ctx->last_error = "host allocation failed";
-        return PODCG_ERR_OOM;
-    } catch (...) {
-        ctx->last_error = "unexpected exception";
-        return PODCG_ERR_HIP;
-    }
-}
+}  // namespace podcg_host
+
+namespace {
 
 void release(podcg_ctx* ctx) {
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,

@@ -1,0 +1,501 @@
+// Batched solves of many independent sequences (the podcg_batch_* calls of
+// include/podcg.h).
+//
+// A batch groups existing contexts (its members).  Per solve, every member
+// gets its own basis setup and Stage 1 (Alg. 2) with the single-sequence
+// kernels; then the loop of augmented PCG (Alg. 1) runs for all members
+// together: per iteration one launch of each batched loop kernel over a work
+// list of row ranges of all members still running.  Blocks of iterations are
+// captured once into a HIP graph (list compaction + graph_iters iterations)
+// and replayed; the host polls one device counter (members still running)
+// after each block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "podcg.h"
+#include "podcg_device.h"
+#include "podcg_host.h"
+
+using namespace podcg;
+using namespace podcg_host;
+
+struct podcg_batch {
+    std::vector<podcg_ctx*> members;
+    hipStream_t stream = nullptr;          // owned; default priority
+    hipStream_t cap_stream = nullptr;      // owned; only ever used for graph capture
+    int device = 0;
+    podcg_batch_options opt{};
+
+    BatchMember* d_mem = nullptr;
+    BatchMember* h_mem = nullptr;           // pinned staging of the member table
+    BatchItem *d_spmv_full = nullptr, *d_vec_full = nullptr;
+    BatchItem *d_spmv = nullptr, *d_vec = nullptr;
+    size_t cap_spmv = 0, cap_vec = 0;
+    std::vector<int> spmv_items, vec_items, spmv_first, vec_first;
+    int* d_counts = nullptr;
+    int* d_active = nullptr;
+    PollBlock* d_gather = nullptr;
+    PollBlock* h_gather = nullptr;          // pinned
+    int* h_active = nullptr;                // pinned
+
+    struct Graph {
+        int yb, grid, iters;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    int prev_iters[2] = {0, 0};             // longest member of the last augmented / plain solve
+    std::vector<hipEvent_t> member_ev;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr;
+    std::string last_error;
+};
+
+namespace {
+
+constexpr int kMinRowsPerItem = kBlock;
+
+void check_batch_opts(podcg_batch* ctx, const podcg_batch_options& o) {
+    if (o.slices_per_item < 1 || o.rows_per_item < kMinRowsPerItem || o.rows_per_item % kWave != 0 ||
+        o.grid < 1 || o.grid > 65536 || o.graph_iters < 0 || o.graph_iters > 1024 || o.check_every < 1)
+        fail(ctx, PODCG_ERR_INVALID_ARG, "batch options out of range");
+}
+
+// Work lists for the current item sizes (uploaded; the capacity was sized
+// for the finest allowed partition at creation).
+void build_lists(podcg_batch* ctx) {
+    std::vector<BatchItem> s, v;
+    const int count = (int)ctx->members.size();
+    ctx->spmv_items.assign(count, 0);
+    ctx->vec_items.assign(count, 0);
+    ctx->spmv_first.assign(count, 0);
+    ctx->vec_first.assign(count, 0);
+    for (int m = 0; m < count; ++m) {
+        const podcg_ctx* c = ctx->members[m];
+        ctx->spmv_first[m] = (int)s.size();
+        int local = 0;
+        for (int b = 0; b < c->nslices; b += ctx->opt.slices_per_item)
+            s.push_back({m, b, std::min(c->nslices, b + ctx->opt.slices_per_item), local++});
+        ctx->spmv_items[m] = local;
+        ctx->vec_first[m] = (int)v.size();
+        local = 0;
+        const int n = (int)c->n;
+        for (int b = 0; b < n; b += ctx->opt.rows_per_item)
+            v.push_back({m, b, std::min(n, b + ctx->opt.rows_per_item), local++});
+        ctx->vec_items[m] = local;
+        // partial-sum slots of the member: one per item and reduced value
+        if ((size_t)ctx->vec_items[m] * kNVMax > (size_t)kPartials || ctx->spmv_items[m] > kPartials)
+            fail(ctx, PODCG_ERR_INVALID_ARG, "work items too small for this member size");
+    }
+    if (s.size() > ctx->cap_spmv || v.size() > ctx->cap_vec)
+        fail(ctx, PODCG_ERR_INVALID_ARG, "work list exceeds its capacity");
+    HIPCHECK(hipMemcpy(ctx->d_spmv_full, s.data(), s.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(ctx->d_vec_full, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+}
+
+// Member table for one solve (y = kept rank, or 0 for plain PCG).
+void upload_members(podcg_batch* ctx, double* const* x, bool plain) {
+    const int count = (int)ctx->members.size();
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        BatchMember M{};
+        M.B = bufs(c);
+        M.r = c->d_r;
+        M.z = c->d_z;
+        M.p = c->d_p;
+        M.q = c->d_q;
+        M.x = x[m];
+        M.W = c->d_W;
+        M.AW = c->d_AW;
+        M.y = plain ? 0 : c->y_kept;
+        M.spmv_items = ctx->spmv_items[m];
+        M.vec_items = ctx->vec_items[m];
+        M.spmv_first = ctx->spmv_first[m];
+        M.vec_first = ctx->vec_first[m];
+        ctx->h_mem[m] = M;
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->d_mem, ctx->h_mem, count * sizeof(BatchMember), hipMemcpyHostToDevice,
+                            ctx->stream));
+}
+
+// One block of iterations: list compaction, then `iters` x (SpMV, update,
+// direction).
+void enqueue_block(podcg_batch* ctx, hipStream_t s, int yb, int iters) {
+    const int count = (int)ctx->members.size();
+    const int grid = ctx->opt.grid;
+    HIPCHECK(launch_batch_compact(ctx->d_mem, count, ctx->d_spmv_full, ctx->d_vec_full, ctx->d_spmv,
+                                  ctx->d_vec, ctx->d_counts, ctx->d_active, s));
+    for (int k = 0; k < iters; ++k) {
+        HIPCHECK(launch_batch_spmv(ctx->d_mem, ctx->d_spmv, ctx->d_counts, ctx->d_active, grid, s));
+        HIPCHECK(launch_batch_update(yb, ctx->d_mem, ctx->d_vec, ctx->d_counts, ctx->d_active, grid, s));
+        HIPCHECK(launch_batch_dir(yb, ctx->d_mem, ctx->d_vec, ctx->d_counts, grid, s));
+    }
+}
+
+hipGraphExec_t block_graph(podcg_batch* ctx, int yb) {
+    const int grid = ctx->opt.grid, iters = ctx->opt.graph_iters;
+    for (const auto& g : ctx->graphs)
+        if (g.yb == yb && g.grid == grid && g.iters == iters) return g.exec;
+    hipGraph_t graph = nullptr;
+    // captured on a stream that never carries other work; replayed on ctx->stream
+    HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+        enqueue_block(ctx, ctx->cap_stream, yb, iters);
+    } catch (...) {
+        (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHECK(hipStreamEndCapture(ctx->cap_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(e);
+    ctx->graphs.push_back({yb, grid, iters, exec});
+    return exec;
+}
+
+// Run loop blocks until no member is running or `cap` iterations were
+// launched.  Returns the number of polls.
+int run_batch_loop(podcg_batch* ctx, int yb, int cap, int first) {
+    const int per = ctx->opt.graph_iters > 0 ? ctx->opt.graph_iters : ctx->opt.check_every;
+    hipGraphExec_t exec = ctx->opt.graph_iters > 0 ? block_graph(ctx, yb) : nullptr;
+    int launched = 0, polls = 0;
+    while (launched < cap) {
+        if (exec)
+            HIPCHECK(hipGraphLaunch(exec, ctx->stream));
+        else
+            enqueue_block(ctx, ctx->stream, yb, per);
+        launched += per;
+        if (launched < first) continue;
+        HIPCHECK(hipMemcpyAsync(ctx->h_active, ctx->d_active, sizeof(int), hipMemcpyDeviceToHost,
+                                ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        ++polls;
+        if (*ctx->h_active == 0) break;
+    }
+    return polls;
+}
+
+// Setup (where the basis changed) and Stage 1 of every member, all on the
+// batch stream after the members' own streams.
+void stage1_all(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
+                const int* maxit, bool plain) {
+    const int count = (int)ctx->members.size();
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        if (!plain && !c->setup_valid) setup_basis(c);
+        HIPCHECK(hipEventRecord(ctx->member_ev[m], c->stream));
+        HIPCHECK(hipStreamWaitEvent(ctx->stream, ctx->member_ev[m], 0));
+    }
+    HIPCHECK(hipEventRecord(ctx->ev_b, ctx->stream));
+    hipStream_t s = ctx->stream;
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        const int y = plain ? 0 : c->y_kept;
+        const int yb = basis_tier(y);
+        DevBufs B = bufs(c);
+        HIPCHECK(launch_state_init(c->d_st, maxit[m], rtol[m] * rtol[m], y, s));
+        HIPCHECK(launch_resid(B, yb, y, b[m], x[m], c->d_r, c->d_W, true, true, s));
+        HIPCHECK(launch_stage1_apply(B, yb, y, x[m], c->d_r, c->d_z, c->d_W, c->d_AW, s));
+        HIPCHECK(launch_dir(B, yb, y, c->d_p, x[m], c->d_z, c->d_W, true, s));
+    }
+}
+
+void check_solve_args(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol) {
+    if (!b || !x) fail(ctx, PODCG_ERR_INVALID_ARG, "null b or x array");
+    for (size_t m = 0; m < ctx->members.size(); ++m) {
+        if (!b[m] || !x[m]) fail(ctx, PODCG_ERR_INVALID_ARG, "null member vector");
+        if (rtol && !(rtol[m] >= 0.0)) fail(ctx, PODCG_ERR_INVALID_ARG, "bad member tolerance");
+        if (!ctx->members[m]->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "member without a matrix");
+    }
+}
+
+int batch_yb(podcg_batch* ctx, bool plain) {
+    int ymax = 0;
+    if (!plain)
+        for (podcg_ctx* c : ctx->members) ymax = std::max(ymax, c->y_kept);
+    return batch_tier(ymax);
+}
+
+int batch_solve_impl(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
+                     bool plain, podcg_stats* stats) {
+    check_solve_args(ctx, b, x, rtol);
+    if (!rtol) fail(ctx, PODCG_ERR_INVALID_ARG, "null tolerance array");
+    const int count = (int)ctx->members.size();
+    hipStream_t s = ctx->stream;
+    HIPCHECK(hipEventRecord(ctx->ev_a, s));
+    std::vector<int> maxit(count);
+    int cap = 0;
+    for (int m = 0; m < count; ++m) {
+        maxit[m] = ctx->members[m]->opt.maxit;
+        cap = std::max(cap, maxit[m]);
+    }
+    std::vector<char> did_setup(count);
+    for (int m = 0; m < count; ++m)
+        did_setup[m] = !plain && !ctx->members[m]->setup_valid && ctx->members[m]->y > 0;
+    stage1_all(ctx, b, x, rtol, maxit.data(), plain);
+    const int yb = batch_yb(ctx, plain);
+    upload_members(ctx, x, plain);
+    const int slot = plain ? 1 : 0;
+    const int first = (int)(0.85 * ctx->prev_iters[slot]);
+    const int polls = run_batch_loop(ctx, yb, cap + 1, first);
+    for (int m = 0; m < count; ++m) {   // true residuals
+        podcg_ctx* c = ctx->members[m];
+        HIPCHECK(launch_resid(bufs(c), 0, 0, b[m], x[m], nullptr, nullptr, false, false, s));
+    }
+    HIPCHECK(launch_batch_gather(ctx->d_mem, count, ctx->d_gather, s));
+    HIPCHECK(hipMemcpyAsync(ctx->h_gather, ctx->d_gather, count * sizeof(PollBlock),
+                            hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipEventRecord(ctx->ev_c, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    float setup_ms = 0.f, solve_ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&setup_ms, ctx->ev_a, ctx->ev_b));
+    HIPCHECK(hipEventElapsedTime(&solve_ms, ctx->ev_b, ctx->ev_c));
+    int worst = PODCG_OK, longest = 0;
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        const PollBlock& P = ctx->h_gather[m];
+        const int y = plain ? 0 : c->y_kept;
+        podcg_stats S{};
+        S.iters = P.iter;
+        S.rank = y;
+        const double bn = std::sqrt(P.bnorm2);
+        S.bnorm = bn;
+        S.stage1_relres = bn > 0 ? std::sqrt(P.rr0) / bn : std::sqrt(P.rr0);
+        S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
+        S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
+        S.cond_G = y > 0 ? c->cond_G : 1.0;
+        S.matvecs = P.iter + 2 + (did_setup[m] ? c->y : 0);
+        S.polls = polls;
+        S.setup_ms = setup_ms;
+        S.solve_ms = solve_ms;
+        int code = P.status;
+        if (P.done == kFailed) code = fail_code(c, P);
+        else if (code == PODCG_OK && !plain && c->rank_reduced) code = PODCG_RANK_REDUCED;
+        S.status = code;
+        c->prev_iters[slot] = P.iter;
+        longest = std::max(longest, P.iter);
+        if (stats) stats[m] = S;
+        // report the most severe outcome: errors < 0, then NOT_CONVERGED, then RANK_REDUCED
+        if (code < 0) {
+            if (worst >= 0) worst = code;
+        } else if (worst >= 0 && code == PODCG_NOT_CONVERGED) {
+            worst = code;
+        } else if (worst == PODCG_OK && code == PODCG_RANK_REDUCED) {
+            worst = code;
+        }
+    }
+    ctx->prev_iters[slot] = longest;
+    if (worst < 0) ctx->last_error = "a member failed; see its status";
+    return worst;
+}
+
+void release_batch(podcg_batch* ctx) {
+    for (auto& g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+    void* dev[] = {ctx->d_mem, ctx->d_spmv_full, ctx->d_vec_full, ctx->d_spmv, ctx->d_vec,
+                   ctx->d_counts, ctx->d_active, ctx->d_gather};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (ctx->h_mem) (void)hipHostFree(ctx->h_mem);
+    if (ctx->h_gather) (void)hipHostFree(ctx->h_gather);
+    if (ctx->h_active) (void)hipHostFree(ctx->h_active);
+    for (hipEvent_t e : ctx->member_ev)
+        if (e) (void)hipEventDestroy(e);
+    hipEvent_t evs[] = {ctx->ev_a, ctx->ev_b, ctx->ev_c};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+void podcg_batch_default_options(podcg_batch_options* o) {
+    if (!o) return;
+    o->slices_per_item = 8;
+    o->rows_per_item = 2048;
+    o->grid = 1024;
+    o->graph_iters = 16;
+    o->check_every = 16;
+}
+
+const char* podcg_batch_last_error(podcg_batch* ctx) {
+    return ctx ? ctx->last_error.c_str() : "null batch";
+}
+
+int podcg_batch_create(podcg_batch** out, int32_t count, podcg_ctx* const* members,
+                       const podcg_batch_options* opt) {
+    if (!out) return PODCG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count < 1 || count > kBatchMaxMembers || !members) return PODCG_ERR_INVALID_ARG;
+    int device = -1;
+    for (int m = 0; m < count; ++m) {
+        if (!members[m] || members[m]->opt.precision != 0) return PODCG_ERR_INVALID_ARG;
+        if (device >= 0 && members[m]->device != device) return PODCG_ERR_INVALID_ARG;
+        device = members[m]->device;
+        for (int k = 0; k < m; ++k)
+            if (members[k] == members[m]) return PODCG_ERR_INVALID_ARG;
+    }
+    podcg_batch* ctx = new (std::nothrow) podcg_batch();
+    if (!ctx) return PODCG_ERR_OOM;
+    ctx->device = device;
+    ctx->members.assign(members, members + count);
+    podcg_batch_default_options(&ctx->opt);
+    if (opt) ctx->opt = *opt;
+    int rc = guarded(ctx, [&]() {
+        check_batch_opts(ctx, ctx->opt);
+        HIPCHECK(hipStreamCreate(&ctx->stream));
+        HIPCHECK(hipStreamCreate(&ctx->cap_stream));
+        size_t ns = 0, nv = 0;
+        for (podcg_ctx* c : ctx->members) {
+            ns += (size_t)c->nslices;
+            nv += (size_t)((c->n + kMinRowsPerItem - 1) / kMinRowsPerItem);
+        }
+        ctx->cap_spmv = ns;
+        ctx->cap_vec = nv;
+        dalloc(ctx, &ctx->d_mem, count);
+        dalloc(ctx, &ctx->d_spmv_full, ns);
+        dalloc(ctx, &ctx->d_vec_full, nv);
+        dalloc(ctx, &ctx->d_spmv, ns);
+        dalloc(ctx, &ctx->d_vec, nv);
+        dalloc(ctx, &ctx->d_counts, 2);
+        dalloc(ctx, &ctx->d_active, 1);
+        dalloc(ctx, &ctx->d_gather, count);
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_mem, count * sizeof(BatchMember), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_gather, count * sizeof(PollBlock), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_active, sizeof(int), hipHostMallocDefault));
+        ctx->member_ev.assign(count, nullptr);
+        for (auto& e : ctx->member_ev) HIPCHECK(hipEventCreate(&e));
+        HIPCHECK(hipEventCreate(&ctx->ev_a));
+        HIPCHECK(hipEventCreate(&ctx->ev_b));
+        HIPCHECK(hipEventCreate(&ctx->ev_c));
+        build_lists(ctx);
+        return PODCG_OK;
+    });
+    if (rc != PODCG_OK) {
+        release_batch(ctx);
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return PODCG_OK;
+}
+
+int podcg_batch_destroy(podcg_batch* ctx) {
+    if (!ctx) return PODCG_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    release_batch(ctx);
+    delete ctx;
+    return PODCG_OK;
+}
+
+int podcg_batch_set_options(podcg_batch* ctx, const podcg_batch_options* opt) {
+    return guarded(ctx, [&]() {
+        if (!opt) fail(ctx, PODCG_ERR_INVALID_ARG, "null options");
+        check_batch_opts(ctx, *opt);
+        const podcg_batch_options old = ctx->opt;
+        ctx->opt = *opt;
+        try {
+            if (opt->slices_per_item != old.slices_per_item || opt->rows_per_item != old.rows_per_item)
+                build_lists(ctx);
+        } catch (...) {
+            ctx->opt = old;
+            build_lists(ctx);
+            throw;
+        }
+        return PODCG_OK;
+    });
+}
+
+int podcg_batch_get_options(podcg_batch* ctx, podcg_batch_options* opt) {
+    if (!ctx || !opt) return PODCG_ERR_INVALID_ARG;
+    *opt = ctx->opt;
+    return PODCG_OK;
+}
+
+int podcg_batch_solve(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
+                      int32_t plain, podcg_stats* stats) {
+    return guarded(ctx, [&]() { return batch_solve_impl(ctx, b, x, rtol, plain != 0, stats); });
+}
+
+int podcg_batch_tune(podcg_batch* ctx, const double* const* b, double* const* x, int32_t iters,
+                     podcg_batch_options* chosen, double* best_ms) {
+    return guarded(ctx, [&]() {
+        check_solve_args(ctx, b, x, nullptr);
+        if (iters < 1 || iters > 100000) fail(ctx, PODCG_ERR_INVALID_ARG, "bad tuning length");
+        const int count = (int)ctx->members.size();
+        std::vector<double> zero(count, 0.0);
+        std::vector<int> maxit(count, iters);
+        // time `iters` loop iterations of every member (tolerance 0: no member
+        // stops early) for the current options
+        auto measure = [&]() -> double {
+            stage1_all(ctx, b, x, zero.data(), maxit.data(), false);
+            const int yb = batch_yb(ctx, false);
+            upload_members(ctx, x, false);
+            (void)block_graph(ctx, yb);   // capture outside the timed region
+            HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
+            (void)run_batch_loop(ctx, yb, iters + 1, iters + 1);
+            HIPCHECK(hipEventRecord(ctx->ev_c, ctx->stream));
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_c));
+            return ms;
+        };
+        podcg_batch_options best = ctx->opt;
+        double tbest = measure();
+        auto try_opt = [&](const podcg_batch_options& o) {
+            podcg_batch_options prev = ctx->opt;
+            ctx->opt = o;
+            try {
+                build_lists(ctx);
+            } catch (const Fail&) {   // partition not allowed for these sizes
+                ctx->opt = prev;
+                build_lists(ctx);
+                ctx->last_error.clear();
+                return;
+            }
+            const double t = measure();
+            if (t < tbest) {
+                tbest = t;
+                best = o;
+            }
+            ctx->opt = best;
+            build_lists(ctx);
+        };
+        // coordinate descent: SpMV item size, vector item size, grid
+        for (int sp : {2, 4, 8, 16, 32}) {
+            podcg_batch_options o = best;
+            o.slices_per_item = sp;
+            if (sp != best.slices_per_item) try_opt(o);
+        }
+        for (int rp : {512, 1024, 2048, 4096, 8192}) {
+            podcg_batch_options o = best;
+            o.rows_per_item = rp;
+            if (rp != best.rows_per_item) try_opt(o);
+        }
+        for (int g : {512, 1024, 2048, 4096, 8192}) {
+            podcg_batch_options o = best;
+            o.grid = g;
+            if (g != best.grid) try_opt(o);
+        }
+        ctx->opt = best;
+        build_lists(ctx);
+        for (podcg_ctx* c : ctx->members) c->prev_iters[0] = 0;
+        ctx->prev_iters[0] = 0;
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = tbest;
+        return PODCG_OK;
+    });
+}
+
+}  // extern "C"

@@ -169,6 +169,41 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + t;
 }
 
+// Row (64 s + lane) of A x for the slice s handled by this wave.  Slices of
+// width <= 8 (stencil matrices) take a branch-free path: all column indices
+// and values are loaded first (padding slots re-read the last valid slot and
+// are skipped with a select), then all gathers, then the sums in order j =
+// 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
+// slice bounds are scalar loads.
+template <typename T>
+__device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
+                                           const int* __restrict__ cols,
+                                           const T* __restrict__ vals, int s, int lane,
+                                           const T* __restrict__ x) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int64_t base = sptr[s];
+    const int w = (int)((sptr[s + 1] - base) / kSlice);
+    const int* c = cols + base + lane;
+    const T* v = vals + base + lane;
+    double acc = 0.0;   // FP32 operands multiply exactly in FP64; the row sum is FP64
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        int ci[8];
+        T vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u, w - 1);
+            ci[u] = __builtin_nontemporal_load(c + j * kSlice);
+            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
+        }
+        T xi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xi[u] = x[ci[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = (j0 + u < w) ? fma((double)vi[u], (double)xi[u], acc) : acc;
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------ launchers
 // Device buffers of one context, passed to the launchers.
 struct DevBufs {
@@ -266,6 +301,50 @@ template <int YB>
 __device__ __forceinline__ bool tier_live(int k, int y) {
     return YB <= kExactTierMax ? true : k < y;
 }
+
+// ------------------------------------------------------------------ batches
+// One member (an independent sequence) of a batched solve, as the batched loop
+// kernels see it.  Rebuilt by the host before every batched solve.
+struct BatchMember {
+    DevBufs B;                 // the member context's matrix, state and scratch
+    double* r;
+    double* z;
+    double* p;
+    double* q;
+    double* x;
+    const double* W;
+    const double* AW;
+    int y;                     // basis columns used in this solve (0 = plain PCG)
+    int spmv_items;            // work items of this member in the SpMV list
+    int vec_items;             // work items of this member in the vector list
+    int spmv_first;            // offset of its items in the full SpMV list
+    int vec_first;             // offset of its items in the full vector list
+    int pad[3];
+};
+
+// A contiguous range of one member: SELL slices [begin, end) in the SpMV
+// list, rows [begin, end) in the vector list.  `local` numbers the items of
+// the member (its partial-sum slot).
+struct BatchItem {
+    int member, begin, end, local;
+};
+
+constexpr int kBatchMaxMembers = 1024;
+
+// Batched loop kernels (k_batch.hip).  `counts` holds the lengths of the
+// compacted SpMV and vector lists; `active` the number of members still
+// iterating.
+int batch_tier(int y);   // smallest compiled batched tier >= y
+hipError_t launch_batch_compact(const BatchMember* mem, int count, const BatchItem* spmv_full,
+                                const BatchItem* vec_full, BatchItem* spmv, BatchItem* vec,
+                                int* counts, int* active, hipStream_t s);
+hipError_t launch_batch_spmv(const BatchMember* mem, const BatchItem* items, const int* counts,
+                             int* active, int grid, hipStream_t s);
+hipError_t launch_batch_update(int yb, const BatchMember* mem, const BatchItem* items,
+                               const int* counts, int* active, int grid, hipStream_t s);
+hipError_t launch_batch_dir(int yb, const BatchMember* mem, const BatchItem* items, const int* counts,
+                            int grid, hipStream_t s);
+hipError_t launch_batch_gather(const BatchMember* mem, int count, PollBlock* out, hipStream_t s);
 
 // Single-workgroup dense kernels (k_small.hip)
 // G (m x m row-major, symmetrised here) -> R, Ginv = G^{-1} on the accepted

@@ -154,3 +154,85 @@ class PodCG:
                                                _ptr(b, torch.float64), _ptr(c, torch.float64),
                                                a.numel(), float(s), int(reps), C.byref(ms)))
         return ms.value
+
+
+class PodCGBatch:
+    """Independent sequences advanced together (podcg_batch_* of include/podcg.h).
+
+    `members` are PodCG contexts (FP64); each keeps its own matrix, snapshots
+    and basis and is still driven with set_matrix / push_snapshot / build_pod.
+    solve() runs one system of every member in one batched loop."""
+
+    def __init__(self, members, slices_per_item: int | None = None, rows_per_item: int | None = None,
+                 grid: int | None = None, graph_iters: int | None = None,
+                 check_every: int | None = None):
+        self._L = L.load()
+        self.members = list(members)
+        opt = L.BatchOptions()
+        self._L.podcg_batch_default_options(C.byref(opt))
+        for k, v in (("slices_per_item", slices_per_item), ("rows_per_item", rows_per_item),
+                     ("grid", grid), ("graph_iters", graph_iters), ("check_every", check_every)):
+            if v is not None:
+                setattr(opt, k, int(v))
+        arr = (C.c_void_p * len(self.members))(*[m._h for m in self.members])
+        h = C.c_void_p()
+        rc = self._L.podcg_batch_create(C.byref(h), len(self.members), arr, C.byref(opt))
+        if rc != 0:
+            raise PodCGError(rc, self._L.podcg_strerror(rc).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.podcg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise PodCGError(rc, self._L.podcg_batch_last_error(self._h).decode())
+        return rc
+
+    def _arrays(self, bs, xs):
+        if len(bs) != len(self.members) or len(xs) != len(self.members):
+            raise ValueError("one b and one x per member")
+        for m, b, x in zip(self.members, bs, xs):
+            if b.numel() != m.n or x.numel() != m.n:
+                raise ValueError("vector length differs from the member size")
+        pb = (C.c_void_p * len(bs))(*[_ptr(b, torch.float64).value for b in bs])
+        px = (C.c_void_p * len(xs))(*[_ptr(x, torch.float64).value for x in xs])
+        return pb, px
+
+    @property
+    def options(self) -> dict:
+        opt = L.BatchOptions()
+        self._check(self._L.podcg_batch_get_options(self._h, C.byref(opt)))
+        return opt.as_dict()
+
+    def set_options(self, **kw):
+        opt = L.BatchOptions()
+        self._check(self._L.podcg_batch_get_options(self._h, C.byref(opt)))
+        for k, v in kw.items():
+            setattr(opt, k, int(v))
+        self._check(self._L.podcg_batch_set_options(self._h, C.byref(opt)))
+
+    def solve(self, bs, xs, rtol, plain: bool = False):
+        """One system per member; returns (code, [Stats per member])."""
+        pb, px = self._arrays(bs, xs)
+        tol = rtol if hasattr(rtol, "__len__") else [rtol] * len(self.members)
+        ptol = (C.c_double * len(self.members))(*[float(t) for t in tol])
+        stats = (L.Stats * len(self.members))()
+        rc = self._check(self._L.podcg_batch_solve(self._h, pb, px, ptol, 1 if plain else 0, stats))
+        return rc, list(stats)
+
+    def tune(self, bs, xs, iters: int = 32):
+        """Autotune work-item sizes and grid; x is overwritten.  Returns (options, ms)."""
+        pb, px = self._arrays(bs, xs)
+        opt = L.BatchOptions()
+        ms = C.c_double()
+        self._check(self._L.podcg_batch_tune(self._h, pb, px, int(iters), C.byref(opt), C.byref(ms)))
+        return opt.as_dict(), ms.value

@@ -12,10 +12,13 @@ from .configs import (
     Config1Diffusion2D,
     Config2Diffusion3D,
     Config3Elasticity,
+    Config4Batch,
+    Config4Member,
     Config5Adjoint,
     config1,
     config2,
     config3,
+    config4,
     config5,
 )
 from .elasticity import Q1Elasticity
@@ -29,8 +32,11 @@ __all__ = [
     "config1",
     "config2",
     "config3",
+    "config4",
     "config5",
     "Config3Elasticity",
+    "Config4Batch",
+    "Config4Member",
     "Config5Adjoint",
     "Q1Elasticity",
     "tiny",

@@ -30,6 +30,15 @@ Every constant lives here, so a run can record exactly what it solved.
   bump (width 0.15, amplitude 1) whose centre moves along x with j, which
   makes the solutions genuinely change.
 
+* Config 4 -- a batch of 64 independent config-1-type sequences with uneven
+  sizes: side N_i drawn uniformly from {64, ..., 512} (seed 3), member i
+  with coefficient field seed 1000 + 2 i and load field seed 1001 + 2 i;
+  A_j = (1 + 0.01 j) A_0 per member, b_j the load field rotated by 0.05 j rad
+  about the centre; 20 systems, snapshot memory 10, POD rank 6, relative
+  tolerance 1e-8, FP64.  The rotated load is evaluated on the grid as a
+  Fourier field with rotated frequencies (same function as config 1's
+  pointwise evaluation, computed by matrix products).
+
 * Config 5 -- differentiation: the config-2 family at N = 96 (n = 884,736),
   200 systems, snapshot memory 20, POD rank 10, relative tolerance 1e-10.
   Outputs q_j = C x_j with C = 256 distinct seeded rows of the identity
@@ -95,6 +104,60 @@ class Config1Diffusion2D:
         return {"workload": self.name, "N": self.N, "n": self.n, "nnz": self.nnz,
                 "steps": self.steps, "omega": self.omega, "rank": self.rank,
                 "tol": self.tol, "variant": self.variant}
+
+
+class Config4Member:
+    """One sequence of the config-4 batch (config-1 type, side N)."""
+
+    def __init__(self, N: int, seed_kappa: int, seed_rhs: int, steps: int, omega: int, rank: int,
+                 tol: float, corr_len: float = 0.2, sigma: float = 0.5, growth: float = 0.01,
+                 dtheta: float = 0.05):
+        self.N, self.steps, self.omega, self.rank, self.tol = N, steps, omega, rank, tol
+        self.growth, self.dtheta = growth, dtheta
+        self.seed_kappa, self.seed_rhs = seed_kappa, seed_rhs
+        self.fv = FVDiffusion(N, 2)
+        self.n, self.nnz = self.fv.n, self.fv.nnz
+        self.rowptr, self.colind = self.fv.rowptr, self.fv.colind
+        ax = self.fv.node_axis()
+        g = FourierField(2, corr_len, seed_kappa).on_grid(ax, ax)
+        self._vals0 = self.fv.values(np.exp(sigma * g))
+        self._f = FourierField(2, corr_len, seed_rhs)
+        self._ax = (np.arange(N, dtype=np.float64) + 1.0) * self.fv.h
+
+    def matrix_values(self, j: int) -> np.ndarray:
+        return self._vals0 * (1.0 + self.growth * j)
+
+    def rhs(self, j: int, x_prev: np.ndarray | None = None) -> np.ndarray:
+        f = self._f.rotated(self.dtheta * j, (0.5, 0.5))
+        return f.on_grid(self._ax, self._ax).ravel()
+
+
+@dataclass
+class Config4Batch:
+    members_count: int = 64
+    n_min: int = 64
+    n_max: int = 512
+    steps: int = 20
+    omega: int = 10
+    rank: int = 6
+    tol: float = 1e-8
+    seed_sizes: int = 3
+    name: str = field(default="config4_batched")
+
+    def __post_init__(self):
+        rng = np.random.Generator(np.random.PCG64(self.seed_sizes))
+        self.sides = rng.integers(self.n_min, self.n_max + 1, size=self.members_count)
+        self.members = [Config4Member(int(N), 1000 + 2 * i, 1001 + 2 * i, self.steps, self.omega,
+                                      self.rank, self.tol)
+                        for i, N in enumerate(self.sides)]
+        self.n_total = int(sum(m.n for m in self.members))
+        self.nnz_total = int(sum(m.nnz for m in self.members))
+
+    def describe(self) -> dict:
+        return {"workload": self.name, "sequences": self.members_count,
+                "side_range": [self.n_min, self.n_max], "n_total": self.n_total,
+                "nnz_total": self.nnz_total, "steps": self.steps, "omega": self.omega,
+                "rank": self.rank, "tol": self.tol}
 
 
 @dataclass
@@ -240,6 +303,10 @@ class Config5Adjoint:
         return {"workload": self.name, "N": self.N, "n": self.n, "nnz": self.nnz,
                 "steps": self.steps, "omega": self.omega, "rank": self.rank, "tol": self.tol,
                 "outputs": int(self.outputs.size), "checkpoint_every": self.checkpoint_every}
+
+
+def config4(**kw) -> Config4Batch:
+    return Config4Batch(**kw)
 
 
 def config5(**kw) -> Config5Adjoint:

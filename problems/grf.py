@@ -27,6 +27,20 @@ class FourierField:
         self.phase = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
         self.scale = np.sqrt(2.0 / n_features)
 
+    def rotated(self, theta: float, center) -> "FourierField":
+        """The field x -> g(c + R(theta) (x - c)), itself a Fourier-feature field:
+        w_m . (c + R (x - c)) = (R^T w_m) . x + w_m . c - (R^T w_m) . c (2-D only)."""
+        if self.dim != 2:
+            raise ValueError("rotation is defined for 2-D fields")
+        c = np.asarray(center, dtype=np.float64)
+        rot = np.array([[np.cos(theta), -np.sin(theta)], [np.sin(theta), np.cos(theta)]])
+        out = object.__new__(FourierField)
+        out.dim, out.corr_len, out.n_features = self.dim, self.corr_len, self.n_features
+        out.omega = self.omega @ rot                      # rows (R^T w_m)^T
+        out.phase = self.phase + self.omega @ c - out.omega @ c
+        out.scale = self.scale
+        return out
+
     def at_points(self, pts: np.ndarray, chunk: int = 65536) -> np.ndarray:
         """Evaluate at an (m, dim) array of points."""
         pts = np.asarray(pts, dtype=np.float64).reshape(-1, self.dim)

@@ -52,3 +52,17 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     o.omega = 33
     assert L.podcg_create(ctypes.byref(h), 10, ctypes.byref(o), None) == _lib.ERR_INVALID_ARG
     assert L.podcg_destroy(None) == 0
+
+
+def test_batch_defaults_and_argument_checks_without_gpu():
+    from paper_1512_05820_amd import _lib
+    L = _lib.load()
+    o = _lib.BatchOptions()
+    L.podcg_batch_default_options(ctypes.byref(o))
+    assert o.as_dict() == {"slices_per_item": 8, "rows_per_item": 2048, "grid": 1024,
+                           "graph_iters": 16, "check_every": 16}
+    h = ctypes.c_void_p()
+    assert L.podcg_batch_create(ctypes.byref(h), 0, None, None) == _lib.ERR_INVALID_ARG
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.podcg_batch_create(ctypes.byref(h), 2, arr, None) == _lib.ERR_INVALID_ARG
+    assert L.podcg_batch_destroy(None) == 0

@@ -1,0 +1,232 @@
+"""Batched solves of independent sequences (podcg_batch_*) against the oracle.
+
+Members of uneven sizes (n = 25 .. 10,000, ragged slices, members of one and
+of many work items) are solved together.  Bars: lockstep (the oracle's
+iteration count from identical A, b, W) to 1e-10 relative for every member;
+closed-loop config-4-type sequences meeting the tolerance by the oracle's
+own residual with the oracle's ranks and iteration counts within one; graph
+replays bitwise equal to direct launches; repeat runs bitwise equal; other
+work-item partitions within rounding of each other.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from problems import Config4Member
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SIZES = [5, 8, 23, 40, 64, 100]          # n = 25, 64, 529, 1600, 4096, 10000
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1512_05820_amd as P
+    assert torch.cuda.is_available()
+    P.load()
+    return P
+
+
+def _members(sizes, steps=5, omega=3, rank=2, tol=1e-10):
+    return [Config4Member(N, 1000 + 2 * i, 1001 + 2 * i, steps, omega, rank, tol)
+            for i, N in enumerate(sizes)]
+
+
+def _contexts(P, cfgs, **kw):
+    ctxs = []
+    for c in cfgs:
+        k = P.PodCG(c.n, omega=c.omega, rank_max=c.rank, **kw)
+        k.set_matrix(_dev(c.matrix_values(1)), _dev(c.rowptr, torch.int32), _dev(c.colind, torch.int32))
+        ctxs.append(k)
+    return ctxs
+
+
+def _batched_sequence(P, cfgs, steps, plain=False, **bopt):
+    ctxs = _contexts(P, cfgs)
+    batch = P.PodCGBatch(ctxs, **bopt)
+    out = []
+    for j in range(1, steps + 1):
+        if j > 1:
+            for c, k in zip(cfgs, ctxs):
+                k.set_matrix(_dev(c.matrix_values(j)))
+        bs = [_dev(c.rhs(j)) for c in cfgs]
+        xs = [_dev(np.zeros(c.n)) for c in cfgs]
+        rc, st = batch.solve(bs, xs, [c.tol for c in cfgs], plain=plain)
+        if not plain:
+            for k, x in zip(ctxs, xs):
+                k.push_snapshot(x)
+                k.build_pod()
+        out.append((rc, [s.as_dict() for s in st], [_host(x) for x in xs]))
+    batch.close()
+    return out
+
+
+@pytest.mark.parametrize("items", ["default", "finest"])
+def test_lockstep_every_member_matches_oracle(P, items):
+    cfgs = _members(SIZES)
+    r = np.random.Generator(np.random.PCG64(40))
+    Ws, refs = [], []
+    for i, c in enumerate(cfgs):
+        y = [0, 1, 2, 2, 3, 4][i]                       # mixed ranks, one plain member
+        W = r.standard_normal((c.n, y)) if y else None
+        A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(2))
+        xo, so = oracle.aug_pcg(A, c.rhs(2), np.zeros(c.n), W, tol=1e-10, maxit=20000)
+        assert so.status == 0
+        Ws.append(W)
+        refs.append((xo, so))
+    ctxs = []
+    for c, W, (xo, so) in zip(cfgs, Ws, refs):
+        k = P.PodCG(c.n, rank_max=4, maxit=so.iters)
+        k.set_matrix(_dev(c.matrix_values(2)), _dev(c.rowptr, torch.int32), _dev(c.colind, torch.int32))
+        k.set_basis(None if W is None else _dev(W))
+        ctxs.append(k)
+    kw = {} if items == "default" else {"slices_per_item": 1, "rows_per_item": 256}
+    batch = P.PodCGBatch(ctxs, **kw)
+    xs = [_dev(np.zeros(c.n)) for c in cfgs]
+    rc, st = batch.solve([_dev(c.rhs(2)) for c in cfgs], xs, [0.0] * len(cfgs))
+    assert rc == 1                                      # tolerance 0: every member stops at its cap
+    for i, (c, (xo, so)) in enumerate(zip(cfgs, refs)):
+        e = _relerr(_host(xs[i]), xo)
+        print(f"member n={c.n} rank {st[i].rank} iters {st[i].iters} (oracle {so.iters}) err {e:.2e}")
+        assert st[i].iters == so.iters
+        assert st[i].rank == (0 if Ws[i] is None else Ws[i].shape[1])
+        assert e <= 1e-10
+
+
+def test_closed_loop_batch_matches_oracle_sequences(P):
+    cfgs = _members(SIZES, steps=5)
+    gpu = _batched_sequence(P, cfgs, 5)
+    for i, c in enumerate(cfgs):
+        orc = oracle.run_sequence(c, "aug", keep_x=True)
+        for j, o in enumerate(orc):
+            rc, st, xs = gpu[j]
+            A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(j + 1))
+            b = o["b"]
+            tr = np.linalg.norm(b - oracle.matvec(A, xs[i])) / np.linalg.norm(b)
+            assert st[i]["status"] in (0, 2)
+            assert tr <= c.tol * 1.01, (c.n, j + 1, tr)
+            assert st[i]["rank"] == o["rank"], (c.n, j + 1)
+            assert abs(st[i]["iters"] - o["iters"]) <= 1, (c.n, j + 1, st[i]["iters"], o["iters"])
+
+
+def test_plain_batch_matches_oracle_plain(P):
+    cfgs = _members(SIZES[:4], steps=2)
+    gpu = _batched_sequence(P, cfgs, 2, plain=True)
+    for i, c in enumerate(cfgs):
+        orc = oracle.run_sequence(c, "plain")
+        for j, o in enumerate(orc):
+            st = gpu[j][1][i]
+            assert st["rank"] == 0 and st["true_relres"] <= c.tol * 1.01
+            assert abs(st["iters"] - o["iters"]) <= 1
+
+
+def test_graph_replays_equal_direct_launches_bitwise(P):
+    cfgs = _members(SIZES, steps=4)
+    a = _batched_sequence(P, cfgs, 4, graph_iters=8)
+    b = _batched_sequence(P, cfgs, 4, graph_iters=0, check_every=8)
+    c = _batched_sequence(P, cfgs, 4, graph_iters=8)
+    for (ra, sa, xa), (rb, sb, xb), (rc, sc, xc) in zip(a, b, c):
+        for i in range(len(cfgs)):
+            assert np.array_equal(xa[i], xb[i]) and np.array_equal(xa[i], xc[i])
+            assert sa[i]["iters"] == sb[i]["iters"] == sc[i]["iters"]
+
+
+def test_item_partitions_agree_to_rounding(P):
+    cfgs = _members(SIZES, steps=3)
+    a = _batched_sequence(P, cfgs, 3, slices_per_item=1, rows_per_item=256, grid=512)
+    b = _batched_sequence(P, cfgs, 3, slices_per_item=16, rows_per_item=8192, grid=2048)
+    for (_, sa, xa), (_, sb, xb) in zip(a, b):
+        for i in range(len(cfgs)):
+            assert abs(sa[i]["iters"] - sb[i]["iters"]) <= 1
+            assert _relerr(xa[i], xb[i]) <= 1e-8
+
+
+def test_batch_agrees_with_single_context_solves(P):
+    cfgs = _members(SIZES, steps=4)
+    gpu = _batched_sequence(P, cfgs, 4)
+    for i, c in enumerate(cfgs):
+        (k,) = _contexts(P, [c])
+        for j in range(1, 5):
+            if j > 1:
+                k.set_matrix(_dev(c.matrix_values(j)))
+            x = _dev(np.zeros(c.n))
+            st = k.solve(_dev(c.rhs(j)), x, c.tol)
+            k.push_snapshot(x)
+            k.build_pod()
+            sb = gpu[j - 1][1][i]
+            assert st.rank == sb["rank"] and abs(st.iters - sb["iters"]) <= 1
+            assert _relerr(_host(x), gpu[j - 1][2][i]) <= 1e-8
+
+
+def test_mixed_outcomes_zero_rhs_and_iteration_cap(P):
+    cfgs = _members(SIZES[:4], steps=1)
+    ctxs = _contexts(P, cfgs)
+    ctxs[2].close()
+    ctxs[2] = P.PodCG(cfgs[2].n, omega=3, rank_max=2, maxit=5)      # capped member
+    ctxs[2].set_matrix(_dev(cfgs[2].matrix_values(1)), _dev(cfgs[2].rowptr, torch.int32),
+                       _dev(cfgs[2].colind, torch.int32))
+    batch = P.PodCGBatch(ctxs)
+    bs = [_dev(c.rhs(1)) for c in cfgs]
+    bs[1] = _dev(np.zeros(cfgs[1].n))                                # zero right-hand side
+    xs = [_dev(np.zeros(c.n)) for c in cfgs]
+    rc, st = batch.solve(bs, xs, [1e-10] * 4)
+    assert rc == 1
+    assert st[1].status == 0 and st[1].iters == 0 and not np.any(_host(xs[1]))
+    assert st[2].status == 1 and st[2].iters == 5
+    for i in (0, 3):
+        assert st[i].status == 0 and st[i].true_relres <= 1e-10 * 1.01
+
+
+def test_tune_picks_valid_options_and_solves_still_match(P):
+    cfgs = _members(SIZES, steps=2)
+    ctxs = _contexts(P, cfgs)
+    batch = P.PodCGBatch(ctxs)
+    bs = [_dev(c.rhs(1)) for c in cfgs]
+    scratch = [_dev(np.zeros(c.n)) for c in cfgs]
+    opt, ms = batch.tune(bs, scratch, iters=16)
+    print("tuned", opt, f"{ms:.3f} ms / 16 iterations")
+    assert ms > 0 and opt["slices_per_item"] >= 1 and opt["rows_per_item"] >= 256
+    assert batch.options == opt
+    xs = [_dev(np.zeros(c.n)) for c in cfgs]
+    rc, st = batch.solve(bs, xs, [c.tol for c in cfgs])
+    assert rc == 0
+    for i, c in enumerate(cfgs):
+        A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(1))
+        b = c.rhs(1)
+        tr = np.linalg.norm(b - oracle.matvec(A, _host(xs[i]))) / np.linalg.norm(b)
+        assert tr <= c.tol * 1.01
+
+
+def test_batch_rejects_bad_members(P):
+    cfgs = _members(SIZES[:2], steps=1)
+    ctxs = _contexts(P, cfgs)
+    with pytest.raises(P.PodCGError):
+        P.PodCGBatch([ctxs[0], ctxs[0]])
+    mixed = P.PodCG(cfgs[1].n, precision="mixed")
+    with pytest.raises(P.PodCGError):
+        P.PodCGBatch([ctxs[0], mixed])
+    with pytest.raises(P.PodCGError):
+        P.PodCGBatch(ctxs, rows_per_item=100)
+    batch = P.PodCGBatch(ctxs)
+    with pytest.raises(P.PodCGError):
+        batch.set_options(grid=0)
+    assert batch.options["grid"] == 1024
