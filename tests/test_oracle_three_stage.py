@@ -1,0 +1,265 @@
+"""Pins of the three-stage oracle (Alg. 3) against what the paper and the
+mathematics fix, and mutants of it that the pins must catch.
+
+* Stage 2 with a zero tolerance reaches the Galerkin solution over range(Y)
+  (a dense solve of Y^T A Y), its directions are A-orthogonal to each other
+  and to W (Section 4.2), and it terminates in at most m - w steps.
+* Stage-3 directions are A-orthogonal to each other and to [W, X]
+  (Section 4.3); the solution is reconstructed exactly from the accumulated
+  vectors and the previous weights (Section 3.3.2).
+* A truncated basis is A_j-orthonormal (Eq. (podOrth)) and equals the POD of
+  the independent C oracle (Alg. pod_evd) when both apply.
+* With rho = 1 and a constant matrix the second solve of the same system
+  needs no Stage-3 iteration (the solution lies in the accumulated span).
+* eta^RBF equals the explicit sum of Section 3.3.2 with weights 2^{1-i}.
+* Theorem wellConditioned: ||Y_j^T A_j Y_j - I|| <= sum ||Y_k||^2 ||A_k - A_{k-1}||.
+"""
+
+import importlib.util
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import three_stage as TS
+from problems import Config4Member
+
+
+def _A(cfg, j):
+    return oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(j))
+
+
+def _dense(A):
+    n = A.n
+    D = np.zeros((n, n))
+    for i in range(n):
+        for e in range(A.rowptr[i], A.rowptr[i + 1]):
+            D[i, A.colind[e]] += A.vals[e]
+    return D
+
+
+def pin_stage2_galerkin(ts):
+    cfg = Config4Member(12, 1000, 1001, 3, 5, 4, 1e-10)
+    A = _A(cfg, 1)
+    r = np.random.Generator(np.random.PCG64(70))
+    Y = r.standard_normal((cfg.n, 10))
+    sel = [0, 1, 2]
+    W = Y[:, sel]
+    AW = np.stack([oracle.matvec(A, W[:, k]) for k in range(3)], axis=1)
+    R, kept = ts._chol_truncated(W.T @ AW)
+    assert kept == 3
+    rbar = cfg.rhs(1)
+    what = ts._chol_solve(R, W.T @ rbar)
+    # finite termination: m - w = 7 steps reach the Galerkin solution over range(Y)
+    xh, X, AX, gh, k, rhn = ts.stage2(A, Y, sel, AW, R, what, rbar, 0.0, 7)
+    D = _dense(A)
+    ref = np.linalg.solve(Y.T @ D @ Y, Y.T @ rbar)
+    assert k == 7
+    assert np.linalg.norm(xh - ref) <= 1e-9 * np.linalg.norm(ref)
+    # X^T A X diagonal (= Gammahat), X^T A W = 0
+    XAX = X.T @ AX
+    off = XAX - np.diag(np.diag(XAX))
+    assert np.abs(off).max() <= 1e-9 * np.abs(np.diag(XAX)).max()
+    assert np.allclose(np.diag(XAX), gh, rtol=1e-10)
+    assert np.abs(X.T @ AW).max() <= 1e-9 * np.linalg.norm(X) * np.linalg.norm(AW)
+
+
+def pin_stage3_orthogonality_and_reconstruction(ts):
+    cfg = Config4Member(14, 1002, 1003, 4, 5, 4, 1e-10)
+    opt = ts.TSOptions(ybar=1000, rho=0.0, stage2_factor=1e-4, stage2_maxit=30)
+    st = ts.TSState(cfg.n)
+    for j in (1, 2):
+        A = _A(cfg, j)
+        b = cfg.rhs(j)
+        keep = {}
+        x, S = ts.ts_solve(A, b, np.zeros(cfg.n), st, cfg.tol, 10000, opt, keep)
+        assert S.true_relres <= cfg.tol * 1.01
+        # x - xbar = Z eta^prev
+        assert np.linalg.norm(keep["Z"] @ keep["eta_prev"] - x) <= 1e-11 * np.linalg.norm(x)
+        V = keep["V"]
+        AV = np.stack([oracle.matvec(A, V[:, k]) for k in range(V.shape[1])], axis=1)
+        G = V.T @ AV
+        assert np.allclose(np.diag(G), keep["gamma"], rtol=1e-10)
+        off = G - np.diag(np.diag(G))
+        assert np.abs(off).max() <= 1e-6 * np.abs(np.diag(G)).max()
+        B = np.concatenate([keep["W"], keep["X"]], axis=1)
+        if B.shape[1]:
+            c = np.abs(B.T @ AV) / (np.linalg.norm(B, axis=0)[:, None] * np.linalg.norm(V, axis=0)[None, :])
+            assert c.max() <= 1e-6
+    assert S.k2 > 0
+
+
+def pin_truncation_orthonormal_and_c_pod(ts):
+    cfg = Config4Member(10, 1004, 1005, 3, 5, 4, 1e-10)
+    A = _A(cfg, 2)
+    r = np.random.Generator(np.random.PCG64(71))
+    Z = r.standard_normal((cfg.n, 12))
+    eta = r.uniform(0.2, 1.0, 12)
+    Yn, lam = ts.pod_evd_dense(A, Z, eta, 6, 1e-12, 1.0)
+    D = _dense(A)
+    assert np.abs(Yn.T @ D @ Yn - np.eye(6)).max() <= 1e-10
+    Wc, lam_c = oracle.pod_evd(A, Z, eta, 6)
+    assert np.allclose(lam, lam_c, rtol=1e-10, atol=1e-12 * lam[0])
+    P1 = Yn @ Yn.T @ D
+    P2 = Wc @ Wc.T @ D
+    assert np.abs(P1 - P2).max() <= 1e-9 * np.abs(P2).max()
+    # energy criterion: smallest y reaching the energy fraction
+    Ye, _ = ts.pod_evd_dense(A, Z, eta, 12, 1e-12, 0.9)
+    frac = np.cumsum(lam) / lam.sum()
+    assert Ye.shape[1] == int(np.argmax(frac >= 0.9)) + 1
+
+
+def pin_exact_recovery(ts):
+    cfg = Config4Member(6, 1006, 1007, 2, 5, 4, 1e-10)
+    A = _A(cfg, 1)
+    b = cfg.rhs(1)
+    for rho in (1.0, 0.0):
+        opt = ts.TSOptions(ybar=1000, rho=rho, w_cap=32, stage2_factor=1e-6, stage2_maxit=32)
+        st = ts.TSState(cfg.n)
+        x1, S1 = ts.ts_solve(A, b, np.zeros(cfg.n), st, cfg.tol, 10000, opt)
+        keep = {}
+        x2, S2 = ts.ts_solve(A, b, np.zeros(cfg.n), st, cfg.tol, 10000, opt, keep)
+        assert S1.k3 > 0 and S1.k3 <= 32
+        assert S2.true_relres <= cfg.tol * 1.01
+        if rho == 1.0:        # Stage 1 alone reproduces x_1
+            assert S2.w == S1.k3 and S2.k3 == 0 and S2.k2 == 0
+        else:                 # Stage 2 reproduces x_1 to its tolerance
+            assert S2.w == 0 and S2.k2 > 0
+            assert np.linalg.norm(keep["x0"] - x1) <= 1e-4 * np.linalg.norm(x1)
+            assert S2.k3 < S1.k3 // 2
+
+
+def pin_rbf_weights(ts):
+    cfg = Config4Member(9, 1008, 1009, 4, 5, 4, 1e-8)
+    opt = ts.TSOptions(ybar=1000, rho=0.0, stage2_maxit=8)
+    st = ts.TSState(cfg.n)
+    hist = []
+    for j in range(1, 5):
+        keep = {}
+        ts.ts_solve(_A(cfg, j), cfg.rhs(j), np.zeros(cfg.n), st, cfg.tol, 10000, opt, keep)
+        hist.append(keep["eta_prev"])
+        L = len(keep["eta_rbf"])
+        expl = np.zeros(L)
+        for i in range(1, len(hist) + 1):
+            e = hist[-i]
+            expl[:len(e)] += 2.0 ** (1 - i) * e
+        assert np.allclose(keep["eta_rbf"], expl, rtol=1e-14, atol=0)
+
+
+def pin_well_conditioned_bound(ts):
+    cfg = Config4Member(8, 1010, 1011, 4, 5, 4, 1e-6)
+    opt = ts.TSOptions(ybar=1000, rho=1.0, w_cap=32, stage2_factor=1e-6)
+    st = ts.TSState(cfg.n)
+    bound = 0.0
+    D_prev = None
+    for j in range(1, 5):
+        A = _A(cfg, j)
+        D = _dense(A)
+        if st.m:
+            Y = st.Y
+            bound += np.linalg.norm(Y, 2) ** 2 * np.linalg.norm(D - D_prev, 2)
+            err = np.linalg.norm(Y.T @ D @ Y - np.eye(st.m), 2)
+            assert err <= bound * (1 + 1e-8) + 1e-10, (j, err, bound)
+        if st.m + 12 > 32:
+            break
+        ts.ts_solve(A, cfg.rhs(j), np.zeros(cfg.n), st, cfg.tol, 10000, opt)
+        assert st.sel == list(range(st.m))            # W = Y throughout
+        D_prev = D
+    assert st.m > 0
+
+
+def pin_stage3_exact_factor(ts):
+    cfg = Config4Member(16, 1014, 1015, 3, 5, 4, 1e-10)
+    opt = ts.TSOptions(ybar=1000, rho=0.0, stage2_maxit=20, stage3_gram="exact")
+    st = ts.TSState(cfg.n)
+    for j in (1, 2, 3):
+        A = _A(cfg, j)
+        keep = {}
+        x, S = ts.ts_solve(A, cfg.rhs(j), np.zeros(cfg.n), st, cfg.tol, 10000, opt, keep)
+        assert S.status == 0 and S.true_relres <= cfg.tol * 1.01
+    B = np.concatenate([keep["W"], keep["X"]], axis=1)
+    AB = np.stack([oracle.matvec(A, B[:, k]) for k in range(B.shape[1])], axis=1)
+    kb = keep["Ginv"].shape[0]
+    assert np.abs(keep["Ginv"] @ (B[:, :kb].T @ AB[:, :kb]) - np.eye(kb)).max() <= 1e-8
+    V = keep["V"]
+    AV = np.stack([oracle.matvec(A, V[:, k]) for k in range(V.shape[1])], axis=1)
+    c = np.abs(B[:, :kb].T @ AV) / (np.linalg.norm(B[:, :kb], axis=0)[:, None] * np.linalg.norm(V, axis=0)[None, :])
+    assert c.max() <= 1e-8
+
+
+PINS = [pin_stage2_galerkin, pin_stage3_orthogonality_and_reconstruction, pin_stage3_exact_factor,
+        pin_truncation_orthonormal_and_c_pod, pin_exact_recovery, pin_rbf_weights,
+        pin_well_conditioned_bound]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
+def test_three_stage_oracle_pins(pin):
+    pin(TS)
+
+
+def test_three_stage_sequence_with_truncations_meets_tolerance():
+    cfg = Config4Member(20, 1012, 1013, 6, 5, 4, 1e-8)
+    opt = TS.TSOptions(ybar=40, y_trunc=12, w_max=4, rho=1e-3, stage2_maxit=20)
+    out = TS.run_three_stage(cfg, opt)
+    ex = TS.run_three_stage(cfg, TS.TSOptions(ybar=40, y_trunc=12, w_max=4, rho=1e-3,
+                                              stage2_maxit=20, stage3_gram="exact"))
+    for a, e in zip(out, ex):
+        assert e["status"] == 0 and abs(a["k3"] - e["k3"]) <= max(2, a["k3"] // 10)
+    assert any(o["truncated"] for o in out)
+    for o in out:
+        assert o["status"] == 0 and o["true_relres"] <= cfg.tol * 1.01
+        assert o["m_next"] <= max(opt.ybar, o["m"]) + o["k3"]
+    later = [o["k3"] for o in out[2:]]
+    assert max(later) < out[0]["k3"]
+
+
+# ------------------------------------------------------------------ mutants
+
+SRC = TS.__file__
+
+MUTANTS = {
+    "new_vectors_scaled_by_sqrt_gamma": (
+        "Znew = V / np.sqrt(gam)[None, :] if kr else np.zeros((n, 0))",
+        "Znew = V * np.sqrt(gam)[None, :] if kr else np.zeros((n, 0))"),
+    "stage2_without_projection": (
+        "        ph = zh + beta * ph\n        if w:\n            ph[sel] -= mu",
+        "        ph = zh + beta * ph\n        if False:\n            ph[sel] -= mu"),
+    "rbf_factor_quarter": ("eta_acc = eta_prev + 0.5 * eta_acc", "eta_acc = eta_prev + 0.25 * eta_acc"),
+    "stage3_residual_ignores_x0": ("    r = b - matvec(A, x)\n    z = dinv * r",
+                                   "    r = b.copy()\n    z = dinv * r"),
+    "stage2_rhs_without_stage1": ("rh = Y.T @ (rbar - _mv(A, Y @ xh))", "rh = Y.T @ rbar"),
+    "stage3_exact_gram_without_A": ("RB, kb = _chol_truncated(B.T @ AB)", "RB, kb = _chol_truncated(B.T @ B)"),
+    "pod_missing_weight": ("T = (eta[:, None] * V[:, :y]) / np.sqrt(lam[:y])[None, :]",
+                           "T = V[:, :y] / np.sqrt(lam[:y])[None, :]"),
+}
+
+
+def _load_mutant(name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    src = src.replace(old, new).replace("from . import CSR, matvec", "from oracle import CSR, matvec")
+    d = tempfile.mkdtemp()
+    path = os.path.join(d, f"ts_{name}.py")
+    with open(path, "w") as f:
+        f.write(src)
+    spec = importlib.util.spec_from_file_location(f"ts_mutant_{name}", path)
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_three_stage_mutant_is_caught(name):
+    mod = _load_mutant(name)
+    caught = []
+    for pin in PINS:
+        try:
+            pin(mod)
+        except Exception:
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"
