@@ -255,6 +255,82 @@ int podcg_batch_tune(podcg_batch* batch, const double* const* b, double* const* 
 
 const char* podcg_batch_last_error(podcg_batch* batch);
 
+/* ------------------------------------------------- three-stage method
+ * The paper's full method (Alg. 3, Section 4) with the non-iterative Stage 3
+ * (Section 4.3).  The context keeps an accumulated basis Y (m <= cap columns,
+ * device memory) and a stage-1 basis W made of columns of Y.  One
+ * podcg_ts_solve runs, for the current matrix A_j:
+ *   Stage 1 (Alg. 2)       the direct Galerkin solve over W from x (= xbar);
+ *   Stage 2 (Section 4.2)  augmented CG with M = I on Y^T A_j Y (never formed:
+ *                          each step is Y p, one SpMV and Y^T q), augmented by
+ *                          W, to the stage-2 tolerance
+ *                          max(stage2_factor * rtol * ||b||, 1e-6 ||Y^T r||),
+ *                          at most min(stage2_maxit, 32 - w) steps;
+ *   Stage 3 (Section 4.3)  augmented PCG (Alg. 1, Jacobi) from the Stage-2
+ *                          solution over [W, X] (X: the Stage-2 directions)
+ *                          with the reused factor blockdiag(R, sqrt(Gammahat))
+ *                          (stage3_gram = 0) or the computed and factored Gram
+ *                          (stage3_gram = 1), to ||b - A x|| <= rtol ||b||;
+ * then the Stage-3 directions, scaled to unit A_j-norm, are appended to Y.
+ * If Y then has more than ybar columns it is replaced by its POD (metric A_j,
+ * weights: RBF 2^{1-i} over the systems since the last truncation or the
+ * previous weights, Section 3.3.2; at most y_trunc vectors, energy_y) and W by
+ * its leading vectors (w_max, energy_w); otherwise W gains the new vectors the
+ * rho rule selects (rho = 0 none, rho = 1 all, else gamma_k / sum gamma > rho),
+ * up to w_cap columns.  Directions beyond `cap - m` are not recorded.
+ * The three-stage calls leave the context's own basis (podcg_set_basis /
+ * podcg_build_pod / podcg_solve) untouched.  Precision 0 only. */
+typedef struct {
+    int32_t ybar;          /* truncate when Y would exceed ybar columns (1 <= ybar < cap)  */
+    int32_t y_trunc;       /* POD dimension after a truncation (1..ybar)                    */
+    int32_t w_max;         /* stage-1 dimension after a truncation (0..min(32, y_trunc))    */
+    int32_t w_cap;         /* largest stage-1 dimension between truncations (0..32)         */
+    int32_t stage2_maxit;  /* Stage-2 step cap (0..32)                                      */
+    int32_t cap;           /* column capacity of Y (2..512)                                 */
+    int32_t weights;       /* 0 = RBF weights, 1 = previous weights                          */
+    int32_t stage3_gram;   /* 0 = reused block-diagonal factor, 1 = computed Gram            */
+    double energy_y;       /* energy criterion of the truncated basis, (0, 1], 1 = off       */
+    double energy_w;       /* energy criterion of the stage-1 basis, (0, 1], 1 = off         */
+    double rho;            /* new-vector rule, [0, 1]                                        */
+    double stage2_factor;  /* stage-2 tolerance relative to rtol ||b|| (>= 0)                */
+} podcg_ts_options;
+
+typedef struct {
+    int32_t w, m;          /* stage-1 dimension used, dim Y at the start                     */
+    int32_t k2, k3;        /* Stage-2 steps, Stage-3 iterations (preconditioner applications) */
+    int32_t matvecs;
+    int32_t truncated;     /* 1 if Y was truncated after this solve                          */
+    int32_t m_next, w_next;
+    int32_t status;
+    int32_t jacobi_sweeps; /* sweeps of the truncation's eigen-solver                        */
+    double stage1_relres, stage2_relres, relres, true_relres, bnorm;
+    double stage12_ms, stage3_ms, accum_ms;
+} podcg_ts_stats;
+
+/* Defaults: ybar 200, y_trunc 100, w_max 5, w_cap 16, stage2_maxit 24, cap 512,
+ * RBF weights, reused factor, energies 1, rho 0, stage2_factor 1e-4. */
+void podcg_ts_default_options(podcg_ts_options* opt);
+
+/* Turns the three-stage mode on (or resets it) with an empty Y; allocates two
+ * n x cap blocks.  opt may be NULL.  Errors: INVALID_ARG, OOM, HIP. */
+int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt);
+
+/* One system of Alg. 3 with the current matrix.  b, x: device, n float64
+ * (x: in xbar, out x_j).  stats (host) may be NULL.  Returns the Stage-3
+ * status (OK, NOT_CONVERGED) or an error (NOT_SPD, NONFINITE, NO_MATRIX,
+ * INVALID_ARG, HIP). */
+int podcg_ts_solve(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_ts_stats* stats);
+
+/* Y (device, n x m column-major, may be NULL) and the stage-1 columns sel
+ * (host, w entries, may be NULL). */
+int podcg_ts_get_state(podcg_ctx* ctx, double* Y, int32_t* m, int32_t* sel, int32_t* w);
+
+/* Replaces Y (device, n x m column-major, m <= ybar), the stage-1 columns
+ * (host, w entries, each < m) and the RBF weight accumulator (host, m
+ * entries, NULL = zeros).  For tests and restarts. */
+int podcg_ts_set_state(podcg_ctx* ctx, const double* Y, int32_t m, const int32_t* sel, int32_t w,
+                       const double* eta_acc);
+
 /* Text of a status code (static storage). */
 const char* podcg_strerror(int code);
 

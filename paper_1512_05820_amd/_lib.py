@@ -22,6 +22,8 @@ EXPORTED = [
     "podcg_batch_default_options", "podcg_batch_create", "podcg_batch_destroy",
     "podcg_batch_set_options", "podcg_batch_get_options", "podcg_batch_solve", "podcg_batch_tune",
     "podcg_batch_last_error",
+    "podcg_ts_default_options", "podcg_ts_enable", "podcg_ts_solve", "podcg_ts_get_state",
+    "podcg_ts_set_state",
 ]
 
 
@@ -35,6 +37,28 @@ class Options(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("slices_per_item", C.c_int32), ("rows_per_item", C.c_int32), ("grid", C.c_int32),
                 ("graph_iters", C.c_int32), ("check_every", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TsOptions(C.Structure):
+    _fields_ = [("ybar", C.c_int32), ("y_trunc", C.c_int32), ("w_max", C.c_int32), ("w_cap", C.c_int32),
+                ("stage2_maxit", C.c_int32), ("cap", C.c_int32), ("weights", C.c_int32),
+                ("stage3_gram", C.c_int32), ("energy_y", C.c_double), ("energy_w", C.c_double),
+                ("rho", C.c_double), ("stage2_factor", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TsStats(C.Structure):
+    _fields_ = [("w", C.c_int32), ("m", C.c_int32), ("k2", C.c_int32), ("k3", C.c_int32),
+                ("matvecs", C.c_int32), ("truncated", C.c_int32), ("m_next", C.c_int32),
+                ("w_next", C.c_int32), ("status", C.c_int32), ("jacobi_sweeps", C.c_int32),
+                ("stage1_relres", C.c_double), ("stage2_relres", C.c_double), ("relres", C.c_double),
+                ("true_relres", C.c_double), ("bnorm", C.c_double), ("stage12_ms", C.c_double),
+                ("stage3_ms", C.c_double), ("accum_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -94,6 +118,11 @@ def load(path: str = LIB_PATH):
         "podcg_batch_tune": ([P, C.POINTER(P), C.POINTER(P), I32, C.POINTER(BatchOptions),
                              C.POINTER(D)], C.c_int),
         "podcg_batch_last_error": ([P], C.c_char_p),
+        "podcg_ts_default_options": ([C.POINTER(TsOptions)], None),
+        "podcg_ts_enable": ([P, C.POINTER(TsOptions)], C.c_int),
+        "podcg_ts_solve": ([P, P, P, D, C.POINTER(TsStats)], C.c_int),
+        "podcg_ts_get_state": ([P, P, C.POINTER(I32), P, C.POINTER(I32)], C.c_int),
+        "podcg_ts_set_state": ([P, P, I32, P, I32, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

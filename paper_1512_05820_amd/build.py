@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpodcg.so")
-SOURCES = ["podcg_api.hip", "podcg_batch.hip", "k_sell.hip", "k_vec.hip", "k_small.hip", "k_batch.hip"]
+SOURCES = ["podcg_api.hip", "podcg_batch.hip", "podcg_three.hip", "k_sell.hip", "k_vec.hip", "k_small.hip",
+           "k_batch.hip", "k_three.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -36,7 +37,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     bad = [src for p, src in procs if p.wait() != 0]
     if bad:
         raise RuntimeError(f"hipcc failed for {bad}")
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs,
+           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

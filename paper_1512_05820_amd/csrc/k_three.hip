@@ -1,0 +1,472 @@
+// Kernels of the three-stage method (Alg. 3): products with the tall
+// accumulated basis Y (n x m, m <= kTsCap, column-major with leading dimension
+// ld), the reduced iteration of Stage 2 (Section 4.2), the factor of the
+// Stage-3 basis, the bookkeeping of the accumulated vectors and weights
+// (Section 3.3.2) and the eigen-decomposition of the weighted snapshot Gram of
+// a truncation (Alg. pod_evd).
+#include "podcg_device.h"
+
+namespace podcg {
+
+// ------------------------------------------------------------ tall products
+
+// out = sign * Y c (accumulate: out += sign * Y c); c has m entries.
+__global__ __launch_bounds__(kBlock) void k_gemv_n(int n, size_t ld, const double* __restrict__ Y, int m,
+                                                   const double* __restrict__ c, double* __restrict__ out,
+                                                   double sign, int accumulate) {
+    __shared__ double cs[kTsCap];
+    for (int k = threadIdx.x; k < m; k += kBlock) cs[k] = c[k];
+    __syncthreads();
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < m; ++k) acc += Y[(size_t)k * ld + i] * cs[k];
+        out[i] = accumulate ? out[i] + sign * acc : sign * acc;
+    }
+}
+
+// part[g * m + k] = sum over the rows of chunk g of Y(i, k) v(i): one wave per
+// column at a time, lanes over the rows.
+__global__ __launch_bounds__(kBlock) void k_gemv_t_part(int n, size_t ld, const double* __restrict__ Y,
+                                                        int m, const double* __restrict__ v,
+                                                        double* __restrict__ part, int rows) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int r0 = blockIdx.x * rows;
+    const int r1 = min(n, r0 + rows);
+    for (int k = wid; k < m; k += kWavesPerBlock) {
+        const double* __restrict__ yk = Y + (size_t)k * ld;
+        double acc = 0.0;
+        for (int i = r0 + lane; i < r1; i += kWave) acc += yk[i] * v[i];
+        acc = wave_sum(acc);
+        if (lane == 0) part[(size_t)blockIdx.x * m + k] = acc;
+    }
+}
+
+// out[k] = sum_g part[g * m + k], in chunk order.
+__global__ __launch_bounds__(kBlock) void k_gemv_t_reduce(const double* __restrict__ part, int chunks, int m,
+                                                          double* __restrict__ out) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= m) return;
+    double s = 0.0;
+    for (int g = 0; g < chunks; ++g) s += part[(size_t)g * m + k];
+    out[k] = s;
+}
+
+// ------------------------------------------------------------------ Stage 2
+// Augmented CG (Alg. 1 with M = I) on Ghat = Y^T A Y in reduced coordinates,
+// augmented by What (W = Y What: the columns sel of Y).  The solves with
+// What^T Ghat What = W^T A W reuse G_W^{-1} from Stage 1; What^T Ghat z is
+// (A W)^T Y z = wtgy z with wtgy = (A W)^T Y computed once per system.
+
+// Sum of a value over the workgroup, fixed order; every thread gets it.
+__device__ __forceinline__ double ts_block_sum(double v, double* lds) {
+    double a[1] = {v};
+    block_sum<1>(a, lds);
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// mu = G_W^{-1} (wtgy z) into mu_s (LDS, w entries); then p = z + beta p - What mu.
+__device__ __forceinline__ void ts_project(TsDev* T, int m, const int* sel, int w, const double* GinvW,
+                                           double beta, bool first, double* c_s, double* mu_s) {
+    const int t = threadIdx.x;
+    if (t < w) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += T->wtgy[(size_t)t * m + k] * T->rh[k];
+        c_s[t] = s;
+    }
+    __syncthreads();
+    if (t < w) {
+        double s = 0.0;
+        for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * c_s[j];
+        mu_s[t] = s;
+    }
+    __syncthreads();
+    for (int k = t; k < m; k += kBlock) T->ph[k] = first ? T->rh[k] : T->rh[k] + beta * T->ph[k];
+    __syncthreads();
+    if (t < w) T->ph[sel[t]] -= mu_s[t];
+    __syncthreads();
+}
+
+// Start of Stage 2: rh = Y^T (b - A xbar - A W what) is already in T->rh.
+// xh = What what, p = z - What mu, rz = (r, z), the tolerance
+// max(tau_rel ||b||, floor ||rh||) and the iteration cap.
+__global__ __launch_bounds__(kBlock) void k_ts_s2_init(TsDev* T, const DevState* st, int m,
+                                                       const int* __restrict__ sel, int w,
+                                                       const double* __restrict__ GinvW, double tau_rel,
+                                                       double floor_rel, int k2max) {
+    __shared__ double lds[kWavesPerBlock + 2];
+    __shared__ double c_s[kYMax], mu_s[kYMax];
+    const int t = threadIdx.x;
+    for (int k = t; k < m; k += kBlock) T->xh[k] = 0.0;
+    __syncthreads();
+    if (t < w) T->xh[sel[t]] = st->what[t];
+    double a = 0.0;
+    for (int k = t; k < m; k += kBlock) a += T->rh[k] * T->rh[k];
+    const double rz = ts_block_sum(a, lds);
+    ts_project(T, m, sel, w, GinvW, 0.0, true, c_s, mu_s);
+    if (t == 0) {
+        const double rn0 = sqrt(rz);
+        T->rz2 = rz;
+        T->rn0 = rn0;
+        T->rn = rn0;
+        T->tau = fmax(tau_rel * sqrt(st->bnorm2), floor_rel * rn0);
+        T->k2 = 0;
+        T->k2max = k2max;
+        T->done2 = (rn0 <= T->tau || k2max <= 0) ? 1 : 0;
+    }
+}
+
+// One Stage-2 iteration once gh = Ghat p is in T->gh.
+__global__ __launch_bounds__(kBlock) void k_ts_s2_step(TsDev* T, int m, const int* __restrict__ sel, int w,
+                                                       const double* __restrict__ GinvW) {
+    __shared__ double lds[kWavesPerBlock + 2];
+    __shared__ double c_s[kYMax], mu_s[kYMax];
+    __shared__ int stop;
+    const int t = threadIdx.x;
+    if (T->done2) return;
+    double a = 0.0;
+    for (int k = t; k < m; k += kBlock) a += T->ph[k] * T->gh[k];
+    const double g = ts_block_sum(a, lds);
+    if (t == 0) stop = !(g > 0.0);
+    __syncthreads();
+    if (stop) {
+        if (t == 0) T->done2 = 1;
+        return;
+    }
+    const double alpha = T->rz2 / g;
+    double b2 = 0.0;
+    for (int k = t; k < m; k += kBlock) {
+        T->xh[k] += alpha * T->ph[k];
+        const double r = T->rh[k] - alpha * T->gh[k];
+        T->rh[k] = r;
+        b2 += r * r;
+    }
+    const double rz_new = ts_block_sum(b2, lds);
+    const double beta = rz_new / T->rz2;
+    const int k2 = T->k2;
+    __syncthreads();   // every thread has read rz2 and k2
+    if (t == 0) {
+        T->gam2[k2] = g;
+        T->alp2[k2] = alpha;
+        T->rz2 = rz_new;
+        T->k2 = k2 + 1;
+        T->rn = sqrt(rz_new);
+        T->done2 = (sqrt(rz_new) <= T->tau || k2 + 1 >= T->k2max) ? 1 : 0;
+    }
+    ts_project(T, m, sel, w, GinvW, beta, false, c_s, mu_s);
+}
+
+// ------------------------------------------------------------------ Stage 3
+// Inverse of the reused factor blockdiag(R, sqrt(Gammahat)) of [W, X]^T A [W, X]
+// (Section 4.3): blockdiag(G_W^{-1}, Gammahat^{-1}), row-major (w + k2)^2.
+__global__ void k_ts_ginv_blockdiag(const double* __restrict__ GinvW, int w, const TsDev* T, int k2,
+                                    double* __restrict__ GinvB) {
+    const int y = w + k2;
+    for (int e = threadIdx.x; e < y * y; e += blockDim.x) {
+        const int i = e / y, j = e % y;
+        double v = 0.0;
+        if (i < w && j < w) v = GinvW[i * w + j];
+        else if (i == j) v = 1.0 / T->gam2[i - w];
+        GinvB[e] = v;
+    }
+}
+
+// ------------------------------------------------------- accumulated vectors
+
+// Columns c < k of Y (the recorded directions) scaled by 1 / sqrt(gamma_c).
+__global__ __launch_bounds__(kBlock) void k_ts_scale_cols(double* __restrict__ Y, size_t ld, int n,
+                                                          const double* __restrict__ gam) {
+    const int c = blockIdx.y;
+    const double s = 1.0 / sqrt(gam[c]);
+    double* __restrict__ yc = Y + (size_t)c * ld;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) yc[i] *= s;
+}
+
+// eta_prev = [xh (m); alpha_k sqrt(gamma_k) (kr)] (coefficients of x - xbar in
+// Z = [Y, V Gamma^{-1/2}]); eta_acc = eta_prev + eta_acc / 2 (RBF weights with
+// 2^{1-i}, Section 3.3.2).
+__global__ __launch_bounds__(kBlock) void k_ts_eta(TsDev* T, int m, int kr) {
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < m + kr; e += gridDim.x * kBlock) {
+        const double prev = e < m ? T->xh[e] : T->alp3[e - m] * sqrt(T->gam3[e - m]);
+        T->eta_prev[e] = prev;
+        T->eta_acc[e] = prev + 0.5 * T->eta_acc[e];
+    }
+}
+
+// B(:, c) = Y(:, sel[c]).
+__global__ __launch_bounds__(kBlock) void k_ts_gather(const double* __restrict__ Y, size_t ld, int n,
+                                                      const int* __restrict__ sel, double* __restrict__ B) {
+    const int c = blockIdx.y;
+    const double* __restrict__ src = Y + (size_t)sel[c] * ld;
+    double* __restrict__ dst = B + (size_t)c * ld;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------- truncation
+
+// G <- diag(eta) sym(G) diag(eta), M x M.
+__global__ __launch_bounds__(kBlock) void k_ts_weight_sym(double* __restrict__ G, int M,
+                                                          const double* __restrict__ eta) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= M * M) return;
+    const int i = e / M, j = e % M;
+    if (j < i) return;
+    const double s = 0.5 * (G[i * M + j] + G[j * M + i]) * eta[i] * eta[j];
+    G[i * M + j] = s;
+    G[j * M + i] = s;
+}
+
+constexpr int kJacobiThreads = 1024;
+
+// Cyclic Jacobi eigen-decomposition of the symmetric M x M matrix A
+// (row-major, destroyed) by one workgroup: each sweep runs M - 1 rounds of
+// M / 2 disjoint rotations (round-robin pairing), applied to rows, then to
+// columns and to V; the (p, q) entry is set to zero after its rotation.
+// Sweeps stop when the off-diagonal norm is <= 1e-15 of the Frobenius norm.
+// Output: lam (descending) and, in A, the eigenvectors as columns
+// (A[k * M + c] = component k of eigenvector c) with the largest-magnitude
+// component of each positive.  V is M x M scratch.
+__global__ __launch_bounds__(kJacobiThreads) void k_ts_jacobi(double* __restrict__ A, int M,
+                                                              double* __restrict__ V,
+                                                              double* __restrict__ lam, int* info) {
+    __shared__ double cs[kTsCap / 2], sn[kTsCap / 2];
+    __shared__ int pp[kTsCap / 2], qq[kTsCap / 2];
+    __shared__ double red[2 * (kJacobiThreads / kWave) + 2];
+    __shared__ int done;
+    const int t = threadIdx.x;
+    const int nt = blockDim.x;
+    const int Mp = M + (M & 1);
+    const int npairs = Mp / 2;
+    for (int e = t; e < M * M; e += nt) V[e] = (e / M == e % M) ? 1.0 : 0.0;
+    __syncthreads();
+    int sweep = 0;
+    for (; sweep < 60; ++sweep) {
+        // convergence test on the current matrix
+        double off = 0.0, fro = 0.0;
+        for (int e = t; e < M * M; e += nt) {
+            const double v = A[e] * A[e];
+            fro += v;
+            if (e / M != e % M) off += v;
+        }
+        off = wave_sum(off);
+        fro = wave_sum(fro);
+        if ((t & (kWave - 1)) == 0) {
+            red[2 * (t / kWave)] = off;
+            red[2 * (t / kWave) + 1] = fro;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double o = 0.0, f = 0.0;
+            for (int w = 0; w < nt / kWave; ++w) {
+                o += red[2 * w];
+                f += red[2 * w + 1];
+            }
+            done = (o <= 1e-30 * f) ? 1 : 0;
+        }
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < Mp - 1; ++r) {
+            for (int i = t; i < npairs; i += nt) {
+                int a, b;
+                if (i == 0) {
+                    a = Mp - 1;
+                    b = r;
+                } else {
+                    a = (r + i) % (Mp - 1);
+                    b = (r - i + Mp - 1) % (Mp - 1);
+                }
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                if (q < M) {
+                    const double apq = A[p * M + q];
+                    if (apq != 0.0) {
+                        const double tau = (A[q * M + q] - A[p * M + p]) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                }
+                cs[i] = c;
+                sn[i] = s;
+                pp[i] = p;
+                qq[i] = q < M ? q : -1;
+            }
+            __syncthreads();
+            for (int e = t; e < npairs * M; e += nt) {      // rows p, q
+                const int i = e / M, k = e % M;
+                const int p = pp[i], q = qq[i];
+                if (q < 0 || sn[i] == 0.0) continue;
+                const double c = cs[i], s = sn[i];
+                const double apk = A[p * M + k], aqk = A[q * M + k];
+                A[p * M + k] = c * apk - s * aqk;
+                A[q * M + k] = s * apk + c * aqk;
+            }
+            __syncthreads();
+            for (int e = t; e < npairs * M; e += nt) {      // columns p, q and V
+                const int i = e / M, k = e % M;
+                const int p = pp[i], q = qq[i];
+                if (q < 0 || sn[i] == 0.0) continue;
+                const double c = cs[i], s = sn[i];
+                const double akp = A[k * M + p], akq = A[k * M + q];
+                A[k * M + p] = c * akp - s * akq;
+                A[k * M + q] = s * akp + c * akq;
+                const double vkp = V[k * M + p], vkq = V[k * M + q];
+                V[k * M + p] = c * vkp - s * vkq;
+                V[k * M + q] = s * vkp + c * vkq;
+            }
+            __syncthreads();
+            for (int i = t; i < npairs; i += nt) {
+                const int p = pp[i], q = qq[i];
+                if (q < 0 || sn[i] == 0.0) continue;
+                A[p * M + q] = 0.0;
+                A[q * M + p] = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    // eigenvalues, rank of each (descending, ties by index), sorted output
+    __shared__ int rk[kTsCap];
+    for (int i = t; i < M; i += nt) lam[i] = A[i * M + i];
+    __syncthreads();
+    for (int i = t; i < M; i += nt) {
+        const double li = lam[i];
+        int rank = 0;
+        for (int j = 0; j < M; ++j) rank += (lam[j] > li) || (lam[j] == li && j < i);
+        rk[i] = rank;
+    }
+    __syncthreads();
+    for (int e = t; e < M * M; e += nt) {               // column i of V -> column rk[i] of A
+        const int k = e / M, i = e % M;
+        A[k * M + rk[i]] = V[k * M + i];
+    }
+    __syncthreads();
+    for (int i = t; i < M; i += nt) V[i] = lam[i];      // V is free: unsorted copy
+    __syncthreads();
+    for (int i = t; i < M; i += nt) lam[rk[i]] = V[i];
+    __syncthreads();
+    for (int c = t; c < M; c += nt) {                   // sign convention
+        int kmax = 0;
+        double vmax = -1.0;
+        for (int k = 0; k < M; ++k) {
+            const double v = fabs(A[k * M + c]);
+            if (v > vmax) {
+                vmax = v;
+                kmax = k;
+            }
+        }
+        if (A[kmax * M + c] < 0.0)
+            for (int k = 0; k < M; ++k) A[k * M + c] = -A[k * M + c];
+    }
+    if (t == 0) *info = sweep;
+}
+
+// T(k, c) = eta_k V(k, c) / sqrt(lam_c), column-major M x y (a GEMM operand).
+__global__ __launch_bounds__(kBlock) void k_ts_pod_coeffs(const double* __restrict__ Vs, int M,
+                                                          const double* __restrict__ lam,
+                                                          const double* __restrict__ eta, int y,
+                                                          double* __restrict__ T) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= M * y) return;
+    const int k = e % M, c = e / M;
+    T[e] = eta[k] * Vs[k * M + c] / sqrt(lam[c]);
+}
+
+// ---------------------------------------------------------------- launchers
+
+namespace {
+int rows_grid(int n) {
+    int g = (n + kBlock - 1) / kBlock;
+    return g < 1024 ? (g < 1 ? 1 : g) : 1024;
+}
+}  // namespace
+
+hipError_t launch_gemv_n(int n, size_t ld, const double* Y, int m, const double* c, double* out,
+                         double sign, bool accumulate, hipStream_t s) {
+    if (m < 0 || m > kTsCap) return hipErrorInvalidValue;
+    if (m == 0 && accumulate) return hipSuccess;
+    hipLaunchKernelGGL(k_gemv_n, dim3(rows_grid(n)), dim3(kBlock), 0, s, n, ld, Y, m, c, out, sign,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_t(int n, size_t ld, const double* Y, int m, const double* v, double* part,
+                         double* out, hipStream_t s) {
+    if (m < 1 || m > kTsCap) return hipErrorInvalidValue;
+    int chunks = (n + 2047) / 2048;
+    if (chunks > kTsChunks) chunks = kTsChunks;
+    if (chunks < 1) chunks = 1;
+    int rows = (n + chunks - 1) / chunks;
+    rows = (rows + kWave - 1) / kWave * kWave;
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(chunks), dim3(kBlock), 0, s, n, ld, Y, m, v, part, rows);
+    hipLaunchKernelGGL(k_gemv_t_reduce, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part,
+                       chunks, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel, int w,
+                             const double* GinvW, double tau_rel, double floor_rel, int k2max,
+                             hipStream_t s) {
+    if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_s2_init, dim3(1), dim3(kBlock), 0, s, T, st, m, sel, w, GinvW, tau_rel,
+                       floor_rel, k2max);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_ts_s2_step, dim3(1), dim3(kBlock), 0, s, T, m, sel, w, GinvW);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
+                                    hipStream_t s) {
+    if (w + k2 > kYMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_ginv_blockdiag, dim3(1), dim3(kBlock), 0, s, GinvW, w, T, k2, GinvB);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_scale_cols(double* Y, size_t ld, int n, int k, const double* gam, hipStream_t s) {
+    if (k < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ts_scale_cols, dim3(rows_grid(n) < 64 ? rows_grid(n) : 64, k), dim3(kBlock), 0, s,
+                       Y, ld, n, gam);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s) {
+    if (m + kr > kTsCap) return hipErrorInvalidValue;
+    if (m + kr == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ts_eta, dim3((m + kr + kBlock - 1) / kBlock), dim3(kBlock), 0, s, T, m, kr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_gather(const double* Y, size_t ld, int n, const int* sel, int w, double* B,
+                            hipStream_t s) {
+    if (w < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ts_gather, dim3(rows_grid(n) < 64 ? rows_grid(n) : 64, w), dim3(kBlock), 0, s, Y,
+                       ld, n, sel, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t s) {
+    if (M < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ts_weight_sym, dim3((M * M + kBlock - 1) / kBlock), dim3(kBlock), 0, s, G, M, eta);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_jacobi(double* A, int M, double* V, double* lam, int* info, hipStream_t s) {
+    if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_jacobi, dim3(1), dim3(kJacobiThreads), 0, s, A, M, V, lam, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,
+                                double* T, hipStream_t s) {
+    if (y < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ts_pod_coeffs, dim3((M * y + kBlock - 1) / kBlock), dim3(kBlock), 0, s, Vs, M, lam,
+                       eta, y, T);
+    return hipGetLastError();
+}
+
+}  // namespace podcg

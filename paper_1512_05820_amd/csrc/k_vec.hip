@@ -94,10 +94,20 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 // The solution x is always FP64: with FP32 vectors (mixed precision) the
 // update x += alpha p is carried out in FP64, so the correction of a
 // refinement step is accumulated without FP32 rounding.
-template <typename T, int YB, bool INIT, bool NTB = false>
+// Directions recorded by REC (the Krylov basis V and Gamma, alpha of Alg. 1's
+// outputs): p_k goes to column k of V while k < cap, with gamma_k and alpha_k.
+struct DirRecord {
+    double* V;
+    size_t ld;
+    int cap;
+    double* gamma;
+    double* alpha;
+};
+
+template <typename T, int YB, bool INIT, bool NTB = false, bool REC = false>
 __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict__ p,
                                                 double* __restrict__ x, const T* __restrict__ z,
-                                                const T* __restrict__ W) {
+                                                const T* __restrict__ W, DirRecord rec) {
     const DevState* st = B.st;
     const int done = st->done;
     if (INIT) {
@@ -113,6 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
     for (int k = 0; k < YB; ++k) mu[k] = k < y ? (T)st->mu[k] : (T)0;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
+    // index of the direction applied in this launch (the update kernel has
+    // already counted its iteration)
+    const int krec = REC && !INIT ? st->iter - 1 : -1;
+    double* __restrict__ vrec = (REC && krec >= 0 && krec < rec.cap) ? rec.V + (size_t)krec * rec.ld : nullptr;
+    if (REC && vrec && blockIdx.x == 0 && threadIdx.x == 0) {
+        rec.gamma[krec] = st->gamma;
+        rec.alpha[krec] = alpha;
+    }
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         T s;
         if (INIT) {
@@ -120,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         } else {
             const T pi = p[i];
             x[i] += alpha * (double)pi;
+            if (REC && vrec) vrec[i] = (double)pi;
             if (!new_dir) continue;
             s = z[i] + beta * pi;
         }
@@ -249,6 +268,7 @@ __global__ void k_state_init(DevState* st, int maxit, double tol2, int y) {
     st->rr = st->rr0 = st->bnorm2 = st->true_rr = 0.0;
     st->tol2 = tol2;
     st->rho = st->alpha = st->beta = st->gamma = 0.0;
+    for (int k = 0; k < kYMax; ++k) st->mu[k] = st->what[k] = 0.0;
 }
 
 // Stage 1 of one refinement step of the mixed-precision solve.  In FP64:
@@ -360,9 +380,23 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<double, T, true, true>), g, t, 0, s, B, y, p, x, z, W); \
-        else hipLaunchKernelGGL((k_dir<double, T, false, true>), g, t, 0, s, B, y, p, x, z, W);     \
+        if (init) hipLaunchKernelGGL((k_dir<double, T, true, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{}); \
+        else hipLaunchKernelGGL((k_dir<double, T, false, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});     \
         break;
+        PODCG_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
+                          const double* W, double* V, size_t ldv, int cap, double* gamma,
+                          double* alpha, hipStream_t s) {
+    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
+    const DirRecord rec{V, ldv, cap, gamma, alpha};
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_dir<double, T, false, true, true>), g, t, 0, s, B, y, p, x, z, W, rec); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -439,8 +473,8 @@ hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, co
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<float, T, true, true>), g, t, 0, s, B, y, p, x, z, W);  \
-        else hipLaunchKernelGGL((k_dir<float, T, false, true>), g, t, 0, s, B, y, p, x, z, W);      \
+        if (init) hipLaunchKernelGGL((k_dir<float, T, true, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});  \
+        else hipLaunchKernelGGL((k_dir<float, T, false, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});      \
         break;
         PODCG_TIERS(CASE)
 #undef CASE

@@ -93,44 +93,6 @@ void setup_basis(podcg_ctx* ctx) {
 
 void record(podcg_ctx* ctx, hipEvent_t e) { HIPCHECK(hipEventRecord(e, ctx->stream)); }
 
-// Launch loop iterations in batches until the device reports that the solve
-// finished, or maxit iterations were launched.  `iter3(t, ev)` enqueues one
-// iteration (SpMV, update, direction), recording ev[0..3] around the kernels
-// when t.  The first convergence check comes after most of the previous
-// solve's iteration count (kernels after convergence are no-ops), then every
-// check_every iterations.  Returns the iteration indices that were timed.
-template <class F>
-std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
-    const int timing = ctx->opt.timing;
-    std::vector<int> timed;
-    int launched = 0;
-    ctx->h_poll->done = kRunning;   // the loop kernels are no-ops once Stage 1 has finished
-    int first = (int)(0.85 * ctx->prev_iters[slot]);
-    first = std::max(first, ctx->opt.check_every);
-    while (ctx->h_poll->done == kRunning && launched < ctx->opt.maxit) {
-        const int want = launched == 0 ? first : ctx->opt.check_every;
-        const int batch = std::min(want, ctx->opt.maxit - launched);
-        for (int k = 0; k < batch; ++k, ++launched) {
-            const bool t = timing > 0 && (launched % timing) == 0;
-            hipEvent_t* ev = nullptr;
-            if (t) {
-                const size_t base = timed.size() * 4;
-                while (ctx->tev.size() < base + 4) {
-                    hipEvent_t e;
-                    HIPCHECK(hipEventCreate(&e));
-                    ctx->tev.push_back(e);
-                }
-                timed.push_back(launched);
-                ev = &ctx->tev[base];
-            }
-            iter3(t, ev);
-        }
-        poll(ctx);
-        ++*polls;
-    }
-    return timed;
-}
-
 // Add the event-timed kernel durations of the first `iters` iterations.
 void add_timing(podcg_ctx* ctx, const std::vector<int>& timed, int iters, podcg_stats& S) {
     for (size_t k = 0; k < timed.size(); ++k) {
@@ -288,6 +250,7 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
 namespace {
 
 void release(podcg_ctx* ctx) {
+    ts_release(ctx);
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,

@@ -346,6 +346,46 @@ hipError_t launch_batch_dir(int yb, const BatchMember* mem, const BatchItem* ite
                             int grid, hipStream_t s);
 hipError_t launch_batch_gather(const BatchMember* mem, int count, PollBlock* out, hipStream_t s);
 
+// ------------------------------------------------------------ three stages
+constexpr int kTsCap = 512;      // largest accumulated basis (columns of Y / Z)
+constexpr int kTsChunks = 256;   // row chunks of the tall transposed products
+
+// Device state of the three-stage method: the reduced vectors of Stage 2,
+// the recorded Stage-3 scalars and the POD weights of the accumulated vectors.
+struct TsDev {
+    double xh[kTsCap], rh[kTsCap], ph[kTsCap], gh[kTsCap];
+    double wtgy[kYMax * kTsCap];   // (A W)^T Y, w x m row-major
+    double alp2[kYMax], gam2[kYMax];
+    double rz2, rn0, rn, tau;
+    int k2, done2, k2max, pad;
+    double gam3[kTsCap], alp3[kTsCap];
+    double eta_prev[kTsCap], eta_acc[kTsCap];
+};
+
+hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
+                          const double* W, double* V, size_t ldv, int cap, double* gamma,
+                          double* alpha, hipStream_t s);
+hipError_t launch_gemv_n(int n, size_t ld, const double* Y, int m, const double* c, double* out,
+                         double sign, bool accumulate, hipStream_t s);
+// out = Y^T v through kTsChunks row chunks (part: kTsChunks x m scratch).
+hipError_t launch_gemv_t(int n, size_t ld, const double* Y, int m, const double* v, double* part,
+                         double* out, hipStream_t s);
+hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel, int w,
+                             const double* GinvW, double tau_rel, double floor_rel, int k2max,
+                             hipStream_t s);
+hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW,
+                             hipStream_t s);
+hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
+                                    hipStream_t s);
+hipError_t launch_ts_scale_cols(double* Y, size_t ld, int n, int k, const double* gam, hipStream_t s);
+hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s);
+hipError_t launch_ts_gather(const double* Y, size_t ld, int n, const int* sel, int w, double* B,
+                            hipStream_t s);
+hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t s);
+hipError_t launch_ts_jacobi(double* A, int M, double* V, double* lam, int* info, hipStream_t s);
+hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,
+                                double* T, hipStream_t s);
+
 // Single-workgroup dense kernels (k_small.hip)
 // G (m x m row-major, symmetrised here) -> R, Ginv = G^{-1} on the accepted
 // leading block, kept rank written to st->y, eigenvalues of G to lam (cond).

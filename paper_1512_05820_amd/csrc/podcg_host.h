@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,10 @@ struct Fail {
 };
 
 }  // namespace podcg_host
+
+namespace podcg_host {
+struct TsHost;   // three-stage state (podcg_three.hip)
+}
 
 struct podcg_ctx {
     int64_t n = 0;
@@ -70,6 +75,8 @@ struct podcg_ctx {
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
     std::vector<hipEvent_t> tev;     // per-iteration kernel timing events
     int prev_iters[2] = {0, 0};      // iterations of the last augmented / plain solve
+
+    podcg_host::TsHost* ts = nullptr;    // three-stage mode, when enabled
 
     std::string last_error;
 };
@@ -124,5 +131,45 @@ void poll(podcg_ctx* ctx);
 // A W, G = W^T A W, its factor and inverse, the kept rank (synchronises).
 void setup_basis(podcg_ctx* ctx);
 int fail_code(podcg_ctx* ctx, const podcg::PollBlock& P);
+void record(podcg_ctx* ctx, hipEvent_t e);
+// Launch loop iterations in batches until the device reports that the solve
+// finished, or maxit iterations were launched.  `iter3(t, ev)` enqueues one
+// iteration (SpMV, update, direction), recording ev[0..3] around the kernels
+// when t.  The first convergence check comes after most of the previous
+// solve's iteration count (kernels after convergence are no-ops), then every
+// check_every iterations.  Returns the iteration indices that were timed.
+template <class F>
+std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
+    const int timing = ctx->opt.timing;
+    std::vector<int> timed;
+    int launched = 0;
+    ctx->h_poll->done = podcg::kRunning;   // the loop kernels are no-ops once Stage 1 has finished
+    int first = (int)(0.85 * ctx->prev_iters[slot]);
+    first = std::max(first, ctx->opt.check_every);
+    while (ctx->h_poll->done == podcg::kRunning && launched < ctx->opt.maxit) {
+        const int want = launched == 0 ? first : ctx->opt.check_every;
+        const int batch = std::min(want, ctx->opt.maxit - launched);
+        for (int k = 0; k < batch; ++k, ++launched) {
+            const bool t = timing > 0 && (launched % timing) == 0;
+            hipEvent_t* ev = nullptr;
+            if (t) {
+                const size_t base = timed.size() * 4;
+                while (ctx->tev.size() < base + 4) {
+                    hipEvent_t e;
+                    HIPCHECK(hipEventCreate(&e));
+                    ctx->tev.push_back(e);
+                }
+                timed.push_back(launched);
+                ev = &ctx->tev[base];
+            }
+            iter3(t, ev);
+        }
+        poll(ctx);
+        ++*polls;
+    }
+    return timed;
+}
+
+void ts_release(podcg_ctx* ctx);
 
 }  // namespace podcg_host

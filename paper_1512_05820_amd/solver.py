@@ -148,6 +148,46 @@ class PodCG:
                                                 _ptr(out, torch.float64)))
         return out
 
+    # ------------------------------------------------------- three-stage method
+    def ts_enable(self, **kw) -> dict:
+        """Three-stage mode (Alg. 3); keyword options as in podcg_ts_options."""
+        opt = L.TsOptions()
+        self._L.podcg_ts_default_options(C.byref(opt))
+        for k, v in kw.items():
+            if k in ("weights",) and isinstance(v, str):
+                v = {"rbf": 0, "previous": 1}[v]
+            if k in ("stage3_gram",) and isinstance(v, str):
+                v = {"blockdiag": 0, "exact": 1}[v]
+            setattr(opt, k, v)
+        self._check(self._L.podcg_ts_enable(self._h, C.byref(opt)))
+        return opt.as_dict()
+
+    def ts_solve(self, b: torch.Tensor, x: torch.Tensor, rtol: float) -> L.TsStats:
+        st = L.TsStats()
+        self._check(self._L.podcg_ts_solve(self._h, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                           float(rtol), C.byref(st)))
+        return st
+
+    def ts_state(self):
+        """(Y (n, m) tensor, stage-1 column list)."""
+        m, w = C.c_int32(), C.c_int32()
+        self._check(self._L.podcg_ts_get_state(self._h, None, C.byref(m), None, C.byref(w)))
+        Y = torch.empty((max(m.value, 1), self.n), dtype=torch.float64, device="cuda")
+        sel = (C.c_int32 * max(w.value, 1))()
+        self._check(self._L.podcg_ts_get_state(self._h, _ptr(Y, torch.float64), C.byref(m), sel,
+                                               C.byref(w)))
+        return Y[:m.value].T, [sel[i] for i in range(w.value)]
+
+    def ts_set_state(self, Y: torch.Tensor | None, sel, eta_acc=None):
+        m = 0 if Y is None else Y.shape[1]
+        Yc = None if Y is None else Y.T.contiguous()
+        arr = (C.c_int32 * max(len(sel), 1))(*sel)
+        eta = None
+        if eta_acc is not None:
+            eta = (C.c_double * m)(*[float(v) for v in eta_acc])
+        self._check(self._L.podcg_ts_set_state(self._h, None if Yc is None else _ptr(Yc, torch.float64),
+                                               m, arr, len(sel), eta))
+
     def stream_triad(self, a, b, c, s: float = 3.0, reps: int = 20) -> float:
         ms = C.c_double()
         self._check(self._L.podcg_stream_triad(self._h, _ptr(a, torch.float64),
