@@ -298,6 +298,86 @@ def bench_config4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_three_stage(args):
+    """The paper's full three-stage method (Alg. 3, non-iterative Stage 3) on the
+    3-D diffusion sequence, next to the POD-of-solutions augmented PCG and plain
+    PCG on the same systems.  Variants: ybar 200, POD to 100 vectors, stage-1
+    basis 5, rho 0 (the POD(5,95) family), with the reused block-diagonal factor
+    and with the computed Gram of [W, X] in Stage 3."""
+    import torch
+    import paper_1512_05820_amd as P
+    from problems import config2
+
+    torch.cuda.set_device(0)
+    cfg = config2(N=args.N, steps=args.systems)
+    vals_dev = [torch.from_numpy(cfg.matrix_values(j)).cuda() for j in range(1, cfg.steps + 1)]
+    rowptr = torch.from_numpy(cfg.rowptr).cuda()
+    colind = torch.from_numpy(cfg.colind).cuda()
+    ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000)
+    ctx.set_matrix(vals_dev[0], rowptr, colind)
+    runs = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t1), out
+
+    ms, st = timed(lambda: run_sequence(torch, ctx, cfg, vals_dev, "aug"))
+    runs["pod_of_solutions"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
+    log("pod_of_solutions", runs["pod_of_solutions"])
+    if not args.no_plain:
+        ms, st = timed(lambda: run_sequence(torch, ctx, cfg, vals_dev, "plain", warm=True))
+        runs["plain_warm"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
+        log("plain_warm", runs["plain_warm"])
+
+    def three_stage(gram):
+        ctx.ts_enable(ybar=200, y_trunc=100, w_max=5, w_cap=16, stage2_maxit=24, rho=0.0,
+                      stage2_factor=1e-4, stage3_gram=gram)
+        src = torch.full((cfg.n,), cfg.source, dtype=torch.float64, device="cuda")
+        x_prev = torch.zeros(cfg.n, dtype=torch.float64, device="cuda")
+        sts = []
+        for j in range(1, cfg.steps + 1):
+            ctx.set_matrix(vals_dev[j - 1])
+            b = torch.add(src, x_prev, alpha=1.0 / cfg.dt) if j > 1 else src.clone()
+            x = torch.zeros(cfg.n, dtype=torch.float64, device="cuda")
+            S = ctx.ts_solve(b, x, cfg.tol)
+            if S.status != 0:
+                raise RuntimeError(f"three-stage system {j}: status {S.status}")
+            sts.append(S.as_dict())
+            x_prev = x
+        return sts
+
+    for gram in ("blockdiag", "exact"):
+        ms, sts = timed(lambda: three_stage(gram))
+        runs[f"three_stage_{gram}"] = {
+            "ms": round(ms, 1),
+            "stage3_iters": sum(s["k3"] for s in sts),
+            "stage2_steps": sum(s["k2"] for s in sts),
+            "matvecs": sum(s["matvecs"] for s in sts),
+            "truncations": sum(s["truncated"] for s in sts),
+            "stage12_ms": round(sum(s["stage12_ms"] for s in sts), 1),
+            "stage3_ms": round(sum(s["stage3_ms"] for s in sts), 1),
+            "accumulate_truncate_ms": round(sum(s["accum_ms"] for s in sts), 1),
+            "max_jacobi_sweeps": max(s["jacobi_sweeps"] for s in sts),
+            "max_true_relres": max(s["true_relres"] for s in sts),
+            "k3_per_system": [s["k3"] for s in sts],
+            "m_per_system": [s["m"] for s in sts],
+        }
+        log(f"three_stage_{gram}", {k: v for k, v in runs[f"three_stage_{gram}"].items()
+                                    if not k.endswith("per_system")})
+    v = runs["three_stage_blockdiag"]["ms"]
+    out = {"metric": METRIC, "value": v, "unit": "ms/sequence", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": v, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "three_stage_" + cfg.name, "N": cfg.N, "n": cfg.n, "nnz": cfg.nnz,
+                      "systems": cfg.steps, "rel_tol": cfg.tol, "ybar": 200, "y_trunc": 100, "w_max": 5,
+                      "rho": 0.0, "stage2_factor": 1e-4},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def bench_config5(args):
     """Differentiation at the stated size: 96^3 diffusion, 200 systems, outputs at
     256 dofs, gradients of J = sum_j w_j . q_j with respect to log kappa and the
@@ -377,9 +457,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--adjoint-basis", default="forward", choices=["forward", "adjoint", "none"],
                     help="config5: basis of the adjoint solves")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "three_stage"],
                     help="config2 (default, the headline), config3 (mixed precision), "
-                         "config4 (batched sequences) or config5 (adjoint gradients)")
+                         "config4 (batched sequences), config5 (adjoint gradients) or three_stage "
+                         "(the full method of Alg. 3 on the config-2 sequence)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -393,6 +474,9 @@ def main():
         return
     if args.workload == "config5":
         bench_config5(args)
+        return
+    if args.workload == "three_stage":
+        bench_three_stage(args)
         return
 
     import torch

@@ -221,132 +221,157 @@ __global__ __launch_bounds__(kBlock) void k_ts_weight_sym(double* __restrict__ G
 constexpr int kJacobiThreads = 1024;
 
 // Cyclic Jacobi eigen-decomposition of the symmetric M x M matrix A
-// (row-major, destroyed) by one workgroup: each sweep runs M - 1 rounds of
-// M / 2 disjoint rotations (round-robin pairing), applied to rows, then to
-// columns and to V; the (p, q) entry is set to zero after its rotation.
-// Sweeps stop when the off-diagonal norm is <= 1e-15 of the Frobenius norm.
-// Output: lam (descending) and, in A, the eigenvectors as columns
-// (A[k * M + c] = component k of eigenvector c) with the largest-magnitude
-// component of each positive.  V is M x M scratch.
-__global__ __launch_bounds__(kJacobiThreads) void k_ts_jacobi(double* __restrict__ A, int M,
-                                                              double* __restrict__ V,
-                                                              double* __restrict__ lam, int* info) {
-    __shared__ double cs[kTsCap / 2], sn[kTsCap / 2];
-    __shared__ int pp[kTsCap / 2], qq[kTsCap / 2];
-    __shared__ double red[2 * (kJacobiThreads / kWave) + 2];
-    __shared__ int done;
-    const int t = threadIdx.x;
-    const int nt = blockDim.x;
+// (row-major), spread over the whole GPU: each sweep runs Mp - 1 rounds
+// (Mp = M rounded up to even) of Mp / 2 disjoint rotations in round-robin
+// pairing; a round is three launches -- the rotations (one workgroup, which
+// also sets the previous round's (p, q) entries to zero), the row update
+// and the column update of A and V.  J holds the round's rotations:
+// J[i] = {c, s} and the pair indices in Jp.
+
+__device__ __forceinline__ void jac_pair(int i, int r, int Mp, int& p, int& q) {
+    int a, b;
+    if (i == 0) {
+        a = Mp - 1;
+        b = r;
+    } else {
+        a = (r + i) % (Mp - 1);
+        b = (r - i + Mp - 1) % (Mp - 1);
+    }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_jac_rot(double* __restrict__ A, int M, int r,
+                                                    double* __restrict__ J, int* __restrict__ Jp) {
     const int Mp = M + (M & 1);
-    const int npairs = Mp / 2;
-    for (int e = t; e < M * M; e += nt) V[e] = (e / M == e % M) ? 1.0 : 0.0;
-    __syncthreads();
-    int sweep = 0;
-    for (; sweep < 60; ++sweep) {
-        // convergence test on the current matrix
-        double off = 0.0, fro = 0.0;
-        for (int e = t; e < M * M; e += nt) {
-            const double v = A[e] * A[e];
-            fro += v;
-            if (e / M != e % M) off += v;
-        }
-        off = wave_sum(off);
-        fro = wave_sum(fro);
-        if ((t & (kWave - 1)) == 0) {
-            red[2 * (t / kWave)] = off;
-            red[2 * (t / kWave) + 1] = fro;
-        }
-        __syncthreads();
-        if (t == 0) {
-            double o = 0.0, f = 0.0;
-            for (int w = 0; w < nt / kWave; ++w) {
-                o += red[2 * w];
-                f += red[2 * w + 1];
-            }
-            done = (o <= 1e-30 * f) ? 1 : 0;
-        }
-        __syncthreads();
-        if (done) break;
-        for (int r = 0; r < Mp - 1; ++r) {
-            for (int i = t; i < npairs; i += nt) {
-                int a, b;
-                if (i == 0) {
-                    a = Mp - 1;
-                    b = r;
-                } else {
-                    a = (r + i) % (Mp - 1);
-                    b = (r - i + Mp - 1) % (Mp - 1);
-                }
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
-                if (q < M) {
-                    const double apq = A[p * M + q];
-                    if (apq != 0.0) {
-                        const double tau = (A[q * M + q] - A[p * M + p]) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
-                }
-                cs[i] = c;
-                sn[i] = s;
-                pp[i] = p;
-                qq[i] = q < M ? q : -1;
-            }
-            __syncthreads();
-            for (int e = t; e < npairs * M; e += nt) {      // rows p, q
-                const int i = e / M, k = e % M;
-                const int p = pp[i], q = qq[i];
-                if (q < 0 || sn[i] == 0.0) continue;
-                const double c = cs[i], s = sn[i];
-                const double apk = A[p * M + k], aqk = A[q * M + k];
-                A[p * M + k] = c * apk - s * aqk;
-                A[q * M + k] = s * apk + c * aqk;
-            }
-            __syncthreads();
-            for (int e = t; e < npairs * M; e += nt) {      // columns p, q and V
-                const int i = e / M, k = e % M;
-                const int p = pp[i], q = qq[i];
-                if (q < 0 || sn[i] == 0.0) continue;
-                const double c = cs[i], s = sn[i];
-                const double akp = A[k * M + p], akq = A[k * M + q];
-                A[k * M + p] = c * akp - s * akq;
-                A[k * M + q] = s * akp + c * akq;
-                const double vkp = V[k * M + p], vkq = V[k * M + q];
-                V[k * M + p] = c * vkp - s * vkq;
-                V[k * M + q] = s * vkp + c * vkq;
-            }
-            __syncthreads();
-            for (int i = t; i < npairs; i += nt) {
-                const int p = pp[i], q = qq[i];
-                if (q < 0 || sn[i] == 0.0) continue;
-                A[p * M + q] = 0.0;
-                A[q * M + p] = 0.0;
-            }
-            __syncthreads();
+    for (int i = threadIdx.x; i < Mp / 2; i += kBlock) {
+        const int pp = Jp[2 * i], qq = Jp[2 * i + 1];     // previous round
+        if (qq >= 0 && J[2 * i + 1] != 0.0) {
+            A[pp * M + qq] = 0.0;
+            A[qq * M + pp] = 0.0;
         }
     }
-    // eigenvalues, rank of each (descending, ties by index), sorted output
+    __syncthreads();
+    if (r < 0) return;                                    // final clean-up only
+    for (int i = threadIdx.x; i < Mp / 2; i += kBlock) {
+        int p, q;
+        jac_pair(i, r, Mp, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < M) {
+            const double apq = A[p * M + q];
+            if (apq != 0.0) {
+                const double tau = (A[q * M + q] - A[p * M + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                c = 1.0 / sqrt(1.0 + t * t);
+                s = t * c;
+            }
+        }
+        J[2 * i] = c;
+        J[2 * i + 1] = s;
+        Jp[2 * i] = p;
+        Jp[2 * i + 1] = q < M ? q : -1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_jac_rows(double* __restrict__ A, int M,
+                                                     const double* __restrict__ J, const int* __restrict__ Jp) {
+    const int np = (M + (M & 1)) / 2;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < np * M; e += gridDim.x * kBlock) {
+        const int i = e / M, k = e % M;
+        const int p = Jp[2 * i], q = Jp[2 * i + 1];
+        const double s = J[2 * i + 1];
+        if (q < 0 || s == 0.0) continue;
+        const double c = J[2 * i];
+        const double apk = A[p * M + k], aqk = A[q * M + k];
+        A[p * M + k] = c * apk - s * aqk;
+        A[q * M + k] = s * apk + c * aqk;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_jac_cols(double* __restrict__ A, double* __restrict__ V, int M,
+                                                     const double* __restrict__ J, const int* __restrict__ Jp) {
+    const int np = (M + (M & 1)) / 2;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < np * M; e += gridDim.x * kBlock) {
+        const int k = e / np, i = e % np;      // consecutive threads: different pairs of row k
+        const int p = Jp[2 * i], q = Jp[2 * i + 1];
+        const double s = J[2 * i + 1];
+        if (q < 0 || s == 0.0) continue;
+        const double c = J[2 * i];
+        const double akp = A[k * M + p], akq = A[k * M + q];
+        A[k * M + p] = c * akp - s * akq;
+        A[k * M + q] = s * akp + c * akq;
+        const double vkp = V[k * M + p], vkq = V[k * M + q];
+        V[k * M + p] = c * vkp - s * vkq;
+        V[k * M + q] = s * vkp + c * vkq;
+    }
+}
+
+// V = I; Jp = -1 (no previous round).
+__global__ __launch_bounds__(kBlock) void k_jac_init(double* __restrict__ V, int M, double* __restrict__ J,
+                                                     int* __restrict__ Jp) {
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < M * M; e += gridDim.x * kBlock)
+        V[e] = (e / M == e % M) ? 1.0 : 0.0;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < kTsCap; e += gridDim.x * kBlock) {
+        Jp[e] = -1;
+        J[e] = 0.0;
+    }
+}
+
+// off = sum of squared off-diagonal entries, fro = all; flag = off <= 1e-30 fro
+// (off-diagonal norm <= 1e-15 of the Frobenius norm).  One workgroup.
+__global__ __launch_bounds__(kJacobiThreads) void k_jac_offnorm(const double* __restrict__ A, int M,
+                                                                int* __restrict__ flag) {
+    __shared__ double red[2 * (kJacobiThreads / kWave)];
+    const int t = threadIdx.x;
+    double off = 0.0, fro = 0.0;
+    for (int e = t; e < M * M; e += kJacobiThreads) {
+        const double v = A[e] * A[e];
+        fro += v;
+        if (e / M != e % M) off += v;
+    }
+    off = wave_sum(off);
+    fro = wave_sum(fro);
+    if ((t & (kWave - 1)) == 0) {
+        red[2 * (t / kWave)] = off;
+        red[2 * (t / kWave) + 1] = fro;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double o = 0.0, f = 0.0;
+        for (int w = 0; w < kJacobiThreads / kWave; ++w) {
+            o += red[2 * w];
+            f += red[2 * w + 1];
+        }
+        *flag = (o <= 1e-30 * f) ? 1 : 0;
+    }
+}
+
+// Eigenvalues (diagonal of A) sorted descending (ties by index) into lam; the
+// eigenvectors (columns of V) in the same order into A (A[k * M + c] =
+// component k of eigenvector c) with the largest-magnitude component of each
+// positive.  One workgroup.
+__global__ __launch_bounds__(kJacobiThreads) void k_jac_finish(double* __restrict__ A, int M,
+                                                               double* __restrict__ V,
+                                                               double* __restrict__ lam) {
     __shared__ int rk[kTsCap];
-    for (int i = t; i < M; i += nt) lam[i] = A[i * M + i];
+    __shared__ double d[kTsCap];
+    const int t = threadIdx.x, nt = kJacobiThreads;
+    for (int i = t; i < M; i += nt) d[i] = A[i * M + i];
     __syncthreads();
     for (int i = t; i < M; i += nt) {
-        const double li = lam[i];
+        const double li = d[i];
         int rank = 0;
-        for (int j = 0; j < M; ++j) rank += (lam[j] > li) || (lam[j] == li && j < i);
+        for (int j = 0; j < M; ++j) rank += (d[j] > li) || (d[j] == li && j < i);
         rk[i] = rank;
+        lam[rank] = li;
     }
     __syncthreads();
-    for (int e = t; e < M * M; e += nt) {               // column i of V -> column rk[i] of A
+    for (int e = t; e < M * M; e += nt) {
         const int k = e / M, i = e % M;
         A[k * M + rk[i]] = V[k * M + i];
     }
     __syncthreads();
-    for (int i = t; i < M; i += nt) V[i] = lam[i];      // V is free: unsorted copy
-    __syncthreads();
-    for (int i = t; i < M; i += nt) lam[rk[i]] = V[i];
-    __syncthreads();
-    for (int c = t; c < M; c += nt) {                   // sign convention
+    for (int c = t; c < M; c += nt) {
         int kmax = 0;
         double vmax = -1.0;
         for (int k = 0; k < M; ++k) {
@@ -359,7 +384,6 @@ __global__ __launch_bounds__(kJacobiThreads) void k_ts_jacobi(double* __restrict
         if (A[kmax * M + c] < 0.0)
             for (int k = 0; k < M; ++k) A[k * M + c] = -A[k * M + c];
     }
-    if (t == 0) *info = sweep;
 }
 
 // T(k, c) = eta_k V(k, c) / sqrt(lam_c), column-major M x y (a GEMM operand).
@@ -455,9 +479,35 @@ hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_ts_jacobi(double* A, int M, double* V, double* lam, int* info, hipStream_t s) {
+hipError_t launch_ts_jacobi_init(double* V, int M, double* J, int* Jp, hipStream_t s) {
     if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ts_jacobi, dim3(1), dim3(kJacobiThreads), 0, s, A, M, V, lam, info);
+    hipLaunchKernelGGL(k_jac_init, dim3(rows_grid(M * M)), dim3(kBlock), 0, s, V, M, J, Jp);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_jacobi_sweep(double* A, double* V, int M, double* J, int* Jp, int* flag,
+                                  hipStream_t s) {
+    if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
+    const int Mp = M + (M & 1);
+    const int g = rows_grid((Mp / 2) * M);
+    for (int r = 0; r < Mp - 1; ++r) {
+        hipLaunchKernelGGL(k_jac_rot, dim3(1), dim3(kBlock), 0, s, A, M, r, J, Jp);
+        hipLaunchKernelGGL(k_jac_rows, dim3(g), dim3(kBlock), 0, s, A, M, (const double*)J, (const int*)Jp);
+        hipLaunchKernelGGL(k_jac_cols, dim3(g), dim3(kBlock), 0, s, A, V, M, (const double*)J, (const int*)Jp);
+    }
+    hipLaunchKernelGGL(k_jac_rot, dim3(1), dim3(kBlock), 0, s, A, M, -1, J, Jp);   // last zeroing
+    hipLaunchKernelGGL(k_jac_offnorm, dim3(1), dim3(kJacobiThreads), 0, s, (const double*)A, M, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_jacobi_offnorm(const double* A, int M, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_jac_offnorm, dim3(1), dim3(kJacobiThreads), 0, s, A, M, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_jacobi_finish(double* A, int M, double* V, double* lam, hipStream_t s) {
+    if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jac_finish, dim3(1), dim3(kJacobiThreads), 0, s, A, M, V, lam);
     return hipGetLastError();
 }
 

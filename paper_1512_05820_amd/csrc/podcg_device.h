@@ -382,7 +382,14 @@ hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s);
 hipError_t launch_ts_gather(const double* Y, size_t ld, int n, const int* sel, int w, double* B,
                             hipStream_t s);
 hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t s);
-hipError_t launch_ts_jacobi(double* A, int M, double* V, double* lam, int* info, hipStream_t s);
+// Cyclic Jacobi eigen-solver of a symmetric M x M matrix (row-major, in place):
+// init (V = I), sweeps (each ends with the convergence flag), finish (sorted
+// eigenvalues, eigenvectors as columns of A).  J, Jp: kTsCap scratch each.
+hipError_t launch_ts_jacobi_init(double* V, int M, double* J, int* Jp, hipStream_t s);
+hipError_t launch_ts_jacobi_sweep(double* A, double* V, int M, double* J, int* Jp, int* flag,
+                                  hipStream_t s);
+hipError_t launch_ts_jacobi_offnorm(const double* A, int M, int* flag, hipStream_t s);
+hipError_t launch_ts_jacobi_finish(double* A, int M, double* V, double* lam, hipStream_t s);
 hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,
                                 double* T, hipStream_t s);
 

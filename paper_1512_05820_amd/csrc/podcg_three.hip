@@ -41,6 +41,8 @@ struct TsHost {
     double *d_lamG = nullptr, *d_Gbig = nullptr, *d_Vbig = nullptr, *d_lam = nullptr, *d_T = nullptr;
     int* d_sel = nullptr;
     int* d_info = nullptr;
+    double* d_J = nullptr;       // Jacobi rotations of one round
+    int* d_Jp = nullptr;
     TsDev* d_ts = nullptr;
     double* h_dbl = nullptr;     // pinned, kTsCap + 8
     int* h_int = nullptr;        // pinned, kYMax + 8
@@ -52,7 +54,8 @@ void ts_release(podcg_ctx* ctx) {
     TsHost* T = ctx->ts;
     if (!T) return;
     void* dev[] = {T->d_Y, T->d_AZ, T->d_B, T->d_AB, T->d_part, T->d_G, T->d_R, T->d_GinvW, T->d_GinvB,
-                   T->d_lamG, T->d_Gbig, T->d_Vbig, T->d_lam, T->d_T, T->d_sel, T->d_info, T->d_ts};
+                   T->d_lamG, T->d_Gbig, T->d_Vbig, T->d_lam, T->d_T, T->d_sel, T->d_info, T->d_ts,
+                   T->d_J, T->d_Jp};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (T->h_dbl) (void)hipHostFree(T->h_dbl);
@@ -69,6 +72,7 @@ void ts_release(podcg_ctx* ctx) {
 namespace {
 
 constexpr double kStage2Floor = 1e-6;   // stage-2 tolerance floor, relative to ||Y^T r||
+constexpr int kJacobiMaxSweeps = 60;
 
 #define BLASCHECK(expr)                                                                             \
     do {                                                                                            \
@@ -124,12 +128,22 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
                             T->d_Y, (int)ld, T->d_AZ, (int)ld, &zero, T->d_Gbig, M));
     const double* eta = T->opt.weights == 0 ? TSF(T, eta_acc) : TSF(T, eta_prev);
     HIPCHECK(launch_ts_weight_sym(T->d_Gbig, M, eta, s));
-    HIPCHECK(launch_ts_jacobi(T->d_Gbig, M, T->d_Vbig, T->d_lam, T->d_info, s));
+    // Jacobi sweeps until the off-diagonal norm is <= 1e-15 of the Frobenius norm
+    HIPCHECK(launch_ts_jacobi_init(T->d_Vbig, M, T->d_J, T->d_Jp, s));
+    HIPCHECK(launch_ts_jacobi_offnorm(T->d_Gbig, M, T->d_info, s));
+    int sweeps = 0;
+    for (;;) {
+        HIPCHECK(hipMemcpyAsync(T->h_int, T->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (T->h_int[0] || sweeps >= kJacobiMaxSweeps) break;
+        HIPCHECK(launch_ts_jacobi_sweep(T->d_Gbig, T->d_Vbig, M, T->d_J, T->d_Jp, T->d_info, s));
+        ++sweeps;
+    }
+    HIPCHECK(launch_ts_jacobi_finish(T->d_Gbig, M, T->d_Vbig, T->d_lam, s));
     HIPCHECK(hipMemcpyAsync(T->h_dbl, T->d_lam, sizeof(double) * M, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(T->h_int, T->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     const double* lam = T->h_dbl;
-    S.jacobi_sweeps = T->h_int[0];
+    S.jacobi_sweeps = sweeps;
     int y = 0;
     if (lam[0] > 0.0)
         for (int i = 0; i < M; ++i)
@@ -358,6 +372,8 @@ int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
         dalloc(ctx, &T->d_T, (size_t)kTsCap * kTsCap);
         dalloc(ctx, &T->d_sel, kYMax);
         dalloc(ctx, &T->d_info, 4);
+        dalloc(ctx, &T->d_J, kTsCap);
+        dalloc(ctx, &T->d_Jp, kTsCap);
         dalloc(ctx, &T->d_ts, 1);
         HIPCHECK(hipMemsetAsync(T->d_Y, 0, sizeof(double) * ld * (size_t)o.cap, s));
         HIPCHECK(hipMemsetAsync(T->d_AZ, 0, sizeof(double) * ld * (size_t)o.cap, s));

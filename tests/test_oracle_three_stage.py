@@ -200,6 +200,20 @@ def test_three_stage_oracle_pins(pin):
     pin(TS)
 
 
+def test_e6_reduced_matrix_is_scaled_identity_after_truncation():
+    """Synthetic rerun of the paper's reduced-matrix diagnostic: with
+    A_j = (1 + 0.01 j) A_0, a basis truncated with the metric A_{j-1} gives
+    Y_j^T A_j Y_j = (1 + 0.01 j) / (1 + 0.01 (j - 1)) I, condition number 1."""
+    cfg = Config4Member(16, 1030, 1031, 7, 5, 4, 1e-8)
+    opt = TS.TSOptions(ybar=30, y_trunc=10, w_max=3, stage2_maxit=10)
+    out = TS.run_three_stage(cfg, opt)
+    after = [o for prev, o in zip(out, out[1:]) if prev["truncated"]]
+    assert after
+    for o in after:
+        print(f"j={o['j']} m={o['m']} cond(Y^T A Y) = {o['cond_YAY']:.12f}")
+        assert abs(o["cond_YAY"] - 1.0) <= 1e-9
+
+
 def test_three_stage_sequence_with_truncations_meets_tolerance():
     cfg = Config4Member(20, 1012, 1013, 6, 5, 4, 1e-8)
     opt = TS.TSOptions(ybar=40, y_trunc=12, w_max=4, rho=1e-3, stage2_maxit=20)
