@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __rest
         double* __restrict__ q = M.q;
         double g[1] = {0.0};
         for (int s = it.begin + wid; s < it.end; s += kWavesPerBlock) {
-            const double acc = sell_row<double>(M.B.sptr, M.B.cols, M.B.vals, s, lane, p);
+            const double acc = sell_row<double>(M.B, M.B.vals, s, lane, p);
             const int row = s * kSlice + lane;
             if (row < M.B.n) {
                 q[row] = acc;

@@ -100,6 +100,32 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(int n, int nslices,
     }
 }
 
+// One wave per slice: 16-bit column offsets when they all fit (rows < n);
+// padding rows (>= n) store 0 and gather entry 0.
+__global__ __launch_bounds__(kBlock) void k_fill_offsets16(int n, int nslices, const int64_t* __restrict__ sptr,
+                                                           const int* __restrict__ cols,
+                                                           int16_t* __restrict__ cols16,
+                                                           uint8_t* __restrict__ sflag) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int s = blockIdx.x * kWavesPerBlock + wid; s < nslices; s += gridDim.x * kWavesPerBlock) {
+        const int64_t base = sptr[s];
+        const int w = (int)((sptr[s + 1] - base) / kSlice);
+        const int row = s * kSlice + lane;
+        bool fits = true;
+        for (int j = 0; j < w; ++j) {
+            const int d = cols[base + (int64_t)j * kSlice + lane] - row;
+            if (row < n && (d > 32767 || d < -32767)) fits = false;
+        }
+        const bool all = __all(fits);
+        if (all)
+            for (int j = 0; j < w; ++j) {
+                const int64_t slot = base + (int64_t)j * kSlice + lane;
+                cols16[slot] = row < n ? (int16_t)(cols[slot] - row) : (int16_t)0;
+            }
+        if (lane == 0) sflag[s] = all ? 1 : 0;
+    }
+}
+
 // SELL values from CSR values, and dinv = 1 / (sum of the diagonal entries).
 // flag |= 4: a diagonal entry missing or not positive; |= 8: non-finite value.
 __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
@@ -185,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double acc = sell_row<T>(B.sptr, B.cols, mat_vals<T>(B), s, lane, p);
+            const double acc = sell_row<T>(B, mat_vals<T>(B), s, lane, p);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 const T qv = (T)acc;
@@ -214,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_matvec(DevBufs B, const double* __re
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double acc = sell_row<double>(B.sptr, B.cols, B.vals, s, lane, x);
+            const double acc = sell_row<double>(B, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) y[row] = acc;
         }
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
     for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
         if (s < B.nslices) {
-            const double ax = sell_row<double>(B.sptr, B.cols, B.vals, s, lane, x);
+            const double ax = sell_row<double>(B, B.vals, s, lane, x);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 const double bi = b[row];
@@ -419,9 +445,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
 
 // ---------------------------------------------------------------- launchers
 
-static int grid_for_slices(int nslices) {
+static int grid_for_slices(int nslices, int cap = kSpmvGrid) {
     const int groups = (nslices + kWavesPerBlock - 1) / kWavesPerBlock;
-    return groups < kSpmvGrid ? groups : kSpmvGrid;
+    if (cap <= 0) cap = kSpmvGrid;
+    return groups < cap ? groups : cap;
 }
 
 static int grid_for(int64_t items, int cap) {
@@ -455,6 +482,13 @@ hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const 
     return hipGetLastError();
 }
 
+hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const int* cols, int16_t* cols16,
+                                 uint8_t* sflag, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_offsets16, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock), 0, s, n,
+                       nslices, sptr, cols, cols16, sflag);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
                               const int* map, const double* csr_vals, double* vals, double* dinv,
                               int* flag, hipStream_t s) {
@@ -472,13 +506,13 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
 }
 
 hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B,
+    hipLaunchKernelGGL((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), 0, s, B,
                        p, q);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices)), dim3(kBlock), 0, s, B,
+    hipLaunchKernelGGL((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), 0, s, B,
                        p, q);
     return hipGetLastError();
 }

@@ -357,6 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ 
 // ---------------------------------------------------------------- launchers
 
 static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
+    if (cap <= 0) cap = kVecBlocksMax;
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
     return (int)(g < cap ? g : cap);
@@ -364,7 +365,7 @@ static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
 
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
                          const double* AW, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_update<double, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
@@ -376,7 +377,7 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
 
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                       const double* W, bool init, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
@@ -393,7 +394,7 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
                           double* alpha, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     const DirRecord rec{V, ldv, cap, gamma, alpha};
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_dir<double, T, false, true, true>), g, t, 0, s, B, y, p, x, z, W, rec); break;
@@ -406,7 +407,7 @@ hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x,
 
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_stage1_apply<T>), g, t, 0, s, B, y, x, r, z, W, AW); break;
         PODCG_TIERS(CASE)
@@ -457,7 +458,7 @@ namespace podcg {
 
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
                            const float* AW, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_update<float, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
@@ -469,7 +470,7 @@ hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, 
 
 hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
                         const float* W, bool init, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kDirGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
@@ -486,7 +487,7 @@ hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, co
 hipError_t launch_stage1_mixed(const DevBufs& B, int yb, int y, double* x64, const double* r64,
                                float* r32, float* z32, const double* W, const double* AW,
                                const float* AW32, double inner_rtol, hipStream_t s) {
-    dim3 g(vec_grid(B.n, kUpdateGrid)), t(kBlock);
+    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     const double r2 = inner_rtol * inner_rtol;
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_stage1_mixed<T>), g, t, 0, s, B, y, x64, r64, r32, z32, W, AW, AW32, r2); break;

@@ -31,6 +31,8 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.ld = ctx->ld;
     B.sptr = ctx->d_sptr;
     B.cols = ctx->d_cols;
+    B.cols16 = ctx->d_cols16;
+    B.sflag = ctx->d_sflag;
     B.vals = ctx->d_vals;
     B.dinv = ctx->d_dinv;
     B.st = ctx->d_st;
@@ -39,6 +41,9 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.Ginv = ctx->d_Ginv;
     B.vals32 = ctx->d_vals32;
     B.dinv32 = ctx->d_dinv32;
+    B.spmv_grid = ctx->opt.spmv_grid > 0 ? ctx->opt.spmv_grid : kSpmvGrid;
+    B.update_grid = ctx->opt.update_grid > 0 ? ctx->opt.update_grid : kUpdateGrid;
+    B.dir_grid = ctx->opt.dir_grid > 0 ? ctx->opt.dir_grid : kDirGrid;
     return B;
 }
 
@@ -54,7 +59,9 @@ void check_opts(const podcg_options& o) {
     if (o.omega < 1 || o.omega > PODCG_MAX_BASIS || o.rank_max < 0 || o.rank_max > PODCG_MAX_BASIS ||
         o.maxit < 0 || o.check_every < 1 || (o.weights != 0 && o.weights != 1) || o.timing < 0 ||
         !(o.rank_rtol >= 0.0) || !(o.energy > 0.0) || (o.precision != 0 && o.precision != 1) ||
-        o.max_refine < 1 || !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0))
+        o.max_refine < 1 || !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0) || o.spmv_grid < 0 ||
+        o.spmv_grid > kLoopGridMax || o.update_grid < 0 || o.update_grid > kLoopGridMax || o.dir_grid < 0 ||
+        o.dir_grid > kLoopGridMax)
         throw Fail{PODCG_ERR_INVALID_ARG};
 }
 
@@ -251,7 +258,7 @@ namespace {
 
 void release(podcg_ctx* ctx) {
     ts_release(ctx);
-    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
+    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
                    ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag,
@@ -287,6 +294,10 @@ void podcg_default_options(podcg_options* o) {
     o->precision = 0;
     o->max_refine = 20;
     o->inner_rtol = 1e-6;
+    o->spmv_grid = 0;
+    o->update_grid = 0;
+    o->dir_grid = 0;
+    o->reserved = 0;
 }
 
 const char* podcg_strerror(int code) {
@@ -333,6 +344,7 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
     int rc = guarded(ctx, [&]() {
         const size_t ld = ctx->ld;
         dalloc(ctx, &ctx->d_sptr, (size_t)ctx->nslices + 1);
+        dalloc(ctx, &ctx->d_sflag, (size_t)ctx->nslices);
         dalloc(ctx, &ctx->d_dinv, ld);
         dalloc(ctx, &ctx->d_r, ld);
         dalloc(ctx, &ctx->d_z, ld);
@@ -427,6 +439,7 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             if (nsell > ctx->sell_cap) {
                 ctx->has_pattern = ctx->has_values = false;
                 dalloc(ctx, &ctx->d_cols, (size_t)nsell);
+                dalloc(ctx, &ctx->d_cols16, (size_t)nsell);
                 dalloc(ctx, &ctx->d_map, (size_t)nsell);
                 dalloc(ctx, &ctx->d_vals, (size_t)nsell);
                 if (ctx->opt.precision == 1) dalloc(ctx, &ctx->d_vals32, (size_t)nsell);
@@ -435,6 +448,8 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             ctx->nsell = nsell;
             HIPCHECK(launch_fill_pattern(n, ctx->nslices, rowptr, colind, ctx->d_sptr, ctx->d_cols,
                                          ctx->d_map, s));
+            HIPCHECK(launch_fill_offsets16(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_cols16,
+                                           ctx->d_sflag, s));
             ctx->has_pattern = true;
             ctx->nnz = nnz;
         } else {

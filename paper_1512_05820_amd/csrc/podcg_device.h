@@ -16,12 +16,13 @@ constexpr int kYMax = 32;                 // largest basis / snapshot count
 constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
 constexpr int kVecBlocksMax = 2048;       // partial-sum capacity of the streaming kernels
 constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL kernels
-// Launch grids of the loop kernels (measured best on MI355X at 128^3 for the
-// three-kernel iteration: fewer, longer-lived workgroups shorten the
-// reduction tails without starving the memory system).
+// Default launch grids of the loop kernels (measured on MI355X at 128^3: the
+// two reducing kernels prefer fewer, longer-lived workgroups, which shorten
+// the reduction tails; the direction kernel, which reduces nothing, prefers
+// more).  Options override them.
 constexpr int kSpmvGrid = 1024;
 constexpr int kUpdateGrid = 512;
-constexpr int kDirGrid = 1024;
+constexpr int kDirGrid = 4096;
 constexpr int kCounters = 1 + kSpmvBlocksMax;        // arrival counters (level 2 + groups)
 constexpr int kGramBlocksMax = 512;       // grid cap of the fused SpMM + Gram kernel
 // doubles in the partials buffer: the larger of the loop kernels' need and the
@@ -174,17 +175,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // and values are loaded first (padding slots re-read the last valid slot and
 // are skipped with a select), then all gathers, then the sums in order j =
 // 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
-// slice bounds are scalar loads.
-template <typename T>
-__device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
-                                           const int* __restrict__ cols,
-                                           const T* __restrict__ vals, int s, int lane,
-                                           const T* __restrict__ x) {
-    s = __builtin_amdgcn_readfirstlane(s);
-    const int64_t base = sptr[s];
-    const int w = (int)((sptr[s + 1] - base) / kSlice);
-    const int* c = cols + base + lane;
-    const T* v = vals + base + lane;
+// slice bounds and the index-width flag are scalar loads.  A slice whose
+// column offsets col - row all fit in 16 bits reads them from cols16 (2 bytes
+// per entry instead of 4); rows past n gather entry 0.
+template <typename T, typename C>
+__device__ __forceinline__ double sell_row_cols(const C* __restrict__ c, const T* __restrict__ v, int w,
+                                                int rb, const T* __restrict__ x) {
     double acc = 0.0;   // FP32 operands multiply exactly in FP64; the row sum is FP64
     for (int j0 = 0; j0 < w; j0 += 8) {
         int ci[8];
@@ -192,7 +188,7 @@ __device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = min(j0 + u, w - 1);
-            ci[u] = __builtin_nontemporal_load(c + j * kSlice);
+            ci[u] = rb + (int)__builtin_nontemporal_load(c + j * kSlice);
             vi[u] = __builtin_nontemporal_load(v + j * kSlice);
         }
         T xi[8];
@@ -204,6 +200,7 @@ __device__ __forceinline__ double sell_row(const int64_t* __restrict__ sptr,
     return acc;
 }
 
+
 // ------------------------------------------------------------------ launchers
 // Device buffers of one context, passed to the launchers.
 struct DevBufs {
@@ -212,6 +209,8 @@ struct DevBufs {
     size_t ld;                 // leading dimension of column blocks (W, AW, S, AS)
     const int64_t* sptr;       // slice offsets, nslices + 1
     const int* cols;           // SELL column indices
+    const int16_t* cols16;     // column offsets col - row of the 16-bit slices
+    const uint8_t* sflag;      // per slice: 1 = read cols16, 0 = read cols
     const double* vals;        // SELL values
     const double* dinv;        // 1 / diag(A)
     DevState* st;
@@ -220,7 +219,24 @@ struct DevBufs {
     const double* Ginv;        // y x y row-major
     const float* vals32;       // FP32 copy of the SELL values (mixed precision)
     const float* dinv32;       // FP32 copy of dinv
+    int spmv_grid, update_grid, dir_grid;   // launch grids of the loop kernels
 };
+
+constexpr int kLoopGridMax = 4096;        // largest loop grid (partial and counter capacity)
+
+template <typename T>
+__device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict__ vals, int s, int lane,
+                                          const T* __restrict__ x) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int64_t base = B.sptr[s];
+    const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+    const T* v = vals + base + lane;
+    if (B.sflag[s]) {
+        const int row = s * kSlice + lane;
+        return sell_row_cols<T, int16_t>(B.cols16 + base + lane, v, w, row < B.n ? row : 0, x);
+    }
+    return sell_row_cols<T, int>(B.cols + base + lane, v, w, 0, x);
+}
 
 // Matrix values and Jacobi inverse in the storage type T of a kernel.
 template <typename T> __device__ __forceinline__ const T* mat_vals(const DevBufs& B);
@@ -237,6 +253,10 @@ hipError_t launch_slice_widths(int n, int nslices, const int32_t* rowptr, int64_
 hipError_t launch_scan_slices(int nslices, int64_t* sptr, hipStream_t s);
 hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const int32_t* colind,
                                const int64_t* sptr, int* cols, int* map, hipStream_t s);
+// cols16 / sflag from cols: a slice gets 16-bit offsets when every entry of
+// its rows < n has |col - row| <= 32767 (padding slots have col = row).
+hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const int* cols, int16_t* cols16,
+                                 uint8_t* sflag, hipStream_t s);
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
                               const int* map, const double* csr_vals, double* vals, double* dinv,
                               int* flag, hipStream_t s);

@@ -38,6 +38,8 @@ struct podcg_ctx {
     int64_t nnz = 0, nsell = 0, sell_cap = 0;
     int64_t* d_sptr = nullptr;
     int* d_cols = nullptr;
+    int16_t* d_cols16 = nullptr;
+    uint8_t* d_sflag = nullptr;
     int* d_map = nullptr;
     double* d_vals = nullptr;
     double* d_dinv = nullptr;

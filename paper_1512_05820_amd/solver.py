@@ -37,7 +37,8 @@ class PodCG:
     def __init__(self, n: int, omega: int = 20, rank_max: int = 10, maxit: int = 10000,
                  check_every: int = 16, weights: str = "idw", timing: int = 0,
                  rank_rtol: float = 1e-12, energy: float = 1.0, precision: str = "fp64",
-                 max_refine: int = 20, inner_rtol: float = 1e-6, stream=None):
+                 max_refine: int = 20, inner_rtol: float = 1e-6, spmv_grid: int = 0,
+                 update_grid: int = 0, dir_grid: int = 0, stream=None):
         self._L = L.load()
         opt = L.Options()
         self._L.podcg_default_options(C.byref(opt))
@@ -47,6 +48,7 @@ class PodCG:
         opt.rank_rtol, opt.energy = rank_rtol, energy
         opt.precision = {"fp64": 0, "mixed": 1}[precision]
         opt.max_refine, opt.inner_rtol = max_refine, inner_rtol
+        opt.spmv_grid, opt.update_grid, opt.dir_grid = spmv_grid, update_grid, dir_grid
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -95,6 +95,38 @@ def test_matvec_general_sparsity_ragged_rows(P):
     assert _relerr(_host(y), A @ x) <= 1e-13
 
 
+def test_matvec_mixes_16_and_32_bit_column_slices(P):
+    """Slices whose column offsets exceed 16 bits keep 32-bit indices, the
+    others read 16-bit offsets; rows of both kinds, a ragged last slice."""
+    r = _rng(5)
+    n = 90_001
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for d in (-301, -1, 0, 1, 301):
+            j = i + d
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+                vals.append(10.0 if d == 0 else -1.0 + 0.1 * r.standard_normal())
+    far = r.choice(n - 60_000, size=40, replace=False)
+    for i in far:                      # symmetric long-range couplings (offset 60,000)
+        rows += [i, i + 60_000]
+        cols += [i + 60_000, i]
+        vals += [0.5, 0.5]
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = np.array(rows)[order], np.array(cols)[order], np.array(vals)[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    A = oracle.CSR(rowptr, cols.astype(np.int32), vals)
+    x = r.standard_normal(n)
+    ctx = _ctx(P, n)
+    _set(ctx, rowptr, cols.astype(np.int32), vals)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), oracle.matvec(A, x)) <= 1e-14
+
+
 def test_stage1_matches_closed_form_projection(P):
     cfg = config2(N=19, steps=3)
     vals = cfg.matrix_values(1)
