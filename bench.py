@@ -43,7 +43,7 @@ def log(*a):
 def kernel_bytes(n: int, nnz: int, y: int) -> dict:
     """Algorithmic bytes of one launch of each loop kernel (FP64 values, int32 columns)."""
     return {
-        "spmv": 12 * nnz + 16 * n,            # A values + columns, read p, write q
+        "spmv": 12 * nnz + 4 * (n + 1) + 16 * n,   # CSR values + int32 columns + row offsets, read p, write q
         "update": (5 + y) * 8 * n,             # read r, q, dinv, A W; write r, z
         "dir": (5 + y) * 8 * n,                # read z, p, x, W; write p, x
     }
@@ -590,6 +590,8 @@ def main():
                      "traffic": (measured_traffic() if dom == "spmv" and cfg.N == 128 else None),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "algorithmic_bytes": kernel_bytes(cfg.n, cfg.nnz, 0)[dom] if dom == "spmv" else None,
+                     "format_bytes": (10 * cfg.nnz + 16 * cfg.n + 9 * ((cfg.n + 63) // 64)
+                                      if dom == "spmv" else None),
                      "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
                      "timed_launches": launches},
         "cpu_baseline": cpu,

@@ -505,15 +505,17 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), 0, s, B,
-                       p, q);
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+    PODCG_LAUNCH((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), s, e0, e1,
+                 B, p, q);
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), 0, s, B,
-                       p, q);
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+    PODCG_LAUNCH((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), s, e0, e1,
+                 B, p, q);
     return hipGetLastError();
 }
 

@@ -364,10 +364,10 @@ static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
 }
 
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
-                         const double* AW, hipStream_t s) {
+                         const double* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     switch (yb) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_update<double, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_update<double, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -376,13 +376,14 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
 }
 
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
-                      const double* W, bool init, hipStream_t s) {
+                      const double* W, bool init, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
+    const DirRecord none{};
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<double, T, true, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{}); \
-        else hipLaunchKernelGGL((k_dir<double, T, false, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});     \
+        if (init) PODCG_LAUNCH((k_dir<double, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none); \
+        else PODCG_LAUNCH((k_dir<double, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);     \
         break;
         PODCG_TIERS(CASE)
 #undef CASE
@@ -393,11 +394,11 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
 
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
-                          double* alpha, hipStream_t s) {
+                          double* alpha, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     const DirRecord rec{V, ldv, cap, gamma, alpha};
     switch (yb) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_dir<double, T, false, true, true>), g, t, 0, s, B, y, p, x, z, W, rec); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_dir<double, T, false, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, rec); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -457,10 +458,10 @@ hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStr
 namespace podcg {
 
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
-                           const float* AW, hipStream_t s) {
+                           const float* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
     switch (yb) {
-#define CASE(T) case T: hipLaunchKernelGGL((k_update<float, T, true>), g, t, 0, s, B, y, r, z, q, AW); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_update<float, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -469,13 +470,14 @@ hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, 
 }
 
 hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
-                        const float* W, bool init, hipStream_t s) {
+                        const float* W, bool init, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
+    const DirRecord none{};
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) hipLaunchKernelGGL((k_dir<float, T, true, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});  \
-        else hipLaunchKernelGGL((k_dir<float, T, false, true>), g, t, 0, s, B, y, p, x, z, W, DirRecord{});      \
+        if (init) PODCG_LAUNCH((k_dir<float, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);  \
+        else PODCG_LAUNCH((k_dir<float, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);      \
         break;
         PODCG_TIERS(CASE)
 #undef CASE

@@ -105,9 +105,9 @@ void add_timing(podcg_ctx* ctx, const std::vector<int>& timed, int iters, podcg_
     for (size_t k = 0; k < timed.size(); ++k) {
         if (timed[k] >= iters) break;
         float a = 0, b = 0, c = 0;
-        HIPCHECK(hipEventElapsedTime(&a, ctx->tev[4 * k + 0], ctx->tev[4 * k + 1]));
-        HIPCHECK(hipEventElapsedTime(&b, ctx->tev[4 * k + 1], ctx->tev[4 * k + 2]));
-        HIPCHECK(hipEventElapsedTime(&c, ctx->tev[4 * k + 2], ctx->tev[4 * k + 3]));
+        HIPCHECK(hipEventElapsedTime(&a, ctx->tev[6 * k + 0], ctx->tev[6 * k + 1]));
+        HIPCHECK(hipEventElapsedTime(&b, ctx->tev[6 * k + 2], ctx->tev[6 * k + 3]));
+        HIPCHECK(hipEventElapsedTime(&c, ctx->tev[6 * k + 4], ctx->tev[6 * k + 5]));
         S.spmv_ms += a;
         S.update_ms += b;
         S.dir_ms += c;
@@ -152,13 +152,11 @@ int solve_mixed(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_s
                                      ctx->d_AW, ctx->d_AW32, ctx->opt.inner_rtol, s));
         HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, true, s));
         std::vector<int> timed = run_loop(ctx, slot, &polls, [&](bool t, hipEvent_t* ev) {
-            if (t) record(ctx, ev[0]);
-            HIPCHECK(launch_spmv_gamma32(B, ctx->d_p32, ctx->d_q32, s));
-            if (t) record(ctx, ev[1]);
-            HIPCHECK(launch_update32(B, yb, y, ctx->d_r32, ctx->d_z32, ctx->d_q32, ctx->d_AW32, s));
-            if (t) record(ctx, ev[2]);
-            HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, false, s));
-            if (t) record(ctx, ev[3]);
+            hipEvent_t none[6] = {};
+            hipEvent_t* e = t ? ev : none;
+            HIPCHECK(launch_spmv_gamma32(B, ctx->d_p32, ctx->d_q32, s, e[0], e[1]));
+            HIPCHECK(launch_update32(B, yb, y, ctx->d_r32, ctx->d_z32, ctx->d_q32, ctx->d_AW32, s, e[2], e[3]));
+            HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, false, s, e[4], e[5]));
         });
         poll(ctx);
         const PollBlock P = *ctx->h_poll;
@@ -215,13 +213,11 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
         int polls = 0;
         std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev) {
-            if (t) record(ctx, ev[0]);
-            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s));
-            if (t) record(ctx, ev[1]);
-            HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s));
-            if (t) record(ctx, ev[2]);
-            HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s));
-            if (t) record(ctx, ev[3]);
+            hipEvent_t none[6] = {};
+            hipEvent_t* e = t ? ev : none;
+            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s, e[0], e[1]));
+            HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
+            HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s, e[4], e[5]));
         });
         // true residual ||b - A x||
         HIPCHECK(launch_resid(B, 0, 0, b, x, nullptr, nullptr, false, false, s));

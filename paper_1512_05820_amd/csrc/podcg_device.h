@@ -2,6 +2,7 @@
 // the kernel launchers shared by the translation units.  Not a public header.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -222,7 +223,14 @@ struct DevBufs {
     int spmv_grid, update_grid, dir_grid;   // launch grids of the loop kernels
 };
 
-constexpr int kLoopGridMax = 4096;        // largest loop grid (partial and counter capacity)
+constexpr int kLoopGridMax = 4096;
+
+// Launch through hipExtLaunchKernel when timing events are given.
+#define PODCG_LAUNCH(K, G, T, S, E0, E1, ...)                                                        \
+    do {                                                                                            \
+        if ((E0) || (E1)) hipExtLaunchKernelGGL(K, G, T, 0, S, E0, E1, 0, __VA_ARGS__);              \
+        else hipLaunchKernelGGL(K, G, T, 0, S, __VA_ARGS__);                                        \
+    } while (0)        // largest loop grid (partial and counter capacity)
 
 template <typename T>
 __device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict__ vals, int s, int lane,
@@ -263,8 +271,12 @@ hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int
 hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const int* cols, const int* map,
                                 const double* u, const double* v, double scale, double* out,
                                 hipStream_t s);
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s);
-hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s);
+// The loop launchers take optional start/stop events that the dispatch itself
+// records (hipExtLaunchKernel): the kernel time without event-marker overhead.
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s,
+                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);
 hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x,
                         double* r, const double* W, bool store, bool stage1, hipStream_t s);
@@ -275,16 +287,18 @@ hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX
 // Streaming vector kernels (k_vec.hip)
 int basis_tier(int y);   // smallest compiled register tier >= y
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
-                         const double* AW, hipStream_t s);
+                         const double* AW, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
-                      const double* W, bool init, hipStream_t s);
+                      const double* W, bool init, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s);
 // FP32 loop kernels of the mixed-precision inner solve (same state machine).
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
-                           const float* AW, hipStream_t s);
+                           const float* AW, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
-                        const float* W, bool init, hipStream_t s);
+                        const float* W, bool init, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 // Mixed-precision Stage 1 of one refinement step: from the FP64 residual r64
 // (and what = G^{-1} W^T r64 in the state), x64 += W what, r = r64 - (A W) what
 // in FP64, then r32 = r, z32 = M^{-1} r32, sums (r, z), (r, r), (A W)^T z; the
@@ -384,7 +398,7 @@ struct TsDev {
 
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
-                          double* alpha, hipStream_t s);
+                          double* alpha, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_gemv_n(int n, size_t ld, const double* Y, int m, const double* c, double* out,
                          double sign, bool accumulate, hipStream_t s);
 // out = Y^T v through kTsChunks row chunks (part: kTsChunks x m scratch).

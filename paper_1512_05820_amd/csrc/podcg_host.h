@@ -136,8 +136,8 @@ int fail_code(podcg_ctx* ctx, const podcg::PollBlock& P);
 void record(podcg_ctx* ctx, hipEvent_t e);
 // Launch loop iterations in batches until the device reports that the solve
 // finished, or maxit iterations were launched.  `iter3(t, ev)` enqueues one
-// iteration (SpMV, update, direction), recording ev[0..3] around the kernels
-// when t.  The first convergence check comes after most of the previous
+// iteration (SpMV, update, direction); when t, ev[2k], ev[2k + 1] are the
+// start/stop events of kernel k, recorded by the dispatches themselves.  The first convergence check comes after most of the previous
 // solve's iteration count (kernels after convergence are no-ops), then every
 // check_every iterations.  Returns the iteration indices that were timed.
 template <class F>
@@ -155,8 +155,8 @@ std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
             const bool t = timing > 0 && (launched % timing) == 0;
             hipEvent_t* ev = nullptr;
             if (t) {
-                const size_t base = timed.size() * 4;
-                while (ctx->tev.size() < base + 4) {
+                const size_t base = timed.size() * 6;
+                while (ctx->tev.size() < base + 6) {
                     hipEvent_t e;
                     HIPCHECK(hipEventCreate(&e));
                     ctx->tev.push_back(e);
