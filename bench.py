@@ -463,8 +463,8 @@ def main():
                          "(the full method of Alg. 3 on the config-2 sequence)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs one sequence (or one batch) per GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "config3":
         bench_config3(args)
