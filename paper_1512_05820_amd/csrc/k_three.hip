@@ -25,20 +25,34 @@ __global__ __launch_bounds__(kBlock) void k_gemv_n(int n, size_t ld, const doubl
     }
 }
 
-// part[g * m + k] = sum over the rows of chunk g of Y(i, k) v(i): one wave per
-// column at a time, lanes over the rows.
+// part[g * m + k] = sum over the rows of chunk g of Y(i, k) v(i): each wave
+// takes 8 columns at a time (one load of v per row for all 8), lanes over the
+// rows; the last group re-reads the last column instead of branching.
+constexpr int kGemvCols = 8;
 __global__ __launch_bounds__(kBlock) void k_gemv_t_part(int n, size_t ld, const double* __restrict__ Y,
                                                         int m, const double* __restrict__ v,
                                                         double* __restrict__ part, int rows) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int r0 = blockIdx.x * rows;
     const int r1 = min(n, r0 + rows);
-    for (int k = wid; k < m; k += kWavesPerBlock) {
-        const double* __restrict__ yk = Y + (size_t)k * ld;
-        double acc = 0.0;
-        for (int i = r0 + lane; i < r1; i += kWave) acc += yk[i] * v[i];
-        acc = wave_sum(acc);
-        if (lane == 0) part[(size_t)blockIdx.x * m + k] = acc;
+    for (int k0 = wid * kGemvCols; k0 < m; k0 += kWavesPerBlock * kGemvCols) {
+        double acc[kGemvCols];
+        const double* __restrict__ yk[kGemvCols];
+#pragma unroll
+        for (int u = 0; u < kGemvCols; ++u) {
+            acc[u] = 0.0;
+            yk[u] = Y + (size_t)min(k0 + u, m - 1) * ld;
+        }
+        for (int i = r0 + lane; i < r1; i += kWave) {
+            const double vi = v[i];
+#pragma unroll
+            for (int u = 0; u < kGemvCols; ++u) acc[u] += yk[u][i] * vi;
+        }
+#pragma unroll
+        for (int u = 0; u < kGemvCols; ++u) {
+            const double t = wave_sum(acc[u]);
+            if (lane == 0 && k0 + u < m) part[(size_t)blockIdx.x * m + k0 + u] = t;
+        }
     }
 }
 
@@ -175,15 +189,6 @@ __global__ void k_ts_ginv_blockdiag(const double* __restrict__ GinvW, int w, con
 
 // ------------------------------------------------------- accumulated vectors
 
-// Columns c < k of Y (the recorded directions) scaled by 1 / sqrt(gamma_c).
-__global__ __launch_bounds__(kBlock) void k_ts_scale_cols(double* __restrict__ Y, size_t ld, int n,
-                                                          const double* __restrict__ gam) {
-    const int c = blockIdx.y;
-    const double s = 1.0 / sqrt(gam[c]);
-    double* __restrict__ yc = Y + (size_t)c * ld;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) yc[i] *= s;
-}
-
 // eta_prev = [xh (m); alpha_k sqrt(gamma_k) (kr)] (coefficients of x - xbar in
 // Z = [Y, V Gamma^{-1/2}]); eta_acc = eta_prev + eta_acc / 2 (RBF weights with
 // 2^{1-i}, Section 3.3.2).
@@ -223,10 +228,12 @@ constexpr int kJacobiThreads = 1024;
 // Cyclic Jacobi eigen-decomposition of the symmetric M x M matrix A
 // (row-major), spread over the whole GPU: each sweep runs Mp - 1 rounds
 // (Mp = M rounded up to even) of Mp / 2 disjoint rotations in round-robin
-// pairing; a round is three launches -- the rotations (one workgroup, which
-// also sets the previous round's (p, q) entries to zero), the row update
-// and the column update of A and V.  J holds the round's rotations:
-// J[i] = {c, s} and the pair indices in Jp.
+// pairing.  Disjoint rotations commute, so J^T A J splits into independent
+// 2 x 2 blocks (rows of pair a, columns of pair b): one launch per round
+// reads A from one buffer and writes the rotated blocks to the other (every
+// entry is written once), and the (p, q) entries of the rotated pairs are set
+// to zero.  Every workgroup first forms the round's rotations from the input
+// buffer.
 
 __device__ __forceinline__ void jac_pair(int i, int r, int Mp, int& p, int& q) {
     int a, b;
@@ -241,19 +248,13 @@ __device__ __forceinline__ void jac_pair(int i, int r, int Mp, int& p, int& q) {
     q = a < b ? b : a;
 }
 
-__global__ __launch_bounds__(kBlock) void k_jac_rot(double* __restrict__ A, int M, int r,
-                                                    double* __restrict__ J, int* __restrict__ Jp) {
+__global__ __launch_bounds__(kBlock) void k_jac_round(const double* __restrict__ A, double* __restrict__ An,
+                                                      double* __restrict__ V, int M, int r) {
+    __shared__ double cs[kTsCap / 2], sn[kTsCap / 2];
+    __shared__ int pp[kTsCap / 2], qq[kTsCap / 2];
     const int Mp = M + (M & 1);
-    for (int i = threadIdx.x; i < Mp / 2; i += kBlock) {
-        const int pp = Jp[2 * i], qq = Jp[2 * i + 1];     // previous round
-        if (qq >= 0 && J[2 * i + 1] != 0.0) {
-            A[pp * M + qq] = 0.0;
-            A[qq * M + pp] = 0.0;
-        }
-    }
-    __syncthreads();
-    if (r < 0) return;                                    // final clean-up only
-    for (int i = threadIdx.x; i < Mp / 2; i += kBlock) {
+    const int np = Mp / 2;
+    for (int i = threadIdx.x; i < np; i += kBlock) {
         int p, q;
         jac_pair(i, r, Mp, p, q);
         double c = 1.0, s = 0.0;
@@ -266,54 +267,63 @@ __global__ __launch_bounds__(kBlock) void k_jac_rot(double* __restrict__ A, int 
                 s = t * c;
             }
         }
-        J[2 * i] = c;
-        J[2 * i + 1] = s;
-        Jp[2 * i] = p;
-        Jp[2 * i + 1] = q < M ? q : -1;
+        cs[i] = c;
+        sn[i] = s;
+        pp[i] = p;
+        qq[i] = q < M ? q : -1;
+    }
+    __syncthreads();
+    const int nblk = np * np;
+    const int total = nblk + M * np;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < total; e += gridDim.x * kBlock) {
+        if (e < nblk) {                                   // block (a, b) of A
+            const int a = e / np, b = e % np;
+            const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+            const double ca = cs[a], sa = sn[a], cb = cs[b], sb = sn[b];
+            const double x11 = A[pa * M + pb];
+            const double x12 = qb >= 0 ? A[pa * M + qb] : 0.0;
+            const double x21 = qa >= 0 ? A[qa * M + pb] : 0.0;
+            const double x22 = (qa >= 0 && qb >= 0) ? A[qa * M + qb] : 0.0;
+            const double y11 = ca * x11 - sa * x21, y21 = sa * x11 + ca * x21;
+            const double y12 = ca * x12 - sa * x22, y22 = sa * x12 + ca * x22;
+            double z11 = cb * y11 - sb * y12, z12 = sb * y11 + cb * y12;
+            double z21 = cb * y21 - sb * y22;
+            const double z22 = sb * y21 + cb * y22;
+            if (a == b && sa != 0.0) {
+                z12 = 0.0;
+                z21 = 0.0;
+            }
+            An[pa * M + pb] = z11;
+            if (qb >= 0) An[pa * M + qb] = z12;
+            if (qa >= 0) An[qa * M + pb] = z21;
+            if (qa >= 0 && qb >= 0) An[qa * M + qb] = z22;
+        } else {                                          // columns p_b, q_b of V
+            const int f = e - nblk;
+            const int k = f / np, b = f % np;
+            const int pb = pp[b], qb = qq[b];
+            const double sb = sn[b];
+            if (qb < 0 || sb == 0.0) continue;
+            const double cb = cs[b];
+            const double vkp = V[k * M + pb], vkq = V[k * M + qb];
+            V[k * M + pb] = cb * vkp - sb * vkq;
+            V[k * M + qb] = sb * vkp + cb * vkq;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_jac_rows(double* __restrict__ A, int M,
-                                                     const double* __restrict__ J, const int* __restrict__ Jp) {
-    const int np = (M + (M & 1)) / 2;
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < np * M; e += gridDim.x * kBlock) {
-        const int i = e / M, k = e % M;
-        const int p = Jp[2 * i], q = Jp[2 * i + 1];
-        const double s = J[2 * i + 1];
-        if (q < 0 || s == 0.0) continue;
-        const double c = J[2 * i];
-        const double apk = A[p * M + k], aqk = A[q * M + k];
-        A[p * M + k] = c * apk - s * aqk;
-        A[q * M + k] = s * apk + c * aqk;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_jac_cols(double* __restrict__ A, double* __restrict__ V, int M,
-                                                     const double* __restrict__ J, const int* __restrict__ Jp) {
-    const int np = (M + (M & 1)) / 2;
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < np * M; e += gridDim.x * kBlock) {
-        const int k = e / np, i = e % np;      // consecutive threads: different pairs of row k
-        const int p = Jp[2 * i], q = Jp[2 * i + 1];
-        const double s = J[2 * i + 1];
-        if (q < 0 || s == 0.0) continue;
-        const double c = J[2 * i];
-        const double akp = A[k * M + p], akq = A[k * M + q];
-        A[k * M + p] = c * akp - s * akq;
-        A[k * M + q] = s * akp + c * akq;
-        const double vkp = V[k * M + p], vkq = V[k * M + q];
-        V[k * M + p] = c * vkp - s * vkq;
-        V[k * M + q] = s * vkp + c * vkq;
-    }
-}
-
-// V = I; Jp = -1 (no previous round).
-__global__ __launch_bounds__(kBlock) void k_jac_init(double* __restrict__ V, int M, double* __restrict__ J,
-                                                     int* __restrict__ Jp) {
+// V = I.
+__global__ __launch_bounds__(kBlock) void k_jac_init(double* __restrict__ V, int M) {
     for (int e = blockIdx.x * kBlock + threadIdx.x; e < M * M; e += gridDim.x * kBlock)
         V[e] = (e / M == e % M) ? 1.0 : 0.0;
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < kTsCap; e += gridDim.x * kBlock) {
-        Jp[e] = -1;
-        J[e] = 0.0;
+}
+
+// Gbar = sum over the row chunks of the partial Grams, in chunk order.
+__global__ __launch_bounds__(kBlock) void k_ts_sum_parts(const double* __restrict__ parts, int nparts,
+                                                         size_t stride, int count, double* __restrict__ G) {
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < count; e += gridDim.x * kBlock) {
+        double s = 0.0;
+        for (int c = 0; c < nparts; ++c) s += parts[(size_t)c * stride + e];
+        G[e] = s;
     }
 }
 
@@ -451,13 +461,6 @@ hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, 
     return hipGetLastError();
 }
 
-hipError_t launch_ts_scale_cols(double* Y, size_t ld, int n, int k, const double* gam, hipStream_t s) {
-    if (k < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_ts_scale_cols, dim3(rows_grid(n) < 64 ? rows_grid(n) : 64, k), dim3(kBlock), 0, s,
-                       Y, ld, n, gam);
-    return hipGetLastError();
-}
-
 hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s) {
     if (m + kr > kTsCap) return hipErrorInvalidValue;
     if (m + kr == 0) return hipSuccess;
@@ -479,24 +482,33 @@ hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_ts_jacobi_init(double* V, int M, double* J, int* Jp, hipStream_t s) {
+hipError_t launch_ts_jacobi_init(double* V, int M, hipStream_t s) {
     if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jac_init, dim3(rows_grid(M * M)), dim3(kBlock), 0, s, V, M, J, Jp);
+    hipLaunchKernelGGL(k_jac_init, dim3(rows_grid(M * M)), dim3(kBlock), 0, s, V, M);
     return hipGetLastError();
 }
 
-hipError_t launch_ts_jacobi_sweep(double* A, double* V, int M, double* J, int* Jp, int* flag,
-                                  hipStream_t s) {
+// One sweep; the matrix alternates between *A and *A2 (the pointers are
+// swapped so that *A holds the current matrix on return); ends with the
+// convergence flag of the result.
+hipError_t launch_ts_jacobi_sweep(double** A, double** A2, double* V, int M, int* flag, hipStream_t s) {
     if (M < 1 || M > kTsCap) return hipErrorInvalidValue;
     const int Mp = M + (M & 1);
-    const int g = rows_grid((Mp / 2) * M);
+    const int np = Mp / 2;
+    const int g = rows_grid(np * np + M * np);
     for (int r = 0; r < Mp - 1; ++r) {
-        hipLaunchKernelGGL(k_jac_rot, dim3(1), dim3(kBlock), 0, s, A, M, r, J, Jp);
-        hipLaunchKernelGGL(k_jac_rows, dim3(g), dim3(kBlock), 0, s, A, M, (const double*)J, (const int*)Jp);
-        hipLaunchKernelGGL(k_jac_cols, dim3(g), dim3(kBlock), 0, s, A, V, M, (const double*)J, (const int*)Jp);
+        hipLaunchKernelGGL(k_jac_round, dim3(g), dim3(kBlock), 0, s, (const double*)*A, *A2, V, M, r);
+        double* t = *A;
+        *A = *A2;
+        *A2 = t;
     }
-    hipLaunchKernelGGL(k_jac_rot, dim3(1), dim3(kBlock), 0, s, A, M, -1, J, Jp);   // last zeroing
-    hipLaunchKernelGGL(k_jac_offnorm, dim3(1), dim3(kJacobiThreads), 0, s, (const double*)A, M, flag);
+    hipLaunchKernelGGL(k_jac_offnorm, dim3(1), dim3(kJacobiThreads), 0, s, (const double*)*A, M, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_sum_parts(const double* parts, int nparts, size_t stride, int count, double* G,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_ts_sum_parts, dim3(rows_grid(count)), dim3(kBlock), 0, s, parts, nparts, stride, count, G);
     return hipGetLastError();
 }
 

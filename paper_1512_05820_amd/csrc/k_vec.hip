@@ -95,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 // update x += alpha p is carried out in FP64, so the correction of a
 // refinement step is accumulated without FP32 rounding.
 // Directions recorded by REC (the Krylov basis V and Gamma, alpha of Alg. 1's
-// outputs): p_k goes to column k of V while k < cap, with gamma_k and alpha_k.
+// outputs): p_k / sqrt(gamma_k) (unit A-norm) goes to column k of V while
+// k < cap, with gamma_k and alpha_k.
 struct DirRecord {
     double* V;
     size_t ld;
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
     // already counted its iteration)
     const int krec = REC && !INIT ? st->iter - 1 : -1;
     double* __restrict__ vrec = (REC && krec >= 0 && krec < rec.cap) ? rec.V + (size_t)krec * rec.ld : nullptr;
+    const double vscale = REC ? 1.0 / sqrt(st->gamma) : 1.0;
     if (REC && vrec && blockIdx.x == 0 && threadIdx.x == 0) {
         rec.gamma[krec] = st->gamma;
         rec.alpha[krec] = alpha;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         } else {
             const T pi = p[i];
             x[i] += alpha * (double)pi;
-            if (REC && vrec) vrec[i] = (double)pi;
+            if (REC && vrec) vrec[i] = (double)pi * vscale;
             if (!new_dir) continue;
             s = z[i] + beta * pi;
         }

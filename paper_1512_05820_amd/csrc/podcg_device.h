@@ -411,17 +411,19 @@ hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const doubl
                              hipStream_t s);
 hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
                                     hipStream_t s);
-hipError_t launch_ts_scale_cols(double* Y, size_t ld, int n, int k, const double* gam, hipStream_t s);
 hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s);
 hipError_t launch_ts_gather(const double* Y, size_t ld, int n, const int* sel, int w, double* B,
                             hipStream_t s);
 hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t s);
-// Cyclic Jacobi eigen-solver of a symmetric M x M matrix (row-major, in place):
-// init (V = I), sweeps (each ends with the convergence flag), finish (sorted
-// eigenvalues, eigenvectors as columns of A).  J, Jp: kTsCap scratch each.
-hipError_t launch_ts_jacobi_init(double* V, int M, double* J, int* Jp, hipStream_t s);
-hipError_t launch_ts_jacobi_sweep(double* A, double* V, int M, double* J, int* Jp, int* flag,
-                                  hipStream_t s);
+// Cyclic Jacobi eigen-solver of a symmetric M x M matrix (row-major): init
+// (V = I), sweeps over two alternating buffers (each ends with the
+// convergence flag), finish (sorted eigenvalues, eigenvectors as columns of
+// the current buffer).
+hipError_t launch_ts_jacobi_init(double* V, int M, hipStream_t s);
+hipError_t launch_ts_jacobi_sweep(double** A, double** A2, double* V, int M, int* flag, hipStream_t s);
+// G = sum of nparts partial Grams (stride apart), in order.
+hipError_t launch_ts_sum_parts(const double* parts, int nparts, size_t stride, int count, double* G,
+                               hipStream_t s);
 hipError_t launch_ts_jacobi_offnorm(const double* A, int M, int* flag, hipStream_t s);
 hipError_t launch_ts_jacobi_finish(double* A, int M, double* V, double* lam, hipStream_t s);
 hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,

@@ -41,8 +41,8 @@ struct TsHost {
     double *d_lamG = nullptr, *d_Gbig = nullptr, *d_Vbig = nullptr, *d_lam = nullptr, *d_T = nullptr;
     int* d_sel = nullptr;
     int* d_info = nullptr;
-    double* d_J = nullptr;       // Jacobi rotations of one round
-    int* d_Jp = nullptr;
+    double* d_Gbig2 = nullptr;   // second buffer of the Jacobi rounds
+    double* d_Gparts = nullptr;  // partial Grams of the row chunks
     TsDev* d_ts = nullptr;
     double* h_dbl = nullptr;     // pinned, kTsCap + 8
     int* h_int = nullptr;        // pinned, kYMax + 8
@@ -55,7 +55,7 @@ void ts_release(podcg_ctx* ctx) {
     if (!T) return;
     void* dev[] = {T->d_Y, T->d_AZ, T->d_B, T->d_AB, T->d_part, T->d_G, T->d_R, T->d_GinvW, T->d_GinvB,
                    T->d_lamG, T->d_Gbig, T->d_Vbig, T->d_lam, T->d_T, T->d_sel, T->d_info, T->d_ts,
-                   T->d_J, T->d_Jp};
+                   T->d_Gbig2, T->d_Gparts};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (T->h_dbl) (void)hipHostFree(T->h_dbl);
@@ -73,6 +73,7 @@ namespace {
 
 constexpr double kStage2Floor = 1e-6;   // stage-2 tolerance floor, relative to ||Y^T r||
 constexpr int kJacobiMaxSweeps = 60;
+constexpr int kGramChunks = 64;         // row chunks of the truncation Gram
 
 #define BLASCHECK(expr)                                                                             \
     do {                                                                                            \
@@ -123,23 +124,38 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
         const int kc = std::min(kYMax, M - c0);
         HIPCHECK(launch_spmm_gram(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, true, T->d_G, s));
     }
+    // Z^T (A Z) split over row chunks (one GEMM per chunk, batched), then the
+    // partial Grams summed in chunk order: a single GEMM of this shape (M x M
+    // output, n-long inner dimension) leaves most of the GPU idle
     const double one = 1.0, zero = 0.0;
-    BLASCHECK(rocblas_dgemm(T->blas, rocblas_operation_transpose, rocblas_operation_none, M, M, n, &one,
-                            T->d_Y, (int)ld, T->d_AZ, (int)ld, &zero, T->d_Gbig, M));
+    const int chunk = (n + kGramChunks - 1) / kGramChunks;
+    const int full = n / chunk, rem = n - full * chunk;
+    const rocblas_stride pstride = (rocblas_stride)kTsCap * kTsCap;
+    if (full > 0)
+        BLASCHECK(rocblas_dgemm_strided_batched(T->blas, rocblas_operation_transpose, rocblas_operation_none, M, M,
+                                                chunk, &one, T->d_Y, (int)ld, chunk, T->d_AZ, (int)ld, chunk, &zero,
+                                                T->d_Gparts, M, pstride, full));
+    if (rem > 0)
+        BLASCHECK(rocblas_dgemm(T->blas, rocblas_operation_transpose, rocblas_operation_none, M, M, rem, &one,
+                                T->d_Y + (size_t)full * chunk, (int)ld, T->d_AZ + (size_t)full * chunk, (int)ld,
+                                &zero, T->d_Gparts + (size_t)full * pstride, M));
+    HIPCHECK(launch_ts_sum_parts(T->d_Gparts, full + (rem > 0 ? 1 : 0), (size_t)pstride, M * M, T->d_Gbig, s));
     const double* eta = T->opt.weights == 0 ? TSF(T, eta_acc) : TSF(T, eta_prev);
     HIPCHECK(launch_ts_weight_sym(T->d_Gbig, M, eta, s));
     // Jacobi sweeps until the off-diagonal norm is <= 1e-15 of the Frobenius norm
-    HIPCHECK(launch_ts_jacobi_init(T->d_Vbig, M, T->d_J, T->d_Jp, s));
+    HIPCHECK(launch_ts_jacobi_init(T->d_Vbig, M, s));
     HIPCHECK(launch_ts_jacobi_offnorm(T->d_Gbig, M, T->d_info, s));
+    double* cur = T->d_Gbig;
+    double* other = T->d_Gbig2;
     int sweeps = 0;
     for (;;) {
         HIPCHECK(hipMemcpyAsync(T->h_int, T->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         if (T->h_int[0] || sweeps >= kJacobiMaxSweeps) break;
-        HIPCHECK(launch_ts_jacobi_sweep(T->d_Gbig, T->d_Vbig, M, T->d_J, T->d_Jp, T->d_info, s));
+        HIPCHECK(launch_ts_jacobi_sweep(&cur, &other, T->d_Vbig, M, T->d_info, s));
         ++sweeps;
     }
-    HIPCHECK(launch_ts_jacobi_finish(T->d_Gbig, M, T->d_Vbig, T->d_lam, s));
+    HIPCHECK(launch_ts_jacobi_finish(cur, M, T->d_Vbig, T->d_lam, s));
     HIPCHECK(hipMemcpyAsync(T->h_dbl, T->d_lam, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     const double* lam = T->h_dbl;
@@ -153,7 +169,7 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
     int w = std::min(T->opt.w_max, y);
     w = energy_count(lam, M, w, T->opt.energy_w);
     if (y > 0) {
-        HIPCHECK(launch_ts_pod_coeffs(T->d_Gbig, M, T->d_lam, eta, y, T->d_T, s));
+        HIPCHECK(launch_ts_pod_coeffs(cur, M, T->d_lam, eta, y, T->d_T, s));
         BLASCHECK(rocblas_dgemm(T->blas, rocblas_operation_none, rocblas_operation_none, n, y, M, &one, T->d_Y,
                                 (int)ld, T->d_T, M, &zero, T->d_AZ, (int)ld));
         std::swap(T->d_Y, T->d_AZ);
@@ -286,7 +302,6 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     // ---- accumulation (Alg. 3): Z = [Y, V Gamma^{-1/2}], weights, truncation
     if (code >= 0) {
         const int kr = std::min(k3, cap_rec);
-        HIPCHECK(launch_ts_scale_cols(vrec, ld, n, kr, TSF(T, gam3), s));
         HIPCHECK(launch_ts_eta(T->d_ts, m, kr, s));
         const int M = m + kr;
         if (M > T->opt.ybar) {
@@ -372,8 +387,8 @@ int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
         dalloc(ctx, &T->d_T, (size_t)kTsCap * kTsCap);
         dalloc(ctx, &T->d_sel, kYMax);
         dalloc(ctx, &T->d_info, 4);
-        dalloc(ctx, &T->d_J, kTsCap);
-        dalloc(ctx, &T->d_Jp, kTsCap);
+        dalloc(ctx, &T->d_Gbig2, (size_t)kTsCap * kTsCap);
+        dalloc(ctx, &T->d_Gparts, (size_t)(kGramChunks + 1) * kTsCap * kTsCap);
         dalloc(ctx, &T->d_ts, 1);
         HIPCHECK(hipMemsetAsync(T->d_Y, 0, sizeof(double) * ld * (size_t)o.cap, s));
         HIPCHECK(hipMemsetAsync(T->d_AZ, 0, sizeof(double) * ld * (size_t)o.cap, s));
