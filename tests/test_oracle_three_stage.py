@@ -277,3 +277,59 @@ def test_three_stage_mutant_is_caught(name):
         except Exception:
             caught.append(pin.__name__)
     assert caught, f"mutant {name} passed every pin"
+
+
+def test_e8_pod_weights_synthetic():
+    """Synthetic rerun of the paper's POD-weights experiment (Section 5.3): the
+    vectors accumulated over systems 1..10 (no truncation) are truncated by POD
+    in the metric A_10 with the ideal, previous and RBF weights, and system 11
+    is solved over the first k POD vectors.  Reported: the A_11-norm error of
+    the Stage-1 solution and the Stage-3 iterations to 1e-6.  Pinned: the
+    error is non-increasing in k for every weighting (nested subspaces), and the
+    ideal weights are at least as good as the computable ones at the largest k
+    (within 5%)."""
+    cfg = Config4Member(18, 1040, 1041, 11, 5, 4, 1e-6)
+    opt = TS.TSOptions(ybar=10_000, cap=10_000, rho=0.0, stage2_maxit=8)
+    st = TS.TSState(cfg.n)
+    prev = []
+    for j in range(1, 11):
+        keep = {}
+        TS.ts_solve(_A(cfg, j), cfg.rhs(j), np.zeros(cfg.n), st, cfg.tol, 10_000, opt, keep)
+        prev.append(keep["eta_prev"])
+    Z = st.Y
+    A10, A11 = _A(cfg, 10), _A(cfg, 11)
+    D11 = _dense(A11)
+    b11 = cfg.rhs(11)
+    x11 = np.linalg.solve(D11, b11)
+    AZ11 = D11 @ Z
+    # Eq. (weightsIdealAj) with xbar = 0.  The accumulated Krylov vectors of ten
+    # similar solves are linearly dependent in floating point (Z^T A Z has
+    # eigenvalues at rounding level), so the weights are the minimum-norm
+    # solution: eigenvalues below 1e-12 of the largest are dropped
+    G = Z.T @ AZ11
+    lam, U = np.linalg.eigh(0.5 * (G + G.T))
+    live = lam > 1e-12 * lam[-1]
+    ideal = U[:, live] @ ((U[:, live].T @ (Z.T @ b11)) / lam[live])
+    rbf = np.zeros(Z.shape[1])
+    for i, e in enumerate(reversed(prev), start=1):
+        rbf[:len(e)] += 2.0 ** (1 - i) * e
+    weights = {"ideal": ideal, "previous": prev[-1], "rbf": rbf}
+    ks = [1, 2, 4, 8, 16]
+    rows = []
+    for name, eta in weights.items():
+        basis, _ = TS.pod_evd_dense(A10, Z, eta, max(ks), 1e-12, 1.0)
+        errs, its = [], []
+        for k in ks:
+            W = basis[:, :k]
+            c = np.linalg.solve(W.T @ D11 @ W, W.T @ b11)
+            d = x11 - W @ c
+            errs.append(float(np.sqrt(d @ D11 @ d) / np.sqrt(x11 @ D11 @ x11)))
+            _, so = oracle.aug_pcg(A11, b11, np.zeros(cfg.n), W, cfg.tol, 10_000)
+            its.append(so.iters)
+        rows.append((name, errs, its))
+        assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) + 1e-14 for i in range(len(errs) - 1)), (name, errs)
+    final = {name: errs[-1] for name, errs, _ in rows}
+    assert final["ideal"] <= 1.05 * min(final["previous"], final["rbf"])
+    print(f"\nE8 synthetic: Z_10 has {Z.shape[1]} vectors; k = {ks}")
+    for name, errs, its in rows:
+        print(f"{name:9s} A-norm error {' '.join(f'{e:.2e}' for e in errs)} | stage-3 iterations {its}")
