@@ -40,12 +40,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(n: int, nnz: int, y: int) -> dict:
-    """Algorithmic bytes of one launch of each loop kernel (FP64 values, int32 columns)."""
+def kernel_bytes(n: int, nnz: int, y: int, implicit: bool = True) -> dict:
+    """Algorithmic bytes of one launch of each loop kernel (FP64 values, int32 columns).
+    In the implicit form of the direction (p = pt - W nu) the direction kernel
+    reads no basis column."""
     return {
         "spmv": 12 * nnz + 4 * (n + 1) + 16 * n,   # CSR values + int32 columns + row offsets, read p, write q
         "update": (5 + y) * 8 * n,             # read r, q, dinv, A W; write r, z
-        "dir": (5 + y) * 8 * n,                # read z, p, x, W; write p, x
+        "dir": (5 + (0 if implicit else y)) * 8 * n,   # read z, p, x (, W); write p, x
     }
 
 
@@ -455,6 +457,10 @@ def main():
     ap.add_argument("--cpu-systems", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the context run of the other direction form")
+    ap.add_argument("--projection", default="implicit", choices=["implicit", "explicit"],
+                    help="form of the direction recurrence in the augmented loop")
     ap.add_argument("--adjoint-basis", default="forward", choices=["forward", "adjoint", "none"],
                     help="config5: basis of the adjoint solves")
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "three_stage"],
@@ -492,7 +498,8 @@ def main():
     log(f"generated and uploaded {cfg.steps} matrices n={cfg.n} nnz={cfg.nnz} "
         f"in {time.perf_counter() - t0:.1f}s")
 
-    ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, timing=TIMING_STRIDE)
+    ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, timing=TIMING_STRIDE,
+                  projection=args.projection)
     ctx.set_matrix(vals_dev[0], rowptr, colind)
 
     # achievable bandwidth probe (not part of the method)
@@ -528,7 +535,7 @@ def main():
     tot = {"spmv": [0.0, 0.0], "update": [0.0, 0.0], "dir": [0.0, 0.0]}
     for _, sts in per_step:
         for s in sts:
-            kb = kernel_bytes(cfg.n, cfg.nnz, s["rank"])
+            kb = kernel_bytes(cfg.n, cfg.nnz, s["rank"], implicit=args.projection == "implicit")
             for key, ms_key in (("spmv", "spmv_ms"), ("update", "update_ms"), ("dir", "dir_ms")):
                 tot[key][0] += s["timed_iters"] * kb[key]
                 tot[key][1] += s[ms_key]
@@ -550,6 +557,22 @@ def main():
             plain[key] = {"ms": 1e3 * (time.perf_counter() - t1),
                           "iters": sum(s["iters"] for s in sts)}
             log(f"plain {key}: {plain[key]['ms']:.1f} ms, iters {plain[key]['iters']}")
+
+    # the other form of the direction recurrence, once, for context
+    other_rec = None
+    if not args.no_other:
+        other = "explicit" if args.projection == "implicit" else "implicit"
+        ctx_o = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, projection=other)
+        ctx_o.set_matrix(vals_dev[0], rowptr, colind)
+        run_sequence(torch, ctx_o, cfg, vals_dev, "aug")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sts = run_sequence(torch, ctx_o, cfg, vals_dev, "aug")
+        torch.cuda.synchronize()
+        other_rec = {"projection": other, "ms": round(1e3 * (time.perf_counter() - t1), 3),
+                     "iters": sum(s["iters"] for s in sts)}
+        log(f"aug {other}: {other_rec['ms']:.1f} ms, iters {other_rec['iters']}")
+        del ctx_o
 
     cpu = None
     if not args.no_cpu:
@@ -573,12 +596,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "N": cfg.N, "n": cfg.n, "nnz": cfg.nnz,
                    "systems": cfg.steps, "omega": cfg.omega, "rank_max": cfg.rank,
-                   "rel_tol": cfg.tol, "dt": cfg.dt, "preconditioner": "jacobi"},
+                   "rel_tol": cfg.tol, "dt": cfg.dt, "preconditioner": "jacobi",
+                   "projection": args.projection},
         "aug_iters_total": aug_iters,
         "aug_iters_per_system": [s["iters"] for s in aug_stats],
         "aug_rank_per_system": [s["rank"] for s in aug_stats],
         "max_true_relres": max(s["true_relres"] for s in aug_stats),
         "plain_gpu": plain,
+        "aug_other_form": other_rec,
         "speedup_vs_plain_warm": (round(plain["warm"]["ms"] / ms_per_step, 3) if plain else None),
         "iters_saved_vs_plain_warm": (1 - aug_iters / plain["warm"]["iters"]) if plain else None,
         "loop_kernels_GBps": {k: round(v, 1) for k, v in gbps.items()},

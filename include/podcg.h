@@ -72,8 +72,15 @@ typedef struct {
     double  inner_rtol;   /* relative tolerance of each FP32 inner solve (precision = 1)      */
     int32_t spmv_grid;    /* workgroups of the loop SpMV (0 = default 1024; at most 4096)     */
     int32_t update_grid;  /* workgroups of the residual-update kernel (0 = default 512; <= 4096) */
-    int32_t dir_grid;     /* workgroups of the direction kernel (0 = default 1024; <= 4096)   */
-    int32_t reserved;
+    int32_t dir_grid;     /* workgroups of the direction kernel (0 = default 4096; <= 4096)   */
+    int32_t projection;   /* form of the direction recurrence of Alg. 1 in FP64 solves:
+                             0 explicit: p = z + beta p - W mu is formed every iteration;
+                             1 implicit: the loop keeps pt = z + beta pt and the coefficients
+                               nu of p = pt - W nu (nu = mu + beta nu), forms A p as
+                               A pt - (A W) nu inside the residual update and x as
+                               xt - W xi once at exit, so W is not read in the loop.  The
+                               iterates are the same in exact arithmetic.  Mixed precision
+                               (precision = 1) and plain PCG always use the explicit form. */
 } podcg_options;
 
 typedef struct {
@@ -100,7 +107,8 @@ typedef struct {
 
 /* Fill *opt with defaults: omega 20, rank_max 10, maxit 10000, check_every 16,
  * inverse-distance weights, no timing, rank_rtol 1e-12, energy 1 (off),
- * precision 0 (FP64), max_refine 20, inner_rtol 1e-6. */
+ * precision 0 (FP64), max_refine 20, inner_rtol 1e-6, default loop grids,
+ * projection 1 (implicit). */
 void podcg_default_options(podcg_options* opt);
 
 /* Create a context for systems of size n.  opt may be NULL (defaults).

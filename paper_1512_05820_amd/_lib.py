@@ -32,7 +32,7 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("weights", C.c_int32), ("timing", C.c_int32),
                 ("rank_rtol", C.c_double), ("energy", C.c_double), ("precision", C.c_int32),
                 ("max_refine", C.c_int32), ("inner_rtol", C.c_double), ("spmv_grid", C.c_int32),
-                ("update_grid", C.c_int32), ("dir_grid", C.c_int32), ("reserved", C.c_int32)]
+                ("update_grid", C.c_int32), ("dir_grid", C.c_int32), ("projection", C.c_int32)]
 
 
 class BatchOptions(C.Structure):

@@ -221,7 +221,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
         }
     }
     if (grid_sum_last<1>(g, B.part, B.counter, lds) && threadIdx.x == 0) {
-        const double gamma = lds[0];
+        // gcorr is 0 unless the direction is kept in implicit form (then p is
+        // pt - W nu, this kernel multiplies pt, and gcorr = nu^T (A W)^T pt)
+        const double gamma = lds[0] - st->gcorr;
         st->gamma = gamma;
         if (!(gamma > 0.0) || !is_finite(gamma)) {
             st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;

@@ -87,6 +87,102 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
     }
 }
 
+// Loop kernel 2 in the implicit form of the direction, p = pt - W nu.  The
+// SpMV has produced qt = A pt, and
+//   A p = A pt - (A W) nu,  r <- r - alpha A p,  z <- M^{-1} r,
+// with the sums (r, z), (r, r), c = (A W)^T z: each column of A W is loaded
+// once and serves both A p and c.  The last workgroup forms beta and
+// mu = G^{-1} c as in the explicit form and then advances
+//   xi <- xi + alpha nu        (x += alpha p is alpha pt, minus W alpha nu),
+//   nu <- mu + beta nu         (p' = z + beta p - W mu = pt' - W nu'),
+//   a  <- c + beta a           (a = (A W)^T pt, by the same recurrence),
+//   gcorr = nu^T a,
+// so that the next SpMV turns (A pt, pt) into (A p, p) = (A pt, pt) - nu^T a
+// (this uses (A W)^T p = 0, the property Alg. 1's projection maintains).
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double* __restrict__ r,
+                                                       double* __restrict__ z,
+                                                       const double* __restrict__ qt,
+                                                       const double* __restrict__ AW) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    DevState* st = B.st;
+    if (st->done != kRunning) return;
+    const double alpha = st->alpha;
+    double nu[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int k = 0; k < YB; ++k) nu[k] = k < y ? st->nu[k] : 0.0;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double a[YB > 0 ? YB : 1];
+        double qi = qt[i];
+#pragma unroll
+        for (int k = 0; k < YB; ++k) {
+            a[k] = basis_load<true>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
+            if (tier_live<YB>(k, y)) qi -= a[k] * nu[k];
+        }
+        const double ri = r[i] - alpha * qi;
+        const double zi = B.dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        v[0] += ri * zi;
+        v[1] += ri * ri;
+#pragma unroll
+        for (int k = 0; k < YB; ++k)
+            if (tier_live<YB>(k, y)) v[2 + k] += a[k] * zi;
+    }
+    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rz = lds[0], rr = lds[1];
+        const int it = st->iter + 1;
+        st->iter = it;
+        st->rr = rr;
+        double beta = 0.0, stepped = 1.0;
+        if (!is_finite(rr) || !is_finite(rz)) {
+            st->status = kStNonfinite;
+            st->done = kFailed;
+            stepped = 0.0;     // the direction kernel will not apply this step to x
+        } else {
+            beta = rz / st->rho;
+            st->beta = beta;
+            st->rho = rz;
+            if (rr <= st->tol2) {
+                st->status = kStOk;
+                st->done = kConvergedPending;
+            } else if (it >= st->maxit) {
+                st->status = kStNotConverged;
+                st->done = kCapPending;
+            }
+        }
+        lds[NV] = beta;
+        lds[NV + 1] = stepped;
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int k = threadIdx.x;
+        double prod = 0.0;
+        if (k < y) {
+            double mu = 0.0;
+            for (int j = 0; j < y; ++j) mu += B.Ginv[k * y + j] * lds[2 + j];
+            st->mu[k] = mu;
+            const double beta = lds[NV];
+            const double nu_old = st->nu[k];
+            if (lds[NV + 1] != 0.0) st->xi[k] += alpha * nu_old;
+            const double nu_new = mu + beta * nu_old;
+            const double a_new = lds[2 + k] + beta * st->acc[k];
+            st->nu[k] = nu_new;
+            st->acc[k] = a_new;
+            prod = nu_new * a_new;
+        }
+        prod = wave_sum(prod);
+        if (k == 0) st->gcorr = prod;
+    }
+}
+
 // Loop kernel 3: x <- x + alpha p, then (while iterating) the new direction
 //   p <- z + beta p - W mu,
 // which keeps p A-orthogonal to range(W) (Alg. 1).  INIT forms the first
@@ -214,10 +310,47 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
             st->done = kFinished;
         }
     }
-    if (threadIdx.x < y) {
+    // implicit form: the first direction is p = z - W mu = pt - W nu with
+    // pt = z, nu = mu, a = (A W)^T z and xi = 0
+    const bool imp = st->implicit != 0;
+    if (threadIdx.x < kWave) {
+        const int k = threadIdx.x;
+        double prod = 0.0;
+        if (k < y) {
+            double s = 0.0;
+            for (int j = 0; j < y; ++j) s += B.Ginv[k * y + j] * lds[2 + j];
+            st->mu[k] = s;
+            if (imp) {
+                st->nu[k] = s;
+                st->acc[k] = lds[2 + k];
+                st->xi[k] = 0.0;
+                prod = s * lds[2 + k];
+            }
+        }
+        if (imp) {
+            prod = wave_sum(prod);
+            if (k == 0) st->gcorr = prod;
+        }
+    }
+}
+
+// Implicit form, after the loop: x = xt - W xi.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_implicit_finish(DevBufs B, int y, double* __restrict__ x,
+                                                            const double* __restrict__ W) {
+    const DevState* st = B.st;
+    double xi[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int k = 0; k < YB; ++k) xi[k] = k < y ? st->xi[k] : 0.0;
+    const int n = B.n;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         double s = 0.0;
-        for (int j = 0; j < y; ++j) s += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
-        st->mu[threadIdx.x] = s;
+#pragma unroll
+        for (int k = 0; k < YB; ++k) {
+            const double w = basis_load<true>(W + (size_t)tier_col<YB>(k, y) * B.ld + i);
+            if (tier_live<YB>(k, y)) s += w * xi[k];
+        }
+        x[i] -= s;
     }
 }
 
@@ -260,8 +393,11 @@ __global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
         c[i] = a[i] + s * b[i];
 }
 
-__global__ void k_state_init(DevState* st, int maxit, double tol2, int y) {
+__global__ void k_state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
     if (threadIdx.x != 0) return;
+    st->implicit = implicit;
+    st->gcorr = 0.0;
+    for (int k = 0; k < kYMax; ++k) st->nu[k] = st->acc[k] = st->xi[k] = 0.0;
     st->iter = 0;
     st->done = kRunning;
     st->status = kStNotConverged;
@@ -377,6 +513,31 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
     return hipGetLastError();
 }
 
+hipError_t launch_update_implicit(const DevBufs& B, int yb, int y, double* r, double* z, const double* qt,
+                                  const double* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (y < 1) return hipErrorInvalidValue;
+    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: PODCG_LAUNCH((k_update_imp<T>), g, t, s, e0, e1, B, y, r, z, qt, AW); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_implicit_finish(const DevBufs& B, int yb, int y, double* x, const double* W, hipStream_t s) {
+    if (y < 1) return hipErrorInvalidValue;
+    dim3 g(vec_grid(B.n)), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_implicit_finish<T>), g, t, 0, s, B, y, x, W); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                       const double* W, bool init, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
@@ -450,8 +611,8 @@ hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, d
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s) {
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, tol2, y);
+hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s, bool implicit) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, tol2, y, implicit ? 1 : 0);
     return hipGetLastError();
 }
 

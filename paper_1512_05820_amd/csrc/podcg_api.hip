@@ -61,7 +61,7 @@ void check_opts(const podcg_options& o) {
         !(o.rank_rtol >= 0.0) || !(o.energy > 0.0) || (o.precision != 0 && o.precision != 1) ||
         o.max_refine < 1 || !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0) || o.spmv_grid < 0 ||
         o.spmv_grid > kLoopGridMax || o.update_grid < 0 || o.update_grid > kLoopGridMax || o.dir_grid < 0 ||
-        o.dir_grid > kLoopGridMax)
+        o.dir_grid > kLoopGridMax || (o.projection != 0 && o.projection != 1))
         throw Fail{PODCG_ERR_INVALID_ARG};
 }
 
@@ -204,21 +204,28 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         HIPCHECK(hipEventRecord(ctx->ev_c, s));
         sync(ctx);
     } else {
-        HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s));
+        // implicit form: d_p holds pt and the direction kernel carries no basis
+        const bool imp = y > 0 && ctx->opt.projection == 1;
+        const int dyb = imp ? 0 : yb, dy = imp ? 0 : y;
+        HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s, imp));
         // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
         HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
         // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r, mu = G^{-1} (A W)^T z
         HIPCHECK(launch_stage1_apply(B, yb, y, x, ctx->d_r, ctx->d_z, ctx->d_W, ctx->d_AW, s));
-        // p = z - W mu
-        HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
+        // p = z - W mu (explicit), pt = z (implicit)
+        HIPCHECK(launch_dir(B, dyb, dy, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
         int polls = 0;
         std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev) {
             hipEvent_t none[6] = {};
             hipEvent_t* e = t ? ev : none;
             HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s, e[0], e[1]));
-            HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
-            HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s, e[4], e[5]));
+            if (imp)
+                HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
+            else
+                HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
+            HIPCHECK(launch_dir(B, dyb, dy, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s, e[4], e[5]));
         });
+        if (imp) HIPCHECK(launch_implicit_finish(B, yb, y, x, ctx->d_W, s));   // x = xt - W xi
         // true residual ||b - A x||
         HIPCHECK(launch_resid(B, 0, 0, b, x, nullptr, nullptr, false, false, s));
         HIPCHECK(hipEventRecord(ctx->ev_c, s));
@@ -293,7 +300,7 @@ void podcg_default_options(podcg_options* o) {
     o->spmv_grid = 0;
     o->update_grid = 0;
     o->dir_grid = 0;
-    o->reserved = 0;
+    o->projection = 1;
 }
 
 const char* podcg_strerror(int code) {

@@ -43,12 +43,16 @@ constexpr int kFailed = -1;
 // what the host polls.
 struct DevState {
     int iter, done, status, y;
-    int maxit, pad0, pad1, pad2;
+    int maxit, implicit, pad1, pad2;   // implicit: the direction is kept as p = pt - W nu
     double rr, rr0, bnorm2, true_rr;
     double tol2, rho, alpha, beta, gamma;
-    double pad3[3];
+    double gcorr;          // implicit form: nu^T a, subtracted from (A pt, pt) to give (A p, p)
+    double pad3[2];
     double mu[kYMax];      // projection coefficients G^{-1} (A W)^T z
     double what[kYMax];    // Stage-1 coefficients G^{-1} W^T rbar
+    double nu[kYMax];      // implicit form: p = pt - W nu
+    double acc[kYMax];     // implicit form: a = (A W)^T pt, carried by its recurrence
+    double xi[kYMax];      // implicit form: x = xt - W xi
 };
 
 struct PollBlock {         // host mirror of the first 48 bytes of DevState
@@ -293,6 +297,15 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
                       hipEvent_t e1 = nullptr);
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s);
+// Implicit form of the direction (state flag `implicit`): the loop keeps
+// pt = z + beta pt and the coefficients nu of p = pt - W nu, so the direction
+// kernel runs with no basis columns and the update kernel forms
+// A p = A pt - (A W) nu from the columns of A W it already streams.  The
+// solution accumulates x = xt - W xi; launch_implicit_finish applies W xi once.
+hipError_t launch_update_implicit(const DevBufs& B, int yb, int y, double* r, double* z, const double* qt,
+                                  const double* AW, hipStream_t s, hipEvent_t e0 = nullptr,
+                                  hipEvent_t e1 = nullptr);
+hipError_t launch_implicit_finish(const DevBufs& B, int yb, int y, double* x, const double* W, hipStream_t s);
 // FP32 loop kernels of the mixed-precision inner solve (same state machine).
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
                            const float* AW, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
@@ -312,7 +325,8 @@ hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const d
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, double sc,
                         hipStream_t s);
-hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s);
+hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStream_t s,
+                             bool implicit = false);
 
 // Register tiers compiled for the basis dimension.  Up to 16 the kernels are
 // instantiated for the exact dimension (every column load is unconditional

@@ -38,7 +38,7 @@ class PodCG:
                  check_every: int = 16, weights: str = "idw", timing: int = 0,
                  rank_rtol: float = 1e-12, energy: float = 1.0, precision: str = "fp64",
                  max_refine: int = 20, inner_rtol: float = 1e-6, spmv_grid: int = 0,
-                 update_grid: int = 0, dir_grid: int = 0, stream=None):
+                 update_grid: int = 0, dir_grid: int = 0, projection: str = "implicit", stream=None):
         self._L = L.load()
         opt = L.Options()
         self._L.podcg_default_options(C.byref(opt))
@@ -49,6 +49,7 @@ class PodCG:
         opt.precision = {"fp64": 0, "mixed": 1}[precision]
         opt.max_refine, opt.inner_rtol = max_refine, inner_rtol
         opt.spmv_grid, opt.update_grid, opt.dir_grid = spmv_grid, update_grid, dir_grid
+        opt.projection = {"explicit": 0, "implicit": 1}[projection]
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

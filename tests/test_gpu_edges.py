@@ -44,8 +44,8 @@ def _ctx(P, n, rowptr, colind, vals, **kw):
     return c
 
 
-@pytest.mark.parametrize("y", [17, 24, 32])
-def test_lockstep_wide_basis_tiers(P, y):
+@pytest.mark.parametrize("y,projection", [(17, "implicit"), (24, "implicit"), (32, "explicit"), (32, "implicit")])
+def test_lockstep_wide_basis_tiers(P, y, projection):
     cfg = config2(N=16, steps=3)
     vals = cfg.matrix_values(2)
     A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
@@ -53,7 +53,7 @@ def test_lockstep_wide_basis_tiers(P, y):
     W = r.standard_normal((cfg.n, y))
     b = cfg.rhs(2, r.standard_normal(cfg.n) * 1e-3)
     xo, so = oracle.aug_pcg(A, b, np.zeros(cfg.n), W, tol=1e-10, maxit=20000)
-    ctx = _ctx(P, cfg.n, cfg.rowptr, cfg.colind, vals, rank_max=32, maxit=so.iters)
+    ctx = _ctx(P, cfg.n, cfg.rowptr, cfg.colind, vals, rank_max=32, maxit=so.iters, projection=projection)
     ctx.set_basis(_dev(W))
     x = _dev(np.zeros(cfg.n))
     st = ctx.solve(_dev(b), x, 0.0)

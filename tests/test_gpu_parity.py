@@ -203,11 +203,11 @@ def test_pod_rank_cut_on_duplicate_snapshots(P):
 
 # ------------------------------------------------------------------- solves
 
-def _lockstep(P, cfg, vals, b, xbar, W, tol, maxit=20000):
+def _lockstep(P, cfg, vals, b, xbar, W, tol, maxit=20000, projection="implicit"):
     A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
     xo, so = oracle.aug_pcg(A, b, xbar, W, tol=tol, maxit=maxit)
     y = 0 if W is None else W.shape[1]
-    ctx = _ctx(P, cfg.n, rank_max=max(y, 1), maxit=so.iters)
+    ctx = _ctx(P, cfg.n, rank_max=max(y, 1), maxit=so.iters, projection=projection)
     _set(ctx, cfg.rowptr, cfg.colind, vals)
     ctx.set_basis(None if W is None else _dev(W))
     x = _dev(xbar)
@@ -215,31 +215,32 @@ def _lockstep(P, cfg, vals, b, xbar, W, tol, maxit=20000):
     return xo, so, _host(x), st
 
 
-@pytest.mark.parametrize("use_basis", [False, True])
-def test_lockstep_config1(P, use_basis):
+@pytest.mark.parametrize("use_basis,projection", [(False, "implicit"), (True, "explicit"), (True, "implicit")])
+def test_lockstep_config1(P, use_basis, projection):
     cfg = config1()
     vals = cfg.matrix_values(3)
     b = cfg.rhs(3)
     W = _rng(9).standard_normal((cfg.n, 4)) if use_basis else None
-    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol)
+    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol, projection=projection)
     assert so.status == 0 and st.iters == so.iters
     assert _relerr(xg, xo) <= 1e-10
 
 
+@pytest.mark.parametrize("projection", ["explicit", "implicit"])
 @pytest.mark.parametrize("N", [24, 33])
-def test_lockstep_config2_small(P, N):
+def test_lockstep_config2_small(P, N, projection):
     cfg = config2(N=N, steps=4)
     vals = cfg.matrix_values(2)
     r = _rng(N)
     b = cfg.rhs(2, r.standard_normal(cfg.n) * 1e-3)
     W = r.standard_normal((cfg.n, 10))
-    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol)
+    xo, so, xg, st = _lockstep(P, cfg, vals, b, np.zeros(cfg.n), W, cfg.tol, projection=projection)
     assert so.status == 0 and st.iters == so.iters
     assert _relerr(xg, xo) <= 1e-10
 
 
-def _gpu_sequence(P, cfg, steps, method="aug", warm=False):
-    ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank)
+def _gpu_sequence(P, cfg, steps, method="aug", warm=False, projection="implicit"):
+    ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank, projection=projection)
     rowptr, colind = _dev(cfg.rowptr, torch.int32), _dev(cfg.colind, torch.int32)
     out = []
     x_prev = None
@@ -265,8 +266,9 @@ def _gpu_sequence(P, cfg, steps, method="aug", warm=False):
     return out
 
 
-@pytest.mark.parametrize("which", ["c1", "c1_r2", "c2_small"])
-def test_closed_loop_sequence(P, which):
+@pytest.mark.parametrize("which,projection", [("c1", "implicit"), ("c1_r2", "implicit"),
+                                              ("c2_small", "explicit"), ("c2_small", "implicit")])
+def test_closed_loop_sequence(P, which, projection):
     if which == "c1":
         cfg = config1()
     elif which == "c1_r2":
@@ -274,7 +276,7 @@ def test_closed_loop_sequence(P, which):
     else:
         cfg = config2(N=26, steps=8)
     orc = oracle.run_sequence(cfg, "aug")
-    gpu = _gpu_sequence(P, cfg, cfg.steps)
+    gpu = _gpu_sequence(P, cfg, cfg.steps, projection=projection)
     for o, (st, x, b, vals) in zip(orc, gpu):
         A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
         tr = np.linalg.norm(b - oracle.matvec(A, x)) / np.linalg.norm(b)
@@ -404,6 +406,51 @@ def test_exact_recovery_zero_iterations(P):
     st = ctx.solve(_dev(b), x, 1e-10)
     assert st.iters == 0 and st.status == 0
     assert _relerr(_host(x), W @ c) <= 1e-12
+
+
+def test_implicit_and_explicit_direction_forms_agree(P):
+    """The implicit form (p = pt - W nu, x = xt - W xi) against the explicit
+    form of Alg. 1 on a POD basis built from a sequence: same iteration
+    counts, solutions within 1e-12; a solve stopped by the iteration cap
+    returns a consistent x (the reported true residual is the oracle's
+    residual of the returned x)."""
+    cfg = config2(N=30, steps=6)
+    rp, ci = _dev(cfg.rowptr, torch.int32), _dev(cfg.colind, torch.int32)
+    ctx = {f: _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank, projection=f) for f in ("explicit", "implicit")}
+    capped = {f: _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank, projection=f, maxit=7)
+              for f in ("explicit", "implicit")}
+    x_prev = None
+    for j in range(1, cfg.steps + 1):
+        vals = cfg.matrix_values(j)
+        A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+        b = cfg.rhs(j, x_prev)
+        out, cap = {}, {}
+        for f in ("explicit", "implicit"):
+            for c in (ctx[f], capped[f]):
+                if j == 1:
+                    c.set_matrix(_dev(vals), rp, ci)
+                else:
+                    c.set_matrix(_dev(vals))
+            x = _dev(np.zeros(cfg.n))
+            out[f] = (ctx[f].solve(_dev(b), x, cfg.tol), _host(x))
+            xc = _dev(np.zeros(cfg.n))
+            cap[f] = (capped[f].solve(_dev(b), xc, 0.0), _host(xc))
+        (se, xe), (si, xi) = out["explicit"], out["implicit"]
+        assert se.rank == si.rank and se.iters == si.iters, (j, se.iters, si.iters)
+        assert _relerr(xi, xe) <= 1e-12
+        assert si.true_relres <= cfg.tol * 1.01
+        (ce, xce), (ci_, xci) = cap["explicit"], cap["implicit"]
+        if si.rank > 0:
+            assert ci_.status == 1 and ci_.iters == 7
+        assert _relerr(xci, xce) <= 1e-12
+        res = np.linalg.norm(b - oracle.matvec(A, xci)) / np.linalg.norm(b)
+        assert abs(res - ci_.true_relres) <= 1e-6 * res
+        for f in ("explicit", "implicit"):
+            ctx[f].push_snapshot(_dev(out[f][1]))
+            ctx[f].build_pod()
+            capped[f].push_snapshot(_dev(out[f][1]))
+            capped[f].build_pod()
+        x_prev = xe
 
 
 # ------------------------------------------------------------------- full size
