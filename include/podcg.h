@@ -72,7 +72,7 @@ typedef struct {
     double  inner_rtol;   /* relative tolerance of each FP32 inner solve (precision = 1)      */
     int32_t spmv_grid;    /* workgroups of the loop SpMV (0 = default 1024; at most 4096)     */
     int32_t update_grid;  /* workgroups of the residual-update kernel (0 = default 512; <= 4096) */
-    int32_t dir_grid;     /* workgroups of the direction kernel (0 = default 4096; <= 4096)   */
+    int32_t dir_grid;     /* workgroups of the direction kernel (0 = default 1024; <= 4096)   */
     int32_t projection;   /* form of the direction recurrence of Alg. 1 in FP64 solves:
                              0 explicit: p = z + beta p - W mu is formed every iteration;
                              1 implicit: the loop keeps pt = z + beta pt and the coefficients

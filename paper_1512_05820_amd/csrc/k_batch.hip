@@ -288,7 +288,7 @@ __global__ void k_batch_gather(const BatchMember* __restrict__ mem, int count, P
     P.status = st->status;
     P.y = st->y;
     P.maxit = st->maxit;
-    P.pad0 = P.pad1 = P.pad2 = 0;
+    P.pad0 = P.stop = P.pad2 = 0;
     P.rr = st->rr;
     P.rr0 = st->rr0;
     P.bnorm2 = st->bnorm2;

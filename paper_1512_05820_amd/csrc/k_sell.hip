@@ -188,22 +188,18 @@ __global__ __launch_bounds__(kBlock) void k_pattern_outer(int n, int nslices,
 
 // ---------------------------------------------------------------- products
 
-// Loop kernel 1 of augmented PCG (Alg. 1): q = A p and gamma = (A p, p);
-// the last workgroup forms alpha = (r, z) / gamma.  T is the storage type of
-// the matrix and vectors (FP64, or FP32 for the inner solve of mixed
-// precision); row sums and gamma are accumulated in FP64 and q is rounded to
-// T once.
+// Loop kernel 1 of augmented PCG (Alg. 1), iteration k: q = A p and the
+// workgroup's share of gamma = (A p, p), stored in gpart[block].  The update
+// kernel that follows sums the partials itself (every workgroup, in the same
+// order) and forms alpha = (r, z) / gamma, so this kernel ends without a
+// serial reduction tail.  T is the storage type of the matrix and vectors
+// (FP64, or FP32 for the inner solve of mixed precision); row sums and gamma
+// are accumulated in FP64 and q is rounded to T once.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __restrict__ p,
-                                                       T* __restrict__ q) {
+                                                       T* __restrict__ q, int k) {
     __shared__ double lds[kWavesPerBlock * 1 + 1 + 1];
-    DevState* st = B.st;
-    const int done = st->done;
-    if (done != kRunning) {
-        if ((done == kConvergedPending || done == kCapPending) && blockIdx.x == 0 && threadIdx.x == 0)
-            st->done = kFinished;
-        return;
-    }
+    if (k >= B.st->stop) return;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int nb = gridDim.x;
     const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -220,18 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
             }
         }
     }
-    if (grid_sum_last<1>(g, B.part, B.counter, lds) && threadIdx.x == 0) {
-        // gcorr is 0 unless the direction is kept in implicit form (then p is
-        // pt - W nu, this kernel multiplies pt, and gcorr = nu^T (A W)^T pt)
-        const double gamma = lds[0] - st->gcorr;
-        st->gamma = gamma;
-        if (!(gamma > 0.0) || !is_finite(gamma)) {
-            st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
-            st->done = kFailed;
-        } else {
-            st->alpha = st->rho / gamma;
-        }
-    }
+    block_sum<1>(g, lds);
+    if (threadIdx.x == 0) store_shared(B.gpart + blockIdx.x, lds[0]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_matvec(DevBufs B, const double* __restrict__ x,
@@ -296,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
             if (!is_finite(bb) || !is_finite(lds[1])) {
                 st->status = kStNonfinite;
                 st->done = kFailed;
+                st->stop = 0;       // no loop kernel runs
             }
         }
         if (threadIdx.x < y) {
@@ -453,6 +440,8 @@ static int grid_for_slices(int nslices, int cap = kSpmvGrid) {
     return groups < cap ? groups : cap;
 }
 
+int spmv_blocks(const DevBufs& B) { return grid_for_slices(B.nslices, B.spmv_grid); }
+
 static int grid_for(int64_t items, int cap) {
     int64_t g = (items + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -507,17 +496,15 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s, hipEvent_t e0,
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1) {
-    PODCG_LAUNCH((k_spmv_gamma<double>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), s, e0, e1,
-                 B, p, q);
+    PODCG_LAUNCH((k_spmv_gamma<double>), dim3(spmv_blocks(B)), dim3(kBlock), s, e0, e1, B, p, q, k);
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s, hipEvent_t e0,
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, int k, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
-    PODCG_LAUNCH((k_spmv_gamma<float>), dim3(grid_for_slices(B.nslices, B.spmv_grid)), dim3(kBlock), s, e0, e1,
-                 B, p, q);
+    PODCG_LAUNCH((k_spmv_gamma<float>), dim3(spmv_blocks(B)), dim3(kBlock), s, e0, e1, B, p, q, k);
     return hipGetLastError();
 }
 

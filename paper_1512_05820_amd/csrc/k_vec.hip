@@ -16,12 +16,6 @@ int basis_tier(int y) {
     return -1;
 }
 
-// Loop kernel 2 of augmented PCG (Alg. 1): with alpha from kernel 1,
-//   r <- r - alpha q,  z <- M^{-1} r  (Jacobi),
-// and the sums (r, z), (r, r), c = (A W)^T z.  The last workgroup forms
-//   beta = (r', z') / (r, z),  mu = G^{-1} c  (the solve with W^T A W of
-// Alg. 1, with G^{-1} from the Cholesky factor of Stage 1),
-// counts the iteration and tests ||r|| <= tol ||b||.
 // Column of W or A W: read once per iteration, so loaded nontemporally when
 // NTB (keeps the smaller vectors resident in the caches).
 template <bool NTB, typename T>
@@ -29,164 +23,216 @@ __device__ __forceinline__ T basis_load(const T* p) {
     return NTB ? __builtin_nontemporal_load(p) : *p;
 }
 
+// alpha of iteration k, at the start of every update workgroup: the SpMV's
+// per-workgroup partials of (A p, p) are summed here in a fixed order (the
+// same in every workgroup), minus gcorr in the implicit form.  Workgroup 0
+// records alpha and gamma in slot k & 1.  Returns false when gamma is not
+// positive and finite; then workgroup 0 records the failure and stops the loop.
+__device__ __forceinline__ bool loop_alpha(const DevBufs& B, int k, int nsp, double gcorr, double* ldsg,
+                                           double& alpha) {
+    DevState* st = B.st;
+    const int par = k & 1;
+    const double rho = st->lrho[par];       // read next to the partials, before the barrier
+    double g[1] = {0.0};
+    // the SpMV is the previous kernel of the stream: plain loads see its writes
+    for (int t = threadIdx.x; t < nsp; t += kBlock) g[0] += B.gpart[t];
+    block_sum<1>(g, ldsg);
+    const double gamma = ldsg[0] - gcorr;
+    const bool ok = gamma > 0.0 && is_finite(gamma);
+    if (ok) alpha = rho / gamma;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->gamma = gamma;
+        if (ok) {
+            st->lgamma[par] = gamma;
+            st->lalpha[par] = alpha;
+            st->alpha = alpha;
+        } else {
+            st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
+            st->done = kFailed;
+            st->stop = k;
+        }
+    }
+    return ok;
+}
+
+// Loop kernel 2 of augmented PCG (Alg. 1), iteration k: with alpha from the
+// SpMV's partials,
+//   r <- r - alpha q,  z <- M^{-1} r  (Jacobi),
+// and the sums (r, z), (r, r), c = (A W)^T z, reduced per group of
+// workgroups; the direction kernel finishes the sums.
 // T: storage and arithmetic type of the vectors and of A W (FP64, or FP32
 // for the inner solve of mixed precision); all sums are accumulated in FP64.
 template <typename T, int YB, bool NTB = false>
 __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restrict__ r,
                                                    T* __restrict__ z, const T* __restrict__ q,
-                                                   const T* __restrict__ AW) {
+                                                   const T* __restrict__ AW, int k, int nsp) {
     constexpr int NV = 2 + YB;
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
-    DevState* st = B.st;
-    if (st->done != kRunning) return;
-    const T alpha = (T)st->alpha;
+    __shared__ double ldsg[kWavesPerBlock + 2];
+    if (k >= B.st->stop) return;
     const T* __restrict__ dinv = mat_dinv<T>(B);
-    double v[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = 0.0;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const T ri = r[i] - alpha * q[i];
-        const T zi = dinv[i] * ri;
+    // the first element's operands are loaded before alpha is formed, so the
+    // memory system is busy while every workgroup sums the SpMV partials
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    T r0 = 0, q0 = 0, d0 = 0, a0[YB > 0 ? YB : 1];
+    if (i0 < n) {
+        r0 = r[i0];
+        q0 = q[i0];
+        d0 = dinv[i0];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) a0[j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i0);
+    }
+    double alpha_d;
+    if (!loop_alpha(B, k, nsp, 0.0, ldsg, alpha_d)) return;
+    const T alpha = (T)alpha_d;
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = 0.0;
+    auto step = [&](int i, T rold, T qi, T di, const T* a) {
+        const T ri = rold - alpha * qi;
+        const T zi = di * ri;
         r[i] = ri;
         z[i] = zi;
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
 #pragma unroll
-        for (int k = 0; k < YB; ++k) {
-            const T a = basis_load<NTB>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
-            if (tier_live<YB>(k, y)) v[2 + k] += (double)a * (double)zi;
-        }
+        for (int j = 0; j < YB; ++j)
+            if (tier_live<YB>(j, y)) v[2 + j] += (double)a[j] * (double)zi;
+    };
+    if (i0 < n) step(i0, r0, q0, d0, a0);
+    for (int i = i0 + stride; i < n; i += stride) {
+        T a[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) a[j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i);
+        step(i, r[i], q[i], dinv[i], a);
     }
-    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
-    if (threadIdx.x == 0) {
-        const double rz = lds[0], rr = lds[1];
-        const int it = st->iter + 1;
-        st->iter = it;
-        st->rr = rr;
-        if (!is_finite(rr) || !is_finite(rz)) {
-            st->status = kStNonfinite;
-            st->done = kFailed;
-        } else {
-            st->beta = rz / st->rho;
-            st->rho = rz;
-            if (rr <= st->tol2) {
-                st->status = kStOk;
-                st->done = kConvergedPending;
-            } else if (it >= st->maxit) {
-                st->status = kStNotConverged;
-                st->done = kCapPending;
-            }
-        }
-    }
-    if (threadIdx.x < y) {
-        double s = 0.0;
-        for (int j = 0; j < y; ++j) s += B.Ginv[threadIdx.x * y + j] * lds[2 + j];
-        st->mu[threadIdx.x] = s;
-    }
+    group_sum_store<NV>(v, B.part, B.counter, lds);
 }
 
 // Loop kernel 2 in the implicit form of the direction, p = pt - W nu.  The
 // SpMV has produced qt = A pt, and
 //   A p = A pt - (A W) nu,  r <- r - alpha A p,  z <- M^{-1} r,
 // with the sums (r, z), (r, r), c = (A W)^T z: each column of A W is loaded
-// once and serves both A p and c.  The last workgroup forms beta and
-// mu = G^{-1} c as in the explicit form and then advances
-//   xi <- xi + alpha nu        (x += alpha p is alpha pt, minus W alpha nu),
-//   nu <- mu + beta nu         (p' = z + beta p - W mu = pt' - W nu'),
-//   a  <- c + beta a           (a = (A W)^T pt, by the same recurrence),
-//   gcorr = nu^T a,
-// so that the next SpMV turns (A pt, pt) into (A p, p) = (A pt, pt) - nu^T a
-// (this uses (A W)^T p = 0, the property Alg. 1's projection maintains).
+// once and serves both A p and c.  gamma = (A p, p) = (A pt, pt) - nu^T a with
+// a = (A W)^T pt (this uses (A W)^T p = 0, the property Alg. 1's projection
+// maintains).
 template <int YB>
 __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double* __restrict__ r,
                                                        double* __restrict__ z,
                                                        const double* __restrict__ qt,
-                                                       const double* __restrict__ AW) {
+                                                       const double* __restrict__ AW, int k, int nsp) {
     constexpr int NV = 2 + YB;
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
-    DevState* st = B.st;
-    if (st->done != kRunning) return;
-    const double alpha = st->alpha;
-    double nu[YB > 0 ? YB : 1];
-#pragma unroll
-    for (int k = 0; k < YB; ++k) nu[k] = k < y ? st->nu[k] : 0.0;
-    double v[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    __shared__ double ldsg[kWavesPerBlock + 2];
+    const DevState* st = B.st;
+    if (k >= st->stop) return;
+    const int par = k & 1;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        double a[YB > 0 ? YB : 1];
-        double qi = qt[i];
+    // first element's operands in flight while alpha is formed
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    double r0 = 0.0, q0 = 0.0, d0 = 0.0, a0[YB > 0 ? YB : 1];
+    if (i0 < n) {
+        r0 = r[i0];
+        q0 = qt[i0];
+        d0 = B.dinv[i0];
 #pragma unroll
-        for (int k = 0; k < YB; ++k) {
-            a[k] = basis_load<true>(AW + (size_t)tier_col<YB>(k, y) * B.ld + i);
-            if (tier_live<YB>(k, y)) qi -= a[k] * nu[k];
-        }
-        const double ri = r[i] - alpha * qi;
-        const double zi = B.dinv[i] * ri;
+        for (int j = 0; j < YB; ++j) a0[j] = basis_load<true>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i0);
+    }
+    double nu[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int j = 0; j < YB; ++j) nu[j] = j < y ? st->lnu[par][j] : 0.0;
+    double alpha;
+    if (!loop_alpha(B, k, nsp, st->lgcorr[par], ldsg, alpha)) return;
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = 0.0;
+    auto step = [&](int i, double rold, double qi, double di, const double* a) {
+#pragma unroll
+        for (int j = 0; j < YB; ++j)
+            if (tier_live<YB>(j, y)) qi -= a[j] * nu[j];
+        const double ri = rold - alpha * qi;
+        const double zi = di * ri;
         r[i] = ri;
         z[i] = zi;
         v[0] += ri * zi;
         v[1] += ri * ri;
 #pragma unroll
-        for (int k = 0; k < YB; ++k)
-            if (tier_live<YB>(k, y)) v[2 + k] += a[k] * zi;
+        for (int j = 0; j < YB; ++j)
+            if (tier_live<YB>(j, y)) v[2 + j] += a[j] * zi;
+    };
+    if (i0 < n) step(i0, r0, q0, d0, a0);
+    for (int i = i0 + stride; i < n; i += stride) {
+        double a[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) a[j] = basis_load<true>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i);
+        step(i, r[i], qt[i], B.dinv[i], a);
     }
-    if (!grid_sum_last<NV>(v, B.part, B.counter, lds)) return;
-    if (threadIdx.x == 0) {
-        const double rz = lds[0], rr = lds[1];
-        const int it = st->iter + 1;
-        st->iter = it;
+    group_sum_store<NV>(v, B.part, B.counter, lds);
+}
+
+// Start of loop kernel 3 of iteration k, in every workgroup: the update's
+// group partials summed in group order (lds[0] = (r', z'), lds[1] = (r', r'),
+// lds[2 + j] = c_j); beta = (r', z') / (r, z), the convergence test
+// ||r'|| <= tol ||b||, the iteration cap, and, when MU, mu = G^{-1} c into smu
+// (Alg. 1's projection solve).  Workgroup 0 records the iteration (count,
+// ||r'||^2, (r', z') in slot (k + 1) & 1, status and stop).  Returns false
+// when the sums are not finite (no step is applied then).
+// The scalars of the state and G^{-1} (into sginv) are read at entry, next to
+// the partial loads, so the prologue costs one memory round trip.
+struct DirStep {
+    double alpha, beta;
+    bool new_dir;
+};
+template <int NV, int YB, bool MU>
+__device__ __forceinline__ bool dir_begin(const DevBufs& B, int y, int k, int nbu, double* lds, double* smu,
+                                          double* sginv, DirStep& d) {
+    DevState* st = B.st;
+    const int par = k & 1;
+    const double alpha = st->lalpha[par], rho = st->lrho[par], tol2 = st->tol2;
+    const int maxit = st->maxit;
+    if (MU)
+        for (int e = threadIdx.x; e < y * y; e += kBlock) sginv[e] = B.Ginv[e];
+    group_sum_load<NV>(B.part, nbu, lds);   // ends with a barrier, after which sginv is complete
+    const double rz = lds[0], rr = lds[1];
+    const bool ok = is_finite(rr) && is_finite(rz);
+    const bool conv = rr <= tol2, cap = k + 1 >= maxit;
+    d.alpha = alpha;
+    d.beta = ok ? rz / rho : 0.0;
+    d.new_dir = ok && !conv && !cap;
+    if (MU && threadIdx.x < y) {
+        double s = 0.0;
+        for (int j = 0; j < y; ++j) s += sginv[threadIdx.x * y + j] * lds[2 + j];
+        smu[threadIdx.x] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter = k + 1;
         st->rr = rr;
-        double beta = 0.0, stepped = 1.0;
-        if (!is_finite(rr) || !is_finite(rz)) {
+        if (!ok) {
             st->status = kStNonfinite;
             st->done = kFailed;
-            stepped = 0.0;     // the direction kernel will not apply this step to x
+            st->stop = k;
         } else {
-            beta = rz / st->rho;
-            st->beta = beta;
+            st->beta = d.beta;
             st->rho = rz;
-            if (rr <= st->tol2) {
-                st->status = kStOk;
-                st->done = kConvergedPending;
-            } else if (it >= st->maxit) {
-                st->status = kStNotConverged;
-                st->done = kCapPending;
+            st->lrho[par ^ 1] = rz;
+            if (conv || cap) {
+                st->status = conv ? kStOk : kStNotConverged;
+                st->done = kFinished;
+                st->stop = k + 1;
             }
         }
-        lds[NV] = beta;
-        lds[NV + 1] = stepped;
     }
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-        const int k = threadIdx.x;
-        double prod = 0.0;
-        if (k < y) {
-            double mu = 0.0;
-            for (int j = 0; j < y; ++j) mu += B.Ginv[k * y + j] * lds[2 + j];
-            st->mu[k] = mu;
-            const double beta = lds[NV];
-            const double nu_old = st->nu[k];
-            if (lds[NV + 1] != 0.0) st->xi[k] += alpha * nu_old;
-            const double nu_new = mu + beta * nu_old;
-            const double a_new = lds[2 + k] + beta * st->acc[k];
-            st->nu[k] = nu_new;
-            st->acc[k] = a_new;
-            prod = nu_new * a_new;
-        }
-        prod = wave_sum(prod);
-        if (k == 0) st->gcorr = prod;
-    }
+    if (MU) __syncthreads();
+    return ok;
 }
 
 // Loop kernel 3: x <- x + alpha p, then (while iterating) the new direction
 //   p <- z + beta p - W mu,
 // which keeps p A-orthogonal to range(W) (Alg. 1).  INIT forms the first
-// direction p = z - W mu and leaves x alone.
+// direction p = z - W mu (mu from Stage 1) and leaves x alone.
 // The solution x is always FP64: with FP32 vectors (mixed precision) the
 // update x += alpha p is carried out in FP64, so the correction of a
 // refinement step is accumulated without FP32 rounding.
@@ -204,45 +250,142 @@ struct DirRecord {
 template <typename T, int YB, bool INIT, bool NTB = false, bool REC = false>
 __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict__ p,
                                                 double* __restrict__ x, const T* __restrict__ z,
-                                                const T* __restrict__ W, DirRecord rec) {
+                                                const T* __restrict__ W, DirRecord rec, int k, int nbu) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    __shared__ double smu[YB > 0 ? YB : 1];
+    __shared__ double sginv[YB > 0 ? YB * YB : 1];
     const DevState* st = B.st;
-    const int done = st->done;
-    if (INIT) {
-        if (done != kRunning) return;
-    } else if (done != kRunning && done != kConvergedPending && done != kCapPending) {
-        return;
-    }
-    const bool new_dir = INIT || done == kRunning;
-    const double alpha = st->alpha;
-    const T beta = (T)st->beta;
-    T mu[YB > 0 ? YB : 1];
-#pragma unroll
-    for (int k = 0; k < YB; ++k) mu[k] = k < y ? (T)st->mu[k] : (T)0;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    // index of the direction applied in this launch (the update kernel has
-    // already counted its iteration)
-    const int krec = REC && !INIT ? st->iter - 1 : -1;
-    double* __restrict__ vrec = (REC && krec >= 0 && krec < rec.cap) ? rec.V + (size_t)krec * rec.ld : nullptr;
-    const double vscale = REC ? 1.0 / sqrt(st->gamma) : 1.0;
-    if (REC && vrec && blockIdx.x == 0 && threadIdx.x == 0) {
-        rec.gamma[krec] = st->gamma;
-        rec.alpha[krec] = alpha;
+    DirStep d{0.0, 0.0, true};
+    // the first element's operands are loaded before the reduction is
+    // finished, so the memory system is busy meanwhile
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    T p0 = 0, z0 = 0, w0[YB > 0 ? YB : 1];
+    double x0 = 0.0;
+    if (INIT) {
+        if (st->stop <= 0) return;
+        if (threadIdx.x < y) smu[threadIdx.x] = st->mu[threadIdx.x];
+        __syncthreads();
+    } else {
+        if (k >= st->stop) return;
+        if (i0 < n) {
+            p0 = p[i0];
+            z0 = z[i0];
+            x0 = x[i0];
+#pragma unroll
+            for (int j = 0; j < YB; ++j) w0[j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + i0);
+        }
+        if (!dir_begin<NV, YB, (YB > 0)>(B, y, k, nbu, lds, smu, sginv, d)) return;
     }
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    T mu[YB > 0 ? YB : 1];
+#pragma unroll
+    for (int j = 0; j < YB; ++j) mu[j] = j < y ? (T)smu[j] : (T)0;
+    const T beta = (T)d.beta;
+    const double alpha = d.alpha;
+    double* __restrict__ vrec = (REC && !INIT && k < rec.cap) ? rec.V + (size_t)k * rec.ld : nullptr;
+    const double gamma = REC && !INIT ? st->lgamma[k & 1] : 1.0;
+    const double vscale = REC ? 1.0 / sqrt(gamma) : 1.0;
+    if (REC && vrec && blockIdx.x == 0 && threadIdx.x == 0) {
+        rec.gamma[k] = gamma;
+        rec.alpha[k] = alpha;
+    }
+    auto step = [&](int i, T pi, T zi, double xi, const T* w) {
         T s;
         if (INIT) {
-            s = z[i];
+            s = zi;
         } else {
-            const T pi = p[i];
-            x[i] += alpha * (double)pi;
+            x[i] = xi + alpha * (double)pi;
             if (REC && vrec) vrec[i] = (double)pi * vscale;
-            if (!new_dir) continue;
-            s = z[i] + beta * pi;
+            if (!d.new_dir) return;
+            s = zi + beta * pi;
         }
 #pragma unroll
-        for (int k = 0; k < YB; ++k) s -= basis_load<NTB>(W + (size_t)tier_col<YB>(k, y) * B.ld + i) * mu[k];
+        for (int j = 0; j < YB; ++j) s -= w[j] * mu[j];
         p[i] = s;
+    };
+    int ifirst = i0;
+    if (!INIT) {
+        if (i0 < n) step(i0, p0, z0, x0, w0);
+        ifirst = i0 + stride;
+    }
+    for (int i = ifirst; i < n; i += stride) {
+        T w[YB > 0 ? YB : 1];
+        if (INIT || d.new_dir) {
+#pragma unroll
+            for (int j = 0; j < YB; ++j) w[j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + i);
+        }
+        step(i, INIT ? (T)0 : p[i], (INIT || d.new_dir) ? z[i] : (T)0, INIT ? 0.0 : x[i], w);
+    }
+}
+
+// Loop kernel 3 in the implicit form: x <- x + alpha pt and, while iterating,
+// pt <- z + beta pt (no basis column is read).  Workgroup 0 advances the
+// coefficients:
+//   xi <- xi + alpha nu        (x += alpha p is alpha pt, minus W alpha nu),
+//   nu <- mu + beta nu         (p' = z + beta p - W mu = pt' - W nu'),
+//   a  <- c + beta a           (a = (A W)^T pt, by the same recurrence),
+//   gcorr = nu^T a             (for the next update's gamma).
+// YB is the basis tier of the update kernel (the layout of its partials).
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __restrict__ p,
+                                                    double* __restrict__ x, const double* __restrict__ z,
+                                                    int k, int nbu) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    __shared__ double smu[YB > 0 ? YB : 1];
+    DevState* st = B.st;
+    if (k >= st->stop) return;
+    const int n = B.n;
+    const int stride = gridDim.x * kBlock;
+    // the first two elements' operands are in flight while the reduction is
+    // finished
+    const int i0 = blockIdx.x * kBlock + threadIdx.x, i1 = i0 + stride;
+    double p0 = 0.0, z0 = 0.0, x0 = 0.0, p1 = 0.0, z1 = 0.0, x1 = 0.0;
+    if (i0 < n) {
+        p0 = p[i0];
+        z0 = z[i0];
+        x0 = x[i0];
+    }
+    if (i1 < n) {
+        p1 = p[i1];
+        z1 = z[i1];
+        x1 = x[i1];
+    }
+    DirStep d;
+    if (!dir_begin<NV, YB, false>(B, y, k, nbu, lds, smu, nullptr, d)) return;
+    if (i0 < n) {
+        x[i0] = x0 + d.alpha * p0;
+        if (d.new_dir) p[i0] = z0 + d.beta * p0;
+    }
+    if (i1 < n) {
+        x[i1] = x1 + d.alpha * p1;
+        if (d.new_dir) p[i1] = z1 + d.beta * p1;
+    }
+    for (int i = i1 + stride; i < n; i += stride) {
+        const double pi = p[i];
+        x[i] += d.alpha * pi;
+        if (d.new_dir) p[i] = z[i] + d.beta * pi;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kWave) {
+        // mu = G^{-1} c is needed here only (the direction pt carries no basis)
+        const int j = threadIdx.x;
+        const int par = k & 1;
+        double prod = 0.0;
+        if (j < y) {
+            double mu = 0.0;
+            for (int i = 0; i < y; ++i) mu += B.Ginv[j * y + i] * lds[2 + i];
+            const double nu_old = st->lnu[par][j];
+            st->xi[j] += d.alpha * nu_old;
+            const double nu_new = mu + d.beta * nu_old;
+            const double a_new = lds[2 + j] + d.beta * st->lacc[par][j];
+            st->lnu[par ^ 1][j] = nu_new;
+            st->lacc[par ^ 1][j] = a_new;
+            prod = nu_new * a_new;
+        }
+        prod = wave_sum(prod);
+        if (j == 0) st->lgcorr[par ^ 1] = prod;
     }
 }
 
@@ -297,17 +440,21 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
     if (threadIdx.x == 0) {
         const double rz = lds[0], rr = lds[1];
         st->rho = rz;
+        st->lrho[0] = rz;
         st->rr = rr;
         st->rr0 = rr;
         if (!is_finite(rr) || !is_finite(rz)) {
             st->status = kStNonfinite;
             st->done = kFailed;
+            st->stop = 0;
         } else if (rr <= st->tol2) {
             st->status = kStOk;
             st->done = kFinished;
+            st->stop = 0;
         } else if (st->maxit <= 0) {
             st->status = kStNotConverged;
             st->done = kFinished;
+            st->stop = 0;
         }
     }
     // implicit form: the first direction is p = z - W mu = pt - W nu with
@@ -321,15 +468,15 @@ __global__ __launch_bounds__(kBlock) void k_stage1_apply(DevBufs B, int y, doubl
             for (int j = 0; j < y; ++j) s += B.Ginv[k * y + j] * lds[2 + j];
             st->mu[k] = s;
             if (imp) {
-                st->nu[k] = s;
-                st->acc[k] = lds[2 + k];
+                st->lnu[0][k] = s;
+                st->lacc[0][k] = lds[2 + k];
                 st->xi[k] = 0.0;
                 prod = s * lds[2 + k];
             }
         }
         if (imp) {
             prod = wave_sum(prod);
-            if (k == 0) st->gcorr = prod;
+            if (k == 0) st->lgcorr[0] = prod;
         }
     }
 }
@@ -396,8 +543,12 @@ __global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
 __global__ void k_state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
     if (threadIdx.x != 0) return;
     st->implicit = implicit;
-    st->gcorr = 0.0;
-    for (int k = 0; k < kYMax; ++k) st->nu[k] = st->acc[k] = st->xi[k] = 0.0;
+    st->stop = maxit;
+    for (int h = 0; h < 2; ++h) {
+        st->lrho[h] = st->lalpha[h] = st->lgamma[h] = st->lgcorr[h] = 0.0;
+        for (int k = 0; k < kYMax; ++k) st->lnu[h][k] = st->lacc[h][k] = 0.0;
+    }
+    for (int k = 0; k < kYMax; ++k) st->xi[k] = 0.0;
     st->iter = 0;
     st->done = kRunning;
     st->status = kStNotConverged;
@@ -465,6 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_stage1_mixed(DevBufs B, int y, doubl
     if (threadIdx.x == 0) {
         const double rz = lds[0], rr = lds[1];
         st->rho = rz;
+        st->lrho[0] = rz;
         st->rr = rr;
         st->rr0 = rr;
         // the inner solve aims at inner_rtol relative to its own right-hand
@@ -474,9 +626,11 @@ __global__ __launch_bounds__(kBlock) void k_stage1_mixed(DevBufs B, int y, doubl
         if (!is_finite(rr) || !is_finite(rz)) {
             st->status = kStNonfinite;
             st->done = kFailed;
+            st->stop = 0;
         } else if (rr == 0.0 || st->maxit <= 0) {
             st->status = rr == 0.0 ? kStOk : kStNotConverged;
             st->done = kFinished;
+            st->stop = 0;
         }
     }
     if (threadIdx.x < y) {
@@ -501,11 +655,14 @@ static int vec_grid(int64_t n, int cap = kVecBlocksMax) {
     return (int)(g < cap ? g : cap);
 }
 
+int update_blocks(const DevBufs& B) { return vec_grid(B.n, B.update_grid); }
+
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
-                         const double* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
+                         const double* AW, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    dim3 g(update_blocks(B)), t(kBlock);
+    const int nsp = spmv_blocks(B);
     switch (yb) {
-#define CASE(T) case T: PODCG_LAUNCH((k_update<double, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_update<double, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW, k, nsp); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -514,11 +671,26 @@ hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, 
 }
 
 hipError_t launch_update_implicit(const DevBufs& B, int yb, int y, double* r, double* z, const double* qt,
-                                  const double* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                                  const double* AW, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (y < 1) return hipErrorInvalidValue;
-    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
+    dim3 g(update_blocks(B)), t(kBlock);
+    const int nsp = spmv_blocks(B);
     switch (yb) {
-#define CASE(T) case T: PODCG_LAUNCH((k_update_imp<T>), g, t, s, e0, e1, B, y, r, z, qt, AW); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_update_imp<T>), g, t, s, e0, e1, B, y, r, z, qt, AW, k, nsp); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_implicit(const DevBufs& B, int yb, int y, double* p, double* x, const double* z, int k,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (y < 1) return hipErrorInvalidValue;
+    dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
+    const int nbu = update_blocks(B);
+    switch (yb) {
+#define CASE(T) case T: PODCG_LAUNCH((k_dir_imp<T>), g, t, s, e0, e1, B, y, p, x, z, k, nbu); break;
         PODCG_POS_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -539,14 +711,15 @@ hipError_t launch_implicit_finish(const DevBufs& B, int yb, int y, double* x, co
 }
 
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
-                      const double* W, bool init, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                      const double* W, bool init, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     const DirRecord none{};
+    const int nbu = update_blocks(B);
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) PODCG_LAUNCH((k_dir<double, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none); \
-        else PODCG_LAUNCH((k_dir<double, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);     \
+        if (init) PODCG_LAUNCH((k_dir<double, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none, k, nbu); \
+        else PODCG_LAUNCH((k_dir<double, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none, k, nbu);     \
         break;
         PODCG_TIERS(CASE)
 #undef CASE
@@ -557,11 +730,12 @@ hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, con
 
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
-                          double* alpha, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                          double* alpha, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     const DirRecord rec{V, ldv, cap, gamma, alpha};
+    const int nbu = update_blocks(B);
     switch (yb) {
-#define CASE(T) case T: PODCG_LAUNCH((k_dir<double, T, false, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, rec); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_dir<double, T, false, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, rec, k, nbu); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -621,10 +795,11 @@ hipError_t launch_state_init(DevState* st, int maxit, double tol2, int y, hipStr
 namespace podcg {
 
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
-                           const float* AW, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    dim3 g(vec_grid(B.n, B.update_grid)), t(kBlock);
+                           const float* AW, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    dim3 g(update_blocks(B)), t(kBlock);
+    const int nsp = spmv_blocks(B);
     switch (yb) {
-#define CASE(T) case T: PODCG_LAUNCH((k_update<float, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW); break;
+#define CASE(T) case T: PODCG_LAUNCH((k_update<float, T, true>), g, t, s, e0, e1, B, y, r, z, q, AW, k, nsp); break;
         PODCG_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;
@@ -633,14 +808,15 @@ hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, 
 }
 
 hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
-                        const float* W, bool init, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                        const float* W, bool init, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     dim3 g(vec_grid(B.n, B.dir_grid)), t(kBlock);
     const DirRecord none{};
+    const int nbu = update_blocks(B);
     switch (yb) {
 #define CASE(T)                                                                                    \
     case T:                                                                                        \
-        if (init) PODCG_LAUNCH((k_dir<float, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);  \
-        else PODCG_LAUNCH((k_dir<float, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none);      \
+        if (init) PODCG_LAUNCH((k_dir<float, T, true, true>), g, t, s, e0, e1, B, y, p, x, z, W, none, k, nbu);  \
+        else PODCG_LAUNCH((k_dir<float, T, false, true>), g, t, s, e0, e1, B, y, p, x, z, W, none, k, nbu);      \
         break;
         PODCG_TIERS(CASE)
 #undef CASE

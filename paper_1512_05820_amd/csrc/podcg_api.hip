@@ -38,6 +38,7 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.st = ctx->d_st;
     B.part = ctx->d_part;
     B.counter = ctx->d_counter;
+    B.gpart = ctx->d_gpart;
     B.Ginv = ctx->d_Ginv;
     B.vals32 = ctx->d_vals32;
     B.dinv32 = ctx->d_dinv32;
@@ -150,13 +151,13 @@ int solve_mixed(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_s
         // Stage 1 in FP64, then the FP32 augmented PCG on the correction
         HIPCHECK(launch_stage1_mixed(B, yb, y, x, ctx->d_r, ctx->d_r32, ctx->d_z32, ctx->d_W,
                                      ctx->d_AW, ctx->d_AW32, ctx->opt.inner_rtol, s));
-        HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, true, s));
-        std::vector<int> timed = run_loop(ctx, slot, &polls, [&](bool t, hipEvent_t* ev) {
+        HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, true, -1, s));
+        std::vector<int> timed = run_loop(ctx, slot, &polls, [&](bool t, hipEvent_t* ev, int k) {
             hipEvent_t none[6] = {};
             hipEvent_t* e = t ? ev : none;
-            HIPCHECK(launch_spmv_gamma32(B, ctx->d_p32, ctx->d_q32, s, e[0], e[1]));
-            HIPCHECK(launch_update32(B, yb, y, ctx->d_r32, ctx->d_z32, ctx->d_q32, ctx->d_AW32, s, e[2], e[3]));
-            HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, false, s, e[4], e[5]));
+            HIPCHECK(launch_spmv_gamma32(B, ctx->d_p32, ctx->d_q32, k, s, e[0], e[1]));
+            HIPCHECK(launch_update32(B, yb, y, ctx->d_r32, ctx->d_z32, ctx->d_q32, ctx->d_AW32, k, s, e[2], e[3]));
+            HIPCHECK(launch_dir32(B, yb, y, ctx->d_p32, x, ctx->d_z32, ctx->d_W32, false, k, s, e[4], e[5]));
         });
         poll(ctx);
         const PollBlock P = *ctx->h_poll;
@@ -213,17 +214,19 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r, mu = G^{-1} (A W)^T z
         HIPCHECK(launch_stage1_apply(B, yb, y, x, ctx->d_r, ctx->d_z, ctx->d_W, ctx->d_AW, s));
         // p = z - W mu (explicit), pt = z (implicit)
-        HIPCHECK(launch_dir(B, dyb, dy, ctx->d_p, x, ctx->d_z, ctx->d_W, true, s));
+        HIPCHECK(launch_dir(B, dyb, dy, ctx->d_p, x, ctx->d_z, ctx->d_W, true, -1, s));
         int polls = 0;
-        std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev) {
+        std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev, int k) {
             hipEvent_t none[6] = {};
             hipEvent_t* e = t ? ev : none;
-            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, s, e[0], e[1]));
-            if (imp)
-                HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
-            else
-                HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, s, e[2], e[3]));
-            HIPCHECK(launch_dir(B, dyb, dy, ctx->d_p, x, ctx->d_z, ctx->d_W, false, s, e[4], e[5]));
+            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, k, s, e[0], e[1]));
+            if (imp) {
+                HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, k, s, e[2], e[3]));
+                HIPCHECK(launch_dir_implicit(B, yb, y, ctx->d_p, x, ctx->d_z, k, s, e[4], e[5]));
+            } else {
+                HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, k, s, e[2], e[3]));
+                HIPCHECK(launch_dir(B, yb, y, ctx->d_p, x, ctx->d_z, ctx->d_W, false, k, s, e[4], e[5]));
+            }
         });
         if (imp) HIPCHECK(launch_implicit_finish(B, yb, y, x, ctx->d_W, s));   // x = xt - W xi
         // true residual ||b - A x||
@@ -264,7 +267,7 @@ void release(podcg_ctx* ctx) {
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
-                   ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_flag,
+                   ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_gpart, ctx->d_flag,
                    ctx->d_vals32, ctx->d_dinv32, ctx->d_W32, ctx->d_AW32, ctx->d_r32, ctx->d_z32,
                    ctx->d_p32, ctx->d_q32};
     for (void* p : dev)
@@ -378,6 +381,7 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_st, 1);
         dalloc(ctx, &ctx->d_part, kPartials);
         dalloc(ctx, &ctx->d_counter, kCounters);
+        dalloc(ctx, &ctx->d_gpart, kLoopGridMax);
         dalloc(ctx, &ctx->d_flag, 4);
         HIPCHECK(hipMemsetAsync(ctx->d_counter, 0, kCounters * sizeof(unsigned), ctx->stream));
         HIPCHECK(hipMemsetAsync(ctx->d_r, 0, ld * sizeof(double), ctx->stream));

@@ -202,7 +202,7 @@ void stage1_all(podcg_batch* ctx, const double* const* b, double* const* x, cons
         HIPCHECK(launch_state_init(c->d_st, maxit[m], rtol[m] * rtol[m], y, s));
         HIPCHECK(launch_resid(B, yb, y, b[m], x[m], c->d_r, c->d_W, true, true, s));
         HIPCHECK(launch_stage1_apply(B, yb, y, x[m], c->d_r, c->d_z, c->d_W, c->d_AW, s));
-        HIPCHECK(launch_dir(B, yb, y, c->d_p, x[m], c->d_z, c->d_W, true, s));
+        HIPCHECK(launch_dir(B, yb, y, c->d_p, x[m], c->d_z, c->d_W, true, -1, s));
     }
 }
 

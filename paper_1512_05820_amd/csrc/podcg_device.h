@@ -17,13 +17,13 @@ constexpr int kYMax = 32;                 // largest basis / snapshot count
 constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
 constexpr int kVecBlocksMax = 2048;       // partial-sum capacity of the streaming kernels
 constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL kernels
-// Default launch grids of the loop kernels (measured on MI355X at 128^3: the
-// two reducing kernels prefer fewer, longer-lived workgroups, which shorten
-// the reduction tails; the direction kernel, which reduces nothing, prefers
-// more).  Options override them.
+// Default launch grids of the loop kernels, measured on MI355X at 128^3.
+// Each workgroup of the update and direction kernels first finishes the
+// previous kernel's reduction, so fewer, longer-lived workgroups amortise that
+// prologue.  Options override them.
 constexpr int kSpmvGrid = 1024;
 constexpr int kUpdateGrid = 512;
-constexpr int kDirGrid = 4096;
+constexpr int kDirGrid = 1024;
 constexpr int kCounters = 1 + kSpmvBlocksMax;        // arrival counters (level 2 + groups)
 constexpr int kGramBlocksMax = 512;       // grid cap of the fused SpMM + Gram kernel
 // doubles in the partials buffer: the larger of the loop kernels' need and the
@@ -43,21 +43,28 @@ constexpr int kFailed = -1;
 // what the host polls.
 struct DevState {
     int iter, done, status, y;
-    int maxit, implicit, pad1, pad2;   // implicit: the direction is kept as p = pt - W nu
+    int maxit, implicit, stop, pad2;   // implicit: the direction is kept as p = pt - W nu;
+                                       // stop: loop kernels of iteration k run while k < stop
     double rr, rr0, bnorm2, true_rr;
     double tol2, rho, alpha, beta, gamma;
-    double gcorr;          // implicit form: nu^T a, subtracted from (A pt, pt) to give (A p, p)
-    double pad3[2];
+    double pad3[3];
     double mu[kYMax];      // projection coefficients G^{-1} (A W)^T z
     double what[kYMax];    // Stage-1 coefficients G^{-1} W^T rbar
-    double nu[kYMax];      // implicit form: p = pt - W nu
-    double acc[kYMax];     // implicit form: a = (A W)^T pt, carried by its recurrence
     double xi[kYMax];      // implicit form: x = xt - W xi
+    // Scalars of the loop, in two slots by iteration parity: iteration k reads
+    // slot k & 1 and its direction kernel writes slot (k + 1) & 1, so no kernel
+    // overwrites a value that another workgroup of the same kernel still reads.
+    double lrho[2];        // (r, z) entering iteration k
+    double lalpha[2];      // alpha_k (written by the update kernel)
+    double lgamma[2];      // (A p_k, p_k)
+    double lgcorr[2];      // implicit form: nu^T a, subtracted from (A pt, pt) to give (A p, p)
+    double lnu[2][kYMax];  // implicit form: p = pt - W nu
+    double lacc[2][kYMax]; // implicit form: a = (A W)^T pt, carried by its recurrence
 };
 
 struct PollBlock {         // host mirror of the first 48 bytes of DevState
     int iter, done, status, y;
-    int maxit, pad0, pad1, pad2;
+    int maxit, pad0, stop, pad2;
     double rr, rr0, bnorm2, true_rr;
 };
 
@@ -165,6 +172,46 @@ __device__ __forceinline__ bool grid_sum_last(double (&v)[NV], double* part, uns
     return true;
 }
 
+// The loop kernels split the grid reduction between producer and consumer,
+// so that no kernel ends with a serial tail in one workgroup.
+// Producer side (level 1): the workgroup's NV sums go to part[k * nb + block];
+// the last workgroup of each group of kGroup consecutive workgroups sums the
+// group's entries (in block order) into part[NV * nb + k * ng + group].
+template <int NV>
+__device__ __forceinline__ void group_sum_store(double (&v)[NV], double* part, unsigned* counter, double* lds) {
+    block_sum<NV>(v, lds);
+    const int nb = gridDim.x;
+    const int ng = (nb + kGroup - 1) / kGroup;
+    const int g = blockIdx.x / kGroup;
+    if (threadIdx.x < NV) store_shared(part + (size_t)threadIdx.x * nb + blockIdx.x, lds[threadIdx.x]);
+    const int gsize = min(kGroup, nb - g * kGroup);
+    if (!arrive_last(counter + 1 + g, gsize)) return;
+    double a[NV];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        a[k] = t < gsize ? load_shared(part + (size_t)k * nb + g * kGroup + t) : 0.0;
+    block_sum<NV>(a, lds);
+    if (t < NV) store_shared(part + (size_t)NV * nb + (size_t)t * ng + g, lds[t]);
+}
+// Consumer side (level 2), run by every workgroup of the next kernel: the ng
+// group sums of each value, added in group order (the same order in every
+// workgroup, so every workgroup obtains bitwise the same totals), left in
+// lds[0..NV).  nb is the producer's grid; requires ng <= kBlock.  The
+// producer is an earlier kernel of the same stream, whose writes plain loads
+// see, so these loads may hit in L2 (only the first workgroup on each XCD
+// fetches the partials from memory).
+template <int NV>
+__device__ __forceinline__ void group_sum_load(const double* part, int nb, double* lds) {
+    const int ng = (nb + kGroup - 1) / kGroup;
+    const double* part2 = part + (size_t)NV * nb;
+    double a[NV];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = t < ng ? part2[(size_t)k * ng + t] : 0.0;
+    block_sum<NV>(a, lds);
+}
+
 // Workgroup index remapped so that each XCD (workgroups are dealt to the 8
 // XCDs round-robin) walks a contiguous range of the problem.  A bijection on
 // [0, nb).
@@ -221,6 +268,7 @@ struct DevBufs {
     DevState* st;
     double* part;
     unsigned* counter;
+    double* gpart;             // per-workgroup (A p, p) partials of the loop SpMV
     const double* Ginv;        // y x y row-major
     const float* vals32;       // FP32 copy of the SELL values (mixed precision)
     const float* dinv32;       // FP32 copy of dinv
@@ -277,9 +325,9 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
                                 hipStream_t s);
 // The loop launchers take optional start/stop events that the dispatch itself
 // records (hipExtLaunchKernel): the kernel time without event-marker overhead.
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, hipStream_t s,
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, hipStream_t s,
+hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, int k, hipStream_t s,
                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_matvec(const DevBufs& B, const double* x, double* y, hipStream_t s);
 hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const double* x,
@@ -290,10 +338,18 @@ hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX
 
 // Streaming vector kernels (k_vec.hip)
 int basis_tier(int y);   // smallest compiled register tier >= y
+// Loop kernels of iteration k (0, 1, ...): each is a no-op once k >= stop.
+// The update kernel sums the SpMV's (A p, p) partials itself and forms alpha;
+// the direction kernel sums the update's group partials itself and forms beta,
+// mu and the convergence decision (workgroup 0 records them in the state).
+int spmv_blocks(const DevBufs& B);     // launch grid of the loop SpMV
+int update_blocks(const DevBufs& B);   // launch grid of the update kernels
 hipError_t launch_update(const DevBufs& B, int yb, int y, double* r, double* z, const double* q,
-                         const double* AW, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                         const double* AW, int k, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
+// init: the first direction (k unused); otherwise iteration k
 hipError_t launch_dir(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
-                      const double* W, bool init, hipStream_t s, hipEvent_t e0 = nullptr,
+                      const double* W, bool init, int k, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
 hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, double* r, double* z,
                                const double* W, const double* AW, hipStream_t s);
@@ -303,14 +359,19 @@ hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, doubl
 // A p = A pt - (A W) nu from the columns of A W it already streams.  The
 // solution accumulates x = xt - W xi; launch_implicit_finish applies W xi once.
 hipError_t launch_update_implicit(const DevBufs& B, int yb, int y, double* r, double* z, const double* qt,
-                                  const double* AW, hipStream_t s, hipEvent_t e0 = nullptr,
+                                  const double* AW, int k, hipStream_t s, hipEvent_t e0 = nullptr,
                                   hipEvent_t e1 = nullptr);
+// iteration k of the implicit form: x += alpha pt, pt = z + beta pt, and the
+// coefficient recurrences (yb, y: the update's basis tier and rank)
+hipError_t launch_dir_implicit(const DevBufs& B, int yb, int y, double* p, double* x, const double* z, int k,
+                               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_implicit_finish(const DevBufs& B, int yb, int y, double* x, const double* W, hipStream_t s);
 // FP32 loop kernels of the mixed-precision inner solve (same state machine).
 hipError_t launch_update32(const DevBufs& B, int yb, int y, float* r, float* z, const float* q,
-                           const float* AW, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                           const float* AW, int k, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 hipError_t launch_dir32(const DevBufs& B, int yb, int y, float* p, double* x, const float* z,
-                        const float* W, bool init, hipStream_t s, hipEvent_t e0 = nullptr,
+                        const float* W, bool init, int k, hipStream_t s, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 // Mixed-precision Stage 1 of one refinement step: from the FP64 residual r64
 // (and what = G^{-1} W^T r64 in the state), x64 += W what, r = r64 - (A W) what
@@ -412,7 +473,7 @@ struct TsDev {
 
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
-                          double* alpha, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                          double* alpha, int k, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_gemv_n(int n, size_t ld, const double* Y, int m, const double* c, double* out,
                          double sign, bool accumulate, hipStream_t s);
 // out = Y^T v through kTsChunks row chunks (part: kTsChunks x m scratch).

@@ -69,6 +69,7 @@ struct podcg_ctx {
     podcg::DevState* d_st = nullptr;
     double* d_part = nullptr;
     unsigned* d_counter = nullptr;
+    double* d_gpart = nullptr;              // SpMV partials of (A p, p), one per workgroup
     int* d_flag = nullptr;
     podcg::PollBlock* h_poll = nullptr;     // pinned
     int* h_int = nullptr;            // pinned scratch ints
@@ -135,9 +136,9 @@ void setup_basis(podcg_ctx* ctx);
 int fail_code(podcg_ctx* ctx, const podcg::PollBlock& P);
 void record(podcg_ctx* ctx, hipEvent_t e);
 // Launch loop iterations in batches until the device reports that the solve
-// finished, or maxit iterations were launched.  `iter3(t, ev)` enqueues one
-// iteration (SpMV, update, direction); when t, ev[2k], ev[2k + 1] are the
-// start/stop events of kernel k, recorded by the dispatches themselves.  The first convergence check comes after most of the previous
+// finished, or maxit iterations were launched.  `iter3(t, ev, k)` enqueues
+// iteration k (SpMV, update, direction); when t, ev[2j], ev[2j + 1] are the
+// start/stop events of kernel j, recorded by the dispatches themselves.  The first convergence check comes after most of the previous
 // solve's iteration count (kernels after convergence are no-ops), then every
 // check_every iterations.  Returns the iteration indices that were timed.
 template <class F>
@@ -164,7 +165,7 @@ std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
                 timed.push_back(launched);
                 ev = &ctx->tev[base];
             }
-            iter3(t, ev);
+            iter3(t, ev, launched);
         }
         poll(ctx);
         ++*polls;

@@ -276,15 +276,15 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     // r = b - A x0, with no projection of x0 (what stays zero)
     HIPCHECK(launch_resid(D, 0, 0, b, x, ctx->d_r, nullptr, true, true, s));
     HIPCHECK(launch_stage1_apply(D, yb, y, x, ctx->d_r, ctx->d_z, T->d_B, T->d_AB, s));
-    HIPCHECK(launch_dir(D, yb, y, ctx->d_p, x, ctx->d_z, T->d_B, true, s));
+    HIPCHECK(launch_dir(D, yb, y, ctx->d_p, x, ctx->d_z, T->d_B, true, -1, s));
     const int cap_rec = T->opt.cap - m;
     double* vrec = T->d_Y + (size_t)m * ld;
     int polls = 0;
-    (void)run_loop(ctx, 0, &polls, [&](bool, hipEvent_t*) {
-        HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, s));
-        HIPCHECK(launch_update(D, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, T->d_AB, s));
+    (void)run_loop(ctx, 0, &polls, [&](bool, hipEvent_t*, int k) {
+        HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, s));
+        HIPCHECK(launch_update(D, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, T->d_AB, k, s));
         HIPCHECK(launch_dir_rec(D, yb, y, ctx->d_p, x, ctx->d_z, T->d_B, vrec, ld, cap_rec, TSF(T, gam3),
-                                TSF(T, alp3), s));
+                                TSF(T, alp3), k, s));
     });
     HIPCHECK(launch_resid(D, 0, 0, b, x, nullptr, nullptr, false, false, s));
     poll(ctx);
