@@ -501,6 +501,8 @@ def main():
     ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, timing=TIMING_STRIDE,
                   projection=args.projection)
     ctx.set_matrix(vals_dev[0], rowptr, colind)
+    fmt = ctx.format_info()
+    log(f"matrix storage: {fmt}")
 
     # achievable bandwidth probe (not part of the method)
     m = 1 << 27
@@ -607,6 +609,7 @@ def main():
         "speedup_vs_plain_warm": (round(plain["warm"]["ms"] / ms_per_step, 3) if plain else None),
         "iters_saved_vs_plain_warm": (1 - aug_iters / plain["warm"]["iters"]) if plain else None,
         "loop_kernels_GBps": {k: round(v, 1) for k, v in gbps.items()},
+        "matrix_storage": fmt,
         "spmv_proj_GBps": round(loop_gbps, 1),
         "stream_triad_GBps": round(triad_gbps, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbps[dom], 1),
@@ -615,7 +618,7 @@ def main():
                      "traffic": (measured_traffic() if dom == "spmv" and cfg.N == 128 else None),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "algorithmic_bytes": kernel_bytes(cfg.n, cfg.nnz, 0)[dom] if dom == "spmv" else None,
-                     "format_bytes": (10 * cfg.nnz + 16 * cfg.n + 9 * ((cfg.n + 63) // 64)
+                     "format_bytes": (8 * fmt["slots"] + fmt["column_bytes"] + 16 * cfg.n + 9 * ((cfg.n + 63) // 64)
                                       if dom == "spmv" else None),
                      "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
                      "timed_launches": launches},

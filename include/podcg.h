@@ -170,6 +170,16 @@ int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank);
  * (host, PODCG_MAX_BASIS doubles); *count (host) receives how many. */
 int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count);
 
+/* How the current matrix pattern is stored (the sliced layout of the SpMV
+ * that multiplies by A_j every iteration, Alg. 1): counts (host, 5 int64)
+ * receives the number of 64-row slices whose columns are stored as
+ * [0] int32 indices, [1] 16-bit offsets col - row, [2] one offset table per
+ * slice (rows drawing on at most 8 common offsets, as stencils do); [3] the
+ * stored value slots (nonzeros plus padding); [4] the bytes of column data
+ * one product reads (4 or 2 per slot, 32 per table slice).  Returns
+ * PODCG_ERR_NO_MATRIX before the first pattern. */
+int podcg_get_format(podcg_ctx* ctx, int64_t* counts);
+
 /* Solve A_j x = b (Stage 1 + augmented PCG, Alg. 2 then Alg. 1 with the
  * current basis; plain Jacobi PCG when the basis is empty).
  * b: device, n float64.  x: device, n float64, holds xbar_j on entry and x_j

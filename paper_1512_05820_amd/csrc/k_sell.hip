@@ -102,12 +102,96 @@ __global__ __launch_bounds__(kBlock) void k_fill_pattern(int n, int nslices,
 
 // One wave per slice: 16-bit column offsets when they all fit (rows < n);
 // padding rows (>= n) store 0 and gather entry 0.
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// One wave per slice.  The union of the rows' column offsets is built by
+// repeatedly taking the smallest offset not yet consumed by any lane (rows are
+// checked to be strictly increasing); the slice takes the table form when the
+// union has exactly w entries (w = the slice width <= kTabMax), so its storage
+// does not grow.  Slot j of each row then holds the entry with offset tab[j],
+// or a zero-valued padding slot (map -1, column = the row) when the row has no
+// such neighbour.
+__global__ __launch_bounds__(kBlock) void k_fill_table(int n, int nslices, const int32_t* __restrict__ rowptr,
+                                                       const int64_t* __restrict__ sptr, int* __restrict__ cols,
+                                                       int* __restrict__ map, int* __restrict__ soff,
+                                                       uint8_t* __restrict__ sflag) {
+    constexpr int kNone = 0x7fffffff;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int s = blockIdx.x * kWavesPerBlock + wid; s < nslices; s += gridDim.x * kWavesPerBlock) {
+        const int64_t base = sptr[s];
+        const int w = (int)((sptr[s + 1] - base) / kSlice);
+        bool table = false;
+        int tab[kTabMax];
+        if (w >= 1 && w <= kTabMax) {
+            const int row = s * kSlice + lane;
+            const int beg = row < n ? rowptr[row] : 0;
+            const int len = row < n ? rowptr[row + 1] - beg : 0;
+            int off[kTabMax];
+            bool sorted = true;
+#pragma unroll
+            for (int j = 0; j < kTabMax; ++j) {
+                off[j] = (j < len) ? cols[base + (int64_t)j * kSlice + lane] - row : kNone;
+                if (j > 0 && j < len && off[j] <= off[j - 1]) sorted = false;
+            }
+            int cnt = 0, ptr = 0;
+            for (int round = 0; round <= kTabMax; ++round) {
+                int mine = kNone;
+#pragma unroll
+                for (int j = 0; j < kTabMax; ++j)
+                    if (j == ptr) mine = off[j];
+                const int m = wave_min_int(mine);
+                if (m == kNone) break;
+                if (cnt < kTabMax) {
+#pragma unroll
+                    for (int j = 0; j < kTabMax; ++j)
+                        if (j == cnt) tab[j] = m;
+                }
+                ++cnt;
+                if (mine == m) ++ptr;
+            }
+            table = __all(sorted) && cnt == w;
+            if (table) {
+                int e = 0;
+#pragma unroll
+                for (int j = 0; j < kTabMax; ++j) {
+                    if (j >= w) break;
+                    const int64_t slot = base + (int64_t)j * kSlice + lane;
+                    int cur = kNone;
+#pragma unroll
+                    for (int u = 0; u < kTabMax; ++u)
+                        if (u == e) cur = off[u];
+                    if (e < len && cur == tab[j]) {
+                        cols[slot] = row + tab[j];
+                        map[slot] = beg + e;
+                        ++e;
+                    } else {
+                        cols[slot] = row < n ? row : 0;
+                        map[slot] = -1;
+                    }
+                }
+                if (lane == 0)
+#pragma unroll
+                    for (int j = 0; j < kTabMax; ++j) soff[(size_t)s * kTabMax + j] = j < w ? tab[j] : 0;
+            }
+        }
+        if (lane == 0) sflag[s] = table ? 2 : 0;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_offsets16(int n, int nslices, const int64_t* __restrict__ sptr,
                                                            const int* __restrict__ cols,
                                                            int16_t* __restrict__ cols16,
                                                            uint8_t* __restrict__ sflag) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (int s = blockIdx.x * kWavesPerBlock + wid; s < nslices; s += gridDim.x * kWavesPerBlock) {
+        if (sflag[s] == 2) continue;   // offset-table slice
         const int64_t base = sptr[s];
         const int w = (int)((sptr[s + 1] - base) / kSlice);
         const int row = s * kSlice + lane;
@@ -470,6 +554,13 @@ hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const 
                                const int64_t* sptr, int* cols, int* map, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_pattern, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
                        0, s, n, nslices, rowptr, colind, sptr, cols, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_table(int n, int nslices, const int32_t* rowptr, const int64_t* sptr, int* cols,
+                             int* map, int* soff, uint8_t* sflag, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_table, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock), 0, s, n,
+                       nslices, rowptr, sptr, cols, map, soff, sflag);
     return hipGetLastError();
 }
 

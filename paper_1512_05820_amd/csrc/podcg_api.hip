@@ -33,6 +33,7 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.cols = ctx->d_cols;
     B.cols16 = ctx->d_cols16;
     B.sflag = ctx->d_sflag;
+    B.soff = ctx->d_soff;
     B.vals = ctx->d_vals;
     B.dinv = ctx->d_dinv;
     B.st = ctx->d_st;
@@ -264,7 +265,7 @@ namespace {
 
 void release(podcg_ctx* ctx) {
     ts_release(ctx);
-    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
+    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_soff, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
                    ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_gpart, ctx->d_flag,
@@ -351,6 +352,7 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         const size_t ld = ctx->ld;
         dalloc(ctx, &ctx->d_sptr, (size_t)ctx->nslices + 1);
         dalloc(ctx, &ctx->d_sflag, (size_t)ctx->nslices);
+        dalloc(ctx, &ctx->d_soff, (size_t)ctx->nslices * kTabMax);
         dalloc(ctx, &ctx->d_dinv, ld);
         dalloc(ctx, &ctx->d_r, ld);
         dalloc(ctx, &ctx->d_z, ld);
@@ -455,6 +457,8 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             ctx->nsell = nsell;
             HIPCHECK(launch_fill_pattern(n, ctx->nslices, rowptr, colind, ctx->d_sptr, ctx->d_cols,
                                          ctx->d_map, s));
+            HIPCHECK(launch_fill_table(n, ctx->nslices, rowptr, ctx->d_sptr, ctx->d_cols, ctx->d_map,
+                                       ctx->d_soff, ctx->d_sflag, s));
             HIPCHECK(launch_fill_offsets16(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_cols16,
                                            ctx->d_sflag, s));
             ctx->has_pattern = true;
@@ -586,6 +590,28 @@ int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count) {
         if (count) *count = ctx->pod_count;
         if (lam && ctx->pod_count > 0)
             HIPCHECK(hipMemcpy(lam, ctx->d_lamS, sizeof(double) * ctx->pod_count, hipMemcpyDeviceToHost));
+        return PODCG_OK;
+    });
+}
+
+int podcg_get_format(podcg_ctx* ctx, int64_t* counts) {
+    return guarded(ctx, [&]() {
+        if (!counts) fail(ctx, PODCG_ERR_INVALID_ARG, "counts is NULL");
+        if (!ctx->has_pattern) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix pattern set");
+        std::vector<uint8_t> f((size_t)ctx->nslices);
+        std::vector<int64_t> sp((size_t)ctx->nslices + 1);
+        HIPCHECK(hipMemcpyAsync(f.data(), ctx->d_sflag, f.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(sp.data(), ctx->d_sptr, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                ctx->stream));
+        sync(ctx);
+        for (int k = 0; k < 5; ++k) counts[k] = 0;
+        for (size_t s = 0; s < f.size(); ++s) {
+            const int kind = f[s] <= 2 ? f[s] : 0;
+            const int64_t slots = sp[s + 1] - sp[s];
+            counts[kind] += 1;
+            counts[3] += slots;
+            counts[4] += kind == 2 ? 4 * kTabMax : (kind == 1 ? 2 : 4) * slots;
+        }
         return PODCG_OK;
     });
 }

@@ -14,6 +14,7 @@ constexpr int kBlock = 256;               // threads per workgroup (4 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlice = 64;                // SELL slice height = one row per lane
 constexpr int kYMax = 32;                 // largest basis / snapshot count
+constexpr int kTabMax = 8;                // widest slice stored with a per-slice offset table
 constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
 constexpr int kVecBlocksMax = 2048;       // partial-sum capacity of the streaming kernels
 constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL kernels
@@ -227,9 +228,16 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // and values are loaded first (padding slots re-read the last valid slot and
 // are skipped with a select), then all gathers, then the sums in order j =
 // 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
-// slice bounds and the index-width flag are scalar loads.  A slice whose
-// column offsets col - row all fit in 16 bits reads them from cols16 (2 bytes
-// per entry instead of 4); rows past n gather entry 0.
+// slice bounds and the format flag are scalar loads.  Three storages of the
+// columns, chosen per slice at ingest:
+//   flag 2: every row of the slice draws its columns from one list of w <= 8
+//           offsets (a stencil), stored once per slice (offset j of the list
+//           is slot j of every row; a row without that neighbour holds a zero
+//           value there); the offsets are scalar loads and no per-entry index
+//           is read;
+//   flag 1: per-entry 16-bit offsets col - row (2 bytes per entry);
+//   flag 0: per-entry int32 columns.
+// Gather indices of padding are kept inside [0, n); rows past n read zeros.
 template <typename T, typename C>
 __device__ __forceinline__ double sell_row_cols(const C* __restrict__ c, const T* __restrict__ v, int w,
                                                 int rb, const T* __restrict__ x) {
@@ -262,7 +270,8 @@ struct DevBufs {
     const int64_t* sptr;       // slice offsets, nslices + 1
     const int* cols;           // SELL column indices
     const int16_t* cols16;     // column offsets col - row of the 16-bit slices
-    const uint8_t* sflag;      // per slice: 1 = read cols16, 0 = read cols
+    const uint8_t* sflag;      // per slice: 2 = offset table, 1 = read cols16, 0 = read cols
+    const int* soff;           // per slice: kTabMax offsets (the slices with flag 2)
     const double* vals;        // SELL values
     const double* dinv;        // 1 / diag(A)
     DevState* st;
@@ -291,7 +300,28 @@ __device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict
     const int64_t base = B.sptr[s];
     const int w = (int)((B.sptr[s + 1] - base) / kSlice);
     const T* v = vals + base + lane;
-    if (B.sflag[s]) {
+    const int flag = B.sflag[s];
+    if (flag == 2) {
+        const int row = s * kSlice + lane;
+        const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
+        int ci[kTabMax];
+        T vi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) {
+            const int j = min(u, w - 1);
+            const int c = row + tab[j];
+            ci[u] = c < 0 ? 0 : (c < B.n ? c : B.n - 1);
+            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
+        }
+        T xi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) xi[u] = x[ci[u]];
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) acc = u < w ? fma((double)vi[u], (double)xi[u], acc) : acc;
+        return acc;
+    }
+    if (flag == 1) {
         const int row = s * kSlice + lane;
         return sell_row_cols<T, int16_t>(B.cols16 + base + lane, v, w, row < B.n ? row : 0, x);
     }
@@ -315,6 +345,12 @@ hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const 
                                const int64_t* sptr, int* cols, int* map, hipStream_t s);
 // cols16 / sflag from cols: a slice gets 16-bit offsets when every entry of
 // its rows < n has |col - row| <= 32767 (padding slots have col = row).
+// Per-slice offset tables (flag 2) for the slices whose rows all draw on one
+// list of at most kTabMax offsets, exactly as many as the slice is wide; their
+// slots are re-laid out in table order (cols and map follow).  Other slices
+// get flag 0, and launch_fill_offsets16 then decides between 0 and 1.
+hipError_t launch_fill_table(int n, int nslices, const int32_t* rowptr, const int64_t* sptr, int* cols,
+                             int* map, int* soff, uint8_t* sflag, hipStream_t s);
 hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const int* cols, int16_t* cols16,
                                  uint8_t* sflag, hipStream_t s);
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,

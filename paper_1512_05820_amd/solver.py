@@ -140,6 +140,19 @@ class PodCG:
                                                    C.byref(c)))
         return lam[: c.value].copy()
 
+    def format_info(self) -> dict:
+        """Slices of the stored pattern by column storage (int32, 16-bit offsets, offset
+        table), stored value slots and the column bytes one product reads."""
+        c = np.zeros(5, dtype=np.int64)
+        self._check(self._L.podcg_get_format(self._h, c.ctypes.data_as(C.c_void_p)))
+        return {"int32": int(c[0]), "offset16": int(c[1]), "table": int(c[2]), "slots": int(c[3]),
+                "column_bytes": int(c[4])}
+
+    def format_counts(self) -> dict:
+        """Slices of the stored pattern by column storage (int32, 16-bit offsets, offset table)."""
+        f = self.format_info()
+        return {k: f[k] for k in ("int32", "offset16", "table")}
+
     def matvec(self, x: torch.Tensor, y: torch.Tensor):
         self._check(self._L.podcg_matvec(self._h, _ptr(x, torch.float64), _ptr(y, torch.float64)))
 

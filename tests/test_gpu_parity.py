@@ -95,9 +95,22 @@ def test_matvec_general_sparsity_ragged_rows(P):
     assert _relerr(_host(y), A @ x) <= 1e-13
 
 
-def test_matvec_mixes_16_and_32_bit_column_slices(P):
-    """Slices whose column offsets exceed 16 bits keep 32-bit indices, the
-    others read 16-bit offsets; rows of both kinds, a ragged last slice."""
+def _csr_from_triplets(n, rows, cols, vals, keep_order=False):
+    rows, cols, vals = np.asarray(rows), np.asarray(cols), np.asarray(vals, dtype=np.float64)
+    order = np.arange(len(rows)) if keep_order else np.lexsort((cols, rows))
+    order = order[np.argsort(rows[order], kind="stable")]
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals
+
+
+def test_matvec_mixes_all_three_column_storages(P):
+    """A banded pattern (offsets -301, -1, 0, 1, 301) whose slices take the
+    per-slice offset table; slices where two rows carry different extra
+    offsets cannot (their offset union is wider than the slice) and keep
+    16-bit offsets, or 32-bit columns when an offset exceeds 16 bits; a ragged
+    last slice (n = 90,001)."""
     r = _rng(5)
     n = 90_001
     rows, cols, vals = [], [], []
@@ -108,21 +121,84 @@ def test_matvec_mixes_16_and_32_bit_column_slices(P):
                 rows.append(i)
                 cols.append(j)
                 vals.append(10.0 if d == 0 else -1.0 + 0.1 * r.standard_normal())
-    far = r.choice(n - 60_000, size=40, replace=False)
-    for i in far:                      # symmetric long-range couplings (offset 60,000)
-        rows += [i, i + 60_000]
-        cols += [i + 60_000, i]
-        vals += [0.5, 0.5]
-    order = np.lexsort((cols, rows))
-    rows, cols, vals = np.array(rows)[order], np.array(cols)[order], np.array(vals)[order]
-    rowptr = np.zeros(n + 1, dtype=np.int32)
-    np.add.at(rowptr, rows + 1, 1)
-    rowptr = np.cumsum(rowptr).astype(np.int32)
-    A = oracle.CSR(rowptr, cols.astype(np.int32), vals)
+
+    def couple(i, d, v):                 # symmetric pair (i, i + d), (i + d, i)
+        rows.extend([i, i + d])
+        cols.extend([i + d, i])
+        vals.extend([v, v])
+
+    for t, i in enumerate(range(640, 20_000, 1280)):   # 32-bit: offsets 60,000 and 60,003 in one slice
+        couple(i, 60_000, 0.5)
+        couple(i + 1, 60_003, 0.25)
+    for i in range(30_080, 40_000, 1280):               # 16-bit: offsets 150 and 170 in one slice
+        couple(i, 150, 0.5)
+        couple(i + 1, 170, 0.25)
+    rowptr, colind, vals = _csr_from_triplets(n, rows, cols, vals)
+    A = oracle.CSR(rowptr, colind, vals)
     x = r.standard_normal(n)
     ctx = _ctx(P, n)
-    _set(ctx, rowptr, cols.astype(np.int32), vals)
+    _set(ctx, rowptr, colind, vals)
+    f = ctx.format_counts()
+    print(f)
+    assert f["int32"] >= 8 and f["offset16"] >= 8 and f["table"] >= 1000
+    assert sum(f.values()) == (n + 63) // 64
     y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), oracle.matvec(A, x)) <= 1e-14
+
+
+@pytest.mark.parametrize("N,dim", [(24, 3), (20, 2), (5, 3)])
+def test_stencil_slices_use_offset_tables(P, N, dim):
+    """Every slice of a 2-D or 3-D stencil stores one offset table (boundary
+    rows hold zero-valued slots for their missing neighbours), and the product
+    and a full solve are unchanged."""
+    cfg = config1(N=N) if dim == 2 else config2(N=N, steps=2)
+    vals = cfg.matrix_values(1)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    ctx = _ctx(P, cfg.n)
+    _set(ctx, cfg.rowptr, cfg.colind, vals)
+    f = ctx.format_counts()
+    assert f == {"int32": 0, "offset16": 0, "table": (cfg.n + 63) // 64}
+    x = _rng(N + 7).standard_normal(cfg.n)
+    y = torch.empty(cfg.n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), oracle.matvec(A, x)) <= 1e-14
+    b = cfg.rhs(1, None)
+    xo, so = oracle.plain_pcg(A, b, np.zeros(cfg.n), tol=1e-10, maxit=5000)
+    xg = _dev(np.zeros(cfg.n))
+    st = ctx.solve_plain(_dev(b), xg, 1e-10)
+    assert st.status == 0 and abs(st.iters - so.iters) <= 1
+    assert _relerr(_host(xg), xo) <= 1e-9
+
+
+def test_unsorted_and_duplicate_rows_keep_per_entry_columns(P):
+    """A row whose columns are out of order, and a row with a repeated column
+    (two entries that add up), make their slices keep per-entry columns; the
+    product still matches the oracle's."""
+    cfg = config1(N=20)
+    vals = cfg.matrix_values(1)
+    rowptr, colind = cfg.rowptr.copy(), cfg.colind.copy()
+    i = 70                                        # reverse the columns of row 70 (slice 1)
+    a, b = rowptr[i], rowptr[i + 1]
+    colind[a:b] = colind[a:b][::-1].copy()
+    vals = vals.copy()
+    vals[a:b] = vals[a:b][::-1].copy()
+    rows = np.repeat(np.arange(cfg.n), np.diff(rowptr))
+    rl, cl, vl = list(rows), list(colind), list(vals)
+    j = 300                                       # split the diagonal of row 300 (slice 4) in two
+    k = rowptr[j] + list(colind[rowptr[j]:rowptr[j + 1]]).index(j)
+    rl.append(j)
+    cl.append(j)
+    vl.append(0.25 * vl[k])
+    vl[k] *= 0.75
+    rp, ci, vv = _csr_from_triplets(cfg.n, rl, cl, vl, keep_order=True)
+    A = oracle.CSR(rp, ci, vv)
+    ctx = _ctx(P, cfg.n)
+    _set(ctx, rp, ci, vv)
+    f = ctx.format_counts()
+    assert f["offset16"] == 2 and f["table"] == (cfg.n + 63) // 64 - 2
+    x = _rng(71).standard_normal(cfg.n)
+    y = torch.empty(cfg.n, dtype=torch.float64, device="cuda")
     ctx.matvec(_dev(x), y)
     assert _relerr(_host(y), oracle.matvec(A, x)) <= 1e-14
 
