@@ -77,11 +77,27 @@ void orc_matvec(int64_t n, const int32_t* rowptr, const int32_t* colind,
     }
 }
 
+/* Inner product a^T b.  The sum runs over fixed blocks of 4096 indices (at
+ * most 256 blocks, so blocks grow with n), each summed in index order, and the
+ * block sums are added in block order: the result does not depend on the
+ * number of threads or on their timing (a reduction clause would leave the
+ * combining order open). */
 static double dot(int64_t n, const double* a, const double* b)
 {
+    enum { kBlocks = 256, kMinBlock = 4096 };
+    double part[kBlocks];
+    int64_t nb = (n + kMinBlock - 1) / kMinBlock;
+    if (nb < 1) nb = 1;
+    if (nb > kBlocks) nb = kBlocks;
+    #pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nb; ++t) {
+        const int64_t lo = n * t / nb, hi = n * (t + 1) / nb;
+        double s = 0.0;
+        for (int64_t i = lo; i < hi; ++i) s += a[i] * b[i];
+        part[t] = s;
+    }
     double s = 0.0;
-    #pragma omp parallel for schedule(static) reduction(+ : s)
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int64_t t = 0; t < nb; ++t) s += part[t];
     return s;
 }
 

