@@ -427,9 +427,27 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
             const int w = (int)((B.sptr[s + 1] - base) / kSlice);
             const int* c = B.cols + base + lane;
             const double* vv = B.vals + base + lane;
+            // entry j + 1's value and column are loaded while entry j's k
+            // gathers are in flight; a slice with an offset table computes the
+            // column from its (scalar) offsets, with no index load at all
+            const bool tabled = B.sflag[s] == 2;
+            const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
+            auto column = [&](int j) {
+                if (tabled) {
+                    const int col = row + tab[j];
+                    return col < 0 ? 0 : (col < B.n ? col : B.n - 1);
+                }
+                return c[j * kSlice];
+            };
+            double a_next = vv[0];
+            int col_next = column(0);
             for (int j = 0; j < w; ++j) {
-                const double a = vv[j * kSlice];
-                const int col = c[j * kSlice];
+                const double a = a_next;
+                const int col = col_next;
+                if (j + 1 < w) {
+                    a_next = vv[(j + 1) * kSlice];
+                    col_next = column(j + 1);
+                }
                 double xv[KS];
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) xv[kk] = X[(size_t)(kk < k ? kk : k - 1) * B.ld + col];
