@@ -118,11 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 // once and serves both A p and c.  gamma = (A p, p) = (A pt, pt) - nu^T a with
 // a = (A W)^T pt (this uses (A W)^T p = 0, the property Alg. 1's projection
 // maintains).
+// A W is read from its tiled copy AWt (64-row tiles, the y columns of a tile
+// contiguous), so each wave streams one block instead of y separate columns.
 template <int YB>
 __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double* __restrict__ r,
                                                        double* __restrict__ z,
                                                        const double* __restrict__ qt,
-                                                       const double* __restrict__ AW, int k, int nsp) {
+                                                       const double* __restrict__ AWt, int k, int nsp) {
     constexpr int NV = 2 + YB;
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
     __shared__ double ldsg[kWavesPerBlock + 2];
@@ -138,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
         r0 = r[i0];
         q0 = qt[i0];
         d0 = B.dinv[i0];
+        const double* t0 = AWt + (size_t)(i0 / kSlice) * (kSlice * y) + (i0 % kSlice);
 #pragma unroll
-        for (int j = 0; j < YB; ++j) a0[j] = basis_load<true>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i0);
+        for (int j = 0; j < YB; ++j) a0[j] = basis_load<true>(t0 + tier_col<YB>(j, y) * kSlice);
     }
     double nu[YB > 0 ? YB : 1];
 #pragma unroll
@@ -166,8 +169,9 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
     if (i0 < n) step(i0, r0, q0, d0, a0);
     for (int i = i0 + stride; i < n; i += stride) {
         double a[YB > 0 ? YB : 1];
+        const double* t = AWt + (size_t)(i / kSlice) * (kSlice * y) + (i % kSlice);
 #pragma unroll
-        for (int j = 0; j < YB; ++j) a[j] = basis_load<true>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i);
+        for (int j = 0; j < YB; ++j) a[j] = basis_load<true>(t + tier_col<YB>(j, y) * kSlice);
         step(i, r[i], qt[i], B.dinv[i], a);
     }
     group_sum_store<NV>(v, B.part, B.counter, lds);
@@ -527,6 +531,18 @@ __global__ __launch_bounds__(kBlock) void k_pod_form(int n, size_t ld, const dou
     }
 }
 
+// dst[(i / 64) 64 y + 64 j + i mod 64] = src[j ld + i] for i < ld, j < y.
+__global__ __launch_bounds__(kBlock) void k_tile_columns(const double* __restrict__ src, size_t ld, int y,
+                                                         double* __restrict__ dst) {
+    const size_t total = ld * (size_t)y;
+    const size_t tile = (size_t)kSlice * y;
+    for (size_t e = blockIdx.x * (size_t)kBlock + threadIdx.x; e < total; e += (size_t)gridDim.x * kBlock) {
+        const size_t t = e / tile, rem = e % tile;
+        const size_t j = rem / kSlice, l = rem % kSlice;
+        dst[e] = src[j * ld + t * kSlice + l];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ a, double* __restrict__ c,
                                                  size_t n) {
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
@@ -765,6 +781,14 @@ hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const d
 #undef CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_columns(const double* src, size_t ld, int y, double* dst, hipStream_t s) {
+    if (y < 1 || ld % kSlice != 0) return hipErrorInvalidValue;
+    int64_t g = (int64_t)((ld * (size_t)y + kBlock - 1) / kBlock);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_tile_columns, dim3((int)g), dim3(kBlock), 0, s, src, ld, y, dst);
     return hipGetLastError();
 }
 

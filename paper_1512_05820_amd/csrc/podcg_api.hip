@@ -88,6 +88,8 @@ void setup_basis(podcg_ctx* ctx) {
         HIPCHECK(launch_to_float(ctx->d_W, ctx->d_W32, ctx->ld * (size_t)kept, ctx->stream));
         HIPCHECK(launch_to_float(ctx->d_AW, ctx->d_AW32, ctx->ld * (size_t)kept, ctx->stream));
     }
+    if (ctx->opt.precision == 0 && ctx->opt.projection == 1 && kept > 0)   // the implicit update's tiled copy of A W
+        HIPCHECK(launch_tile_columns(ctx->d_AW, ctx->ld, kept, ctx->d_AWt, ctx->stream));
     if (kept > 0) {
         HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * kept, hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -222,7 +224,7 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
             hipEvent_t* e = t ? ev : none;
             HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, k, s, e[0], e[1]));
             if (imp) {
-                HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, k, s, e[2], e[3]));
+                HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AWt, k, s, e[2], e[3]));
                 HIPCHECK(launch_dir_implicit(B, yb, y, ctx->d_p, x, ctx->d_z, k, s, e[4], e[5]));
             } else {
                 HIPCHECK(launch_update(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AW, k, s, e[2], e[3]));
@@ -266,7 +268,7 @@ namespace {
 void release(podcg_ctx* ctx) {
     ts_release(ctx);
     void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_soff, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
-                   ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_G, ctx->d_R,
+                   ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_AWt, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
                    ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_gpart, ctx->d_flag,
                    ctx->d_vals32, ctx->d_dinv32, ctx->d_W32, ctx->d_AW32, ctx->d_r32, ctx->d_z32,
@@ -360,6 +362,7 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_q, ld);
         dalloc(ctx, &ctx->d_W, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_AW, ld * (size_t)std::max(1, o.rank_max));
+        dalloc(ctx, &ctx->d_AWt, ld * (size_t)std::max(1, o.rank_max));
         dalloc(ctx, &ctx->d_S, ld * (size_t)o.omega);
         if (o.precision == 1) {
             dalloc(ctx, &ctx->d_dinv32, ld);

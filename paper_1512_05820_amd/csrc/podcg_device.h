@@ -394,9 +394,15 @@ hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, doubl
 // kernel runs with no basis columns and the update kernel forms
 // A p = A pt - (A W) nu from the columns of A W it already streams.  The
 // solution accumulates x = xt - W xi; launch_implicit_finish applies W xi once.
+// AWt: A W in 64-row tiles, element (i, j) at (i / 64) 64 y + 64 j + i mod 64
+// (launch_tile_columns), so that the y columns a wave reads are one
+// contiguous block of 512 y bytes.
 hipError_t launch_update_implicit(const DevBufs& B, int yb, int y, double* r, double* z, const double* qt,
-                                  const double* AW, int k, hipStream_t s, hipEvent_t e0 = nullptr,
+                                  const double* AWt, int k, hipStream_t s, hipEvent_t e0 = nullptr,
                                   hipEvent_t e1 = nullptr);
+// dst = the y columns of src (column-major, leading dimension ld, a multiple
+// of 64) in 64-row tiles, as read by the implicit update.
+hipError_t launch_tile_columns(const double* src, size_t ld, int y, double* dst, hipStream_t s);
 // iteration k of the implicit form: x += alpha pt, pt = z + beta pt, and the
 // coefficient recurrences (yb, y: the update's basis tier and rank)
 hipError_t launch_dir_implicit(const DevBufs& B, int yb, int y, double* p, double* x, const double* z, int k,

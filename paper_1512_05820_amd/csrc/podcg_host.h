@@ -54,6 +54,7 @@ struct podcg_ctx {
 
     // basis
     double *d_W = nullptr, *d_AW = nullptr;
+    double* d_AWt = nullptr;                // A W in 64-row tiles (read by the implicit update)
     int y = 0;                 // columns of W
     int y_kept = 0;            // columns accepted by the last factorisation
     bool setup_valid = false;
