@@ -212,8 +212,9 @@ int podcg_pattern_outer(podcg_ctx* ctx, const double* u, const double* v, double
                         double* out_vals);
 
 /* Bandwidth probe for the roofline: c[i] = a[i] + s * b[i] over n float64
- * device elements, launched `reps` times on the context stream; *ms (host)
- * receives the mean GPU time of one launch.  Not part of the method. */
+ * device elements (a, b, c 16-byte aligned, else PODCG_ERR_INVALID_ARG), launched
+ * `reps` times on the context stream; *ms (host) receives the mean GPU time
+ * of one launch.  Not part of the method. */
 int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double* c,
                        int64_t n, double s, int32_t reps, double* ms);
 

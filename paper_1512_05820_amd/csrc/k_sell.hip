@@ -181,7 +181,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_table(int n, int nslices, const
                     for (int j = 0; j < kTabMax; ++j) soff[(size_t)s * kTabMax + j] = j < w ? tab[j] : 0;
             }
         }
-        if (lane == 0) sflag[s] = table ? 2 : 0;
+        if (lane == 0) {
+            sflag[s] = table ? 2 : 0;
+            if (!table)   // defined contents for slices without a table (read, not used, by the SpMV)
+#pragma unroll
+                for (int j = 0; j < kTabMax; ++j) soff[(size_t)s * kTabMax + j] = 0;
+        }
     }
 }
 
@@ -288,10 +293,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
     const int nb = gridDim.x;
     const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
     double g[1] = {0.0};
-    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+    // the next slice's metadata is fetched while this slice is processed; the
+    // wait for it sits at the end of the iteration, when it has long arrived
+    int L = xcd_block(blockIdx.x, nb);
+    const int last = B.nslices - 1;
+    int cur = slice_meta_load(B, min(L * kWavesPerBlock + wid, last));
+    for (; L < ngroups; L += nb) {
         const int s = L * kWavesPerBlock + wid;
+        const int nxt = slice_meta_load(B, min((L + nb) * kWavesPerBlock + wid, last));
         if (s < B.nslices) {
-            const double acc = sell_row<T>(B, mat_vals<T>(B), s, lane, p);
+            const double acc = sell_row_meta<T>(B, slice_meta_unpack(cur), mat_vals<T>(B), s, lane, p);
             const int row = s * kSlice + lane;
             if (row < B.n) {
                 const T qv = (T)acc;
@@ -299,6 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
                 g[0] += (double)qv * (double)p[row];
             }
         }
+        cur = nxt;
     }
     block_sum<1>(g, lds);
     if (threadIdx.x == 0) store_shared(B.gpart + blockIdx.x, lds[0]);
@@ -572,6 +584,30 @@ hipError_t launch_fill_pattern(int n, int nslices, const int32_t* rowptr, const 
                                const int64_t* sptr, int* cols, int* map, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_pattern, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
                        0, s, n, nslices, rowptr, colind, sptr, cols, map);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_meta(int nslices, const int64_t* __restrict__ sptr,
+                                                      const uint8_t* __restrict__ sflag,
+                                                      const int* __restrict__ soff, int* __restrict__ smeta) {
+    const int64_t total = (int64_t)nslices * kMetaWords;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int s = (int)(e / kMetaWords), f = (int)(e % kMetaWords);
+        const int64_t base = sptr[s];
+        int v = 0;
+        if (f == 0) v = (int)(uint32_t)((uint64_t)base & 0xffffffffu);
+        else if (f == 1) v = (int)(uint32_t)((uint64_t)base >> 32);
+        else if (f == 2) v = (int)((sptr[s + 1] - base) / kSlice);
+        else if (f == 3) v = sflag[s];
+        else if (f < 4 + kTabMax) v = soff[(size_t)s * kTabMax + (f - 4)];
+        smeta[e] = v;
+    }
+}
+
+hipError_t launch_fill_meta(int nslices, const int64_t* sptr, const uint8_t* sflag, const int* soff, int* smeta,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_meta, dim3(grid_for((int64_t)nslices * kMetaWords, 8192)), dim3(kBlock), 0, s,
+                       nslices, sptr, sflag, soff, smeta);
     return hipGetLastError();
 }
 

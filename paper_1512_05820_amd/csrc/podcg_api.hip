@@ -34,6 +34,7 @@ DevBufs bufs(podcg_ctx* ctx) {
     B.cols16 = ctx->d_cols16;
     B.sflag = ctx->d_sflag;
     B.soff = ctx->d_soff;
+    B.smeta = ctx->d_smeta;
     B.vals = ctx->d_vals;
     B.dinv = ctx->d_dinv;
     B.st = ctx->d_st;
@@ -267,7 +268,7 @@ namespace {
 
 void release(podcg_ctx* ctx) {
     ts_release(ctx);
-    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_soff, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
+    void* dev[] = {ctx->d_sptr, ctx->d_cols, ctx->d_cols16, ctx->d_sflag, ctx->d_soff, ctx->d_smeta, ctx->d_map, ctx->d_vals, ctx->d_dinv, ctx->d_r,
                    ctx->d_z, ctx->d_p, ctx->d_q, ctx->d_W, ctx->d_AW, ctx->d_AWt, ctx->d_G, ctx->d_R,
                    ctx->d_Ginv, ctx->d_lamG, ctx->d_S, ctx->d_Gs, ctx->d_T,
                    ctx->d_lamS, ctx->d_yout, ctx->d_st, ctx->d_part, ctx->d_counter, ctx->d_gpart, ctx->d_flag,
@@ -355,6 +356,7 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         dalloc(ctx, &ctx->d_sptr, (size_t)ctx->nslices + 1);
         dalloc(ctx, &ctx->d_sflag, (size_t)ctx->nslices);
         dalloc(ctx, &ctx->d_soff, (size_t)ctx->nslices * kTabMax);
+        dalloc(ctx, &ctx->d_smeta, (size_t)ctx->nslices * kMetaWords);
         dalloc(ctx, &ctx->d_dinv, ld);
         dalloc(ctx, &ctx->d_r, ld);
         dalloc(ctx, &ctx->d_z, ld);
@@ -464,6 +466,7 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
                                        ctx->d_soff, ctx->d_sflag, s));
             HIPCHECK(launch_fill_offsets16(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_cols16,
                                            ctx->d_sflag, s));
+            HIPCHECK(launch_fill_meta(ctx->nslices, ctx->d_sptr, ctx->d_sflag, ctx->d_soff, ctx->d_smeta, s));
             ctx->has_pattern = true;
             ctx->nnz = nnz;
         } else {
@@ -651,6 +654,8 @@ int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double*
                        double s, int32_t reps, double* ms) {
     return guarded(ctx, [&]() {
         if (!a || !b || !c || n < 1 || reps < 1) fail(ctx, PODCG_ERR_INVALID_ARG, "bad triad arguments");
+        if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15)
+            fail(ctx, PODCG_ERR_INVALID_ARG, "triad arrays must be 16-byte aligned");
         HIPCHECK(launch_triad(a, b, c, (size_t)n, s, ctx->stream));   // warm-up
         HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
         for (int r = 0; r < reps; ++r) HIPCHECK(launch_triad(a, b, c, (size_t)n, s, ctx->stream));

@@ -15,6 +15,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSlice = 64;                // SELL slice height = one row per lane
 constexpr int kYMax = 32;                 // largest basis / snapshot count
 constexpr int kTabMax = 8;                // widest slice stored with a per-slice offset table
+constexpr int kMetaWords = 16;            // words of a slice's metadata record (64 bytes)
 constexpr int kNVMax = kYMax + 3;         // reduced values carried by one kernel
 constexpr int kVecBlocksMax = 2048;       // partial-sum capacity of the streaming kernels
 constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL kernels
@@ -272,6 +273,7 @@ struct DevBufs {
     const int16_t* cols16;     // column offsets col - row of the 16-bit slices
     const uint8_t* sflag;      // per slice: 2 = offset table, 1 = read cols16, 0 = read cols
     const int* soff;           // per slice: kTabMax offsets (the slices with flag 2)
+    const int* smeta;          // per slice: kMetaWords words {base lo, base hi, w, flag, tab[8], 0...}
     const double* vals;        // SELL values
     const double* dinv;        // 1 / diag(A)
     DevState* st;
@@ -328,6 +330,69 @@ __device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict
     return sell_row_cols<T, int>(B.cols + base + lane, v, w, 0, x);
 }
 
+// The per-slice metadata a wave needs before its first vector load (slice
+// offset, width, column storage, offset table).  The loop SpMV reads it as one
+// 64-byte record per slice with an ordinary vector load (lane l holds word
+// l % 16) and extracts the fields with readlane: vector loads complete in
+// order, so the next slice's record can be requested one slice ahead without
+// any wait on it until it is used.
+struct SliceMeta {
+    int64_t base;
+    int w, flag;
+    int tab[kTabMax];
+};
+__device__ __forceinline__ int slice_meta_load(const DevBufs& B, int s) {
+    return B.smeta[(size_t)s * kMetaWords + (threadIdx.x & (kMetaWords - 1))];
+}
+__device__ __forceinline__ SliceMeta slice_meta_unpack(int v) {
+    SliceMeta m;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(v, 1);
+    m.base = (int64_t)(((uint64_t)hi << 32) | lo);
+    m.w = __builtin_amdgcn_readlane(v, 2);
+    m.flag = __builtin_amdgcn_readlane(v, 3);
+    m.tab[0] = __builtin_amdgcn_readlane(v, 4);
+    m.tab[1] = __builtin_amdgcn_readlane(v, 5);
+    m.tab[2] = __builtin_amdgcn_readlane(v, 6);
+    m.tab[3] = __builtin_amdgcn_readlane(v, 7);
+    m.tab[4] = __builtin_amdgcn_readlane(v, 8);
+    m.tab[5] = __builtin_amdgcn_readlane(v, 9);
+    m.tab[6] = __builtin_amdgcn_readlane(v, 10);
+    m.tab[7] = __builtin_amdgcn_readlane(v, 11);
+    return m;
+}
+// sell_row with the metadata already loaded.
+template <typename T>
+__device__ __forceinline__ double sell_row_meta(const DevBufs& B, const SliceMeta& m, const T* __restrict__ vals,
+                                               int s, int lane, const T* __restrict__ x) {
+    const int w = m.w;
+    const T* v = vals + m.base + lane;
+    const int row = s * kSlice + lane;
+    if (m.flag == 2) {
+        int ci[kTabMax];
+        T vi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) {
+            const int j = min(u, w - 1);
+            int off = m.tab[0];
+#pragma unroll
+            for (int t = 1; t < kTabMax; ++t) off = j == t ? m.tab[t] : off;
+            const int c = row + off;
+            ci[u] = c < 0 ? 0 : (c < B.n ? c : B.n - 1);
+            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
+        }
+        T xi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) xi[u] = x[ci[u]];
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) acc = u < w ? fma((double)vi[u], (double)xi[u], acc) : acc;
+        return acc;
+    }
+    if (m.flag == 1) return sell_row_cols<T, int16_t>(B.cols16 + m.base + lane, v, w, row < B.n ? row : 0, x);
+    return sell_row_cols<T, int>(B.cols + m.base + lane, v, w, 0, x);
+}
+
 // Matrix values and Jacobi inverse in the storage type T of a kernel.
 template <typename T> __device__ __forceinline__ const T* mat_vals(const DevBufs& B);
 template <> __device__ __forceinline__ const double* mat_vals<double>(const DevBufs& B) { return B.vals; }
@@ -353,6 +418,9 @@ hipError_t launch_fill_table(int n, int nslices, const int32_t* rowptr, const in
                              int* map, int* soff, uint8_t* sflag, hipStream_t s);
 hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const int* cols, int16_t* cols16,
                                  uint8_t* sflag, hipStream_t s);
+// The per-slice metadata records read by the loop SpMV (after the flags are final).
+hipError_t launch_fill_meta(int nslices, const int64_t* sptr, const uint8_t* sflag, const int* soff, int* smeta,
+                            hipStream_t s);
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
                               const int* map, const double* csr_vals, double* vals, double* dinv,
                               int* flag, hipStream_t s);

@@ -41,6 +41,7 @@ struct podcg_ctx {
     int16_t* d_cols16 = nullptr;
     uint8_t* d_sflag = nullptr;
     int* d_soff = nullptr;                  // per-slice offset tables, kTabMax each
+    int* d_smeta = nullptr;                 // per-slice metadata records of the loop SpMV
     int* d_map = nullptr;
     double* d_vals = nullptr;
     double* d_dinv = nullptr;
