@@ -34,9 +34,11 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
     __syncthreads();
     for (int sweep = 0; sweep < 100 && m > 1; ++sweep) {
         double o = 0.0;
-        for (int e = lane; e < m * m; e += kWave) {
-            const int i = e / m, j = e % m;
-            if (i != j) o += a[i * kLd + j] * a[i * kLd + j];
+        {
+            const int j = lane & 31;
+            if (j < m)
+                for (int i = lane >> 5; i < m; i += 2)
+                    if (i != j) o += a[i * kLd + j] * a[i * kLd + j];
         }
         const double off = wave_sum(o);
         if (off <= 1.0e-30 * fro) break;
@@ -65,30 +67,33 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
                 cs[2 * lane + 1] = sn;
             }
             __syncthreads();
-            // rows p, q of every pair:  A <- J^T A
-            for (int e = lane; e < npair * m; e += kWave) {
-                const int t = e / m, k = e % m;
-                const int p = pq[2 * t], q = pq[2 * t + 1];
-                if (p < 0) continue;
-                const double c = cs[2 * t], sn = cs[2 * t + 1];
-                const double apk = a[p * kLd + k], aqk = a[q * kLd + k];
-                a[p * kLd + k] = c * apk - sn * aqk;
-                a[q * kLd + k] = sn * apk + c * aqk;
-            }
+            // rows p, q of every pair:  A <- J^T A.  Lane l updates entry
+            // k = l % 32 of pairs t = l / 32, l / 32 + 2, ... (m <= 32, so no
+            // index needs a division)
+            const int kq = lane & 31, t0 = lane >> 5;
+            if (kq < m)
+                for (int t = t0; t < npair; t += 2) {
+                    const int p = pq[2 * t], q = pq[2 * t + 1];
+                    if (p < 0) continue;
+                    const double c = cs[2 * t], sn = cs[2 * t + 1];
+                    const double apk = a[p * kLd + kq], aqk = a[q * kLd + kq];
+                    a[p * kLd + kq] = c * apk - sn * aqk;
+                    a[q * kLd + kq] = sn * apk + c * aqk;
+                }
             __syncthreads();
             // columns p, q of every pair:  A <- A J,  V <- V J
-            for (int e = lane; e < npair * m; e += kWave) {
-                const int t = e / m, k = e % m;
-                const int p = pq[2 * t], q = pq[2 * t + 1];
-                if (p < 0) continue;
-                const double c = cs[2 * t], sn = cs[2 * t + 1];
-                const double akp = a[k * kLd + p], akq = a[k * kLd + q];
-                a[k * kLd + p] = c * akp - sn * akq;
-                a[k * kLd + q] = sn * akp + c * akq;
-                const double vkp = V[k * kLd + p], vkq = V[k * kLd + q];
-                V[k * kLd + p] = c * vkp - sn * vkq;
-                V[k * kLd + q] = sn * vkp + c * vkq;
-            }
+            if (kq < m)
+                for (int t = t0; t < npair; t += 2) {
+                    const int p = pq[2 * t], q = pq[2 * t + 1];
+                    if (p < 0) continue;
+                    const double c = cs[2 * t], sn = cs[2 * t + 1];
+                    const double akp = a[kq * kLd + p], akq = a[kq * kLd + q];
+                    a[kq * kLd + p] = c * akp - sn * akq;
+                    a[kq * kLd + q] = sn * akp + c * akq;
+                    const double vkp = V[kq * kLd + p], vkq = V[kq * kLd + q];
+                    V[kq * kLd + p] = c * vkp - sn * vkq;
+                    V[kq * kLd + q] = sn * vkp + c * vkq;
+                }
             __syncthreads();
             if (lane < npair) {
                 const int p = pq[2 * lane], q = pq[2 * lane + 1];
