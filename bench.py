@@ -277,7 +277,9 @@ def bench_config4(args):
         log(f"one context at a time, augmented: {seq_ms:.1f} ms")
 
     def iter_bytes(m, y):
-        return 12 * m.nnz + 4 * (m.n + 1) + 16 * m.n + 16 * y * m.n + 88 * m.n
+        # CSR A, p and q of the SpMV, the vectors of the update and direction
+        # kernels, and A W once (the implicit form reads no column of W)
+        return 12 * m.nnz + 4 * (m.n + 1) + 16 * m.n + 8 * y * m.n + 88 * m.n
 
     loop_bytes = sum(iter_bytes(m, s["rank"]) * s["iters"] for sts in aug for m, s in zip(mem, sts))
     solve_ms = sum(sts[0]["solve_ms"] for sts in aug)

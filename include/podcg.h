@@ -79,7 +79,8 @@ typedef struct {
                                nu of p = pt - W nu (nu = mu + beta nu), forms A p as
                                A pt - (A W) nu inside the residual update and x as
                                xt - W xi once at exit, so W is not read in the loop.  The
-                               iterates are the same in exact arithmetic.  Mixed precision
+                               iterates are the same in exact arithmetic.  Batched solves
+                               follow each member's setting; mixed precision
                                (precision = 1) and plain PCG always use the explicit form. */
 } podcg_options;
 

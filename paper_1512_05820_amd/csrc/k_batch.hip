@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __rest
         }
         if (member_sum_last<1>(g, M.B.part, M.B.counter, M.spmv_items, it.local, lds) &&
             threadIdx.x == 0) {
-            const double gamma = lds[0];
+            // implicit form: p = pt - W nu and (A p, p) = (A pt, pt) - nu^T a (slot 0 of the state)
+            const double gamma = lds[0] - (M.implicit ? st->lgcorr[0] : 0.0);
             st->gamma = gamma;
             if (!(gamma > 0.0) || !is_finite(gamma)) {
                 st->status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
@@ -114,7 +115,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __rest
 }
 
 // r -= alpha q, z = M^{-1} r, sums (r, z), (r, r), (A W)^T z; the last item of
-// a member forms beta, mu = G^{-1} (A W)^T z and tests convergence.
+// a member forms beta, mu = G^{-1} (A W)^T z and tests convergence.  For a
+// member in the implicit form the SpMV multiplied pt, so A p = q - (A W) nu is
+// formed from the A W columns loaded for the sums, and the last item advances
+// xi += alpha nu, nu = mu + beta nu, a = c + beta a and nu^T a (state slot 0).
 template <int YB>
 __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __restrict__ mem,
                                                          const BatchItem* __restrict__ items,
@@ -139,11 +143,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
         const double* __restrict__ dinv = M.B.dinv;
         const double* __restrict__ AW = M.AW;
         const size_t ld = M.B.ld;
+        const bool imp = M.implicit != 0;
+        double nu[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int k = 0; k < YB; ++k) nu[k] = (imp && k < y) ? st->lnu[0][k] : 0.0;
         double v[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] = 0.0;
         for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
-            const double ri = r[i] - alpha * q[i];
+            double a[YB > 0 ? YB : 1];
+            double qi = q[i];
+            if (YB > 0 && y > 0) {
+#pragma unroll
+                for (int k = 0; k < YB; ++k) {
+                    a[k] = __builtin_nontemporal_load(AW + (size_t)bcol(k, y) * ld + i);
+                    if (imp && k < y) qi -= a[k] * nu[k];
+                }
+            }
+            const double ri = r[i] - alpha * qi;
             const double zi = dinv[i] * ri;
             r[i] = ri;
             z[i] = zi;
@@ -151,10 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
             v[1] += ri * ri;
             if (YB > 0 && y > 0) {
 #pragma unroll
-                for (int k = 0; k < YB; ++k) {
-                    const double a = __builtin_nontemporal_load(AW + (size_t)bcol(k, y) * ld + i);
-                    if (k < y) v[2 + k] += a * zi;
-                }
+                for (int k = 0; k < YB; ++k)
+                    if (k < y) v[2 + k] += a[k] * zi;
             }
         }
         if (member_sum_last<NV>(v, M.B.part, M.B.counter, M.vec_items, it.local, lds)) {
@@ -163,12 +178,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
                 const int iter = st->iter + 1;
                 st->iter = iter;
                 st->rr = rr;
+                double beta = 0.0, stepped = 1.0;
                 if (!is_finite(rr) || !is_finite(rz)) {
                     st->status = kStNonfinite;
                     st->done = kFailed;
                     leave_running(active);
+                    stepped = 0.0;
                 } else {
-                    st->beta = rz / st->rho;
+                    beta = rz / st->rho;
+                    st->beta = beta;
                     st->rho = rz;
                     if (rr <= st->tol2) {
                         st->status = kStOk;
@@ -180,18 +198,40 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
                         leave_running(active);
                     }
                 }
+                lds[NV] = beta;
+                lds[NV + 1] = stepped;
             }
-            if ((int)threadIdx.x < y) {
-                double s = 0.0;
-                for (int j = 0; j < y; ++j) s += M.B.Ginv[threadIdx.x * y + j] * lds[2 + j];
-                st->mu[threadIdx.x] = s;
+            __syncthreads();
+            if ((int)threadIdx.x < kWave) {
+                const int k = threadIdx.x;
+                double prod = 0.0;
+                if (k < y) {
+                    double s = 0.0;
+                    for (int j = 0; j < y; ++j) s += M.B.Ginv[k * y + j] * lds[2 + j];
+                    st->mu[k] = s;
+                    if (imp) {
+                        const double beta = lds[NV];
+                        const double nu_old = st->lnu[0][k];
+                        if (lds[NV + 1] != 0.0) st->xi[k] += alpha * nu_old;
+                        const double nu_new = s + beta * nu_old;
+                        const double a_new = lds[2 + k] + beta * st->lacc[0][k];
+                        st->lnu[0][k] = nu_new;
+                        st->lacc[0][k] = a_new;
+                        prod = nu_new * a_new;
+                    }
+                }
+                if (imp) {
+                    prod = wave_sum(prod);
+                    if (k == 0) st->lgcorr[0] = prod;
+                }
             }
         }
         __syncthreads();   // lds is reused by the next item
     }
 }
 
-// x += alpha p; while iterating p = z + beta p - W mu.
+// x += alpha p; while iterating p = z + beta p - W mu (p = z + beta p for a
+// member in the implicit form, whose basis term is carried by nu).
 template <int YB>
 __global__ __launch_bounds__(kBlock) void k_batch_dir(const BatchMember* __restrict__ mem,
                                                       const BatchItem* __restrict__ items,
@@ -222,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_dir(const BatchMember* __restr
             x[i] += alpha * pi;
             if (!new_dir) continue;
             double s = z[i] + beta * pi;
-            if (YB > 0 && y > 0) {
+            if (YB > 0 && y > 0 && !M.implicit) {
 #pragma unroll
                 for (int k = 0; k < YB; ++k)
                     s -= __builtin_nontemporal_load(W + (size_t)bcol(k, y) * ld + i) * mu[k];

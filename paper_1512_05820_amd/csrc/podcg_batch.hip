@@ -98,6 +98,12 @@ void build_lists(podcg_batch* ctx) {
 }
 
 // Member table for one solve (y = kept rank, or 0 for plain PCG).
+// A member runs the implicit form of the direction (p = pt - W nu) when it
+// has a basis and its options ask for it, as a single-sequence solve would.
+bool member_implicit(const podcg_ctx* c, bool plain) {
+    return !plain && c->y_kept > 0 && c->opt.projection == 1;
+}
+
 void upload_members(podcg_batch* ctx, double* const* x, bool plain) {
     const int count = (int)ctx->members.size();
     for (int m = 0; m < count; ++m) {
@@ -112,6 +118,7 @@ void upload_members(podcg_batch* ctx, double* const* x, bool plain) {
         M.W = c->d_W;
         M.AW = c->d_AW;
         M.y = plain ? 0 : c->y_kept;
+        M.implicit = member_implicit(c, plain) ? 1 : 0;
         M.spmv_items = ctx->spmv_items[m];
         M.vec_items = ctx->vec_items[m];
         M.spmv_first = ctx->spmv_first[m];
@@ -199,10 +206,12 @@ void stage1_all(podcg_batch* ctx, const double* const* b, double* const* x, cons
         const int y = plain ? 0 : c->y_kept;
         const int yb = basis_tier(y);
         DevBufs B = bufs(c);
-        HIPCHECK(launch_state_init(c->d_st, maxit[m], rtol[m] * rtol[m], y, s));
+        const bool imp = member_implicit(c, plain);
+        HIPCHECK(launch_state_init(c->d_st, maxit[m], rtol[m] * rtol[m], y, s, imp));
         HIPCHECK(launch_resid(B, yb, y, b[m], x[m], c->d_r, c->d_W, true, true, s));
         HIPCHECK(launch_stage1_apply(B, yb, y, x[m], c->d_r, c->d_z, c->d_W, c->d_AW, s));
-        HIPCHECK(launch_dir(B, yb, y, c->d_p, x[m], c->d_z, c->d_W, true, -1, s));
+        // p = z - W mu (explicit), pt = z (implicit)
+        HIPCHECK(launch_dir(B, imp ? 0 : yb, imp ? 0 : y, c->d_p, x[m], c->d_z, c->d_W, true, -1, s));
     }
 }
 
@@ -244,8 +253,10 @@ int batch_solve_impl(podcg_batch* ctx, const double* const* b, double* const* x,
     const int slot = plain ? 1 : 0;
     const int first = (int)(0.85 * ctx->prev_iters[slot]);
     const int polls = run_batch_loop(ctx, yb, cap + 1, first);
-    for (int m = 0; m < count; ++m) {   // true residuals
+    for (int m = 0; m < count; ++m) {   // x = xt - W xi (implicit form), then the true residuals
         podcg_ctx* c = ctx->members[m];
+        if (member_implicit(c, plain))
+            HIPCHECK(launch_implicit_finish(bufs(c), basis_tier(c->y_kept), c->y_kept, x[m], c->d_W, s));
         HIPCHECK(launch_resid(bufs(c), 0, 0, b[m], x[m], nullptr, nullptr, false, false, s));
     }
     HIPCHECK(launch_batch_gather(ctx->d_mem, count, ctx->d_gather, s));

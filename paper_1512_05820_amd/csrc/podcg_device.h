@@ -538,7 +538,8 @@ struct BatchMember {
     int vec_items;             // work items of this member in the vector list
     int spmv_first;            // offset of its items in the full SpMV list
     int vec_first;             // offset of its items in the full vector list
-    int pad[3];
+    int implicit;              // 1: the direction is kept as p = pt - W nu (state slot 0 holds nu, a)
+    int pad[2];
 };
 
 // A contiguous range of one member: SELL slices [begin, end) in the SpMV
