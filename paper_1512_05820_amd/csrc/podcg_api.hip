@@ -81,25 +81,27 @@ void setup_basis(podcg_ctx* ctx) {
     HIPCHECK(launch_spmm_gram(B, ctx->y, ctx->d_W, ctx->d_AW, true, ctx->d_G, ctx->stream));
     HIPCHECK(launch_reduced_factor(ctx->d_G, ctx->y, ctx->d_R, ctx->d_Ginv, ctx->d_lamG, ctx->d_st,
                                    ctx->stream));
-    poll(ctx);
+    // the kept rank and the eigenvalues of G (for its condition number) come
+    // back under one synchronisation
+    HIPCHECK(hipMemcpyAsync(ctx->h_poll, ctx->d_st, sizeof(PollBlock), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * ctx->y, hipMemcpyDeviceToHost,
+                            ctx->stream));
+    sync(ctx);
     const int kept = ctx->h_poll->y;
     ctx->y_kept = kept;
     ctx->rank_reduced = kept < ctx->y;
+    if (kept > 0) {
+        const double lmax = ctx->h_dbl[0], lmin = ctx->h_dbl[kept - 1];
+        ctx->cond_G = lmin > 0.0 ? lmax / lmin : INFINITY;
+    } else {
+        ctx->cond_G = 1.0;
+    }
     if (ctx->opt.precision == 1 && kept > 0) {
         HIPCHECK(launch_to_float(ctx->d_W, ctx->d_W32, ctx->ld * (size_t)kept, ctx->stream));
         HIPCHECK(launch_to_float(ctx->d_AW, ctx->d_AW32, ctx->ld * (size_t)kept, ctx->stream));
     }
     if (ctx->opt.precision == 0 && ctx->opt.projection == 1 && kept > 0)   // the implicit update's tiled copy of A W
         HIPCHECK(launch_tile_columns(ctx->d_AW, ctx->ld, kept, ctx->d_AWt, ctx->stream));
-    if (kept > 0) {
-        HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * kept, hipMemcpyDeviceToHost,
-                                ctx->stream));
-        sync(ctx);
-        const double lmax = ctx->h_dbl[0], lmin = ctx->h_dbl[kept - 1];
-        ctx->cond_G = lmin > 0.0 ? lmax / lmin : INFINITY;
-    } else {
-        ctx->cond_G = 1.0;
-    }
     ctx->setup_valid = true;
 }
 
