@@ -683,7 +683,14 @@ hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX
                             hipStream_t s) {
     if (k < 1 || k > kYMax) return hipErrorInvalidValue;
     const int groups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
-    dim3 g(groups < kGramBlocksMax ? groups : kGramBlocksMax), t(kBlock);
+    // grid cap measured on MI355X at 128^3: 1024 workgroups for up to 16
+    // columns (6-7 columns: 150-166 us against 223-235 us at 512), 512 above
+    // (20 columns: 350 us against 386 us at 1024); never more than the partial
+    // sums buffer holds (k^2 slots per workgroup plus the group level)
+    int cap = k <= 16 ? 2 * kGramBlocksMax : kGramBlocksMax;
+    const int capk = kPartials / (k * k + (k * k + kGroup - 1) / kGroup + 1);
+    if (cap > capk) cap = capk;
+    dim3 g(groups < cap ? groups : cap), t(kBlock);
     switch (basis_tier(k)) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_spmm_gram<T>), g, t, 0, s, B, k, X, AX, store ? 1 : 0, G, B.part, B.counter); break;
         PODCG_POS_TIERS(CASE)

@@ -2,7 +2,8 @@
 // fused reductions, Stage 1, the tall-skinny Gram products and the POD basis
 // formation.  All column blocks (W, A W, S) are column-major with leading
 // dimension ld, so lane i of a wave touches row i of every column and each
-// load instruction reads 512 contiguous bytes.
+// load instruction reads 512 contiguous bytes; the implicit update also reads
+// a copy of A W in 64-row tiles.
 #include "podcg_device.h"
 
 namespace podcg {
