@@ -134,16 +134,21 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
     const int par = k & 1;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    // first element's operands in flight while alpha is formed
+    // the operands of this thread's first kPrefetch elements are in flight
+    // while alpha is formed (fewer for wide bases, to bound the registers)
+    constexpr int kPrefetch = YB <= 8 ? 4 : (YB <= 16 ? 2 : 1);
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
-    double r0 = 0.0, q0 = 0.0, d0 = 0.0, a0[YB > 0 ? YB : 1];
-    if (i0 < n) {
-        r0 = r[i0];
-        q0 = qt[i0];
-        d0 = B.dinv[i0];
-        const double* t0 = AWt + (size_t)(i0 / kSlice) * (kSlice * y) + (i0 % kSlice);
+    double rf[kPrefetch], qf[kPrefetch], df[kPrefetch], af[kPrefetch][YB > 0 ? YB : 1];
 #pragma unroll
-        for (int j = 0; j < YB; ++j) a0[j] = basis_load<true>(t0 + tier_col<YB>(j, y) * kSlice);
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int i = i0 + u * stride;
+        const int ic = i < n ? i : 0;
+        rf[u] = r[ic];
+        qf[u] = qt[ic];
+        df[u] = B.dinv[ic];
+        const double* t0 = AWt + (size_t)(ic / kSlice) * (kSlice * y) + (ic % kSlice);
+#pragma unroll
+        for (int j = 0; j < YB; ++j) af[u][j] = basis_load<true>(t0 + tier_col<YB>(j, y) * kSlice);
     }
     double nu[YB > 0 ? YB : 1];
 #pragma unroll
@@ -167,8 +172,10 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
         for (int j = 0; j < YB; ++j)
             if (tier_live<YB>(j, y)) v[2 + j] += a[j] * zi;
     };
-    if (i0 < n) step(i0, r0, q0, d0, a0);
-    for (int i = i0 + stride; i < n; i += stride) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u)
+        if (i0 + u * stride < n) step(i0 + u * stride, rf[u], qf[u], df[u], af[u]);
+    for (int i = i0 + kPrefetch * stride; i < n; i += stride) {
         double a[YB > 0 ? YB : 1];
         const double* t = AWt + (size_t)(i / kSlice) * (kSlice * y) + (i % kSlice);
 #pragma unroll
@@ -344,31 +351,30 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
     if (k >= st->stop) return;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    // the first two elements' operands are in flight while the reduction is
-    // finished
-    const int i0 = blockIdx.x * kBlock + threadIdx.x, i1 = i0 + stride;
-    double p0 = 0.0, z0 = 0.0, x0 = 0.0, p1 = 0.0, z1 = 0.0, x1 = 0.0;
-    if (i0 < n) {
-        p0 = p[i0];
-        z0 = z[i0];
-        x0 = x[i0];
-    }
-    if (i1 < n) {
-        p1 = p[i1];
-        z1 = z[i1];
-        x1 = x[i1];
+    // the operands of this thread's first kPrefetch elements (all of them at
+    // the default grid and 128^3) are in flight while the reduction is
+    // finished, so the memory system stays busy during the prologue
+    constexpr int kPrefetch = 8;
+    const int i0 = blockIdx.x * kBlock + threadIdx.x;
+    double pf[kPrefetch], zf[kPrefetch], xf[kPrefetch];
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int i = i0 + u * stride;
+        pf[u] = i < n ? p[i] : 0.0;
+        zf[u] = i < n ? z[i] : 0.0;
+        xf[u] = i < n ? x[i] : 0.0;
     }
     DirStep d;
     if (!dir_begin<NV, YB, false>(B, y, k, nbu, lds, smu, nullptr, d)) return;
-    if (i0 < n) {
-        x[i0] = x0 + d.alpha * p0;
-        if (d.new_dir) p[i0] = z0 + d.beta * p0;
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int i = i0 + u * stride;
+        if (i < n) {
+            x[i] = xf[u] + d.alpha * pf[u];
+            if (d.new_dir) p[i] = zf[u] + d.beta * pf[u];
+        }
     }
-    if (i1 < n) {
-        x[i1] = x1 + d.alpha * p1;
-        if (d.new_dir) p[i1] = z1 + d.beta * p1;
-    }
-    for (int i = i1 + stride; i < n; i += stride) {
+    for (int i = i0 + kPrefetch * stride; i < n; i += stride) {
         const double pi = p[i];
         x[i] += d.alpha * pi;
         if (d.new_dir) p[i] = z[i] + d.beta * pi;

@@ -25,6 +25,7 @@ constexpr int kSpmvBlocksMax = 2048;      // partial-sum capacity of the SELL ke
 // prologue.  Options override them.
 constexpr int kSpmvGrid = 1024;
 constexpr int kUpdateGrid = 512;
+constexpr int kUpdateGridImplicit = 1024;   // the implicit form's update, which prefetches deeper
 constexpr int kDirGrid = 1024;
 constexpr int kCounters = 1 + kSpmvBlocksMax;        // arrival counters (level 2 + groups)
 constexpr int kGramBlocksMax = 512;       // grid cap of the fused SpMM + Gram kernel
