@@ -1,4 +1,4 @@
-// Small dense kernels of libpodcg, each run by one workgroup of one wavefront:
+// Small dense kernels of libpodcg, each run by one workgroup of kBlock threads:
 // the factorisation of the reduced matrix W^T A W (Alg. 2) and the POD
 // coefficients from the eigen-decomposition of the snapshot Gram matrix
 // (Alg. pod_evd).  Matrices are at most 32 x 32 and live in LDS.
@@ -9,46 +9,59 @@ namespace podcg {
 constexpr int kLd = kYMax + 1;   // padded LDS row stride
 
 // Jacobi eigen-decomposition of the symmetric m x m matrix a (LDS, stride
-// kLd) by one wavefront; V (LDS) receives the eigenvectors as columns.  Each
-// rotation is the symmetric Schur decomposition of a 2 x 2 block (Golub & Van
-// Loan).  The rotations of one sweep are grouped by the round-robin
-// (tournament) ordering: each step holds m/2 disjoint pairs, so all their row
-// rotations, then all their column rotations, run in parallel across the
-// lanes.  Sweeps stop when the off-diagonal Frobenius norm drops below 1e-15
-// of the full norm.  On exit lam[0..m) holds the eigenvalues in decreasing
-// order, V is permuted to match, and each eigenvector is signed so that its
-// entry of largest magnitude (first such index) is positive.
-__device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
+// kLd) by one workgroup of kBlock threads; V (LDS) receives the eigenvectors
+// as columns.  Each rotation is the symmetric Schur decomposition of a 2 x 2
+// block (Golub & Van Loan).  The rotations of one sweep are grouped by the
+// round-robin (tournament) ordering: each step holds m/2 disjoint pairs, so
+// the step's whole similarity transform splits into independent 2 x 2 blocks,
+// one per thread, and the eigenvector update into independent column pairs.
+// Sweeps stop when the off-diagonal Frobenius norm drops below 1e-15 of the
+// full norm.  On exit lam[0..m) holds the eigenvalues in decreasing order, V
+// is permuted to match, and each eigenvector is signed so that its entry of
+// largest magnitude (first such index) is positive.
+__device__ void block_jacobi(double* a, double* V, double* lam, int m) {
     __shared__ double cs[2 * (kYMax / 2 + 1)];
     __shared__ int pq[2 * (kYMax / 2 + 1)];
-    const int lane = threadIdx.x;
-    for (int e = lane; e < m * m; e += kWave) V[(e / m) * kLd + e % m] = (e / m == e % m) ? 1.0 : 0.0;
-    double f = 0.0;
-    for (int e = lane; e < m * m; e += kWave) {
+    __shared__ double red[kWavesPerBlock + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += kBlock) V[(e / m) * kLd + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+    double f[1] = {0.0};
+    for (int e = tid; e < m * m; e += kBlock) {
         const double v = a[(e / m) * kLd + e % m];
-        f += v * v;
+        f[0] += v * v;
     }
-    const double fro = wave_sum(f);
+    block_sum<1>(f, red);
+    const double fro = red[0];
     const int me = m + (m & 1);          // players, with a bye when m is odd
     const int npair = me / 2;
+    // this thread's 2 x 2 block of pairs (t, u) (npair^2 <= kBlock), and its
+    // entry kq of the V columns of pairs u0 and u0 + 8 (m <= 32)
+    const bool has_blk = tid < npair * npair;
+    const int bt = tid / npair, bu = tid % npair;
+    const int kq = tid & 31, u0 = tid >> 5;
     __syncthreads();
     for (int sweep = 0; sweep < 100 && m > 1; ++sweep) {
-        double o = 0.0;
-        {
-            const int j = lane & 31;
-            if (j < m)
-                for (int i = lane >> 5; i < m; i += 2)
-                    if (i != j) o += a[i * kLd + j] * a[i * kLd + j];
-        }
-        const double off = wave_sum(o);
+        double o[1] = {0.0};
+        if (kq < m)
+            for (int i = u0; i < m; i += kBlock / 32)
+                if (i != kq) o[0] += a[i * kLd + kq] * a[i * kLd + kq];
+        block_sum<1>(o, red);
+        const double off = red[0];
+        __syncthreads();
         if (off <= 1.0e-30 * fro) break;
         for (int step = 0; step < me - 1; ++step) {
             // pairs of this round: position 0 is fixed, the others rotate
-            if (lane < npair) {
-                const int i0 = lane, i1 = me - 1 - lane;
-                const int p0 = i0 == 0 ? 0 : 1 + (i0 - 1 + step) % (me - 1);
-                const int p1 = 1 + (i1 - 1 + step) % (me - 1);
-                int p = p0 < p1 ? p0 : p1, q = p0 < p1 ? p1 : p0;
+            if (tid < npair) {
+                int p0 = 0, p1 = me - 2 - tid + step;
+                if (tid > 0) {
+                    p0 = tid - 1 + step;
+                    if (p0 >= me - 1) p0 -= me - 1;
+                    ++p0;
+                }
+                if (p1 >= me - 1) p1 -= me - 1;
+                ++p1;
+                const int p = p0 < p1 ? p0 : p1;
+                int q = p0 < p1 ? p1 : p0;
                 double c = 1.0, sn = 0.0;
                 if (q < m) {
                     const double apq = a[p * kLd + q];
@@ -59,67 +72,85 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
                         sn = t * c;
                     }
                 } else {
-                    p = q = -1;                  // bye
+                    q = -1;                      // bye: index p keeps the identity
                 }
-                pq[2 * lane] = p;
-                pq[2 * lane + 1] = q;
-                cs[2 * lane] = c;
-                cs[2 * lane + 1] = sn;
+                pq[2 * tid] = p;
+                pq[2 * tid + 1] = q;
+                cs[2 * tid] = c;
+                cs[2 * tid + 1] = sn;
             }
             __syncthreads();
-            // rows p, q of every pair:  A <- J^T A.  Lane l updates entry
-            // k = l % 32 of pairs t = l / 32, l / 32 + 2, ... (m <= 32, so no
-            // index needs a division)
-            const int kq = lane & 31, t0 = lane >> 5;
-            if (kq < m)
-                for (int t = t0; t < npair; t += 2) {
-                    const int p = pq[2 * t], q = pq[2 * t + 1];
-                    if (p < 0) continue;
-                    const double c = cs[2 * t], sn = cs[2 * t + 1];
-                    const double apk = a[p * kLd + kq], aqk = a[q * kLd + kq];
-                    a[p * kLd + kq] = c * apk - sn * aqk;
-                    a[q * kLd + kq] = sn * apk + c * aqk;
+            // A <- J^T A J with J the direct sum of the pairs' rotations: the
+            // 2 x 2 block of rows {p_t, q_t} and columns {p_u, q_u} becomes
+            // J_t^T A_tu J_u (rows first, then columns).  The blocks partition
+            // A, and V's column pairs are disjoint, so every thread loads all
+            // of its entries before it stores any.
+            double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+            int pt = 0, qt = -1, pu = 0, qu = -1;
+            if (has_blk) {
+                pt = pq[2 * bt];
+                qt = pq[2 * bt + 1];
+                pu = pq[2 * bu];
+                qu = pq[2 * bu + 1];
+                b0 = a[pt * kLd + pu];
+                if (qu >= 0) b1 = a[pt * kLd + qu];
+                if (qt >= 0) b2 = a[qt * kLd + pu];
+                if (qt >= 0 && qu >= 0) b3 = a[qt * kLd + qu];
+            }
+            double vp[2] = {0.0, 0.0}, vq[2] = {0.0, 0.0};
+            int vpu[2] = {0, 0}, vqu[2] = {-1, -1};
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int u = u0 + 8 * r;
+                if (kq < m && u < npair) {
+                    vpu[r] = pq[2 * u];
+                    vqu[r] = pq[2 * u + 1];
+                    vp[r] = V[kq * kLd + vpu[r]];
+                    if (vqu[r] >= 0) vq[r] = V[kq * kLd + vqu[r]];
                 }
-            __syncthreads();
-            // columns p, q of every pair:  A <- A J,  V <- V J
-            if (kq < m)
-                for (int t = t0; t < npair; t += 2) {
-                    const int p = pq[2 * t], q = pq[2 * t + 1];
-                    if (p < 0) continue;
-                    const double c = cs[2 * t], sn = cs[2 * t + 1];
-                    const double akp = a[kq * kLd + p], akq = a[kq * kLd + q];
-                    a[kq * kLd + p] = c * akp - sn * akq;
-                    a[kq * kLd + q] = sn * akp + c * akq;
-                    const double vkp = V[kq * kLd + p], vkq = V[kq * kLd + q];
-                    V[kq * kLd + p] = c * vkp - sn * vkq;
-                    V[kq * kLd + q] = sn * vkp + c * vkq;
+            }
+            if (has_blk) {
+                const double ct = cs[2 * bt], st = cs[2 * bt + 1];
+                const double cu = cs[2 * bu], su = cs[2 * bu + 1];
+                const double rp0 = ct * b0 - st * b2;
+                const double rp1 = ct * b1 - st * b3;
+                const double rq0 = st * b0 + ct * b2;
+                const double rq1 = st * b1 + ct * b3;
+                const bool zero = bt == bu && st != 0.0;   // the pair's own a_pq
+                a[pt * kLd + pu] = cu * rp0 - su * rp1;
+                if (qu >= 0) a[pt * kLd + qu] = zero ? 0.0 : su * rp0 + cu * rp1;
+                if (qt >= 0) {
+                    a[qt * kLd + pu] = zero ? 0.0 : cu * rq0 - su * rq1;
+                    if (qu >= 0) a[qt * kLd + qu] = su * rq0 + cu * rq1;
                 }
-            __syncthreads();
-            if (lane < npair) {
-                const int p = pq[2 * lane], q = pq[2 * lane + 1];
-                if (p >= 0 && cs[2 * lane + 1] != 0.0) {
-                    a[p * kLd + q] = 0.0;
-                    a[q * kLd + p] = 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int u = u0 + 8 * r;
+                if (kq < m && u < npair) {
+                    const double c = cs[2 * u], sn = cs[2 * u + 1];
+                    V[kq * kLd + vpu[r]] = c * vp[r] - sn * vq[r];
+                    if (vqu[r] >= 0) V[kq * kLd + vqu[r]] = sn * vp[r] + c * vq[r];
                 }
             }
             __syncthreads();
         }
     }
-    if (lane < m) lam[lane] = a[lane * kLd + lane];
+    if (tid < m) lam[tid] = a[tid * kLd + tid];
     __syncthreads();
-    // selection sort, decreasing; lanes swap the rows of V in parallel
+    // selection sort, decreasing; threads swap the rows of V in parallel
     for (int i = 0; i < m; ++i) {
         int best = i;
         for (int j = i + 1; j < m; ++j)
             if (lam[j] > lam[best]) best = j;
         __syncthreads();
         if (best != i) {
-            if (lane < m) {
-                const double t = V[lane * kLd + i];
-                V[lane * kLd + i] = V[lane * kLd + best];
-                V[lane * kLd + best] = t;
+            if (tid < m) {
+                const double t = V[tid * kLd + i];
+                V[tid * kLd + i] = V[tid * kLd + best];
+                V[tid * kLd + best] = t;
             }
-            if (lane == 0) {
+            if (tid == 0) {
                 const double t = lam[i];
                 lam[i] = lam[best];
                 lam[best] = t;
@@ -127,12 +158,12 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
         }
         __syncthreads();
     }
-    if (lane < m) {
+    if (tid < m) {
         int big = 0;
         for (int k = 1; k < m; ++k)
-            if (fabs(V[k * kLd + lane]) > fabs(V[big * kLd + lane])) big = k;
-        if (V[big * kLd + lane] < 0.0)
-            for (int k = 0; k < m; ++k) V[k * kLd + lane] = -V[k * kLd + lane];
+            if (fabs(V[k * kLd + tid]) > fabs(V[big * kLd + tid])) big = k;
+        if (V[big * kLd + tid] < 0.0)
+            for (int k = 0; k < m; ++k) V[k * kLd + tid] = -V[k * kLd + tid];
     }
     __syncthreads();
 }
@@ -142,21 +173,21 @@ __device__ void wave_jacobi(double* a, double* V, double* lam, int m) {
 // <= 1e-14 max_i G_ii, and form Ginv = R^{-1} R^{-T} on the kept leading
 // block (row-major, stride = kept rank).  st->y receives the kept rank and
 // lam the eigenvalues of the kept block (for its condition number).
-__global__ __launch_bounds__(kWave) void k_reduced_factor(double* G, int m, double* R, double* Ginv,
+__global__ __launch_bounds__(kBlock) void k_reduced_factor(double* G, int m, double* R, double* Ginv,
                                                           double* lam, DevState* st) {
     __shared__ double g[kYMax * kLd], rr[kYMax * kLd], ri[kYMax * kLd], v[kYMax * kLd];
     __shared__ double lm[kYMax];
     __shared__ int kept_s;
-    const int lane = threadIdx.x;
-    for (int e = lane; e < m * m; e += kWave) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += kBlock) {
         const int i = e / m, j = e % m;
         g[i * kLd + j] = 0.5 * (G[i * m + j] + G[j * m + i]);
     }
     __syncthreads();
-    for (int e = lane; e < m * m; e += kWave) G[e] = g[(e / m) * kLd + e % m];
-    for (int e = lane; e < kYMax * kLd; e += kWave) { rr[e] = 0.0; ri[e] = 0.0; }
+    for (int e = tid; e < m * m; e += kBlock) G[e] = g[(e / m) * kLd + e % m];
+    for (int e = tid; e < kYMax * kLd; e += kBlock) { rr[e] = 0.0; ri[e] = 0.0; }
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
         double dmax = 0.0;
         for (int i = 0; i < m; ++i) dmax = fmax(dmax, g[i * kLd + i]);
         int kept = m;
@@ -176,9 +207,9 @@ __global__ __launch_bounds__(kWave) void k_reduced_factor(double* G, int m, doub
     }
     __syncthreads();
     const int y = kept_s;
-    // column j of R^{-1} (upper) by back substitution, one lane per column
-    if (lane < y) {
-        const int j = lane;
+    // column j of R^{-1} (upper) by back substitution, one thread per column
+    if (tid < y) {
+        const int j = tid;
         for (int i = j; i >= 0; --i) {
             double s = (i == j) ? 1.0 : 0.0;
             for (int k = i + 1; k <= j; ++k) s -= rr[i * kLd + k] * ri[k * kLd + j];
@@ -186,20 +217,20 @@ __global__ __launch_bounds__(kWave) void k_reduced_factor(double* G, int m, doub
         }
     }
     __syncthreads();
-    for (int e = lane; e < y * y; e += kWave) {
+    for (int e = tid; e < y * y; e += kBlock) {
         const int i = e / y, j = e % y;
         double s = 0.0;
         for (int k = (i > j ? i : j); k < y; ++k) s += ri[i * kLd + k] * ri[j * kLd + k];
         Ginv[e] = s;
     }
-    for (int e = lane; e < m * m; e += kWave) R[e] = rr[(e / m) * kLd + e % m];
+    for (int e = tid; e < m * m; e += kBlock) R[e] = rr[(e / m) * kLd + e % m];
     // eigenvalues of the kept block (condition number of W^T A W)
     __syncthreads();
-    for (int e = lane; e < y * y; e += kWave) v[(e / y) * kLd + e % y] = g[(e / y) * kLd + e % y];
+    for (int e = tid; e < y * y; e += kBlock) v[(e / y) * kLd + e % y] = g[(e / y) * kLd + e % y];
     __syncthreads();
-    if (y > 0) wave_jacobi(v, ri, lm, y);
-    if (lane < y) lam[lane] = lm[lane];
-    if (lane == 0) st->y = y;
+    if (y > 0) block_jacobi(v, ri, lm, y);
+    if (tid < y) lam[tid] = lm[tid];
+    if (tid == 0) st->y = y;
 }
 
 struct Weights {
@@ -210,23 +241,23 @@ struct Weights {
 // Gbar = V diag(lam) V^T; y = #{lam_i > rank_rtol lam_1}, capped by rank_max
 // and the energy criterion; T = diag(w) V_y diag(lam_y)^{-1/2} (count x y,
 // row-major).  Writes lam[0..count) and *y_out.
-__global__ __launch_bounds__(kWave) void k_pod_coeffs(const double* Gs, int count, Weights wt,
+__global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int count, Weights wt,
                                                       int rank_max, double rank_rtol, double energy,
                                                       double* T, double* lam_out, int* y_out) {
     __shared__ double a[kYMax * kLd], V[kYMax * kLd];
     __shared__ double lam[kYMax];
     __shared__ int y_s;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int m = count;
-    for (int e = lane; e < m * m; e += kWave) {
+    for (int e = tid; e < m * m; e += kBlock) {
         const int i = e / m, j = e % m;
         const double gij = wt.w[i] * Gs[i * m + j] * wt.w[j];
         const double gji = wt.w[j] * Gs[j * m + i] * wt.w[i];
         a[i * kLd + j] = 0.5 * (gij + gji);
     }
     __syncthreads();
-    wave_jacobi(a, V, lam, m);
-    if (lane == 0) {
+    block_jacobi(a, V, lam, m);
+    if (tid == 0) {
         int y = 0;
         if (lam[0] > 0.0)
             for (int i = 0; i < m; ++i)
@@ -247,17 +278,17 @@ __global__ __launch_bounds__(kWave) void k_pod_coeffs(const double* Gs, int coun
     }
     __syncthreads();
     const int y = y_s;
-    for (int e = lane; e < m * y; e += kWave) {
+    for (int e = tid; e < m * y; e += kBlock) {
         const int k = e / y, i = e % y;
         T[e] = wt.w[k] * V[k * kLd + i] / sqrt(lam[i]);
     }
-    if (lane < m) lam_out[lane] = lam[lane];
+    if (tid < m) lam_out[tid] = lam[tid];
 }
 
 hipError_t launch_reduced_factor(double* G, int m, double* R, double* Ginv, double* lam,
                                  DevState* st, hipStream_t s) {
     if (m < 1 || m > kYMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reduced_factor, dim3(1), dim3(kWave), 0, s, G, m, R, Ginv, lam, st);
+    hipLaunchKernelGGL(k_reduced_factor, dim3(1), dim3(kBlock), 0, s, G, m, R, Ginv, lam, st);
     return hipGetLastError();
 }
 
@@ -267,7 +298,7 @@ hipError_t launch_pod_coeffs(const double* Gs, int count, const double* w, int r
     if (count < 1 || count > kYMax) return hipErrorInvalidValue;
     Weights wt;
     for (int i = 0; i < kYMax; ++i) wt.w[i] = i < count ? w[i] : 0.0;
-    hipLaunchKernelGGL(k_pod_coeffs, dim3(1), dim3(kWave), 0, s, Gs, count, wt, rank_max, rank_rtol,
+    hipLaunchKernelGGL(k_pod_coeffs, dim3(1), dim3(kBlock), 0, s, Gs, count, wt, rank_max, rank_rtol,
                        energy, T, lam, y_out);
     return hipGetLastError();
 }
