@@ -402,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(DevBufs B, int y, const double
 // (padding columns of A X are zero).  Per-workgroup partial Grams are summed
 // in a fixed two-level order.
 typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kMfmaGroup = 4;   // MFMA steps (4 rows each) per X operand load group
 
 template <int KS>
 __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const double* __restrict__ X,
@@ -434,6 +435,24 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) acc[kk] = 0.0;
         const int row = s * kSlice + lane;
+        // X operand of MFMA step st for column tile a: X[row 4 st + r4][col
+        // 16 a + cc] of this slice (rows past n read row n - 1 and count as
+        // zero; columns past k repeat column k - 1 and feed unused G rows).
+        // Group 0 is loaded here, under the SpMM below.
+        double xg[kMfmaGroup][KT];
+        auto load_xgroup = [&](int g) {
+#pragma unroll
+            for (int u = 0; u < kMfmaGroup; ++u)
+#pragma unroll
+                for (int a = 0; a < KT; ++a) {
+                    const int grow = s * kSlice + 4 * (g * kMfmaGroup + u) + r4;
+                    const int colx = 16 * a + cc;
+                    const int colc = colx < k ? colx : k - 1;
+                    const double v = X[(size_t)colc * B.ld + (grow < B.n ? grow : B.n - 1)];
+                    xg[u][a] = grow < B.n ? v : 0.0;
+                }
+        };
+        load_xgroup(0);
         if (sv) {
             const int64_t base = B.sptr[s];
             const int w = (int)((B.sptr[s + 1] - base) / kSlice);
@@ -476,23 +495,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) tw[lane * LDSW + kk] = (kk < k && live) ? acc[kk] : 0.0;
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll 4
-        for (int st = 0; st < kSlice / 4; ++st) {
-            const int rr = 4 * st + r4;
-            const int grow = s * kSlice + rr;
-            double xa[KT], bb[KT];
+        // the X operands of group g + 1 are in flight while group g's MFMAs run
+        double xc[kMfmaGroup][KT];
 #pragma unroll
-            for (int a = 0; a < KT; ++a) {
-                const int colx = 16 * a + cc;
-                const int colc = colx < k ? colx : k - 1;
-                xa[a] = (sv && grow < B.n) ? X[(size_t)colc * B.ld + grow] : 0.0;
-                bb[a] = colx < KS ? tw[rr * LDSW + (colx < KS ? colx : 0)] : 0.0;
+        for (int u = 0; u < kMfmaGroup; ++u)
+#pragma unroll
+            for (int a = 0; a < KT; ++a) xc[u][a] = xg[u][a];
+#pragma unroll
+        for (int g = 0; g < kSlice / 4 / kMfmaGroup; ++g) {
+            if (g + 1 < kSlice / 4 / kMfmaGroup) load_xgroup(g + 1);
+#pragma unroll
+            for (int u = 0; u < kMfmaGroup; ++u) {
+                const int rr = 4 * (g * kMfmaGroup + u) + r4;
+                double bb[KT];
+#pragma unroll
+                for (int b = 0; b < KT; ++b) {
+                    const int colx = 16 * b + cc;
+                    bb[b] = colx < KS ? tw[rr * LDSW + (colx < KS ? colx : 0)] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < KT; ++a)
+#pragma unroll
+                    for (int b = 0; b < KT; ++b)
+                        d[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[u][a], bb[b], d[a][b], 0, 0, 0);
             }
 #pragma unroll
-            for (int a = 0; a < KT; ++a)
+            for (int u = 0; u < kMfmaGroup; ++u)
 #pragma unroll
-                for (int b = 0; b < KT; ++b)
-                    d[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], bb[b], d[a][b], 0, 0, 0);
+                for (int a = 0; a < KT; ++a) xc[u][a] = xg[u][a];
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
