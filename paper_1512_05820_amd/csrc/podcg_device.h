@@ -225,11 +225,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + t;
 }
 
-// Row (64 s + lane) of A x for the slice s handled by this wave.  Slices of
-// width <= 8 (stencil matrices) take a branch-free path: all column indices
-// and values are loaded first (padding slots re-read the last valid slot and
-// are skipped with a select), then all gathers, then the sums in order j =
-// 0, 1, ...; wider slices loop in chunks of 8.  s is wave-uniform, so the
+// Row (64 s + lane) of A x for the slice s handled by this wave.  Offset-table
+// slices (widths 1..8, stencil matrices) branch on their width to a path of
+// exactly that many value and gather loads, then the sums in order j = 0, 1,
+// ...; the other storages loop in chunks of 8 (all column indices and values
+// of a chunk first, padding slots re-reading the last valid slot and skipped
+// with a select, then the gathers, then the sums).  s is wave-uniform, so the
 // slice bounds and the format flag are scalar loads.  Three storages of the
 // columns, chosen per slice at ingest:
 //   flag 2: every row of the slice draws its columns from one list of w <= 8
@@ -296,40 +297,6 @@ constexpr int kLoopGridMax = 4096;
         else hipLaunchKernelGGL(K, G, T, 0, S, __VA_ARGS__);                                        \
     } while (0)        // largest loop grid (partial and counter capacity)
 
-template <typename T>
-__device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict__ vals, int s, int lane,
-                                          const T* __restrict__ x) {
-    s = __builtin_amdgcn_readfirstlane(s);
-    const int64_t base = B.sptr[s];
-    const int w = (int)((B.sptr[s + 1] - base) / kSlice);
-    const T* v = vals + base + lane;
-    const int flag = B.sflag[s];
-    if (flag == 2) {
-        const int row = s * kSlice + lane;
-        const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
-        int ci[kTabMax];
-        T vi[kTabMax];
-#pragma unroll
-        for (int u = 0; u < kTabMax; ++u) {
-            const int j = min(u, w - 1);
-            const int c = row + tab[j];
-            ci[u] = c < 0 ? 0 : (c < B.n ? c : B.n - 1);
-            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
-        }
-        T xi[kTabMax];
-#pragma unroll
-        for (int u = 0; u < kTabMax; ++u) xi[u] = x[ci[u]];
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kTabMax; ++u) acc = u < w ? fma((double)vi[u], (double)xi[u], acc) : acc;
-        return acc;
-    }
-    if (flag == 1) {
-        const int row = s * kSlice + lane;
-        return sell_row_cols<T, int16_t>(B.cols16 + base + lane, v, w, row < B.n ? row : 0, x);
-    }
-    return sell_row_cols<T, int>(B.cols + base + lane, v, w, 0, x);
-}
 
 // The per-slice metadata a wave needs before its first vector load (slice
 // offset, width, column storage, offset table).  The loop SpMV reads it as one
@@ -362,7 +329,76 @@ __device__ __forceinline__ SliceMeta slice_meta_unpack(int v) {
     m.tab[7] = __builtin_amdgcn_readlane(v, 11);
     return m;
 }
-// sell_row with the metadata already loaded.
+// Offset-table widths with a path of their own, the stencil widths first.
+#define PODCG_TAB_WIDTHS(X) X(7) X(5) X(6) X(4) X(3) X(8) X(2) X(1)
+
+// The row of an offset-table slice of width WN: exactly WN value and WN
+// gather loads, each offset read straight from its (scalar) table entry
+// tab(u).
+template <typename T, int WN, typename Tab>
+__device__ __forceinline__ double sell_row_tab(const DevBufs& B, Tab tab, const T* __restrict__ v, int row,
+                                              const T* __restrict__ x) {
+    int ci[WN];
+    T vi[WN];
+#pragma unroll
+    for (int u = 0; u < WN; ++u) {
+        const int c = row + tab(u);
+        ci[u] = c < 0 ? 0 : (c < B.n ? c : B.n - 1);
+        vi[u] = __builtin_nontemporal_load(v + u * kSlice);
+    }
+    T xi[WN];
+#pragma unroll
+    for (int u = 0; u < WN; ++u) xi[u] = x[ci[u]];
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < WN; ++u) acc = fma((double)vi[u], (double)xi[u], acc);
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ double sell_row(const DevBufs& B, const T* __restrict__ vals, int s, int lane,
+                                          const T* __restrict__ x) {
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int64_t base = B.sptr[s];
+    const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+    const T* v = vals + base + lane;
+    const int flag = B.sflag[s];
+    if (flag == 2) {
+        const int row = s * kSlice + lane;
+        const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
+        const auto tabf = [&](int u) { return tab[u]; };
+        switch (w) {
+#define PODCG_TAB_CASE(WN) case WN: return sell_row_tab<T, WN>(B, tabf, v, row, x);
+            PODCG_TAB_WIDTHS(PODCG_TAB_CASE)
+#undef PODCG_TAB_CASE
+            default: break;
+        }
+        int ci[kTabMax];
+        T vi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) {
+            const int j = min(u, w - 1);
+            const int c = row + tab[j];
+            ci[u] = c < 0 ? 0 : (c < B.n ? c : B.n - 1);
+            vi[u] = __builtin_nontemporal_load(v + j * kSlice);
+        }
+        T xi[kTabMax];
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) xi[u] = x[ci[u]];
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kTabMax; ++u) acc = u < w ? fma((double)vi[u], (double)xi[u], acc) : acc;
+        return acc;
+    }
+    if (flag == 1) {
+        const int row = s * kSlice + lane;
+        return sell_row_cols<T, int16_t>(B.cols16 + base + lane, v, w, row < B.n ? row : 0, x);
+    }
+    return sell_row_cols<T, int>(B.cols + base + lane, v, w, 0, x);
+}
+
+// sell_row with the metadata already loaded.  Offset-table slices branch on
+// their (wave-uniform) width to a path of exactly that width.
 template <typename T>
 __device__ __forceinline__ double sell_row_meta(const DevBufs& B, const SliceMeta& m, const T* __restrict__ vals,
                                                int s, int lane, const T* __restrict__ x) {
@@ -370,6 +406,13 @@ __device__ __forceinline__ double sell_row_meta(const DevBufs& B, const SliceMet
     const T* v = vals + m.base + lane;
     const int row = s * kSlice + lane;
     if (m.flag == 2) {
+        const auto tab = [&](int u) { return m.tab[u]; };
+        switch (w) {
+#define PODCG_TAB_CASE(WN) case WN: return sell_row_tab<T, WN>(B, tab, v, row, x);
+            PODCG_TAB_WIDTHS(PODCG_TAB_CASE)
+#undef PODCG_TAB_CASE
+            default: break;
+        }
         int ci[kTabMax];
         T vi[kTabMax];
 #pragma unroll
