@@ -71,8 +71,9 @@ typedef struct {
     int32_t max_refine;   /* refinement steps cap when precision = 1                         */
     double  inner_rtol;   /* relative tolerance of each FP32 inner solve (precision = 1)      */
     int32_t spmv_grid;    /* workgroups of the loop SpMV (0 = default 1024; at most 4096)     */
-    int32_t update_grid;  /* workgroups of the residual-update kernel (0 = default: 1024 for the
-                             implicit form, 512 otherwise; at most 4096)                     */
+    int32_t update_grid;  /* workgroups of the residual-update kernel (0 = default: for the
+                             implicit form one per 2048 rows, rounded up to a multiple of 256
+                             and kept within [512, 1024]; 512 otherwise; at most 4096)        */
     int32_t dir_grid;     /* workgroups of the direction kernel (0 = default 1024; <= 4096)   */
     int32_t projection;   /* form of the direction recurrence of Alg. 1 in FP64 solves:
                              0 explicit: p = z + beta p - W mu is formed every iteration;

@@ -214,7 +214,11 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         // implicit form: d_p holds pt and the direction kernel carries no basis
         const bool imp = y > 0 && ctx->opt.projection == 1;
         const int dyb = imp ? 0 : yb, dy = imp ? 0 : y;
-        if (imp && ctx->opt.update_grid == 0) B.update_grid = kUpdateGridImplicit;
+        // the implicit update by default: about eight rows a thread (one
+        // workgroup per 2048 rows, a multiple of 256, between 512 and 1024)
+        if (imp && ctx->opt.update_grid == 0)
+            B.update_grid = (int)std::min<int64_t>(kUpdateGridImplicit,
+                std::max<int64_t>(kUpdateGrid, ((ctx->n + 2047) / 2048 + 255) / 256 * 256));
         HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s, imp));
         // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
         HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
