@@ -171,6 +171,66 @@ def test_stencil_slices_use_offset_tables(P, N, dim):
     assert _relerr(_host(xg), xo) <= 1e-9
 
 
+@pytest.mark.parametrize("w", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_offset_tables_of_every_width(P, w):
+    """Banded matrices whose slices all draw on one list of w offsets (the
+    first w of 0, 1, -1, 5, -5, 64, -64, 300), n = 5,000 with a ragged last
+    slice: every slice stores an offset table and takes the path of its exact
+    width.  The product matches the oracle's; for the symmetric lists (odd w)
+    plain and augmented solves (random 3-column basis) match the oracle's
+    iterates, which exercises the loop SpMV and the FP32 one of mixed
+    precision."""
+    n = 5_000
+    offs = [0, 1, -1, 5, -5, 64, -64, 300][:w]
+    r = _rng(40 + w)
+    rows, cols, vals = [], [], []
+    sym = {}
+    for i in range(n):
+        for d in offs:
+            j = i + d
+            if 0 <= j < n:
+                if d == 0:
+                    v = 4.0 * len(offs) + r.random()
+                else:
+                    key = (min(i, j), max(i, j))
+                    v = sym.setdefault(key, -0.5 - 0.5 * r.random())
+                rows.append(i)
+                cols.append(j)
+                vals.append(v)
+    rowptr, colind, vals = _csr_from_triplets(n, rows, cols, vals)
+    A = oracle.CSR(rowptr, colind, vals)
+    ctx = _ctx(P, n, rank_max=3)
+    _set(ctx, rowptr, colind, vals)
+    f = ctx.format_counts()
+    assert f == {"int32": 0, "offset16": 0, "table": (n + 63) // 64}
+    x = r.standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.matvec(_dev(x), y)
+    assert _relerr(_host(y), oracle.matvec(A, x)) <= 1e-14
+    if w % 2 == 0:
+        return
+    b = r.standard_normal(n)
+    xo, so = oracle.plain_pcg(A, b, np.zeros(n), tol=1e-10, maxit=5000)
+    xg = _dev(np.zeros(n))
+    st = ctx.solve_plain(_dev(b), xg, 1e-10)
+    assert st.status == 0 and abs(st.iters - so.iters) <= 1
+    assert _relerr(_host(xg), xo) <= 1e-9
+    W = r.standard_normal((n, 3))
+    xa, sa = oracle.aug_pcg(A, b, np.zeros(n), W, 1e-10, 5000)
+    ctx.set_basis(_dev(W))
+    xg = _dev(np.zeros(n))
+    st = ctx.solve(_dev(b), xg, 1e-10)
+    assert st.status == 0 and abs(st.iters - sa.iters) <= 1
+    assert _relerr(_host(xg), xa) <= 1e-9
+    mixed = _ctx(P, n, rank_max=3, precision="mixed")
+    _set(mixed, rowptr, colind, vals)
+    mixed.set_basis(_dev(W))
+    xm = _dev(np.zeros(n))
+    st = mixed.solve(_dev(b), xm, 1e-10)
+    assert st.status == 0
+    assert np.linalg.norm(b - oracle.matvec(A, _host(xm))) / np.linalg.norm(b) <= 1.01e-10
+
+
 def test_unsorted_and_duplicate_rows_keep_per_entry_columns(P):
     """A row whose columns are out of order, and a row with a repeated column
     (two entries that add up), make their slices keep per-entry columns; the
