@@ -221,23 +221,50 @@ __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
                                                         const int64_t* __restrict__ sptr,
                                                         const int* __restrict__ cols,
                                                         const int* __restrict__ map,
+                                                        const uint8_t* __restrict__ sflag,
+                                                        const int* __restrict__ soff,
                                                         const double* __restrict__ csr_vals,
                                                         double* __restrict__ vals,
                                                         double* __restrict__ dinv, int* flag) {
     const int total = nslices * kSlice;
     int bad = 0;
     for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock) {
-        const int s = row / kSlice, lane = row % kSlice;
+        const int s = row / kSlice, lane = row % kSlice;   // s is wave-uniform
         const int64_t base = sptr[s];
         const int w = (int)((sptr[s + 1] - base) / kSlice);
         double d = 0.0;
-        for (int j = 0; j < w; ++j) {
-            const int64_t slot = base + (int64_t)j * kSlice + lane;
-            const int m = map[slot];
-            const double v = m >= 0 ? csr_vals[m] : 0.0;
-            vals[slot] = v;
-            if (!is_finite(v)) bad |= 8;
-            if (m >= 0 && cols[slot] == row) d += v;
+        if (w <= kTabMax) {
+            // all slot indices, then all value gathers, then the stores; an
+            // offset-table slice takes its diagonal from the zero offset (a
+            // table lists distinct offsets), the others compare columns
+            int m[kTabMax];
+#pragma unroll
+            for (int u = 0; u < kTabMax; ++u) m[u] = u < w ? map[base + (int64_t)u * kSlice + lane] : -1;
+            double v[kTabMax];
+#pragma unroll
+            for (int u = 0; u < kTabMax; ++u) v[u] = m[u] >= 0 ? csr_vals[m[u]] : 0.0;
+            const bool tabled = sflag[s] == 2;
+            int c[kTabMax];
+#pragma unroll
+            for (int u = 0; u < kTabMax; ++u)
+                c[u] = u < w ? (tabled ? row + soff[(size_t)s * kTabMax + u] : cols[base + (int64_t)u * kSlice + lane]) : -1;
+#pragma unroll
+            for (int u = 0; u < kTabMax; ++u) {
+                if (u < w) {
+                    vals[base + (int64_t)u * kSlice + lane] = v[u];
+                    if (!is_finite(v[u])) bad |= 8;
+                    if (m[u] >= 0 && c[u] == row) d += v[u];
+                }
+            }
+        } else {
+            for (int jj = 0; jj < w; ++jj) {
+                const int64_t slot = base + (int64_t)jj * kSlice + lane;
+                const int mm = map[slot];
+                const double vv = mm >= 0 ? csr_vals[mm] : 0.0;
+                vals[slot] = vv;
+                if (!is_finite(vv)) bad |= 8;
+                if (mm >= 0 && cols[slot] == row) d += vv;
+            }
         }
         if (row < n) {
             if (!(d > 0.0)) bad |= 4;
@@ -656,10 +683,10 @@ hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const 
 }
 
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
-                              const int* map, const double* csr_vals, double* vals, double* dinv,
-                              int* flag, hipStream_t s) {
+                              const int* map, const uint8_t* sflag, const int* soff, const double* csr_vals,
+                              double* vals, double* dinv, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_values, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
-                       0, s, n, nslices, sptr, cols, map, csr_vals, vals, dinv, flag);
+                       0, s, n, nslices, sptr, cols, map, sflag, soff, csr_vals, vals, dinv, flag);
     return hipGetLastError();
 }
 

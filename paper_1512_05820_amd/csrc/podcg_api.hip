@@ -481,8 +481,8 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             if (nnz != ctx->nnz) fail(ctx, PODCG_ERR_SIZE, "nnz differs from the cached pattern");
         }
         HIPCHECK(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s));
-        HIPCHECK(launch_fill_values(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_map, vals,
-                                    ctx->d_vals, ctx->d_dinv, ctx->d_flag, s));
+        HIPCHECK(launch_fill_values(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_map, ctx->d_sflag,
+                                    ctx->d_soff, vals, ctx->d_vals, ctx->d_dinv, ctx->d_flag, s));
         HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
         sync(ctx);
         ctx->setup_valid = false;

@@ -466,8 +466,8 @@ hipError_t launch_fill_offsets16(int n, int nslices, const int64_t* sptr, const 
 hipError_t launch_fill_meta(int nslices, const int64_t* sptr, const uint8_t* sflag, const int* soff, int* smeta,
                             hipStream_t s);
 hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int* cols,
-                              const int* map, const double* csr_vals, double* vals, double* dinv,
-                              int* flag, hipStream_t s);
+                              const int* map, const uint8_t* sflag, const int* soff, const double* csr_vals,
+                              double* vals, double* dinv, int* flag, hipStream_t s);
 hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const int* cols, const int* map,
                                 const double* u, const double* v, double scale, double* out,
                                 hipStream_t s);
