@@ -27,7 +27,9 @@ __global__ __launch_bounds__(kBlock) void k_gemv_n(int n, size_t ld, const doubl
 
 // part[g * m + k] = sum over the rows of chunk g of Y(i, k) v(i): each wave
 // takes 8 columns at a time (one load of v per row for all 8), lanes over the
-// rows; the last group re-reads the last column instead of branching.
+// rows; the last group re-reads the last column instead of branching.  The
+// grid is row chunks (x) by groups of 32 columns (y), so a wide Y fills the
+// chip with waves.
 constexpr int kGemvCols = 8;
 __global__ __launch_bounds__(kBlock) void k_gemv_t_part(int n, size_t ld, const double* __restrict__ Y,
                                                         int m, const double* __restrict__ v,
@@ -35,7 +37,8 @@ __global__ __launch_bounds__(kBlock) void k_gemv_t_part(int n, size_t ld, const 
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int r0 = blockIdx.x * rows;
     const int r1 = min(n, r0 + rows);
-    for (int k0 = wid * kGemvCols; k0 < m; k0 += kWavesPerBlock * kGemvCols) {
+    for (int k0 = (blockIdx.y * kWavesPerBlock + wid) * kGemvCols; k0 < m;
+         k0 += gridDim.y * kWavesPerBlock * kGemvCols) {
         double acc[kGemvCols];
         const double* __restrict__ yk[kGemvCols];
 #pragma unroll
@@ -43,6 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_t_part(int n, size_t ld, const 
             acc[u] = 0.0;
             yk[u] = Y + (size_t)min(k0 + u, m - 1) * ld;
         }
+#pragma unroll 2
         for (int i = r0 + lane; i < r1; i += kWave) {
             const double vi = v[i];
 #pragma unroll
@@ -433,7 +437,8 @@ hipError_t launch_gemv_t(int n, size_t ld, const double* Y, int m, const double*
     if (chunks < 1) chunks = 1;
     int rows = (n + chunks - 1) / chunks;
     rows = (rows + kWave - 1) / kWave * kWave;
-    hipLaunchKernelGGL(k_gemv_t_part, dim3(chunks), dim3(kBlock), 0, s, n, ld, Y, m, v, part, rows);
+    const int colgroups = (m + kWavesPerBlock * kGemvCols - 1) / (kWavesPerBlock * kGemvCols);
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(chunks, colgroups), dim3(kBlock), 0, s, n, ld, Y, m, v, part, rows);
     hipLaunchKernelGGL(k_gemv_t_reduce, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part,
                        chunks, m, out);
     return hipGetLastError();
