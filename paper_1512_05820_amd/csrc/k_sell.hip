@@ -329,12 +329,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv_gamma(DevBufs B, const T* __res
         const int s = L * kWavesPerBlock + wid;
         const int nxt = slice_meta_load(B, min((L + nb) * kWavesPerBlock + wid, last));
         if (s < B.nslices) {
-            const double acc = sell_row_meta<T>(B, slice_meta_unpack(cur), mat_vals<T>(B), s, lane, p);
+            const SliceMeta m = slice_meta_unpack(cur);
             const int row = s * kSlice + lane;
+            // offset-table rows return p[row] as gathered at the zero offset,
+            // so the (q, p) partial needs no second load of it
+            RowDiag<T> o{0.0, (T)0, false};
+            if (m.flag == 2 && m.w >= 1 && m.w <= kTabMax) {
+                const auto tab = [&](int u) { return m.tab[u]; };
+                const T* v = mat_vals<T>(B) + m.base + lane;
+                switch (m.w) {
+#define PODCG_TAB_CASE(WN) case WN: o = sell_row_tab_diag<T, WN>(B, tab, v, row, p); break;
+                    PODCG_TAB_WIDTHS(PODCG_TAB_CASE)
+#undef PODCG_TAB_CASE
+                    default: break;
+                }
+            } else {
+                o.acc = sell_row_meta<T>(B, m, mat_vals<T>(B), s, lane, p);
+            }
             if (row < B.n) {
-                const T qv = (T)acc;
+                const T qv = (T)o.acc;
                 q[row] = qv;
-                g[0] += (double)qv * (double)p[row];
+                g[0] += (double)qv * (double)(o.has ? o.xd : p[row]);
             }
         }
         cur = nxt;

@@ -334,10 +334,17 @@ __device__ __forceinline__ SliceMeta slice_meta_unpack(int v) {
 
 // The row of an offset-table slice of width WN: exactly WN value and WN
 // gather loads, each offset read straight from its (scalar) table entry
-// tab(u).
+// tab(u); the row sum and, when the table holds the zero offset, x at the
+// row itself as gathered (has = false otherwise).
+template <typename T>
+struct RowDiag {
+    double acc;
+    T xd;
+    bool has;
+};
 template <typename T, int WN, typename Tab>
-__device__ __forceinline__ double sell_row_tab(const DevBufs& B, Tab tab, const T* __restrict__ v, int row,
-                                              const T* __restrict__ x) {
+__device__ __forceinline__ RowDiag<T> sell_row_tab_diag(const DevBufs& B, Tab tab, const T* __restrict__ v,
+                                                        int row, const T* __restrict__ x) {
     int ci[WN];
     T vi[WN];
 #pragma unroll
@@ -349,10 +356,22 @@ __device__ __forceinline__ double sell_row_tab(const DevBufs& B, Tab tab, const 
     T xi[WN];
 #pragma unroll
     for (int u = 0; u < WN; ++u) xi[u] = x[ci[u]];
-    double acc = 0.0;
+    RowDiag<T> o{0.0, (T)0, false};
 #pragma unroll
-    for (int u = 0; u < WN; ++u) acc = fma((double)vi[u], (double)xi[u], acc);
-    return acc;
+    for (int u = 0; u < WN; ++u) o.acc = fma((double)vi[u], (double)xi[u], o.acc);
+#pragma unroll
+    for (int u = 0; u < WN; ++u) {
+        const bool z = tab(u) == 0;
+        o.xd = z ? xi[u] : o.xd;
+        o.has = o.has || z;
+    }
+    return o;
+}
+
+template <typename T, int WN, typename Tab>
+__device__ __forceinline__ double sell_row_tab(const DevBufs& B, Tab tab, const T* __restrict__ v, int row,
+                                              const T* __restrict__ x) {
+    return sell_row_tab_diag<T, WN>(B, tab, v, row, x).acc;
 }
 
 template <typename T>
