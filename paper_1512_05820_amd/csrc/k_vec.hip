@@ -20,8 +20,8 @@ int basis_tier(int y) {
 // Column of W or A W: read once per iteration, so loaded nontemporally when
 // NTB (keeps the smaller vectors resident in the caches).  The tiled A W of
 // the implicit update is loaded normally: measured at 128^3 and rank 6, the
-// update takes 28.2 us so against 29.0 us nontemporally (the last-level cache
-// then keeps part of it from one iteration to the next).
+// update takes 28.2 us that way against 29.0 us with nontemporal loads (the
+// last-level cache then keeps part of it from one iteration to the next).
 template <bool NTB, typename T>
 __device__ __forceinline__ T basis_load(const T* p) {
     return NTB ? __builtin_nontemporal_load(p) : *p;
