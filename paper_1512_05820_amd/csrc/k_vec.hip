@@ -77,16 +77,21 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
     const T* __restrict__ dinv = mat_dinv<T>(B);
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
-    // the first element's operands are loaded before alpha is formed, so the
-    // memory system is busy while every workgroup sums the SpMV partials
+    // the operands of this thread's first kPrefetch elements are loaded
+    // before alpha is formed, so the memory system is busy while every
+    // workgroup sums the SpMV partials (fewer for wide bases, to bound the
+    // registers)
+    constexpr int kPrefetch = YB <= 8 ? 4 : (YB <= 16 ? 2 : 1);
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
-    T r0 = 0, q0 = 0, d0 = 0, a0[YB > 0 ? YB : 1];
-    if (i0 < n) {
-        r0 = r[i0];
-        q0 = q[i0];
-        d0 = dinv[i0];
+    T rf[kPrefetch], qf[kPrefetch], df[kPrefetch], af[kPrefetch][YB > 0 ? YB : 1];
 #pragma unroll
-        for (int j = 0; j < YB; ++j) a0[j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i0);
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int ic = i0 + u * stride < n ? i0 + u * stride : 0;
+        rf[u] = r[ic];
+        qf[u] = q[ic];
+        df[u] = dinv[ic];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) af[u][j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + ic);
     }
     double alpha_d;
     if (!loop_alpha(B, k, nsp, 0.0, ldsg, alpha_d)) return;
@@ -105,8 +110,10 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
         for (int j = 0; j < YB; ++j)
             if (tier_live<YB>(j, y)) v[2 + j] += (double)a[j] * (double)zi;
     };
-    if (i0 < n) step(i0, r0, q0, d0, a0);
-    for (int i = i0 + stride; i < n; i += stride) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u)
+        if (i0 + u * stride < n) step(i0 + u * stride, rf[u], qf[u], df[u], af[u]);
+    for (int i = i0 + kPrefetch * stride; i < n; i += stride) {
         T a[YB > 0 ? YB : 1];
 #pragma unroll
         for (int j = 0; j < YB; ++j) a[j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i);
