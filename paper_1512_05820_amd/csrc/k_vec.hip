@@ -32,14 +32,29 @@ __device__ __forceinline__ T basis_load(const T* p) {
 // same in every workgroup), minus gcorr in the implicit form.  Workgroup 0
 // records alpha and gamma in slot k & 1.  Returns false when gamma is not
 // positive and finite; then workgroup 0 records the failure and stops the loop.
-__device__ __forceinline__ bool loop_alpha(const DevBufs& B, int k, int nsp, double gcorr, double* ldsg,
-                                           double& alpha) {
+// The first kPartEarly partials of each thread are loaded by loop_partials at
+// the very start of the kernel, ahead of the kernel's own operand prefetch:
+// vector loads complete in order, so the wait for them here does not also wait
+// for the prefetched operands (a wait on a partial loaded after the prefetch
+// would).  The sum keeps the order t, t + kBlock, ... of each thread.
+constexpr int kPartEarly = 4;   // covers SpMV grids up to 1024
+__device__ __forceinline__ void loop_partials(const DevBufs& B, int nsp, double (&gp)[kPartEarly]) {
+#pragma unroll
+    for (int j = 0; j < kPartEarly; ++j) {
+        const int t = threadIdx.x + j * kBlock;
+        gp[j] = t < nsp ? B.gpart[t] : 0.0;   // the SpMV is the previous kernel: plain loads see its writes
+    }
+}
+__device__ __forceinline__ bool loop_alpha(const DevBufs& B, int k, int nsp, const double (&gp)[kPartEarly],
+                                           double gcorr, double* ldsg, double& alpha) {
     DevState* st = B.st;
     const int par = k & 1;
     const double rho = st->lrho[par];       // read next to the partials, before the barrier
     double g[1] = {0.0};
-    // the SpMV is the previous kernel of the stream: plain loads see its writes
-    for (int t = threadIdx.x; t < nsp; t += kBlock) g[0] += B.gpart[t];
+#pragma unroll
+    for (int j = 0; j < kPartEarly; ++j)
+        if ((int)threadIdx.x + j * kBlock < nsp) g[0] += gp[j];
+    for (int t = threadIdx.x + kPartEarly * kBlock; t < nsp; t += kBlock) g[0] += B.gpart[t];
     block_sum<1>(g, ldsg);
     const double gamma = ldsg[0] - gcorr;
     const bool ok = gamma > 0.0 && is_finite(gamma);
@@ -74,6 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
     __shared__ double ldsg[kWavesPerBlock + 2];
     if (k >= B.st->stop) return;
+    double gp[kPartEarly];
+    loop_partials(B, nsp, gp);
     const T* __restrict__ dinv = mat_dinv<T>(B);
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
@@ -94,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
         for (int j = 0; j < YB; ++j) af[u][j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + ic);
     }
     double alpha_d;
-    if (!loop_alpha(B, k, nsp, 0.0, ldsg, alpha_d)) return;
+    if (!loop_alpha(B, k, nsp, gp, 0.0, ldsg, alpha_d)) return;
     const T alpha = (T)alpha_d;
     double v[NV];
 #pragma unroll
@@ -141,6 +158,8 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
     __shared__ double ldsg[kWavesPerBlock + 2];
     const DevState* st = B.st;
     if (k >= st->stop) return;
+    double gp[kPartEarly];
+    loop_partials(B, nsp, gp);
     const int par = k & 1;
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
@@ -164,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
 #pragma unroll
     for (int j = 0; j < YB; ++j) nu[j] = j < y ? st->lnu[par][j] : 0.0;
     double alpha;
-    if (!loop_alpha(B, k, nsp, st->lgcorr[par], ldsg, alpha)) return;
+    if (!loop_alpha(B, k, nsp, gp, st->lgcorr[par], ldsg, alpha)) return;
     double v[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = 0.0;
@@ -202,22 +221,33 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
 // (Alg. 1's projection solve).  Workgroup 0 records the iteration (count,
 // ||r'||^2, (r', z') in slot (k + 1) & 1, status and stop).  Returns false
 // when the sums are not finite (no step is applied then).
-// The scalars of the state and G^{-1} (into sginv) are read at entry, next to
-// the partial loads, so the prologue costs one memory round trip.
+// The group partials ga were loaded by the kernel before its operand
+// prefetch (dir_partials); the state scalars and G^{-1} (into sginv) are read
+// here at entry.
 struct DirStep {
     double alpha, beta;
     bool new_dir;
 };
+// The update's group partials (one per group of kGroup update workgroups,
+// ng <= kBlock), loaded by each kernel before its own operand prefetch, for
+// the same reason as loop_partials.
+template <int NV>
+__device__ __forceinline__ void dir_partials(const DevBufs& B, int nbu, double (&ga)[NV]) {
+    const int ng = (nbu + kGroup - 1) / kGroup;
+    const double* part2 = B.part + (size_t)NV * nbu;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) ga[k] = (int)threadIdx.x < ng ? part2[(size_t)k * ng + threadIdx.x] : 0.0;
+}
 template <int NV, int YB, bool MU>
-__device__ __forceinline__ bool dir_begin(const DevBufs& B, int y, int k, int nbu, double* lds, double* smu,
-                                          double* sginv, DirStep& d) {
+__device__ __forceinline__ bool dir_begin(const DevBufs& B, int y, int k, double (&ga)[NV], double* lds,
+                                          double* smu, double* sginv, DirStep& d) {
     DevState* st = B.st;
     const int par = k & 1;
     const double alpha = st->lalpha[par], rho = st->lrho[par], tol2 = st->tol2;
     const int maxit = st->maxit;
     if (MU)
         for (int e = threadIdx.x; e < y * y; e += kBlock) sginv[e] = B.Ginv[e];
-    group_sum_load<NV>(B.part, nbu, lds);   // ends with a barrier, after which sginv is complete
+    block_sum<NV>(ga, lds);   // the group sums in group order; ends with a barrier, after which sginv is complete
     const double rz = lds[0], rr = lds[1];
     const bool ok = is_finite(rr) && is_finite(rz);
     const bool conv = rr <= tol2, cap = k + 1 >= maxit;
@@ -292,6 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         __syncthreads();
     } else {
         if (k >= st->stop) return;
+        double ga[NV];
+        dir_partials<NV>(B, nbu, ga);
         if (i0 < n) {
             p0 = p[i0];
             z0 = z[i0];
@@ -299,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
 #pragma unroll
             for (int j = 0; j < YB; ++j) w0[j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + i0);
         }
-        if (!dir_begin<NV, YB, (YB > 0)>(B, y, k, nbu, lds, smu, sginv, d)) return;
+        if (!dir_begin<NV, YB, (YB > 0)>(B, y, k, ga, lds, smu, sginv, d)) return;
     }
     T mu[YB > 0 ? YB : 1];
 #pragma unroll
@@ -359,6 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
     __shared__ double smu[YB > 0 ? YB : 1];
     DevState* st = B.st;
     if (k >= st->stop) return;
+    double ga[NV];
+    dir_partials<NV>(B, nbu, ga);
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
     // the operands of this thread's first kPrefetch elements (all of them at
@@ -375,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
         xf[u] = i < n ? x[i] : 0.0;
     }
     DirStep d;
-    if (!dir_begin<NV, YB, false>(B, y, k, nbu, lds, smu, nullptr, d)) return;
+    if (!dir_begin<NV, YB, false>(B, y, k, ga, lds, smu, nullptr, d)) return;
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
         const int i = i0 + u * stride;
