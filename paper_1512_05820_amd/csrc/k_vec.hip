@@ -98,18 +98,22 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
     // before alpha is formed, so the memory system is busy while every
     // workgroup sums the SpMV partials (fewer for wide bases, to bound the
     // registers)
-    constexpr int kPrefetch = YB <= 8 ? 4 : (YB <= 16 ? 2 : 1);
+    constexpr int kPrefetch = YB <= 7 ? 4 : (YB <= 10 ? 3 : (YB <= 14 ? 2 : 1));
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
     T rf[kPrefetch], qf[kPrefetch], df[kPrefetch], af[kPrefetch][YB > 0 ? YB : 1];
+    // elements base, base + stride, ... (kPrefetch of them): all loads first
+    auto load_block = [&](int base) {
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
-        const int ic = i0 + u * stride < n ? i0 + u * stride : 0;
-        rf[u] = r[ic];
-        qf[u] = q[ic];
-        df[u] = dinv[ic];
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int ic = base + u * stride < n ? base + u * stride : 0;
+            rf[u] = r[ic];
+            qf[u] = q[ic];
+            df[u] = dinv[ic];
 #pragma unroll
-        for (int j = 0; j < YB; ++j) af[u][j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + ic);
-    }
+            for (int j = 0; j < YB; ++j) af[u][j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + ic);
+        }
+    };
+    load_block(i0);
     double alpha_d;
     if (!loop_alpha(B, k, nsp, gp, 0.0, ldsg, alpha_d)) return;
     const T alpha = (T)alpha_d;
@@ -127,14 +131,13 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
         for (int j = 0; j < YB; ++j)
             if (tier_live<YB>(j, y)) v[2 + j] += (double)a[j] * (double)zi;
     };
+    // the rest in blocks of kPrefetch elements, each block's loads issued
+    // together (one round trip a block), in the same element order
+    for (int base = i0; base < n; base += kPrefetch * stride) {
+        if (base != i0) load_block(base);
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u)
-        if (i0 + u * stride < n) step(i0 + u * stride, rf[u], qf[u], df[u], af[u]);
-    for (int i = i0 + kPrefetch * stride; i < n; i += stride) {
-        T a[YB > 0 ? YB : 1];
-#pragma unroll
-        for (int j = 0; j < YB; ++j) a[j] = basis_load<NTB>(AW + (size_t)tier_col<YB>(j, y) * B.ld + i);
-        step(i, r[i], q[i], dinv[i], a);
+        for (int u = 0; u < kPrefetch; ++u)
+            if (base + u * stride < n) step(base + u * stride, rf[u], qf[u], df[u], af[u]);
     }
     group_sum_store<NV>(v, B.part, B.counter, lds);
 }
@@ -165,20 +168,24 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
     const int stride = gridDim.x * kBlock;
     // the operands of this thread's first kPrefetch elements are in flight
     // while alpha is formed (fewer for wide bases, to bound the registers)
-    constexpr int kPrefetch = YB <= 8 ? 4 : (YB <= 16 ? 2 : 1);
+    constexpr int kPrefetch = YB <= 7 ? 4 : (YB <= 10 ? 3 : (YB <= 14 ? 2 : 1));
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
     double rf[kPrefetch], qf[kPrefetch], df[kPrefetch], af[kPrefetch][YB > 0 ? YB : 1];
+    // elements base, base + stride, ... (kPrefetch of them): all loads first
+    auto load_block = [&](int base) {
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
-        const int i = i0 + u * stride;
-        const int ic = i < n ? i : 0;
-        rf[u] = r[ic];
-        qf[u] = qt[ic];
-        df[u] = B.dinv[ic];
-        const double* t0 = AWt + (size_t)(ic / kSlice) * (kSlice * y) + (ic % kSlice);
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int i = base + u * stride;
+            const int ic = i < n ? i : 0;
+            rf[u] = r[ic];
+            qf[u] = qt[ic];
+            df[u] = B.dinv[ic];
+            const double* t0 = AWt + (size_t)(ic / kSlice) * (kSlice * y) + (ic % kSlice);
 #pragma unroll
-        for (int j = 0; j < YB; ++j) af[u][j] = basis_load<false>(t0 + tier_col<YB>(j, y) * kSlice);
-    }
+            for (int j = 0; j < YB; ++j) af[u][j] = basis_load<false>(t0 + tier_col<YB>(j, y) * kSlice);
+        }
+    };
+    load_block(i0);
     double nu[YB > 0 ? YB : 1];
 #pragma unroll
     for (int j = 0; j < YB; ++j) nu[j] = j < y ? st->lnu[par][j] : 0.0;
@@ -201,15 +208,13 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
         for (int j = 0; j < YB; ++j)
             if (tier_live<YB>(j, y)) v[2 + j] += a[j] * zi;
     };
+    // the rest in blocks of kPrefetch elements, each block's loads issued
+    // together (one round trip a block), in the same element order
+    for (int base = i0; base < n; base += kPrefetch * stride) {
+        if (base != i0) load_block(base);
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u)
-        if (i0 + u * stride < n) step(i0 + u * stride, rf[u], qf[u], df[u], af[u]);
-    for (int i = i0 + kPrefetch * stride; i < n; i += stride) {
-        double a[YB > 0 ? YB : 1];
-        const double* t = AWt + (size_t)(i / kSlice) * (kSlice * y) + (i % kSlice);
-#pragma unroll
-        for (int j = 0; j < YB; ++j) a[j] = basis_load<false>(t + tier_col<YB>(j, y) * kSlice);
-        step(i, r[i], qt[i], B.dinv[i], a);
+        for (int u = 0; u < kPrefetch; ++u)
+            if (base + u * stride < n) step(base + u * stride, rf[u], qf[u], df[u], af[u]);
     }
     group_sum_store<NV>(v, B.part, B.counter, lds);
 }
