@@ -316,11 +316,27 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
     DirStep d{0.0, 0.0, true};
-    // the first element's operands are loaded before the reduction is
-    // finished, so the memory system is busy meanwhile
+    // the operands of this thread's first kPrefetch elements are loaded before
+    // the reduction is finished, so the memory system is busy meanwhile; the
+    // rest follow in blocks of kPrefetch elements, each block's loads issued
+    // together (fewer for wide bases, to bound the registers)
+    constexpr int kPrefetch = YB == 0 ? 4 : (YB <= 6 ? 2 : 1);
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
-    T p0 = 0, z0 = 0, w0[YB > 0 ? YB : 1];
-    double x0 = 0.0;
+    T pf[kPrefetch], zf[kPrefetch], wf[kPrefetch][YB > 0 ? YB : 1];
+    double xf[kPrefetch];
+    auto load_block = [&](int base, bool need_w) {
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int ic = base + u * stride < n ? base + u * stride : 0;
+            pf[u] = p[ic];
+            zf[u] = z[ic];
+            xf[u] = x[ic];
+            if (need_w) {
+#pragma unroll
+                for (int j = 0; j < YB; ++j) wf[u][j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + ic);
+            }
+        }
+    };
     if (INIT) {
         if (st->stop <= 0) return;
         if (threadIdx.x < y) smu[threadIdx.x] = st->mu[threadIdx.x];
@@ -329,13 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         if (k >= st->stop) return;
         double ga[NV];
         dir_partials<NV>(B, nbu, ga);
-        if (i0 < n) {
-            p0 = p[i0];
-            z0 = z[i0];
-            x0 = x[i0];
-#pragma unroll
-            for (int j = 0; j < YB; ++j) w0[j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + i0);
-        }
+        load_block(i0, true);
         if (!dir_begin<NV, YB, (YB > 0)>(B, y, k, ga, lds, smu, sginv, d)) return;
     }
     T mu[YB > 0 ? YB : 1];
@@ -364,18 +374,20 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         for (int j = 0; j < YB; ++j) s -= w[j] * mu[j];
         p[i] = s;
     };
-    int ifirst = i0;
-    if (!INIT) {
-        if (i0 < n) step(i0, p0, z0, x0, w0);
-        ifirst = i0 + stride;
-    }
-    for (int i = ifirst; i < n; i += stride) {
-        T w[YB > 0 ? YB : 1];
-        if (INIT || d.new_dir) {
+    if (INIT) {
+        for (int i = i0; i < n; i += stride) {
+            T w[YB > 0 ? YB : 1];
 #pragma unroll
             for (int j = 0; j < YB; ++j) w[j] = basis_load<NTB>(W + (size_t)tier_col<YB>(j, y) * B.ld + i);
+            step(i, (T)0, z[i], 0.0, w);
         }
-        step(i, INIT ? (T)0 : p[i], (INIT || d.new_dir) ? z[i] : (T)0, INIT ? 0.0 : x[i], w);
+        return;
+    }
+    for (int base = i0; base < n; base += kPrefetch * stride) {
+        if (base != i0) load_block(base, d.new_dir);
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u)
+            if (base + u * stride < n) step(base + u * stride, pf[u], zf[u], xf[u], wf[u]);
     }
 }
 
