@@ -406,10 +406,29 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
     constexpr int NV = 2 + YB;
     __shared__ double lds[kWavesPerBlock * NV + NV + 1];
     __shared__ double smu[YB > 0 ? YB : 1];
+    __shared__ double sgi[YB > 0 ? YB * YB : 1];
     DevState* st = B.st;
     if (k >= st->stop) return;
     double ga[NV];
     dir_partials<NV>(B, nbu, ga);
+    // workgroup 0's inputs of the coefficient recurrences (G^{-1}, nu, a, xi)
+    // are requested up front as well, so its work after the streaming needs no
+    // memory round trip
+    const int par = k & 1;
+    constexpr int kGi = YB > 0 ? (YB * YB + kBlock - 1) / kBlock : 1;
+    double gi[kGi], nu_old = 0.0, acc_old = 0.0, xi_old = 0.0;
+    if (YB > 0 && blockIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < kGi; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            gi[u] = e < y * y ? B.Ginv[e] : 0.0;
+        }
+        if ((int)threadIdx.x < y) {
+            nu_old = st->lnu[par][threadIdx.x];
+            acc_old = st->lacc[par][threadIdx.x];
+            xi_old = st->xi[threadIdx.x];
+        }
+    }
     const int n = B.n;
     const int stride = gridDim.x * kBlock;
     // the operands of this thread's first kPrefetch elements (all of them at
@@ -424,6 +443,13 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
         pf[u] = i < n ? p[i] : 0.0;
         zf[u] = i < n ? z[i] : 0.0;
         xf[u] = i < n ? x[i] : 0.0;
+    }
+    if (YB > 0 && blockIdx.x == 0) {   // visible to wave 0 after dir_begin's barriers
+#pragma unroll
+        for (int u = 0; u < kGi; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            if (e < y * y) sgi[e] = gi[u];
+        }
     }
     DirStep d;
     if (!dir_begin<NV, YB, false>(B, y, k, ga, lds, smu, nullptr, d)) return;
@@ -443,15 +469,13 @@ __global__ __launch_bounds__(kBlock) void k_dir_imp(DevBufs B, int y, double* __
     if (blockIdx.x == 0 && threadIdx.x < kWave) {
         // mu = G^{-1} c is needed here only (the direction pt carries no basis)
         const int j = threadIdx.x;
-        const int par = k & 1;
         double prod = 0.0;
         if (j < y) {
             double mu = 0.0;
-            for (int i = 0; i < y; ++i) mu += B.Ginv[j * y + i] * lds[2 + i];
-            const double nu_old = st->lnu[par][j];
-            st->xi[j] += d.alpha * nu_old;
+            for (int i = 0; i < y; ++i) mu += sgi[j * y + i] * lds[2 + i];
+            st->xi[j] = xi_old + d.alpha * nu_old;
             const double nu_new = mu + d.beta * nu_old;
-            const double a_new = lds[2 + j] + d.beta * st->lacc[par][j];
+            const double a_new = lds[2 + j] + d.beta * acc_old;
             st->lnu[par ^ 1][j] = nu_new;
             st->lacc[par ^ 1][j] = a_new;
             prod = nu_new * a_new;
