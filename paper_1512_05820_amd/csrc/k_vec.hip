@@ -227,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
 // ||r'||^2, (r', z') in slot (k + 1) & 1, status and stop).  Returns false
 // when the sums are not finite (no step is applied then).
 // The group partials ga were loaded by the kernel before its operand
-// prefetch (dir_partials); the state scalars and G^{-1} (into sginv) are read
+// prefetch (dir_partials), and when MU the caller has filled sginv with
+// G^{-1} (from registers loaded at the same time); the state scalars are read
 // here at entry.
 struct DirStep {
     double alpha, beta;
@@ -250,8 +251,6 @@ __device__ __forceinline__ bool dir_begin(const DevBufs& B, int y, int k, double
     const int par = k & 1;
     const double alpha = st->lalpha[par], rho = st->lrho[par], tol2 = st->tol2;
     const int maxit = st->maxit;
-    if (MU)
-        for (int e = threadIdx.x; e < y * y; e += kBlock) sginv[e] = B.Ginv[e];
     block_sum<NV>(ga, lds);   // the group sums in group order; ends with a barrier, after which sginv is complete
     const double rz = lds[0], rr = lds[1];
     const bool ok = is_finite(rr) && is_finite(rz);
@@ -345,7 +344,21 @@ __global__ __launch_bounds__(kBlock) void k_dir(DevBufs B, int y, T* __restrict_
         if (k >= st->stop) return;
         double ga[NV];
         dir_partials<NV>(B, nbu, ga);
+        constexpr int kGi = YB > 0 ? (YB * YB + kBlock - 1) / kBlock : 1;
+        double gi[kGi];
+#pragma unroll
+        for (int u = 0; u < kGi; ++u) {
+            const int e = threadIdx.x + u * kBlock;
+            gi[u] = YB > 0 && e < y * y ? B.Ginv[e] : 0.0;
+        }
         load_block(i0, true);
+        if (YB > 0) {
+#pragma unroll
+            for (int u = 0; u < kGi; ++u) {
+                const int e = threadIdx.x + u * kBlock;
+                if (e < y * y) sginv[e] = gi[u];
+            }
+        }
         if (!dir_begin<NV, YB, (YB > 0)>(B, y, k, ga, lds, smu, sginv, d)) return;
     }
     T mu[YB > 0 ? YB : 1];
