@@ -589,6 +589,46 @@ def test_implicit_and_explicit_direction_forms_agree(P):
         x_prev = xe
 
 
+@pytest.mark.parametrize("projection", ["implicit", "explicit"])
+def test_small_loop_grids_match_the_default_grids(P, projection):
+    """Tiny launch grids (SpMV 4, update 3, direction 2 workgroups) make every
+    loop kernel walk many slices or load blocks per thread and run the
+    direction kernels' remainder loops; along a POD sequence (and for warm
+    plain PCG) the solutions agree with the default grids' to rounding, with
+    iteration counts within one, and meet the tolerance by the oracle's
+    residual."""
+    cfg = config2(N=24, steps=4)
+    rp, ci = _dev(cfg.rowptr, torch.int32), _dev(cfg.colind, torch.int32)
+    kw = dict(omega=cfg.omega, rank_max=cfg.rank, projection=projection)
+    ctx = {"default": _ctx(P, cfg.n, **kw),
+           "small": _ctx(P, cfg.n, spmv_grid=4, update_grid=3, dir_grid=2, **kw)}
+    x_prev = None
+    for j in range(1, cfg.steps + 1):
+        vals = cfg.matrix_values(j)
+        A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+        b = cfg.rhs(j, x_prev)
+        out, outp = {}, {}
+        for name, c in ctx.items():
+            if j == 1:
+                c.set_matrix(_dev(vals), rp, ci)
+            else:
+                c.set_matrix(_dev(vals))
+            x = _dev(np.zeros(cfg.n))
+            out[name] = (c.solve(_dev(b), x, cfg.tol), _host(x))
+            xp = _dev(np.zeros(cfg.n) if x_prev is None else x_prev)
+            outp[name] = (c.solve_plain(_dev(b), xp, cfg.tol), _host(xp))
+        for o in (out, outp):
+            (sd, xd), (ss, xs) = o["default"], o["small"]
+            assert sd.status == 0 and ss.status == 0
+            assert abs(sd.iters - ss.iters) <= 1 and sd.rank == ss.rank
+            assert _relerr(xs, xd) <= 1e-9
+            assert np.linalg.norm(b - oracle.matvec(A, xs)) / np.linalg.norm(b) <= cfg.tol * 1.01
+        for name, c in ctx.items():
+            c.push_snapshot(_dev(out[name][1]))
+            c.build_pod()
+        x_prev = out["default"][1]
+
+
 # ------------------------------------------------------------------- full size
 
 def test_full_size_config2_matvec_and_first_solves(P):
