@@ -81,7 +81,7 @@ def lib():
         L.orc_reduced_setup.argtypes = [C.c_int64, P, P, P, P, C.c_int32, P, P, P]
         L.orc_reduced_setup.restype = C.c_int
         L.orc_aug_pcg.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_double,
-                                  C.c_int32, C.POINTER(_Stats), P, P]
+                                  C.c_int32, C.POINTER(_Stats), P, P, P]
         L.orc_aug_pcg.restype = C.c_int
         L.orc_plain_pcg.argtypes = [C.c_int64, P, P, P, P, P, C.c_double, C.c_int32,
                                     C.POINTER(_Stats), P, P]
@@ -153,11 +153,12 @@ def reduced_setup(A: CSR, W: np.ndarray):
     return AW.T.copy(), G, R, kept
 
 
-def aug_pcg(A: CSR, b, xbar, W=None, tol=1e-8, maxit=10000, record=False):
+def aug_pcg(A: CSR, b, xbar, W=None, tol=1e-8, maxit=10000, record=False, coefs=False):
     """Stage 1 + augmented PCG.  W is (n, y) or None.
 
     Returns (x, Stats) or, with record=True, (x, Stats, dirs, iterates) where
-    dirs is (k, n) and iterates is (k + 1, n)."""
+    dirs is (k, n) and iterates is (k + 1, n).  With coefs=True a last element
+    is appended: the (k, 2) array of the iterations' (alpha, beta)."""
     n = A.n
     b = _f64(b)
     x = _f64(np.array(xbar, dtype=np.float64, copy=True))
@@ -169,16 +170,34 @@ def aug_pcg(A: CSR, b, xbar, W=None, tol=1e-8, maxit=10000, record=False):
     st = _Stats()
     dirs = np.zeros((maxit, n)) if record else None
     its = np.zeros((maxit + 1, n)) if record else None
+    ab = np.zeros((max(int(maxit), 1), 2)) if coefs else None
     lib().orc_aug_pcg(*A.args(), _p(b), _p(x), _p(Wc), y, float(tol), int(maxit),
-                      C.byref(st), _p(dirs), _p(its))
+                      C.byref(st), _p(dirs), _p(its), _p(ab))
     s = Stats(**{f: getattr(st, f) for f, _ in _Stats._fields_})
-    if record:
-        return x, s, dirs[: s.iters], its[: s.iters + 1]
-    return x, s
+    out = (x, s, dirs[: s.iters], its[: s.iters + 1]) if record else (x, s)
+    if coefs:
+        out = out + (ab[: s.iters].copy(),)
+    return out
 
 
-def plain_pcg(A: CSR, b, xbar, tol=1e-8, maxit=10000, record=False):
-    return aug_pcg(A, b, xbar, None, tol, maxit, record)
+def plain_pcg(A: CSR, b, xbar, tol=1e-8, maxit=10000, record=False, coefs=False):
+    return aug_pcg(A, b, xbar, None, tol, maxit, record, coefs)
+
+
+def lanczos_extremes(ab: np.ndarray):
+    """Extreme eigenvalues of the preconditioned operator M^{-1} A estimated
+    from the (alpha_k, beta_k) of a PCG run: they are the extreme eigenvalues
+    of the Lanczos tridiagonal matrix T with T_kk = 1/alpha_k +
+    beta_{k-1}/alpha_{k-1} and T_k,k+1 = sqrt(beta_k)/alpha_k (the standard
+    CG-Lanczos relation; the estimates lie inside the true spectrum)."""
+    a, b = ab[:, 0], ab[:, 1]
+    k = a.size
+    d = 1.0 / a
+    d[1:] += b[:-1] / a[:-1]
+    e = np.sqrt(b[:-1]) / a[:-1]
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    lam = np.linalg.eigvalsh(T) if k else np.zeros(1)
+    return float(lam[0]), float(lam[-1])
 
 
 def pod_evd(A: CSR, S: np.ndarray, weights, rank_max: int, rank_rtol: float = 1e-12,
@@ -204,4 +223,4 @@ def idw_weights(count: int) -> np.ndarray:
 from .sequence import run_sequence  # noqa: E402
 
 __all__ = ["build", "lib", "use_library", "CSR", "matvec", "cholesky", "sym_eig", "reduced_setup",
-           "aug_pcg", "plain_pcg", "pod_evd", "idw_weights", "run_sequence", "Stats"]
+           "aug_pcg", "plain_pcg", "lanczos_extremes", "pod_evd", "idw_weights", "run_sequence", "Stats"]

@@ -267,12 +267,15 @@ int orc_reduced_setup(int64_t n, const int32_t* rowptr, const int32_t* colind,
  *             G mu = (A W)^T z; p = z + beta p - W mu;  stop when ||r|| <= tol ||b||.
  *   x = xbar + d.
  *
- * Optional recording for tests: dirs (n x maxit, column k = p^k) and iterates
- * (n x (maxit + 1), column k = xbar + d^k).  Either may be NULL.
+ * Optional recording for tests: dirs (n x maxit, column k = p^k), iterates
+ * (n x (maxit + 1), column k = xbar + d^k) and coef (2 maxit: alpha_k, beta_k
+ * of every iteration, the coefficients of the Lanczos tridiagonal matrix that
+ * CG implicitly builds).  Any of them may be NULL.
  */
 int orc_aug_pcg(int64_t n, const int32_t* rowptr, const int32_t* colind, const double* val,
                 const double* b, double* x, const double* W, int32_t y,
-                double tol, int32_t maxit, orc_stats* st, double* dirs, double* iterates)
+                double tol, int32_t maxit, orc_stats* st, double* dirs, double* iterates,
+                double* coef)
 {
     memset(st, 0, sizeof(*st));
     st->cond_G = 1.0;
@@ -377,6 +380,7 @@ int orc_aug_pcg(int64_t n, const int32_t* rowptr, const int32_t* colind, const d
         double rho_new = dot(n, r, z);
         rr = dot(n, r, r);
         double beta = rho_new / rho;
+        if (coef) { coef[2 * k] = alpha; coef[2 * k + 1] = beta; }
         if (yk > 0) {
             for (int32_t j = 0; j < yk; ++j) cbuf[j] = dot(n, AW + j * n, z);
             chol_solve(y, yk, R, cbuf, mu);
@@ -422,7 +426,7 @@ int orc_plain_pcg(int64_t n, const int32_t* rowptr, const int32_t* colind, const
                   const double* b, double* x, double tol, int32_t maxit, orc_stats* st,
                   double* dirs, double* iterates)
 {
-    return orc_aug_pcg(n, rowptr, colind, val, b, x, NULL, 0, tol, maxit, st, dirs, iterates);
+    return orc_aug_pcg(n, rowptr, colind, val, b, x, NULL, 0, tol, maxit, st, dirs, iterates, NULL);
 }
 
 /*

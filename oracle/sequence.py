@@ -17,8 +17,16 @@ import numpy as np
 
 
 def run_sequence(cfg, method: str = "aug", steps: int | None = None, warm: bool = False,
-                 maxit: int = 100000, rank_rtol: float = 1e-12, keep_x: bool = False):
+                 maxit: int = 100000, rank_rtol: float = 1e-12, keep_x: bool = False,
+                 keep_W: bool = False, aug_xbar: str = "zero"):
+    """One pass over the sequence.  aug_xbar chooses the augmented solves'
+    initial guess: "zero" (xbar_j = 0, the snapshots are the solutions) or
+    "prev" (xbar_j = x_{j-1}, the snapshots are the increments).  keep_W adds
+    to each record the basis W_{j+1} built after system j ((n, y) array)."""
     from . import CSR, aug_pcg, idw_weights, plain_pcg, pod_evd
+
+    if aug_xbar not in ("zero", "prev"):
+        raise ValueError("aug_xbar must be 'zero' or 'prev'")
 
     steps = cfg.steps if steps is None else steps
     W = None
@@ -29,7 +37,7 @@ def run_sequence(cfg, method: str = "aug", steps: int | None = None, warm: bool 
         A = CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(j))
         b = cfg.rhs(j, x_prev)
         if method == "aug":
-            xbar = np.zeros(cfg.n)
+            xbar = x_prev.copy() if (aug_xbar == "prev" and x_prev is not None) else np.zeros(cfg.n)
         else:
             xbar = x_prev.copy() if (warm and x_prev is not None) else np.zeros(cfg.n)
         t0 = time.perf_counter()
@@ -55,6 +63,8 @@ def run_sequence(cfg, method: str = "aug", steps: int | None = None, warm: bool 
         if keep_x:
             rec["x"] = x
             rec["b"] = b
+        if keep_W and method == "aug":
+            rec["W"] = np.zeros((cfg.n, 0)) if W is None else W
         out.append(rec)
         x_prev = x
     return out

@@ -347,3 +347,16 @@ def test_exact_recovery_on_r2_sequence(orc):
         assert r["rank"] == 2 and r["rank_next"] == 2
         assert r["stage1_relres"] <= 3 * cfg.tol
         assert r["iters"] <= 5 and r["status"] == orc.OK
+
+
+def test_lanczos_extremes_from_pcg_coefficients(orc):
+    """The (alpha, beta) a PCG run records give the Lanczos tridiagonal matrix
+    of the Jacobi-preconditioned operator: run to near exhaustion on a small
+    system, its extreme eigenvalues are those of D^{-1/2} A D^{-1/2}."""
+    A, b, _ = _system(n=30, cond=1e3, seed=21)
+    _, st, ab = orc.plain_pcg(_csr(orc, A), b, np.zeros(30), tol=1e-15, maxit=60, coefs=True)
+    assert ab.shape == (st.iters, 2) and st.iters >= 25
+    d = 1.0 / np.sqrt(np.diag(A))
+    lam = np.linalg.eigvalsh(d[:, None] * A * d[None, :])
+    lo, hi = orc.lanczos_extremes(ab)
+    assert abs(lo - lam[0]) <= 1e-6 * lam[0] and abs(hi - lam[-1]) <= 1e-8 * lam[-1]
