@@ -84,6 +84,11 @@ typedef struct {
                                iterates are the same in exact arithmetic.  Batched solves
                                follow each member's setting; mixed precision
                                (precision = 1) and plain PCG always use the explicit form. */
+    int32_t lds_solve;    /* 1: systems of at most 1024 unknowns (slices at most 8 entries
+                             wide, basis of at most 5 columns, precision 0) are solved by one
+                             workgroup in a single launch, with every vector in registers and
+                             the search direction in LDS (explicit direction form); 0: always
+                             the multi-kernel loop.  Same arithmetic steps either way.        */
 } podcg_options;
 
 typedef struct {
@@ -104,14 +109,14 @@ typedef struct {
     double  update_ms;      /* ... of the timed update/reduction launches                        */
     double  dir_ms;         /* ... of the timed direction-update launches                        */
     int32_t refine_steps;   /* FP32 inner solves performed (precision = 1; 0 otherwise)          */
-    int32_t reserved;
+    int32_t path;           /* 1: solved by the one-workgroup kernel (lds_solve), 0: multi-kernel loop */
     double  first_inner_relres; /* ||b - A x|| / ||b|| in FP64 after the first FP32 inner solve */
 } podcg_stats;
 
 /* Fill *opt with defaults: omega 20, rank_max 10, maxit 10000, check_every 16,
  * inverse-distance weights, no timing, rank_rtol 1e-12, energy 1 (off),
  * precision 0 (FP64), max_refine 20, inner_rtol 1e-6, default loop grids,
- * projection 1 (implicit). */
+ * projection 1 (implicit), lds_solve 1. */
 void podcg_default_options(podcg_options* opt);
 
 /* Create a context for systems of size n.  opt may be NULL (defaults).

@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("weights", C.c_int32), ("timing", C.c_int32),
                 ("rank_rtol", C.c_double), ("energy", C.c_double), ("precision", C.c_int32),
                 ("max_refine", C.c_int32), ("inner_rtol", C.c_double), ("spmv_grid", C.c_int32),
-                ("update_grid", C.c_int32), ("dir_grid", C.c_int32), ("projection", C.c_int32)]
+                ("update_grid", C.c_int32), ("dir_grid", C.c_int32), ("projection", C.c_int32),
+                ("lds_solve", C.c_int32)]
 
 
 class BatchOptions(C.Structure):
@@ -71,7 +72,7 @@ class Stats(C.Structure):
                 ("true_relres", C.c_double), ("bnorm", C.c_double), ("cond_G", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("timed_iters", C.c_int32),
                 ("polls", C.c_int32), ("spmv_ms", C.c_double), ("update_ms", C.c_double),
-                ("dir_ms", C.c_double), ("refine_steps", C.c_int32), ("reserved", C.c_int32),
+                ("dir_ms", C.c_double), ("refine_steps", C.c_int32), ("path", C.c_int32),
                 ("first_inner_relres", C.c_double)]
 
     def as_dict(self) -> dict:

@@ -64,7 +64,8 @@ void check_opts(const podcg_options& o) {
         !(o.rank_rtol >= 0.0) || !(o.energy > 0.0) || (o.precision != 0 && o.precision != 1) ||
         o.max_refine < 1 || !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0) || o.spmv_grid < 0 ||
         o.spmv_grid > kLoopGridMax || o.update_grid < 0 || o.update_grid > kLoopGridMax || o.dir_grid < 0 ||
-        o.dir_grid > kLoopGridMax || (o.projection != 0 && o.projection != 1))
+        o.dir_grid > kLoopGridMax || (o.projection != 0 && o.projection != 1) ||
+        (o.lds_solve != 0 && o.lds_solve != 1))
         throw Fail{PODCG_ERR_INVALID_ARG};
 }
 
@@ -187,11 +188,79 @@ int solve_mixed(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_s
     return code;
 }
 
+// Whether the one-workgroup solve takes this system: FP64, at most
+// kLdsThreads unknowns, slices at most kLdsWidth wide and a basis (its
+// uncut dimension, an upper bound of the kept rank) within the register tiers.
+bool lds_path(podcg_ctx* ctx, bool plain) {
+    if (ctx->opt.precision != 0 || ctx->opt.lds_solve == 0) return false;
+    if (ctx->max_width < 0 || ctx->max_width > kLdsWidth) return false;
+    return lds_tier((int)ctx->n, plain ? 0 : ctx->y) >= 0;
+}
+
+// Stage 1 + augmented PCG of a small system in one launch (k_lds.hip), after
+// the setup kernels when the basis products are stale.  The kept rank goes
+// from the factor kernel to the solve through the device state, so the host
+// synchronises once, at the end, for the statistics.
+int solve_lds(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats& S, bool plain) {
+    hipStream_t s = ctx->stream;
+    DevBufs B = bufs(ctx);
+    const bool setup = !plain && !ctx->setup_valid && ctx->y > 0;
+    const int y0 = plain ? 0 : (ctx->setup_valid ? ctx->y_kept : ctx->y);
+    HIPCHECK(hipEventRecord(ctx->ev_a, s));
+    HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y0, s));
+    if (setup) {
+        HIPCHECK(launch_spmm_gram(B, ctx->y, ctx->d_W, ctx->d_AW, true, ctx->d_G, s));
+        HIPCHECK(launch_reduced_factor(ctx->d_G, ctx->y, ctx->d_R, ctx->d_Ginv, ctx->d_lamG, ctx->d_st, s));
+    }
+    HIPCHECK(hipEventRecord(ctx->ev_b, s));
+    HIPCHECK(launch_lds_solve(B, plain ? 0 : ctx->y, b, x, ctx->d_W, ctx->d_AW, s));
+    HIPCHECK(hipEventRecord(ctx->ev_c, s));
+    HIPCHECK(hipMemcpyAsync(ctx->h_poll, ctx->d_st, sizeof(PollBlock), hipMemcpyDeviceToHost, s));
+    if (setup)
+        HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_lamG, sizeof(double) * ctx->y, hipMemcpyDeviceToHost, s));
+    sync(ctx);
+    const PollBlock P = *ctx->h_poll;
+    if (setup) {
+        const int kept = P.y;
+        ctx->y_kept = kept;
+        ctx->rank_reduced = kept < ctx->y;
+        const double lmax = kept > 0 ? ctx->h_dbl[0] : 1.0, lmin = kept > 0 ? ctx->h_dbl[kept - 1] : 1.0;
+        ctx->cond_G = kept > 0 ? (lmin > 0.0 ? lmax / lmin : INFINITY) : 1.0;
+        ctx->setup_valid = true;
+    }
+    const int y = plain ? 0 : P.y;
+    const double bn = std::sqrt(P.bnorm2);
+    S.iters = P.iter;
+    S.rank = y;
+    S.bnorm = bn;
+    S.stage1_relres = bn > 0 ? std::sqrt(P.rr0) / bn : std::sqrt(P.rr0);
+    S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
+    S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
+    S.cond_G = y > 0 ? ctx->cond_G : 1.0;
+    S.matvecs = P.iter + 2 + (setup ? ctx->y : 0);
+    S.polls = 1;
+    S.path = 1;
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+    S.setup_ms = setup ? ms : 0.0;
+    HIPCHECK(hipEventElapsedTime(&ms, ctx->ev_b, ctx->ev_c));
+    S.solve_ms = ms;
+    int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
+    if (code == PODCG_OK && !plain && ctx->rank_reduced) code = PODCG_RANK_REDUCED;
+    S.status = code;
+    return code;
+}
+
 int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st, bool plain) {
     if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
     if (!b || !x || !(rtol >= 0.0)) fail(ctx, PODCG_ERR_INVALID_ARG, "bad solve arguments");
     podcg_stats S{};
     float ms = 0.f;
+    if (lds_path(ctx, plain)) {
+        const int code = solve_lds(ctx, b, x, rtol, S, plain);
+        if (st) *st = S;
+        return code;
+    }
 
     HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
     bool did_setup = false;
@@ -315,6 +384,7 @@ void podcg_default_options(podcg_options* o) {
     o->update_grid = 0;
     o->dir_grid = 0;
     o->projection = 1;
+    o->lds_solve = 1;
 }
 
 const char* podcg_strerror(int code) {
@@ -452,11 +522,23 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             }
             HIPCHECK(launch_slice_widths(n, ctx->nslices, rowptr, ctx->d_sptr, s));
             HIPCHECK(launch_scan_slices(ctx->nslices, ctx->d_sptr, s));
-            HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_sptr + ctx->nslices, sizeof(int64_t),
-                                    hipMemcpyDeviceToHost, s));
+            // the total slot count; for systems the one-workgroup solve may take,
+            // every slice offset (their widest slice decides)
+            const bool small = n <= kLdsThreads;
+            const int nsp = small ? ctx->nslices + 1 : 1;
+            HIPCHECK(hipMemcpyAsync(ctx->h_dbl, ctx->d_sptr + (small ? 0 : ctx->nslices),
+                                    nsp * sizeof(int64_t), hipMemcpyDeviceToHost, s));
             sync(ctx);
             int64_t nsell = 0;
-            std::memcpy(&nsell, ctx->h_dbl, sizeof(int64_t));
+            std::memcpy(&nsell, ctx->h_dbl + (nsp - 1), sizeof(int64_t));
+            ctx->max_width = -1;
+            if (small) {
+                int64_t sp[kLdsThreads / kSlice + 1];
+                std::memcpy(sp, ctx->h_dbl, nsp * sizeof(int64_t));
+                int wmax = 0;
+                for (int i = 0; i < ctx->nslices; ++i) wmax = std::max<int>(wmax, (int)((sp[i + 1] - sp[i]) / kSlice));
+                ctx->max_width = wmax;
+            }
             if (nsell > ctx->sell_cap) {
                 ctx->has_pattern = ctx->has_values = false;
                 dalloc(ctx, &ctx->d_cols, (size_t)nsell);

@@ -678,6 +678,19 @@ hipError_t launch_ts_jacobi_finish(double* A, int M, double* V, double* lam, hip
 hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,
                                 double* T, hipStream_t s);
 
+// One-workgroup solve of a small system (k_lds.hip): Stage 1 (Alg. 2) and the
+// loop of Alg. 1 in one launch of kLdsThreads threads, one row per thread, for
+// n <= kLdsThreads, slices at most kLdsWidth wide and a basis of at most
+// kLdsYMax columns.  It reads the kept rank (st->y), maxit and the relative
+// tolerance (st->tol2) from the state set up by launch_state_init (and the
+// factor kernel), and writes the poll block fields as a finished solve does.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsWidth = 8;
+constexpr int kLdsYMax = 5;
+int lds_tier(int n, int y);   // y if the one-workgroup solve covers (n, y), else -1
+hipError_t launch_lds_solve(const DevBufs& B, int yb, const double* b, double* x, const double* W,
+                            const double* AW, hipStream_t s);
+
 // Single-workgroup dense kernels (k_small.hip)
 // G (m x m row-major, symmetrised here) -> R, Ginv = G^{-1} on the accepted
 // leading block, kept rank written to st->y, eigenvalues of G to lam (cond).

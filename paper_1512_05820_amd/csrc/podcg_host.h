@@ -36,6 +36,7 @@ struct podcg_ctx {
     // matrix
     bool has_pattern = false, has_values = false;
     int64_t nnz = 0, nsell = 0, sell_cap = 0;
+    int max_width = -1;                     // widest slice when n <= kLdsThreads (else -1)
     int64_t* d_sptr = nullptr;
     int* d_cols = nullptr;
     int16_t* d_cols16 = nullptr;

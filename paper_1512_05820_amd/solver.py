@@ -38,7 +38,8 @@ class PodCG:
                  check_every: int = 16, weights: str = "idw", timing: int = 0,
                  rank_rtol: float = 1e-12, energy: float = 1.0, precision: str = "fp64",
                  max_refine: int = 20, inner_rtol: float = 1e-6, spmv_grid: int = 0,
-                 update_grid: int = 0, dir_grid: int = 0, projection: str = "implicit", stream=None):
+                 update_grid: int = 0, dir_grid: int = 0, projection: str = "implicit",
+                 lds_solve: bool = True, stream=None):
         self._L = L.load()
         opt = L.Options()
         self._L.podcg_default_options(C.byref(opt))
@@ -50,6 +51,7 @@ class PodCG:
         opt.max_refine, opt.inner_rtol = max_refine, inner_rtol
         opt.spmv_grid, opt.update_grid, opt.dir_grid = spmv_grid, update_grid, dir_grid
         opt.projection = {"explicit": 0, "implicit": 1}[projection]
+        opt.lds_solve = 1 if lds_solve else 0
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
