@@ -202,6 +202,24 @@ int podcg_get_format(podcg_ctx* ctx, int64_t* counts);
  * NO_MATRIX, INVALID_ARG, NOT_SPD, NONFINITE, HIP. */
 int podcg_solve(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): podcg_solve
+ * on a small system, with no allocation of any kind in the call.  Same
+ * arguments, arithmetic and return codes as podcg_solve taking its
+ * one-workgroup path (the basis setup is redone on every call), but the
+ * device state, A W, W^T A W with its factor and inverse, and the setup
+ * kernel's partial sums and counters live in one static device array of the
+ * library (about 46 KB per GPU, held until the process ends) instead of the
+ * context's buffers; the call reads the context's matrix, Jacobi inverse and
+ * basis and writes only x, *st and that array.
+ * Limit: precision 0, n <= 1024, slices at most 8 entries wide, a basis of at
+ * most 5 columns; anything larger returns PODCG_ERR_SIZE (see
+ * podcg_last_error) and runs nothing.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (several host threads, or several streams
+ * without ordering between them) race; calls ordered on one stream are safe.
+ * Synchronises the context stream before returning, like podcg_solve. */
+int podcg_solve_noalloc(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);
+
 /* Plain Jacobi PCG on the current matrix, ignoring the basis (the baseline
  * of the comparison; Eq. (KrylovSolve)).  Same arguments and codes. */
 int podcg_solve_plain(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st);

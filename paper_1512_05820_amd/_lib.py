@@ -17,7 +17,7 @@ EXPORTED = [
     "podcg_default_options", "podcg_create", "podcg_destroy", "podcg_set_matrix",
     "podcg_push_snapshot", "podcg_reset_snapshots", "podcg_build_pod", "podcg_set_basis",
     "podcg_get_basis", "podcg_get_reduced", "podcg_get_pod_spectrum", "podcg_get_format", "podcg_solve",
-    "podcg_solve_plain", "podcg_matvec", "podcg_pattern_outer", "podcg_stream_triad",
+    "podcg_solve_plain", "podcg_solve_noalloc", "podcg_matvec", "podcg_pattern_outer", "podcg_stream_triad",
     "podcg_strerror", "podcg_last_error",
     "podcg_batch_default_options", "podcg_batch_create", "podcg_batch_destroy",
     "podcg_batch_set_options", "podcg_batch_get_options", "podcg_batch_solve", "podcg_batch_tune",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "podcg_get_format": ([P, P], C.c_int),
         "podcg_solve": ([P, P, P, D, C.POINTER(Stats)], C.c_int),
         "podcg_solve_plain": ([P, P, P, D, C.POINTER(Stats)], C.c_int),
+        "podcg_solve_noalloc": ([P, P, P, D, C.POINTER(Stats)], C.c_int),
         "podcg_matvec": ([P, P, P], C.c_int),
         "podcg_pattern_outer": ([P, P, P, D, P], C.c_int),
         "podcg_stream_triad": ([P, P, P, P, I64, D, I32, C.POINTER(D)], C.c_int),

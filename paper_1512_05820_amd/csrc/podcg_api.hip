@@ -429,6 +429,8 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
     ctx->nslices = (int)((n + kSlice - 1) / kSlice);
     ctx->ld = (size_t)ctx->nslices * kSlice;
     int rc = guarded(ctx, [&]() {
+        const int src = noalloc_init(ctx->device, &ctx->last_error);
+        if (src != PODCG_OK) throw Fail{src};
         const size_t ld = ctx->ld;
         dalloc(ctx, &ctx->d_sptr, (size_t)ctx->nslices + 1);
         dalloc(ctx, &ctx->d_sflag, (size_t)ctx->nslices);

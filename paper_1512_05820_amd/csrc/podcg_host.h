@@ -178,5 +178,8 @@ std::vector<int> run_loop(podcg_ctx* ctx, int slot, int* polls, F&& iter3) {
 }
 
 void ts_release(podcg_ctx* ctx);
+// Sets up this device's address of the scratch array of podcg_solve_noalloc
+// (podcg_noalloc.hip); the device must be current.  Once per device.
+int noalloc_init(int device, std::string* err);
 
 }  // namespace podcg_host

@@ -102,6 +102,13 @@ class PodCG:
         return st
 
     # ---------------------------------------------------------------- the rest
+    def solve_noalloc(self, b: torch.Tensor, x: torch.Tensor, rtol: float) -> L.Stats:
+        """podcg_solve_noalloc: the small-system solve with no allocation in the call."""
+        st = L.Stats()
+        self._check(self._L.podcg_solve_noalloc(self._h, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                                float(rtol), C.byref(st)))
+        return st
+
     def solve_plain(self, b: torch.Tensor, x: torch.Tensor, rtol: float) -> L.Stats:
         st = L.Stats()
         self._check(self._L.podcg_solve_plain(self._h, _ptr(b, torch.float64),
