@@ -9,7 +9,10 @@ timed region starts with every input resident in HBM; the right-hand side
 b_j = x_{j-1} / dt + 1 is formed on the device inside the loop.
 
 The same sequence is then solved with plain Jacobi PCG from the library
-(warm start x_{j-1} and cold start 0) for the wall-time comparison.
+(warm start x_{j-1} and cold start 0, median of five sequences each) for the
+wall-time comparison, and the config-1 sequence (32 x 32, 10 systems) is
+timed through the one-workgroup solve and the multi-kernel loop.  The
+oracle's baseline covers the whole config-2 sequence.
 
 Prints one JSON line.  The value is milliseconds per sequence (lower is
 better).  The roofline object covers the loop kernel with the largest share
@@ -98,16 +101,136 @@ def run_sequence(torch, ctx, cfg, vals_dev, method: str, warm: bool = False):
 
 
 def cpu_baseline(cfg, systems: int) -> dict:
-    """The oracle as it stands on the first `systems` systems of the sequence."""
+    """The oracle as it stands on the first `systems` systems of the sequence
+    (all of them by default), on this process's OpenMP threads."""
     import oracle
     res = oracle.run_sequence(cfg, "aug", steps=systems)
     t = sum(r["solve_s"] + r["pod_s"] for r in res)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1e3 * t * cfg.steps / systems, "unit": "ms/sequence", "cores": threads,
+    sample = (f"the whole sequence ({systems} systems)" if systems == cfg.steps else
+              f"first {systems} of {cfg.steps} systems, scaled by {cfg.steps}/{systems}")
+    return {"value": round(1e3 * t * cfg.steps / systems, 1), "unit": "ms/sequence", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {systems} of {cfg.steps} systems (oracle solve + POD time, "
-                      f"generation excluded), scaled by {cfg.steps}/{systems}",
+            "sample": f"{sample}: oracle solve + POD time, generation excluded",
             "iters": [r["iters"] for r in res]}
+
+
+def cpu_oracle_child(workload: str, threads: int, systems: int) -> dict:
+    """cpu_baseline in a child process with OMP_NUM_THREADS = threads (the
+    OpenMP runtime reads it once, at start).  The child runs only the oracle."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--workload", workload,
+           "--systems", str(systems)]
+    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_only(args):
+    """Child mode of cpu_oracle_child: print the oracle's cpu_baseline record."""
+    from problems import config1, config2
+    cfg = config1() if args.workload == "config1" else config2(N=args.N, steps=args.systems)
+    print(json.dumps(cpu_baseline(cfg, cfg.steps)), flush=True)
+
+
+def median(v):
+    v = sorted(v)
+    k = len(v)
+    return v[k // 2] if k % 2 else 0.5 * (v[k // 2 - 1] + v[k // 2])
+
+
+def config1_sequences(torch, P, cfg, reps: int) -> dict:
+    """Config 1: the 10-system 2-D sequence, whole-sequence wall time (median
+    of reps runs after one warm-up) for augmented PCG and plain PCG (warm and
+    cold start), through the one-workgroup solve and through the multi-kernel
+    loop.  Every input is resident on the GPU before the timed runs."""
+    vals = [torch.from_numpy(cfg.matrix_values(j)).cuda() for j in range(1, cfg.steps + 1)]
+    rhs = [torch.from_numpy(cfg.rhs(j)).cuda() for j in range(1, cfg.steps + 1)]
+    rowptr, colind = torch.from_numpy(cfg.rowptr).cuda(), torch.from_numpy(cfg.colind).cuda()
+    res = {}
+    for path, lds in (("one_workgroup", True), ("multi_kernel", False)):
+        ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, lds_solve=lds)
+        ctx.set_matrix(vals[0], rowptr, colind)
+        zeros = torch.zeros(cfg.n, dtype=torch.float64, device="cuda")
+        xs = [torch.zeros(cfg.n, dtype=torch.float64, device="cuda") for _ in range(cfg.steps)]
+        for method in ("aug", "plain_warm", "plain_cold"):
+            def once():
+                ctx.reset_snapshots()
+                ctx.set_basis(None)
+                sts = []
+                for j in range(cfg.steps):
+                    ctx.set_matrix(vals[j])
+                    x = xs[j]
+                    if method == "plain_warm" and j > 0:
+                        x.copy_(xs[j - 1])
+                    else:
+                        x.copy_(zeros)
+                    if method == "aug":
+                        st = ctx.solve(rhs[j], x, cfg.tol)
+                        ctx.push_snapshot(x)
+                        ctx.build_pod()
+                    else:
+                        st = ctx.solve_plain(rhs[j], x, cfg.tol)
+                    if st.status not in (0, 2):
+                        raise RuntimeError(f"config1 {path}/{method} system {j + 1}: status {st.status}")
+                    sts.append(st.as_dict())
+                return sts
+            once()
+            ms = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sts = once()
+                torch.cuda.synchronize()
+                ms.append(1e3 * (time.perf_counter() - t1))
+            iters = sum(s["iters"] for s in sts)
+            solve_ms = sum(s["solve_ms"] for s in sts)
+            res[f"{path}/{method}"] = {
+                "ms": round(median(ms), 3), "ms_runs": [round(v, 3) for v in ms], "iters": iters,
+                "path": sorted({s["path"] for s in sts}),
+                "solve_gpu_ms": round(solve_ms, 3),
+                "us_per_iteration_gpu": round(1e3 * solve_ms / max(iters, 1), 3),
+                "max_true_relres": max(s["true_relres"] for s in sts),
+                "ranks": [s["rank"] for s in sts]}
+            log(f"config1 {path}/{method}: {res[f'{path}/{method}']['ms']:.3f} ms, {iters} iterations")
+        ctx.close()
+    return res
+
+
+def bench_config1(args):
+    """Config 1 on its own line: 2-D 5-point diffusion, 32 x 32, 10 systems,
+    snapshot memory 5, POD rank 4, tolerance 1e-8.  The value is the median
+    wall time of one augmented sequence through the one-workgroup solve; plain
+    PCG and the multi-kernel loop are timed beside it, and the oracle runs the
+    same sequence on one host thread and on all of them."""
+    import torch
+    import paper_1512_05820_amd as P
+    from problems import config1
+
+    torch.cuda.set_device(0)
+    cfg = config1()
+    reps = max(5, args.steps)
+    runs = config1_sequences(torch, P, cfg, reps)
+    v = runs["one_workgroup/aug"]["ms"]
+    cpu = None
+    if not args.no_cpu:
+        nproc = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = cpu_oracle_child("config1", nproc, cfg.steps)
+        cpu["one_thread"] = cpu_oracle_child("config1", 1, cfg.steps)
+    out = {"metric": METRIC, "value": v, "unit": "ms/sequence", "n_gpus": 1, "steps": reps,
+           "warmup": 1, "ms_per_step": v, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": cfg.name, "N": cfg.N, "n": cfg.n, "nnz": cfg.nnz, "systems": cfg.steps,
+                      "omega": cfg.omega, "rank_max": cfg.rank, "rel_tol": cfg.tol,
+                      "preconditioner": "jacobi", "value_is": "median of the augmented sequence, one-workgroup solve"},
+           "speedup_vs_plain_warm": round(runs["one_workgroup/plain_warm"]["ms"] / v, 3),
+           "speedup_vs_multi_kernel_aug": round(runs["multi_kernel/aug"]["ms"] / v, 3),
+           "runs": runs,
+           "roofline": None,
+           "roofline_note": "latency-bound: the one-workgroup solve keeps the system in registers and LDS "
+                            "and moves no HBM traffic per iteration; us_per_iteration_gpu is its measure",
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
 
 
 def bench_config3(args):
@@ -456,17 +579,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid side (128 = the stated workload)")
     ap.add_argument("--systems", type=int, default=50)
-    ap.add_argument("--cpu-systems", type=int, default=25)
+    ap.add_argument("--cpu-systems", type=int, default=0, help="oracle systems for cpu_baseline (0 = all)")
+    ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-reps", type=int, default=5, help="plain-PCG sequences timed (median reported)")
+    ap.add_argument("--no-config1", action="store_true", help="skip the config-1 sequences of the default run")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the context run of the other direction form")
     ap.add_argument("--projection", default="implicit", choices=["implicit", "explicit"],
                     help="form of the direction recurrence in the augmented loop")
     ap.add_argument("--adjoint-basis", default="forward", choices=["forward", "adjoint", "none"],
                     help="config5: basis of the adjoint solves")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5", "three_stage"],
-                    help="config2 (default, the headline), config3 (mixed precision), "
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config3", "config4", "config5", "three_stage"],
+                    help="config2 (default, the headline), config1 (the 32 x 32 sequence, "
+                         "one-workgroup solve), config3 (mixed precision), "
                          "config4 (batched sequences), config5 (adjoint gradients) or three_stage "
                          "(the full method of Alg. 3 on the config-2 sequence)")
     args = ap.parse_args()
@@ -474,6 +602,12 @@ def main():
         print("bench.py measures one GPU only: the library runs one sequence (or one batch) per GPU "
               "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_only:
+        cpu_only(args)
+        return
+    if args.workload == "config1":
+        bench_config1(args)
+        return
     if args.workload == "config3":
         bench_config3(args)
         return
@@ -553,14 +687,17 @@ def main():
     plain = {}
     if not args.no_plain:
         for warm in (True, False):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sts = run_sequence(torch, ctx, cfg, vals_dev, "plain", warm=warm)
-            torch.cuda.synchronize()
+            ms = []
+            for _ in range(args.plain_reps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sts = run_sequence(torch, ctx, cfg, vals_dev, "plain", warm=warm)
+                torch.cuda.synchronize()
+                ms.append(1e3 * (time.perf_counter() - t1))
             key = "warm" if warm else "cold"
-            plain[key] = {"ms": 1e3 * (time.perf_counter() - t1),
+            plain[key] = {"ms": round(median(ms), 3), "ms_runs": [round(v, 1) for v in ms],
                           "iters": sum(s["iters"] for s in sts)}
-            log(f"plain {key}: {plain[key]['ms']:.1f} ms, iters {plain[key]['iters']}")
+            log(f"plain {key}: median {plain[key]['ms']:.1f} ms of {ms}, iters {plain[key]['iters']}")
 
     # the other form of the direction recurrence, once, for context
     other_rec = None
@@ -581,8 +718,18 @@ def main():
     cpu = None
     if not args.no_cpu:
         t1 = time.perf_counter()
-        cpu = cpu_baseline(cfg, min(args.cpu_systems, cfg.steps))
+        cpu = cpu_baseline(cfg, min(args.cpu_systems, cfg.steps) if args.cpu_systems > 0 else cfg.steps)
         log(f"cpu baseline {cpu['value']:.0f} ms/sequence ({time.perf_counter() - t1:.1f}s)")
+
+    # config 1 (32 x 32, 10 systems) beside the headline: latency-bound, so
+    # whole-sequence wall time, one-workgroup solve against the multi-kernel loop
+    c1 = None
+    if not args.no_config1:
+        from problems import config1
+        r1 = config1_sequences(torch, P, config1(), 5)
+        c1 = {"unit": "ms/sequence (median of 5)",
+              **{k: {"ms": v["ms"], "iters": v["iters"], "us_per_iteration_gpu": v["us_per_iteration_gpu"]}
+                 for k, v in r1.items()}}
 
     aug_iters = sum(s["iters"] for s in aug_stats)
     rec = {
@@ -625,6 +772,7 @@ def main():
                      "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
                      "timed_launches": launches},
         "cpu_baseline": cpu,
+        "config1_sequence": c1,
     }
     print(json.dumps(rec), flush=True)
 
