@@ -16,7 +16,7 @@
 // Members that have finished (or failed) drop out of the lists at the start of
 // every block of iterations (k_batch_compact); within a block they exit on
 // their state flag.
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg {
 

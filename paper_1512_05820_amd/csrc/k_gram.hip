@@ -1,0 +1,213 @@
+// The fused SpMM + Gram kernel of libpodcg: A X for k columns (optionally
+// stored) and the k x k product X^T (A X) on the FP64 matrix cores, the
+// products of Alg. 2 (W^T A W) and of Alg. pod_evd (S^T A S).
+#include "podcg_launch.h"
+
+namespace podcg {
+
+// Fused AX = A X (optionally stored) and G = X^T (A X) for k <= KS columns,
+// the products of Alg. 2 (W^T A W) and of Alg. pod_evd (S^T A S).  Each wave
+// computes A X for one slice of 64 rows (lane = row), stages that block in
+// LDS, and accumulates the 64-row contraction X^T (A X) on the FP64 matrix
+// cores with v_mfma_f64_16x16x4f64: per instruction lane l supplies
+// X[row 4 s + l / 16][col l % 16] (loaded directly) and
+// (A X)[row 4 s + l / 16][col l % 16] (from LDS), and register r of lane l
+// accumulates G[4 r + l / 16][l % 16].  Columns are padded to KB = 16 or 32
+// (padding columns of A X are zero).  Per-workgroup partial Grams are summed
+// in a fixed two-level order.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kMfmaGroup = 4;   // MFMA steps (4 rows each) per X operand load group
+
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const double* __restrict__ X,
+                                                      double* __restrict__ AX, int store,
+                                                      double* __restrict__ G, double* part,
+                                                      unsigned* counter) {
+    constexpr int KB = KS <= 16 ? 16 : 32;
+    constexpr int KT = KB / 16;
+    constexpr int LDSW = KS + 1;                               // padded row stride of a tile
+    constexpr int TILE = kSlice * LDSW;                        // doubles per wave tile
+    constexpr int RED = KT * KT * 4 * kWave;                   // doubles per wave accumulator
+    constexpr int SH = kWavesPerBlock * (TILE > RED ? TILE : RED);
+    __shared__ double shm[SH];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    d4_t d[KT][KT];
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b) d[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+    double* tw = shm + wid * (SH / kWavesPerBlock);            // this wave's private tile
+    const int r4 = lane >> 4, cc = lane & 15;
+    // The trip count is uniform over the workgroup; each wave touches only its
+    // own tile, so the only ordering needed is within the wave (s_waitcnt).
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = __builtin_amdgcn_readfirstlane(L * kWavesPerBlock + wid);
+        const bool sv = s < B.nslices;
+        double acc[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) acc[kk] = 0.0;
+        const int row = s * kSlice + lane;
+        // X operand of MFMA step st for column tile a: X[row 4 st + r4][col
+        // 16 a + cc] of this slice (rows past n read row n - 1 and count as
+        // zero; columns past k repeat column k - 1 and feed unused G rows).
+        // Group 0 is loaded here, under the SpMM below.
+        double xg[kMfmaGroup][KT];
+        auto load_xgroup = [&](int g) {
+#pragma unroll
+            for (int u = 0; u < kMfmaGroup; ++u)
+#pragma unroll
+                for (int a = 0; a < KT; ++a) {
+                    const int grow = s * kSlice + 4 * (g * kMfmaGroup + u) + r4;
+                    const int colx = 16 * a + cc;
+                    const int colc = colx < k ? colx : k - 1;
+                    const double v = X[(size_t)colc * B.ld + (grow < B.n ? grow : B.n - 1)];
+                    xg[u][a] = grow < B.n ? v : 0.0;
+                }
+        };
+        load_xgroup(0);
+        if (sv) {
+            const int64_t base = B.sptr[s];
+            const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+            const int* c = B.cols + base + lane;
+            const double* vv = B.vals + base + lane;
+            // entry j + 1's value and column are loaded while entry j's k
+            // gathers are in flight; a slice with an offset table computes the
+            // column from its (scalar) offsets, with no index load at all
+            const bool tabled = B.sflag[s] == 2;
+            const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
+            auto column = [&](int j) {
+                if (tabled) {
+                    const int col = row + tab[j];
+                    return col < 0 ? 0 : (col < B.n ? col : B.n - 1);
+                }
+                return c[j * kSlice];
+            };
+            double a_next = vv[0];
+            int col_next = column(0);
+            for (int j = 0; j < w; ++j) {
+                const double a = a_next;
+                const int col = col_next;
+                if (j + 1 < w) {
+                    a_next = vv[(j + 1) * kSlice];
+                    col_next = column(j + 1);
+                }
+                double xv[KS];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) xv[kk] = X[(size_t)(kk < k ? kk : k - 1) * B.ld + col];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) acc[kk] += a * xv[kk];
+            }
+            if (store && row < B.n) {
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk)
+                    if (kk < k) AX[(size_t)kk * B.ld + row] = acc[kk];
+            }
+        }
+        const bool live = sv && row < B.n;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) tw[lane * LDSW + kk] = (kk < k && live) ? acc[kk] : 0.0;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // the X operands of group g + 1 are in flight while group g's MFMAs run
+        double xc[kMfmaGroup][KT];
+#pragma unroll
+        for (int u = 0; u < kMfmaGroup; ++u)
+#pragma unroll
+            for (int a = 0; a < KT; ++a) xc[u][a] = xg[u][a];
+#pragma unroll
+        for (int g = 0; g < kSlice / 4 / kMfmaGroup; ++g) {
+            if (g + 1 < kSlice / 4 / kMfmaGroup) load_xgroup(g + 1);
+#pragma unroll
+            for (int u = 0; u < kMfmaGroup; ++u) {
+                const int rr = 4 * (g * kMfmaGroup + u) + r4;
+                double bb[KT];
+#pragma unroll
+                for (int b = 0; b < KT; ++b) {
+                    const int colx = 16 * b + cc;
+                    bb[b] = colx < KS ? tw[rr * LDSW + (colx < KS ? colx : 0)] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < KT; ++a)
+#pragma unroll
+                    for (int b = 0; b < KT; ++b)
+                        d[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xc[u][a], bb[b], d[a][b], 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kMfmaGroup; ++u)
+#pragma unroll
+                for (int a = 0; a < KT; ++a) xc[u][a] = xg[u][a];
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+    // sum the four waves' accumulators (fixed order)
+    __syncthreads();
+    double* red = shm;
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wid * RED + ((a * KT + b) * 4 + r) * kWave + lane] = d[a][b][r];
+    __syncthreads();
+    // output entry o = i * k + j of this workgroup's partial, owned by one thread
+    const int nout = k * k;
+    const int ng = (nb + kGroup - 1) / kGroup;
+    const int g = blockIdx.x / kGroup;
+    const int gsize = min(kGroup, nb - g * kGroup);
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        const int i = o / k, j = o % k;
+        const int a = i / 16, b = j / 16, ii = i % 16, jj = j % 16;
+        const int r = ii / 4, ln = (ii % 4) * 16 + jj;
+        const int idx = ((a * KT + b) * 4 + r) * kWave + ln;
+        double v = red[idx];
+#pragma unroll
+        for (int wv = 1; wv < kWavesPerBlock; ++wv) v += red[wv * RED + idx];
+        store_shared(part + (size_t)o * nb + blockIdx.x, v);
+    }
+    if (!arrive_last(counter + 1 + g, gsize)) return;
+    double* part2 = part + (size_t)nout * nb;
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        double t[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) t[q] = q < gsize ? load_shared(part + (size_t)o * nb + g * kGroup + q) : 0.0;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) sum += t[q];
+        store_shared(part2 + (size_t)o * ng + g, sum);
+    }
+    if (!arrive_last(counter, ng)) return;
+    for (int o = threadIdx.x; o < nout; o += kBlock) {
+        double sum = 0.0;
+        for (int q0 = 0; q0 < ng; q0 += kGroup) {
+            double t[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) t[q] = q0 + q < ng ? load_shared(part2 + (size_t)o * ng + q0 + q) : 0.0;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) sum += t[q];
+        }
+        G[o] = sum;
+    }
+}
+
+hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX, bool store, double* G,
+                            hipStream_t s) {
+    if (k < 1 || k > kYMax) return hipErrorInvalidValue;
+    const int groups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    // grid cap measured on MI355X at 128^3: 1024 workgroups for up to 16
+    // columns (6-7 columns: 150-166 us against 223-235 us at 512), 512 above
+    // (20 columns: 350 us against 386 us at 1024); never more than the partial
+    // sums buffer holds (k^2 slots per workgroup plus the group level)
+    int cap = k <= 16 ? 2 * kGramBlocksMax : kGramBlocksMax;
+    const int capk = kPartials / (k * k + (k * k + kGroup - 1) / kGroup + 1);
+    if (cap > capk) cap = capk;
+    dim3 g(groups < cap ? groups : cap), t(kBlock);
+    switch (basis_tier(k)) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_spmm_gram<T>), g, t, 0, s, B, k, X, AX, store ? 1 : 0, G, B.part, B.counter); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace podcg

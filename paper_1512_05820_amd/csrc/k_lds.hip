@@ -19,7 +19,7 @@
 // setup kernels of the multi-kernel path, launched ahead of this kernel on the
 // same stream; the kept rank is read from the device state, so the host does
 // not wait for the factorisation.
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg {
 

@@ -2,7 +2,7 @@
 // the factorisation of the reduced matrix W^T A W (Alg. 2) and the POD
 // coefficients from the eigen-decomposition of the snapshot Gram matrix
 // (Alg. pod_evd).  Matrices are at most 32 x 32 and live in LDS.
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg {
 

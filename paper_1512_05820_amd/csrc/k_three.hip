@@ -4,7 +4,7 @@
 // Stage-3 basis, the bookkeeping of the accumulated vectors and weights
 // (Section 3.3.2) and the eigen-decomposition of the weighted snapshot Gram of
 // a truncation (Alg. pod_evd).
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg {
 

@@ -4,7 +4,7 @@
 // dimension ld, so lane i of a wave touches row i of every column and each
 // load instruction reads 512 contiguous bytes; the implicit update also reads
 // a copy of A W in 64-row tiles.
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg {
 

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "podcg.h"
-#include "podcg_device.h"
+#include "podcg_launch.h"
 #include "podcg_host.h"
 
 using namespace podcg;
@@ -670,14 +670,17 @@ int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank) {
         if (!ctx->setup_valid) setup_basis(ctx);
         const int y = ctx->y_kept;
         if (rank) *rank = y;
+        // copies ordered on the context stream, then that stream alone is awaited
         std::vector<double> g((size_t)kYMax * kYMax);
-        if (G && ctx->y > 0) {
-            HIPCHECK(hipMemcpy(g.data(), ctx->d_G, sizeof(double) * ctx->y * ctx->y, hipMemcpyDeviceToHost));
+        if (G && ctx->y > 0)
+            HIPCHECK(hipMemcpyAsync(g.data(), ctx->d_G, sizeof(double) * ctx->y * ctx->y, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        if (Ginv && y > 0)
+            HIPCHECK(hipMemcpyAsync(Ginv, ctx->d_Ginv, sizeof(double) * y * y, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        if (G && ctx->y > 0)
             for (int i = 0; i < y; ++i)
                 for (int j = 0; j < y; ++j) G[i * y + j] = g[(size_t)i * ctx->y + j];
-        }
-        if (Ginv && y > 0)
-            HIPCHECK(hipMemcpy(Ginv, ctx->d_Ginv, sizeof(double) * y * y, hipMemcpyDeviceToHost));
         return PODCG_OK;
     });
 }
@@ -685,8 +688,11 @@ int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank) {
 int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count) {
     return guarded(ctx, [&]() {
         if (count) *count = ctx->pod_count;
-        if (lam && ctx->pod_count > 0)
-            HIPCHECK(hipMemcpy(lam, ctx->d_lamS, sizeof(double) * ctx->pod_count, hipMemcpyDeviceToHost));
+        if (lam && ctx->pod_count > 0) {
+            HIPCHECK(hipMemcpyAsync(lam, ctx->d_lamS, sizeof(double) * ctx->pod_count, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+            sync(ctx);
+        }
         return PODCG_OK;
     });
 }

@@ -19,7 +19,7 @@
 #include <vector>
 
 #include "podcg.h"
-#include "podcg_device.h"
+#include "podcg_launch.h"
 #include "podcg_host.h"
 
 using namespace podcg;
@@ -93,8 +93,12 @@ void build_lists(podcg_batch* ctx) {
     }
     if (s.size() > ctx->cap_spmv || v.size() > ctx->cap_vec)
         fail(ctx, PODCG_ERR_INVALID_ARG, "work list exceeds its capacity");
-    HIPCHECK(hipMemcpy(ctx->d_spmv_full, s.data(), s.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(ctx->d_vec_full, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    // ordered on the batch stream; the host lists must outlive the copies
+    HIPCHECK(hipMemcpyAsync(ctx->d_spmv_full, s.data(), s.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                            ctx->stream));
+    HIPCHECK(hipMemcpyAsync(ctx->d_vec_full, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                            ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
 }
 
 // Member table for one solve (y = kept rank, or 0 for plain PCG).

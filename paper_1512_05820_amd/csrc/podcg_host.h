@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "podcg.h"
-#include "podcg_device.h"
+#include "podcg_launch.h"
 
 namespace podcg_host {
 

@@ -21,7 +21,7 @@
 #include <string>
 
 #include "podcg.h"
-#include "podcg_device.h"
+#include "podcg_launch.h"
 #include "podcg_host.h"
 
 using namespace podcg;

@@ -23,7 +23,7 @@
 #include <vector>
 
 #include "podcg.h"
-#include "podcg_device.h"
+#include "podcg_launch.h"
 #include "podcg_host.h"
 
 using namespace podcg;
