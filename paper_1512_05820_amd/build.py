@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpodcg.so")
 SOURCES = ["podcg_api.hip", "podcg_batch.hip", "podcg_three.hip", "k_sell.hip", "k_vec.hip", "k_small.hip",
-           "k_batch.hip", "k_three.hip", "k_lds.hip", "k_gram.hip", "podcg_noalloc.hip"]
+           "k_batch.hip", "k_three.hip", "k_lds.hip", "k_gram.hip", "k_gemm.hip", "podcg_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -37,8 +37,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     bad = [src for p, src in procs if p.wait() != 0]
     if bad:
         raise RuntimeError(f"hipcc failed for {bad}")
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -190,6 +190,72 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
     }
 }
 
+// AX = A X for k <= KS columns, with no Gram (the truncation of the
+// three-stage method forms its M x M Gram separately).  One wave per slice of
+// 64 rows, lane = row; entry j + 1's value and column are requested while
+// entry j's k gathers are in flight.
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_spmm(DevBufs B, int k, const double* __restrict__ X,
+                                                 double* __restrict__ AX) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int nb = gridDim.x;
+    const int ngroups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    for (int L = xcd_block(blockIdx.x, nb); L < ngroups; L += nb) {
+        const int s = __builtin_amdgcn_readfirstlane(L * kWavesPerBlock + wid);
+        if (s >= B.nslices) continue;
+        const int row = s * kSlice + lane;
+        double acc[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) acc[kk] = 0.0;
+        const int64_t base = B.sptr[s];
+        const int w = (int)((B.sptr[s + 1] - base) / kSlice);
+        const int* c = B.cols + base + lane;
+        const double* vv = B.vals + base + lane;
+        const bool tabled = B.sflag[s] == 2;
+        const int* __restrict__ tab = B.soff + (size_t)s * kTabMax;
+        auto column = [&](int j) {
+            if (tabled) {
+                const int col = row + tab[j];
+                return col < 0 ? 0 : (col < B.n ? col : B.n - 1);
+            }
+            return c[j * kSlice];
+        };
+        double a_next = w > 0 ? vv[0] : 0.0;
+        int col_next = w > 0 ? column(0) : 0;
+        for (int j = 0; j < w; ++j) {
+            const double a = a_next;
+            const int col = col_next;
+            if (j + 1 < w) {
+                a_next = vv[(j + 1) * kSlice];
+                col_next = column(j + 1);
+            }
+            double xv[KS];
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) xv[kk] = X[(size_t)(kk < k ? kk : k - 1) * B.ld + col];
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) acc[kk] += a * xv[kk];
+        }
+        if (row < B.n) {
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk)
+                if (kk < k) AX[(size_t)kk * B.ld + row] = acc[kk];
+        }
+    }
+}
+
+hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s) {
+    if (k < 1 || k > kYMax) return hipErrorInvalidValue;
+    const int groups = (B.nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+    const dim3 g(groups < 2048 ? groups : 2048), t(kBlock);
+    switch (basis_tier(k)) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_spmm<T>), g, t, 0, s, B, k, X, AX); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX, bool store, double* G,
                             hipStream_t s) {
     if (k < 1 || k > kYMax) return hipErrorInvalidValue;

@@ -45,6 +45,26 @@ hipError_t launch_resid(const DevBufs& B, int yb, int y, const double* b, const 
 hipError_t launch_spmm_gram(const DevBufs& B, int k, const double* X, double* AX, bool store, double* G,
                             hipStream_t s);
 
+// AX = A X for k <= kYMax columns, stored, no Gram (k_gram.hip).
+hipError_t launch_spmm(const DevBufs& B, int k, const double* X, double* AX, hipStream_t s);
+
+// Tall-skinny products on the FP64 matrix cores (k_gemm.hip).  X, Y, Out are
+// column-major with leading dimension ld.
+//   Partial Grams of row chunks: P_c = X(chunk c)^T Y(chunk c), M x N row-major
+//   at P + c pstride with row stride ldp; `chunks` is a request (the launch
+//   rounds the chunk height to whole panels: gemm_tn_chunks gives the count);
+//   sym (M = N, a symmetric product) computes only the tiles on and above the
+//   diagonal.  launch_gram_sum adds the chunks in order (mirroring with sym)
+//   into G (row stride ldg).
+int gemm_tn_chunks(int n, int chunks);
+hipError_t launch_gemm_tn_parts(int n, size_t ld, const double* X, int M, const double* Y, int N, int chunks,
+                                bool sym, double* P, size_t pstride, int ldp, hipStream_t s);
+hipError_t launch_gram_sum(const double* P, int nparts, size_t pstride, int M, int N, int ldp, bool sym,
+                           double* G, int ldg, hipStream_t s);
+//   Out (n x Ny) = X (n x M) T (M x Ny, column-major, leading dimension ldt).
+hipError_t launch_gemm_nn(int n, size_t ld, const double* X, int M, const double* T, int ldt, int Ny,
+                          double* Out, hipStream_t s);
+
 // Streaming vector kernels (k_vec.hip)
 int basis_tier(int y);   // smallest compiled register tier >= y
 // Loop kernels of iteration k (0, 1, ...): each is a no-op once k >= stop.

@@ -9,10 +9,9 @@
 // Z = [Y, V Gamma^{-1/2}] becomes the next Y, or is truncated by POD (metric
 // A_j, previous or RBF weights, Section 3.3.2) when it exceeds ybar.
 //
-// All vector work runs in the library's kernels; the two plain GEMMs of a
-// truncation (Z^T (A Z) and Z T) go to rocBLAS.
+// All of it runs in the library's kernels, the two dense products of a
+// truncation (Z^T (A Z) and Z T) on the FP64 matrix cores (k_gemm.hip).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -46,7 +45,6 @@ struct TsHost {
     TsDev* d_ts = nullptr;
     double* h_dbl = nullptr;     // pinned, kTsCap + 8
     int* h_int = nullptr;        // pinned, kYMax + 8
-    rocblas_handle blas = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -60,7 +58,6 @@ void ts_release(podcg_ctx* ctx) {
         if (p) (void)hipFree(p);
     if (T->h_dbl) (void)hipHostFree(T->h_dbl);
     if (T->h_int) (void)hipHostFree(T->h_int);
-    if (T->blas) (void)rocblas_destroy_handle(T->blas);
     for (hipEvent_t e : T->ev)
         if (e) (void)hipEventDestroy(e);
     delete T;
@@ -74,15 +71,6 @@ namespace {
 constexpr double kStage2Floor = 1e-6;   // stage-2 tolerance floor, relative to ||Y^T r||
 constexpr int kJacobiMaxSweeps = 60;
 constexpr int kGramChunks = 64;         // row chunks of the truncation Gram
-
-#define BLASCHECK(expr)                                                                             \
-    do {                                                                                            \
-        rocblas_status b_ = (expr);                                                                 \
-        if (b_ != rocblas_status_success) {                                                         \
-            ctx->last_error = std::string(#expr) + ": rocBLAS status " + std::to_string((int)b_);   \
-            throw Fail{PODCG_ERR_HIP};                                                              \
-        }                                                                                           \
-    } while (0)
 
 template <class M>
 M* ts_field(TsDev* base, size_t offset) {
@@ -122,24 +110,14 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
     const int n = (int)ctx->n;
     for (int c0 = 0; c0 < M; c0 += kYMax) {
         const int kc = std::min(kYMax, M - c0);
-        HIPCHECK(launch_spmm_gram(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, true, T->d_G, s));
+        HIPCHECK(launch_spmm(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, s));
     }
-    // Z^T (A Z) split over row chunks (one GEMM per chunk, batched), then the
-    // partial Grams summed in chunk order: a single GEMM of this shape (M x M
-    // output, n-long inner dimension) leaves most of the GPU idle
-    const double one = 1.0, zero = 0.0;
-    const int chunk = (n + kGramChunks - 1) / kGramChunks;
-    const int full = n / chunk, rem = n - full * chunk;
-    const rocblas_stride pstride = (rocblas_stride)kTsCap * kTsCap;
-    if (full > 0)
-        BLASCHECK(rocblas_dgemm_strided_batched(T->blas, rocblas_operation_transpose, rocblas_operation_none, M, M,
-                                                chunk, &one, T->d_Y, (int)ld, chunk, T->d_AZ, (int)ld, chunk, &zero,
-                                                T->d_Gparts, M, pstride, full));
-    if (rem > 0)
-        BLASCHECK(rocblas_dgemm(T->blas, rocblas_operation_transpose, rocblas_operation_none, M, M, rem, &one,
-                                T->d_Y + (size_t)full * chunk, (int)ld, T->d_AZ + (size_t)full * chunk, (int)ld,
-                                &zero, T->d_Gparts + (size_t)full * pstride, M));
-    HIPCHECK(launch_ts_sum_parts(T->d_Gparts, full + (rem > 0 ? 1 : 0), (size_t)pstride, M * M, T->d_Gbig, s));
+    // Z^T (A Z): partial Grams of row chunks on the matrix cores (tiles on and
+    // above the diagonal only: the product is symmetric), summed in chunk
+    // order; one M x M output alone would leave most of the GPU idle
+    const size_t pstride = (size_t)kTsCap * kTsCap;
+    HIPCHECK(launch_gemm_tn_parts(n, ld, T->d_Y, M, T->d_AZ, M, kGramChunks, true, T->d_Gparts, pstride, M, s));
+    HIPCHECK(launch_gram_sum(T->d_Gparts, gemm_tn_chunks(n, kGramChunks), pstride, M, M, M, true, T->d_Gbig, M, s));
     const double* eta = T->opt.weights == 0 ? TSF(T, eta_acc) : TSF(T, eta_prev);
     HIPCHECK(launch_ts_weight_sym(T->d_Gbig, M, eta, s));
     // Jacobi sweeps until the off-diagonal norm is <= 1e-15 of the Frobenius norm
@@ -170,8 +148,7 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
     w = energy_count(lam, M, w, T->opt.energy_w);
     if (y > 0) {
         HIPCHECK(launch_ts_pod_coeffs(cur, M, T->d_lam, eta, y, T->d_T, s));
-        BLASCHECK(rocblas_dgemm(T->blas, rocblas_operation_none, rocblas_operation_none, n, y, M, &one, T->d_Y,
-                                (int)ld, T->d_T, M, &zero, T->d_AZ, (int)ld));
+        HIPCHECK(launch_gemm_nn(n, ld, T->d_Y, M, T->d_T, M, y, T->d_AZ, s));
         std::swap(T->d_Y, T->d_AZ);
     }
     T->m = y;
@@ -398,8 +375,6 @@ int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
         HIPCHECK(hipHostMalloc((void**)&T->h_dbl, sizeof(double) * (kTsCap + 8), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&T->h_int, sizeof(int) * (kYMax + 8), hipHostMallocDefault));
         for (auto& e : T->ev) HIPCHECK(hipEventCreate(&e));
-        BLASCHECK(rocblas_create_handle(&T->blas));
-        BLASCHECK(rocblas_set_stream(T->blas, s));
         sync(ctx);
         return PODCG_OK;
     });
