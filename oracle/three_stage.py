@@ -2,7 +2,7 @@
 
 Plain NumPy, FP64, small problems.  One call of `ts_solve` is one pass of the
 loop of Alg. 3 for system j, with the non-iterative Stage 3 (phi = 0,
-Section 4.3):
+Section 4.3) or, with phi = 1, the iterative Stage 3 of Section 4.3.1:
 
   Stage 1 (Alg. 2)     direct Galerkin solve over the stage-1 basis W_j;
   Stage 2 (Sect. 4.2)  augmented CG (Alg. 1, M = I) on the reduced system
@@ -14,6 +14,13 @@ Section 4.3):
                        x0 = Y xhat with the basis [W, X] and the reused
                        factor blockdiag(R, sqrt(Gammahat)), recording its
                        directions V and Gamma = diag(p^T A p);
+  Stage 3, phi = 1      augmented PCG on A from the same x0 with all of Y as
+                       the augmenting basis; each projection
+                       Y^T A Y mu = Y^T A z is solved iteratively (augmented
+                       CG on the reduced matrix, M = I) against the reduced
+                       stage-1 columns, the stage-2 directions and the
+                       directions of the earlier projection solves, with the
+                       block-diagonal factor they share;
   then the accumulated vectors Z_j = [Y_j, V_j Gamma_j^{-1/2}] either become
   Y_{j+1} (W_{j+1} gains the new vectors the rho rule selects) or, when they
   exceed ybar, are truncated by POD (Eq. (podAlgebraicDefinition), metric
@@ -33,7 +40,23 @@ initial reduced residual ||Y^T r|| (the loose end of the paper's range);
 Stage 3 uses the reused block-diagonal factor or, as an option, the computed
 and factored Gram of [W, X]; Stage 2 runs at most
 min(stage2_maxit, basis_max - w) iterations and at most `cap - m` Stage-3
-directions are recorded.
+directions are recorded.  With phi = 1, Stage 2 runs to its tolerance with
+only a rounding-level floor (1e-13 of its initial residual) and up to
+min(stage2_maxit, m - w) steps: Alg. 1 over all of Y never corrects the part
+of the error that lies in range(Y), so that part has to be solved to below
+the overall tolerance first.  The iterative Stage 3 starts each projection solve
+from the Galerkin solution over the augmenting directions it already has (the
+direct block-diagonal solve): Alg. 1 started from zero, as printed, never
+resolves the part of mu in their span, and the outer directions would then not
+be A-orthogonal to them, which the paper states they are.  The projection
+solves stop at inner_rtol times the norm of their right-hand side (the paper
+gives no value; default 1e-6, never below the rounding-level floor) and
+after inner_maxit steps.  Directions formed after a solve's residual (Stage 2
+or a projection solve) has fallen below 1e-6 of its initial value still
+advance that solve but do not join the augmentation: they are orthogonal to
+the earlier ones only to about the rounding error divided by that reduction,
+and the reused block-diagonal factor needs them orthogonal (a late stage-2
+direction made the projection solves diverge).
 """
 
 from __future__ import annotations
@@ -46,6 +69,11 @@ from . import CSR, matvec
 
 BASIS_MAX = 32          # columns of the Stage-1 / Stage-3 augmenting bases
 STAGE2_FLOOR = 1e-6     # stage-2 tolerance floor, relative to the initial reduced residual
+ROUNDING_FLOOR = 1e-13  # phi = 1: floor of Stage 2 and of the projection solves, relative to
+                        # their initial residual
+KEEP_FLOOR = 1e-6       # phi = 1: a direction joins the reduced augmentation only if it was
+                        # formed from a residual at least this fraction of its solve's
+                        # initial residual
 
 
 @dataclass
@@ -64,6 +92,9 @@ class TSOptions:
                                      # (Section 4.3) or "exact" (computed and factored)
     rank_rtol: float = 1e-12
     cap: int = 512             # columns of the accumulated-vector store
+    phi: int = 0               # Stage 3 over [W, X] (0, Section 4.3) or over all of Y (1, Section 4.3.1)
+    inner_rtol: float = 1e-6   # phi = 1: tolerance of each projection solve, relative to its right-hand side
+    inner_maxit: int = 64      # phi = 1: step cap of each projection solve
 
 
 @dataclass
@@ -168,12 +199,17 @@ class TSStats:
     w_next: int = 0         # dim W_{j+1}
     cond_YAY: float = 1.0   # condition number of Y_j^T A_j Y_j (E6 diagnostic)
     status: int = 0
+    k_in: int = 0           # phi = 1: steps of all projection solves
 
 
 def stage2(A: CSR, Y: np.ndarray, sel: list, AW: np.ndarray, R: np.ndarray, what: np.ndarray,
-           rbar: np.ndarray, tol: float, maxit: int):
+           rbar: np.ndarray, tol: float, maxit: int, red: dict | None = None,
+           floor_rel: float = None):
     """Augmented CG on Y^T A Y xhat = Y^T rbar, M = I, from xhat0 = What what,
-    augmented by What (Section 4.2).  Returns (xhat, X, AX, gammahat, k, ||rhat||)."""
+    augmented by What (Section 4.2).  Returns (xhat, X, AX, gammahat, k, ||rhat||);
+    `red`, if given, receives the reduced directions ("P", m x k), Ghat times
+    them ("G") and their (Ghat p, p) ("gam"), of the steps whose direction was
+    formed from a residual of at least KEEP_FLOOR of the initial one."""
     n, m = Y.shape
     w = len(sel)
     xh = np.zeros(m)
@@ -194,11 +230,14 @@ def stage2(A: CSR, Y: np.ndarray, sel: list, AW: np.ndarray, R: np.ndarray, what
     rz = rh @ zh
     X, AX, gam = [], [], []
     k = 0
+    rn0 = float(np.linalg.norm(rh))
     # never below 1e-6 of the initial reduced residual: directions formed from
     # a much smaller residual are A-orthogonal to the earlier ones only to a
     # relative accuracy that breaks the block-diagonal factor reused in Stage 3
-    tol = max(tol, STAGE2_FLOOR * float(np.linalg.norm(rh)))
+    floor_rel = STAGE2_FLOOR if floor_rel is None else floor_rel
+    tol = max(tol, floor_rel * float(np.linalg.norm(rh)))
     while np.linalg.norm(rh) > tol and k < maxit:
+        rn_formed = float(np.linalg.norm(rh))      # the residual ph was formed from
         u = Y @ ph
         q = matvec(A, u)
         gh = Y.T @ q                                   # Ghat p
@@ -215,6 +254,10 @@ def stage2(A: CSR, Y: np.ndarray, sel: list, AW: np.ndarray, R: np.ndarray, what
         X.append(u)
         AX.append(q)
         gam.append(g)
+        if red is not None and rn_formed >= KEEP_FLOOR * rn0:
+            red.setdefault("P", []).append(ph.copy())
+            red.setdefault("G", []).append(gh)
+            red.setdefault("gam", []).append(g)
         k += 1
         mu = proj(zh)
         ph = zh + beta * ph
@@ -222,6 +265,10 @@ def stage2(A: CSR, Y: np.ndarray, sel: list, AW: np.ndarray, R: np.ndarray, what
             ph[sel] -= mu
     X = np.stack(X, axis=1) if X else np.zeros((n, 0))
     AX = np.stack(AX, axis=1) if AX else np.zeros((n, 0))
+    if red is not None:
+        for key in ("P", "G"):
+            red[key] = np.stack(red[key], axis=1) if red.get(key) else np.zeros((m, 0))
+        red["gam"] = np.array(red.get("gam", []))
     return xh, X, AX, np.array(gam), k, float(np.linalg.norm(rh))
 
 
@@ -262,6 +309,159 @@ def stage3(A: CSR, b: np.ndarray, x0: np.ndarray, B: np.ndarray, AB: np.ndarray,
     return x, V, np.array(gam), np.array(alp), k, float(np.linalg.norm(r))
 
 
+class ReducedAugmentation:
+    """The augmenting directions of the projection solves of the iterative
+    Stage 3, in Y coordinates (Section 4.3.1): the stage-1 columns What
+    (W = Y What, a column selection; W^T A W = R^T R), the stage-2 directions
+    and the directions of the earlier projection solves.  They are mutually
+    Ghat-orthogonal (Ghat = Y^T A Y), so (B^T Ghat B)^{-1} is
+    blockdiag(G_W^{-1}, diag(1 / gamma)); Ghat What = Y^T (A W) and Ghat p of
+    every other direction are kept, so no product with Ghat is needed to use
+    them."""
+
+    def __init__(self, Y: np.ndarray, sel: list, AW: np.ndarray, R: np.ndarray, P2: np.ndarray,
+                 G2: np.ndarray, gam2: np.ndarray):
+        self.m = Y.shape[1]
+        self.sel = list(sel)
+        self.R = R
+        self.GW = Y.T @ AW if sel else np.zeros((self.m, 0))
+        self.P = [P2[:, k] for k in range(P2.shape[1])]
+        self.G = [G2[:, k] for k in range(G2.shape[1])]
+        self.gam = [float(g) for g in gam2]
+
+    def solve_coeffs(self, cw: np.ndarray, cd: np.ndarray):
+        """blockdiag(G_W^{-1}, diag(1 / gamma)) applied to (cw, cd)."""
+        nw = _chol_solve(self.R, cw) if self.sel else np.zeros(0)
+        return nw, cd / np.array(self.gam) if self.gam else np.zeros(0)
+
+    def combine(self, nw: np.ndarray, nd: np.ndarray) -> np.ndarray:
+        """B nu in Y coordinates."""
+        v = np.zeros(self.m)
+        if self.sel:
+            v[self.sel] += nw
+        for p, c in zip(self.P, nd):
+            v += c * p
+        return v
+
+    def combine_G(self, nw: np.ndarray, nd: np.ndarray) -> np.ndarray:
+        """Ghat B nu."""
+        v = self.GW @ nw if self.sel else np.zeros(self.m)
+        for g, c in zip(self.G, nd):
+            v = v + c * g
+        return v
+
+    def galerkin(self, c: np.ndarray):
+        """Coefficients of the Galerkin solution of Ghat mu = c over range(B):
+        (B^T Ghat B)^{-1} B^T c."""
+        cw = c[self.sel] if self.sel else np.zeros(0)
+        cd = np.array([p @ c for p in self.P])
+        return self.solve_coeffs(cw, cd)
+
+    def project(self, z: np.ndarray):
+        """Coefficients of steps aug2 / aug3 of Alg. 1 on Ghat: (B^T Ghat B)^{-1} B^T Ghat z."""
+        cw = self.GW.T @ z if self.sel else np.zeros(0)
+        cd = np.array([g @ z for g in self.G])
+        return self.solve_coeffs(cw, cd)
+
+
+def projection_solve(c: np.ndarray, aug: ReducedAugmentation, ghat_mv, tol: float, maxit: int):
+    """Ghat mu = c by augmented CG (Alg. 1, M = I) against the directions of
+    `aug`, from the Galerkin solution over their span.  Its own directions
+    join `aug` afterwards, those formed from a residual of at least KEEP_FLOOR
+    of the initial one (later ones are orthogonal to the earlier directions
+    only to about the rounding error divided by that reduction, and the
+    block-diagonal factor needs them orthogonal).  Returns (mu, steps)."""
+    nw, nd = aug.galerkin(c)
+    mu = aug.combine(nw, nd)
+    r = c - aug.combine_G(nw, nd)
+    z = r.copy()
+    nw, nd = aug.project(z)
+    p = z - aug.combine(nw, nd)
+    rz = r @ z
+    newP, newG, newgam = [], [], []
+    k = 0
+    rn0 = float(np.linalg.norm(r))
+    while np.linalg.norm(r) > tol and k < maxit:
+        keep = float(np.linalg.norm(r)) >= KEEP_FLOOR * rn0     # p was formed from this residual
+        g = ghat_mv(p)
+        gam = p @ g
+        if not gam > 0:
+            break
+        alpha = rz / gam
+        mu += alpha * p
+        r -= alpha * g
+        z = r.copy()
+        rz_new = r @ z
+        beta = rz_new / rz
+        rz = rz_new
+        if keep:
+            newP.append(p.copy())
+            newG.append(g)
+            newgam.append(gam)
+        k += 1
+        nw, nd = aug.project(z)
+        p = z + beta * p - aug.combine(nw, nd)
+    room = max(0, aug.m - len(aug.P))     # at most m mutually Ghat-orthogonal directions
+    aug.P += newP[:room]
+    aug.G += newG[:room]
+    aug.gam += newgam[:room]
+    return mu, k
+
+
+def stage3_iterative(A: CSR, b: np.ndarray, x0: np.ndarray, Y: np.ndarray, aug: ReducedAugmentation,
+                     dinv: np.ndarray, tol: float, maxit: int, rec_max: int, inner_rtol: float,
+                     inner_maxit: int):
+    """Augmented PCG (Alg. 1) from x0 with all of Y as the augmenting basis,
+    each solve Y^T A Y mu = Y^T A z of steps aug2 / aug3 done by
+    projection_solve (Section 4.3.1).  Records up to rec_max directions.
+    Returns (x, V, gamma, alpha, k, ||r||, projection-solve steps, matvecs)."""
+    x = x0.copy()
+    r = b - matvec(A, x)
+    z = dinv * r
+    rz = r @ z
+    V, gam, alp = [], [], []
+    k = kin = 0
+    mv = 1
+
+    def ghat_mv(v):
+        return Y.T @ matvec(A, Y @ v)
+
+    def mu_of(zv):
+        nonlocal kin, mv
+        c = Y.T @ matvec(A, zv)
+        rel = max(inner_rtol, ROUNDING_FLOOR)
+        mu, ks = projection_solve(c, aug, ghat_mv, rel * float(np.linalg.norm(c)), inner_maxit)
+        kin += ks
+        mv += 1 + ks
+        return mu
+
+    if np.linalg.norm(r) > tol and maxit > 0:
+        p = z - Y @ mu_of(z)
+    while np.linalg.norm(r) > tol and k < maxit:
+        q = matvec(A, p)
+        mv += 1
+        g = p @ q
+        if not g > 0:
+            raise RuntimeError("stage 3: (A p, p) <= 0")
+        alpha = rz / g
+        x += alpha * p
+        r -= alpha * q
+        z = dinv * r
+        rz_new = r @ z
+        beta = rz_new / rz
+        rz = rz_new
+        if k < rec_max:
+            V.append(p.copy())
+            gam.append(g)
+            alp.append(alpha)
+        k += 1
+        if np.linalg.norm(r) <= tol or k >= maxit:
+            break
+        p = z + beta * p - Y @ mu_of(z)
+    V = np.stack(V, axis=1) if V else np.zeros((len(b), 0))
+    return x, V, np.array(gam), np.array(alp), k, float(np.linalg.norm(r)), kin, mv
+
+
 def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, maxit: int,
              opt: TSOptions, keep: dict | None = None):
     """One system of Alg. 3 (phi = 0).  Updates st to Y_{j+1}, W_{j+1}.
@@ -300,10 +500,17 @@ def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, 
     x1 = W @ what if w else np.zeros(n)
     S.stage1_relres = float(np.linalg.norm(rbar - (AW @ what if w else 0.0)) / bn) if bn else 0.0
     # Stage 2 over Y
-    k2_max = min(opt.stage2_maxit, BASIS_MAX - w)
+    # phi = 0: [W, X] is Stage 3's augmenting basis, at most BASIS_MAX columns;
+    # phi = 1: the stage-2 directions only join the reduced augmentation, and
+    # Stage 2 runs to its tolerance with no floor (Alg. 1 over all of Y never
+    # corrects the part of the error in range(Y) that Stage 2 leaves)
+    it = opt.phi == 1
+    k2_max = min(opt.stage2_maxit, m - w) if it else min(opt.stage2_maxit, BASIS_MAX - w)
+    red = {}
     if m:
         xh, X, AX, gh, k2, rhn = stage2(A, Y, sel, AW, R, what, rbar,
-                                         opt.stage2_factor * tol, k2_max)
+                                         opt.stage2_factor * tol, k2_max, red,
+                                         floor_rel=ROUNDING_FLOOR if it else STAGE2_FLOOR)
     else:
         xh, X, AX, gh, k2, rhn = np.zeros(0), np.zeros((n, 0)), np.zeros((n, 0)), np.zeros(0), 0, 0.0
     S.k2 = k2
@@ -324,12 +531,20 @@ def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, 
         for k in range(k2):
             Ginv[w + k, w + k] = 1.0 / gh[k]
     rec_max = max(0, opt.cap - m)
-    dx, V, gam, alp, k3, rn = stage3(A, rbar, x0, B, AB, Ginv, dinv, tol, maxit, rec_max)
+    aug = None
+    if opt.phi == 1 and m:
+        aug = ReducedAugmentation(Y, sel, AW, R, red["P"], red["G"], red["gam"])
+        dx, V, gam, alp, k3, rn, kin, mv3 = stage3_iterative(A, rbar, x0, Y, aug, dinv, tol, maxit, rec_max,
+                                                             opt.inner_rtol, opt.inner_maxit)
+        S.k_in = kin
+        S.matvecs = 1 + w + k2 + mv3 + 1
+    else:
+        dx, V, gam, alp, k3, rn = stage3(A, rbar, x0, B, AB, Ginv, dinv, tol, maxit, rec_max)
+        S.matvecs = 1 + w + k2 + 1 + k3 + 1
     x = xbar + dx
     S.k3 = k3
     S.relres = rn / bn if bn else rn
     S.true_relres = float(np.linalg.norm(b - matvec(A, x)) / bn) if bn else 0.0
-    S.matvecs = 1 + w + k2 + 1 + k3 + 1
     S.status = 0 if rn <= tol else 1
     # accumulation: Z_j = [Y_j, V Gamma^{-1/2}], eta^prev = [xhat; alpha sqrt(gamma)]
     kr = V.shape[1]
@@ -341,7 +556,7 @@ def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, 
     if keep is not None:
         keep.update(dict(W=W, X=X, AX=AX, gammahat=gh, V=V, gamma=gam, alpha=alp, xhat=xh,
                          what=what, Z=Z, eta_prev=eta_prev, eta_rbf=eta_acc.copy(), x0=x0,
-                         Ginv=Ginv, sel=list(sel)))
+                         Ginv=Ginv, sel=list(sel), red=red, aug=aug))
     if Z.shape[1] > opt.ybar:
         eta = eta_acc if opt.weights == "rbf" else eta_prev
         Ynew, lam = pod_evd_dense(A, Z, eta, opt.y_trunc, opt.rank_rtol, opt.energy_y)

@@ -13,6 +13,12 @@ mathematics fix, and mutants of it that the pins must catch.
   needs no Stage-3 iteration (the solution lies in the accumulated span).
 * eta^RBF equals the explicit sum of Section 3.3.2 with weights 2^{1-i}.
 * Theorem wellConditioned: ||Y_j^T A_j Y_j - I|| <= sum ||Y_k||^2 ||A_k - A_{k-1}||.
+* Iterative Stage 3 (phi = 1, Section 4.3.1): with tight projection solves it
+  is Alg. 1 with all of Y as the augmenting basis (the C oracle's dense
+  Cholesky projection); its directions are A-orthogonal to all of Y; the
+  augmenting directions of the projection solves stay mutually orthogonal in
+  the reduced metric, so all projection solves together take at most
+  m - w - k2 steps (exact arithmetic; two spare for rounding).
 """
 
 import importlib.util
@@ -190,7 +196,74 @@ def pin_stage3_exact_factor(ts):
     assert c.max() <= 1e-8
 
 
-PINS = [pin_stage2_galerkin, pin_stage3_orthogonality_and_reconstruction, pin_stage3_exact_factor,
+def _dinv(A):
+    d = np.zeros(A.n)
+    for i in range(A.n):
+        for e in range(A.rowptr[i], A.rowptr[i + 1]):
+            if A.colind[e] == i:
+                d[i] += A.vals[e]
+    return 1.0 / d
+
+
+def pin_iterative_stage3_is_full_projection(ts):
+    cfg = Config4Member(12, 1050, 1051, 2, 5, 4, 1e-10)
+    A = _A(cfg, 1)
+    D = _dense(A)
+    r = np.random.Generator(np.random.PCG64(73))
+    m = 12
+    Y = r.standard_normal((cfg.n, m))
+    sel = [0, 1, 2]
+    W = Y[:, sel]
+    AW = D @ W
+    R, kept = ts._chol_truncated(W.T @ AW)
+    rbar = cfg.rhs(1)
+    what = ts._chol_solve(R, W.T @ rbar)
+    red = {}
+    _, X, AX, gh, k2, _ = ts.stage2(A, Y, sel, AW, R, what, rbar, 0.0, 3, red)
+    assert k2 == 3 and red["P"].shape == (m, 3)
+    aug = ts.ReducedAugmentation(Y, sel, AW, R, red["P"], red["G"], gh)
+    # start from the Galerkin solution over range(Y), as the reference does
+    x0 = Y @ np.linalg.solve(Y.T @ D @ Y, Y.T @ rbar)
+    K = 12
+    x, V, gam, alp, k3, rn, kin, mv = ts.stage3_iterative(A, rbar, x0, Y, aug, _dinv(A), 0.0, K, K, 1e-14, 200)
+    xr, so = oracle.aug_pcg(A, rbar, x0, Y, tol=0.0, maxit=K)
+    assert k3 == K == so.iters
+    assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+    assert 0 < kin <= m - len(sel) - k2 + 2
+    assert mv == 1 + K + K + kin      # r0, one A p a step, one A z a projection (K of them), the solve steps
+
+
+def pin_iterative_stage3_orthogonality(ts):
+    cfg = Config4Member(14, 1052, 1053, 3, 5, 4, 1e-10)
+    opt = ts.TSOptions(ybar=1000, rho=0.0, stage2_factor=1e-2, stage2_maxit=512, phi=1, inner_rtol=1e-11,
+                       inner_maxit=32)
+    st = ts.TSState(cfg.n)
+    for j in (1, 2, 3):
+        A = _A(cfg, j)
+        keep = {}
+        Y = st.Y.copy()
+        x, S = ts.ts_solve(A, cfg.rhs(j), np.zeros(cfg.n), st, cfg.tol, 200, opt, keep)
+        assert S.status == 0 and S.true_relres <= cfg.tol * 1.01
+    D = _dense(A)
+    m, w, k2 = Y.shape[1], S.w, S.k2
+    assert m > 0 and S.k_in > 0
+    V = keep["V"]
+    c = np.abs(Y.T @ D @ V) / (np.linalg.norm(Y, axis=0)[:, None] * np.linalg.norm(D @ V, axis=0)[None, :])
+    assert c.max() <= 1e-7, c.max()
+    aug = keep["aug"]
+    P = np.stack(aug.P, axis=1)
+    Gh = Y.T @ D @ Y
+    Q = P.T @ Gh @ P
+    off = Q - np.diag(np.diag(Q))
+    assert np.abs(off).max() <= 1e-7 * np.abs(np.diag(Q)).max()
+    assert np.allclose(np.diag(Q), aug.gam, rtol=1e-9)
+    if w:
+        Wh = np.eye(m)[:, keep["sel"]]
+        assert np.abs(P.T @ Gh @ Wh).max() <= 1e-7 * np.abs(Gh).max()
+    assert S.k_in <= m - w - k2 + 2
+
+
+PINS = [pin_iterative_stage3_is_full_projection, pin_iterative_stage3_orthogonality, pin_stage2_galerkin, pin_stage3_orthogonality_and_reconstruction, pin_stage3_exact_factor,
         pin_truncation_orthonormal_and_c_pod, pin_exact_recovery, pin_rbf_weights,
         pin_well_conditioned_bound]
 
@@ -230,6 +303,22 @@ def test_three_stage_sequence_with_truncations_meets_tolerance():
     assert max(later) < out[0]["k3"]
 
 
+def test_iterative_stage3_sequence_meets_tolerance():
+    """The iterative Stage 3 (phi = 1) over a sequence with truncations meets
+    the tolerance in every system with at most the iterations of the
+    non-iterative Stage 3, whose augmenting space it contains."""
+    cfg = Config4Member(20, 1012, 1013, 6, 5, 4, 1e-8)
+    base = dict(ybar=40, y_trunc=12, w_max=4, rho=1e-3)
+    out0 = TS.run_three_stage(cfg, TS.TSOptions(**base, stage2_maxit=20))
+    out1 = TS.run_three_stage(cfg, TS.TSOptions(**base, stage2_maxit=512, phi=1))
+    for a, b in zip(out0, out1):
+        print(f"j={a['j']}: phi=0 k3 {a['k3']} matvecs {a['matvecs']} | phi=1 k3 {b['k3']} "
+              f"projection steps {b['k_in']} matvecs {b['matvecs']}")
+        assert b["status"] == 0 and b["true_relres"] <= cfg.tol * 1.01
+        assert b["k3"] <= a["k3"]
+    assert sum(b["k_in"] for b in out1) > 0
+
+
 # ------------------------------------------------------------------ mutants
 
 SRC = TS.__file__
@@ -242,10 +331,16 @@ MUTANTS = {
         "        ph = zh + beta * ph\n        if w:\n            ph[sel] -= mu",
         "        ph = zh + beta * ph\n        if False:\n            ph[sel] -= mu"),
     "rbf_factor_quarter": ("eta_acc = eta_prev + 0.5 * eta_acc", "eta_acc = eta_prev + 0.25 * eta_acc"),
-    "stage3_residual_ignores_x0": ("    r = b - matvec(A, x)\n    z = dinv * r",
-                                   "    r = b.copy()\n    z = dinv * r"),
+    "stage3_residual_ignores_x0": ("    y = B.shape[1]\n    x = x0.copy()\n    r = b - matvec(A, x)",
+                                   "    y = B.shape[1]\n    x = x0.copy()\n    r = b.copy()"),
     "stage2_rhs_without_stage1": ("rh = Y.T @ (rbar - _mv(A, Y @ xh))", "rh = Y.T @ rbar"),
     "stage3_exact_gram_without_A": ("RB, kb = _chol_truncated(B.T @ AB)", "RB, kb = _chol_truncated(B.T @ B)"),
+    "projection_solve_from_zero": (
+        "    nw, nd = aug.galerkin(c)\n    mu = aug.combine(nw, nd)\n    r = c - aug.combine_G(nw, nd)",
+        "    mu = np.zeros_like(c)\n    r = c.copy()"),
+    "projection_directions_not_kept": ("    aug.P += newP[:room]\n    aug.G += newG[:room]\n    aug.gam += newgam[:room]",
+                                       "    pass"),
+    "outer_direction_unprojected": ("        p = z + beta * p - Y @ mu_of(z)", "        p = z + beta * p"),
     "pod_missing_weight": ("T = (eta[:, None] * V[:, :y]) / np.sqrt(lam[:y])[None, :]",
                            "T = V[:, :y] / np.sqrt(lam[:y])[None, :]"),
 }
