@@ -306,7 +306,8 @@ const char* podcg_batch_last_error(podcg_batch* batch);
 
 /* ------------------------------------------------- three-stage method
  * The paper's full method (Alg. 3, Section 4) with the non-iterative Stage 3
- * (Section 4.3).  The context keeps an accumulated basis Y (m <= cap columns,
+ * (Section 4.3, phi = 0) or the iterative one (Section 4.3.1, phi = 1).  The
+ * context keeps an accumulated basis Y (m <= cap columns,
  * device memory) and a stage-1 basis W made of columns of Y.  One
  * podcg_ts_solve runs, for the current matrix A_j:
  *   Stage 1 (Alg. 2)       the direct Galerkin solve over W from x (= xbar);
@@ -320,6 +321,19 @@ const char* podcg_batch_last_error(podcg_batch* batch);
  *                          with the reused factor blockdiag(R, sqrt(Gammahat))
  *                          (stage3_gram = 0) or the computed and factored Gram
  *                          (stage3_gram = 1), to ||b - A x|| <= rtol ||b||;
+ *   Stage 3, phi = 1       augmented PCG from the Stage-2 solution with all of Y
+ *                          as the augmenting basis: each projection
+ *                          Y^T A Y mu = Y^T A z is solved by augmented CG on the
+ *                          reduced matrix against the reduced stage-1 columns,
+ *                          the stage-2 directions and the directions of earlier
+ *                          projection solves (block-diagonal factor), started
+ *                          from the Galerkin solution over them, to inner_rtol
+ *                          (default: the solve's rtol -- the error an inexact
+ *                          projection leaves in range(Y) is never corrected);
+ *                          Stage 2 then runs to stage2_factor rtol ||b|| (floor
+ *                          1e-13 of ||Y^T r||, at most min(stage2_maxit, m - w)
+ *                          steps), and directions formed from a residual below
+ *                          1e-6 of their solve's initial one are not kept;
  * then the Stage-3 directions, scaled to unit A_j-norm, are appended to Y.
  * If Y then has more than ybar columns it is replaced by its POD (metric A_j,
  * weights: RBF 2^{1-i} over the systems since the last truncation or the
@@ -342,6 +356,11 @@ typedef struct {
     double energy_w;       /* energy criterion of the stage-1 basis, (0, 1], 1 = off         */
     double rho;            /* new-vector rule, [0, 1]                                        */
     double stage2_factor;  /* stage-2 tolerance relative to rtol ||b|| (>= 0)                */
+    int32_t phi;           /* Stage 3 over [W, X] (0, Section 4.3) or over all of Y (1, the
+                              iterative Stage 3 of Section 4.3.1)                            */
+    int32_t inner_maxit;   /* phi = 1: step cap of each projection solve (>= 0)               */
+    double inner_rtol;     /* phi = 1: tolerance of each projection solve relative to the norm
+                              of its right-hand side Y^T A z (< 1); <= 0: the solve's rtol    */
 } podcg_ts_options;
 
 typedef struct {
@@ -354,10 +373,13 @@ typedef struct {
     int32_t jacobi_sweeps; /* sweeps of the truncation's eigen-solver                        */
     double stage1_relres, stage2_relres, relres, true_relres, bnorm;
     double stage12_ms, stage3_ms, accum_ms;
+    int32_t k_in;          /* phi = 1: steps of all projection solves                        */
+    int32_t projections;   /* phi = 1: projection solves (one per Stage-3 direction)         */
 } podcg_ts_stats;
 
 /* Defaults: ybar 200, y_trunc 100, w_max 5, w_cap 16, stage2_maxit 24, cap 512,
- * RBF weights, reused factor, energies 1, rho 0, stage2_factor 1e-4. */
+ * RBF weights, reused factor, energies 1, rho 0, stage2_factor 1e-4, phi 0,
+ * inner_maxit 64, inner_rtol 0 (the solve's rtol). */
 void podcg_ts_default_options(podcg_ts_options* opt);
 
 /* Turns the three-stage mode on (or resets it) with an empty Y; allocates two

@@ -50,8 +50,11 @@ direct block-diagonal solve): Alg. 1 started from zero, as printed, never
 resolves the part of mu in their span, and the outer directions would then not
 be A-orthogonal to them, which the paper states they are.  The projection
 solves stop at inner_rtol times the norm of their right-hand side (the paper
-gives no value; default 1e-6, never below the rounding-level floor) and
-after inner_maxit steps.  Directions formed after a solve's residual (Stage 2
+gives no value) and after inner_maxit steps; by default that tolerance is the
+solve's own relative tolerance (never below the rounding-level floor): the
+error an inexact projection leaves in range(Y) is never corrected by the later
+directions, which are A-orthogonal to Y, and with 1e-8 against an overall
+1e-10 the iteration diverged after reaching 2e-9.  Directions formed after a solve's residual (Stage 2
 or a projection solve) has fallen below 1e-6 of its initial value still
 advance that solve but do not join the augmentation: they are orthogonal to
 the earlier ones only to about the rounding error divided by that reduction,
@@ -93,7 +96,8 @@ class TSOptions:
     rank_rtol: float = 1e-12
     cap: int = 512             # columns of the accumulated-vector store
     phi: int = 0               # Stage 3 over [W, X] (0, Section 4.3) or over all of Y (1, Section 4.3.1)
-    inner_rtol: float = 1e-6   # phi = 1: tolerance of each projection solve, relative to its right-hand side
+    inner_rtol: float = 0.0    # phi = 1: tolerance of each projection solve, relative to its right-hand
+                               # side; <= 0: the solve's own relative tolerance
     inner_maxit: int = 64      # phi = 1: step cap of each projection solve
 
 
@@ -409,7 +413,7 @@ def projection_solve(c: np.ndarray, aug: ReducedAugmentation, ghat_mv, tol: floa
 
 
 def stage3_iterative(A: CSR, b: np.ndarray, x0: np.ndarray, Y: np.ndarray, aug: ReducedAugmentation,
-                     dinv: np.ndarray, tol: float, maxit: int, rec_max: int, inner_rtol: float,
+                     dinv: np.ndarray, tol: float, maxit: int, rec_max: int, inner_rel: float,
                      inner_maxit: int):
     """Augmented PCG (Alg. 1) from x0 with all of Y as the augmenting basis,
     each solve Y^T A Y mu = Y^T A z of steps aug2 / aug3 done by
@@ -429,7 +433,7 @@ def stage3_iterative(A: CSR, b: np.ndarray, x0: np.ndarray, Y: np.ndarray, aug: 
     def mu_of(zv):
         nonlocal kin, mv
         c = Y.T @ matvec(A, zv)
-        rel = max(inner_rtol, ROUNDING_FLOOR)
+        rel = max(inner_rel, ROUNDING_FLOOR)
         mu, ks = projection_solve(c, aug, ghat_mv, rel * float(np.linalg.norm(c)), inner_maxit)
         kin += ks
         mv += 1 + ks
@@ -534,8 +538,9 @@ def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, 
     aug = None
     if opt.phi == 1 and m:
         aug = ReducedAugmentation(Y, sel, AW, R, red["P"], red["G"], red["gam"])
+        inner_rel = opt.inner_rtol if opt.inner_rtol > 0 else rtol
         dx, V, gam, alp, k3, rn, kin, mv3 = stage3_iterative(A, rbar, x0, Y, aug, dinv, tol, maxit, rec_max,
-                                                             opt.inner_rtol, opt.inner_maxit)
+                                                             inner_rel, opt.inner_maxit)
         S.k_in = kin
         S.matvecs = 1 + w + k2 + mv3 + 1
     else:

@@ -48,7 +48,8 @@ class TsOptions(C.Structure):
     _fields_ = [("ybar", C.c_int32), ("y_trunc", C.c_int32), ("w_max", C.c_int32), ("w_cap", C.c_int32),
                 ("stage2_maxit", C.c_int32), ("cap", C.c_int32), ("weights", C.c_int32),
                 ("stage3_gram", C.c_int32), ("energy_y", C.c_double), ("energy_w", C.c_double),
-                ("rho", C.c_double), ("stage2_factor", C.c_double)]
+                ("rho", C.c_double), ("stage2_factor", C.c_double), ("phi", C.c_int32),
+                ("inner_maxit", C.c_int32), ("inner_rtol", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -60,7 +61,8 @@ class TsStats(C.Structure):
                 ("w_next", C.c_int32), ("status", C.c_int32), ("jacobi_sweeps", C.c_int32),
                 ("stage1_relres", C.c_double), ("stage2_relres", C.c_double), ("relres", C.c_double),
                 ("true_relres", C.c_double), ("bnorm", C.c_double), ("stage12_ms", C.c_double),
-                ("stage3_ms", C.c_double), ("accum_ms", C.c_double)]
+                ("stage3_ms", C.c_double), ("accum_ms", C.c_double), ("k_in", C.c_int32),
+                ("projections", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

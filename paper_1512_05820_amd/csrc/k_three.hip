@@ -110,6 +110,8 @@ __device__ __forceinline__ void ts_project(TsDev* T, int m, const int* sel, int 
 // Start of Stage 2: rh = Y^T (b - A xbar - A W what) is already in T->rh.
 // xh = What what, p = z - What mu, rz = (r, z), the tolerance
 // max(tau_rel ||b||, floor ||rh||) and the iteration cap.
+// The stage-2 increment xinc and the augmentation count of the iterative
+// Stage 3 start at zero.
 __global__ __launch_bounds__(kBlock) void k_ts_s2_init(TsDev* T, const DevState* st, int m,
                                                        const int* __restrict__ sel, int w,
                                                        const double* __restrict__ GinvW, double tau_rel,
@@ -117,7 +119,14 @@ __global__ __launch_bounds__(kBlock) void k_ts_s2_init(TsDev* T, const DevState*
     __shared__ double lds[kWavesPerBlock + 2];
     __shared__ double c_s[kYMax], mu_s[kYMax];
     const int t = threadIdx.x;
-    for (int k = t; k < m; k += kBlock) T->xh[k] = 0.0;
+    for (int k = t; k < m; k += kBlock) {
+        T->xh[k] = 0.0;
+        T->xinc[k] = 0.0;
+    }
+    if (t == 0) {
+        T->naug = 0;
+        T->knew = 0;
+    }
     __syncthreads();
     if (t < w) T->xh[sel[t]] = st->what[t];
     double a = 0.0;
@@ -136,9 +145,13 @@ __global__ __launch_bounds__(kBlock) void k_ts_s2_init(TsDev* T, const DevState*
     }
 }
 
-// One Stage-2 iteration once gh = Ghat p is in T->gh.
+// One Stage-2 iteration once gh = Ghat p is in T->gh.  With aug (the
+// iterative Stage 3), the direction joins the augmentation when it was formed
+// from a residual of at least kTsKeepFloor of the initial one, and the
+// increment sum alpha p is kept in xinc; the per-step scalars of the
+// [W, X] basis are recorded for the first kYMax steps.
 __global__ __launch_bounds__(kBlock) void k_ts_s2_step(TsDev* T, int m, const int* __restrict__ sel, int w,
-                                                       const double* __restrict__ GinvW) {
+                                                       const double* __restrict__ GinvW, double* __restrict__ aug) {
     __shared__ double lds[kWavesPerBlock + 2];
     __shared__ double c_s[kYMax], mu_s[kYMax];
     __shared__ int stop;
@@ -154,9 +167,17 @@ __global__ __launch_bounds__(kBlock) void k_ts_s2_step(TsDev* T, int m, const in
         return;
     }
     const double alpha = T->rz2 / g;
+    const int naug = T->naug;
+    const bool keep = aug && T->rn >= kTsKeepFloor * T->rn0 && naug < m;
+    if (keep)
+        for (int k = t; k < m; k += kBlock) {
+            aug[(size_t)naug * kTsCap + k] = T->ph[k];
+            aug[(size_t)(kTsCap + naug) * kTsCap + k] = T->gh[k];
+        }
     double b2 = 0.0;
     for (int k = t; k < m; k += kBlock) {
         T->xh[k] += alpha * T->ph[k];
+        T->xinc[k] += alpha * T->ph[k];
         const double r = T->rh[k] - alpha * T->gh[k];
         T->rh[k] = r;
         b2 += r * r;
@@ -164,16 +185,190 @@ __global__ __launch_bounds__(kBlock) void k_ts_s2_step(TsDev* T, int m, const in
     const double rz_new = ts_block_sum(b2, lds);
     const double beta = rz_new / T->rz2;
     const int k2 = T->k2;
-    __syncthreads();   // every thread has read rz2 and k2
+    __syncthreads();   // every thread has read rz2, rn, naug and k2
     if (t == 0) {
-        T->gam2[k2] = g;
-        T->alp2[k2] = alpha;
+        if (keep) {
+            T->gam_aug[naug] = g;
+            T->naug = naug + 1;
+        }
+        if (k2 < kYMax) {
+            T->gam2[k2] = g;
+            T->alp2[k2] = alpha;
+        }
         T->rz2 = rz_new;
         T->k2 = k2 + 1;
         T->rn = sqrt(rz_new);
         T->done2 = (sqrt(rz_new) <= T->tau || k2 + 1 >= T->k2max) ? 1 : 0;
     }
     ts_project(T, m, sel, w, GinvW, beta, false, c_s, mu_s);
+}
+
+// ------------------------------------------- iterative Stage 3 (phi = 1)
+// Projection solves Ghat mu = c (Section 4.3.1): augmented CG on Ghat (M = I)
+// against the reduced stage-1 columns What and the kept directions P_l
+// (l < naug0), mutually Ghat-orthogonal, so the solves with B^T Ghat B use
+// blockdiag(G_W^{-1}, diag(1 / gam_aug)); Ghat What = ((A W)^T Y)^T = wtgy^T and
+// Ghat P_l are kept, so no product with Ghat is needed to use them.  One
+// workgroup of kTsThreads threads; vectors of m <= kTsCap entries.
+constexpr int kTsThreads = 1024;
+constexpr int kTsWaves = kTsThreads / kWave;
+
+__device__ __forceinline__ double ts_sum(double v, double* red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int w = 1; w < kTsWaves; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ph = rh + beta ph - What nu_w - sum_{l < na} P_l nu_l with
+// nu = blockdiag(G_W^{-1}, 1 / gam_aug) B^T Ghat rh (the projection of steps
+// aug2 / aug3 of Alg. 1 on Ghat).
+__device__ void ts_in_direction(TsDev* T, const double* __restrict__ aug, int m, const int* __restrict__ sel,
+                                int w, const double* __restrict__ GinvW, int na, double beta, bool first,
+                                double* cw, double* nuw, double* nd) {
+    const int t = threadIdx.x;
+    const double* __restrict__ G = aug + (size_t)kTsCap * kTsCap;
+    if (t < w) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += T->wtgy[(size_t)t * m + k] * T->rh[k];
+        cw[t] = s;
+    }
+    for (int l = t; l < na; l += kTsThreads) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += G[(size_t)l * kTsCap + k] * T->rh[k];
+        nd[l] = s / T->gam_aug[l];
+    }
+    __syncthreads();
+    if (t < w) {
+        double s = 0.0;
+        for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * cw[j];
+        nuw[t] = s;
+    }
+    __syncthreads();
+    for (int k = t; k < m; k += kTsThreads) {
+        double v = first ? T->rh[k] : T->rh[k] + beta * T->ph[k];
+        for (int l = 0; l < na; ++l) v -= aug[(size_t)l * kTsCap + k] * nd[l];
+        for (int i = 0; i < w; ++i) v -= sel[i] == k ? nuw[i] : 0.0;
+        T->ph[k] = v;
+    }
+    __syncthreads();
+}
+
+// Start of a projection solve with its right-hand side c in T->cin: the
+// Galerkin solution over the kept directions (mu = B nu, nu = blockdiag(...)
+// B^T c, B^T c = (c[sel], P_l^T c)), its residual rh = c - Ghat B nu, the
+// tolerance rel ||c||, and the first direction.
+__global__ __launch_bounds__(kTsThreads) void k_ts_in_init(TsDev* T, const double* __restrict__ aug, int m,
+                                                           const int* __restrict__ sel, int w,
+                                                           const double* __restrict__ GinvW, double rel,
+                                                           int kinmax) {
+    __shared__ double red[kTsWaves];
+    __shared__ double cw[kYMax], nuw[kYMax], nd[kTsCap];
+    const int t = threadIdx.x;
+    const int na = T->naug;
+    const double* __restrict__ G = aug + (size_t)kTsCap * kTsCap;
+    if (t < w) cw[t] = T->cin[sel[t]];
+    for (int l = t; l < na; l += kTsThreads) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += aug[(size_t)l * kTsCap + k] * T->cin[k];
+        nd[l] = s / T->gam_aug[l];
+    }
+    __syncthreads();
+    if (t < w) {
+        double s = 0.0;
+        for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * cw[j];
+        nuw[t] = s;
+    }
+    __syncthreads();
+    double rr = 0.0, cc = 0.0;
+    for (int k = t; k < m; k += kTsThreads) {
+        const double c = T->cin[k];
+        double mu = 0.0, r = c;
+        for (int i = 0; i < w; ++i) {
+            mu += sel[i] == k ? nuw[i] : 0.0;
+            r -= T->wtgy[(size_t)i * m + k] * nuw[i];
+        }
+        for (int l = 0; l < na; ++l) {
+            mu += aug[(size_t)l * kTsCap + k] * nd[l];
+            r -= G[(size_t)l * kTsCap + k] * nd[l];
+        }
+        T->muin[k] = mu;
+        T->rh[k] = r;
+        rr += r * r;
+        cc += c * c;
+    }
+    const double rz = ts_sum(rr, red);
+    const double cn = sqrt(ts_sum(cc, red));
+    const double rn0 = sqrt(rz);
+    const double tau = rel * cn;
+    const bool done = rn0 <= tau || kinmax <= 0;
+    if (t == 0) {
+        T->rzin = rz;
+        T->rn0in = rn0;
+        T->tauin = tau;
+        T->kin = 0;
+        T->kinmax = kinmax;
+        T->naug0 = na;
+        T->knew = 0;
+        T->donein = done ? 1 : 0;
+    }
+    if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, 0.0, true, cw, nuw, nd);
+}
+
+// One step of a projection solve once gh = Ghat ph is in T->gh: mu += alpha
+// ph, rh -= alpha gh; the direction joins the augmentation (after the kept
+// ones) when it was formed from a residual of at least kTsKeepFloor of the
+// solve's initial one; then the next direction, projected against the
+// directions kept before this solve.  The solve's own kept directions count
+// from the moment it ends.
+__global__ __launch_bounds__(kTsThreads) void k_ts_in_step(TsDev* T, double* __restrict__ aug, int m,
+                                                           const int* __restrict__ sel, int w,
+                                                           const double* __restrict__ GinvW) {
+    __shared__ double red[kTsWaves];
+    __shared__ double cw[kYMax], nuw[kYMax], nd[kTsCap];
+    const int t = threadIdx.x;
+    if (T->donein) return;
+    double a = 0.0;
+    for (int k = t; k < m; k += kTsThreads) a += T->ph[k] * T->gh[k];
+    const double g = ts_sum(a, red);
+    const double rz = T->rzin;
+    const int na0 = T->naug0, knew = T->knew, kin = T->kin;
+    if (!(g > 0.0)) {
+        if (t == 0) {
+            T->donein = 1;
+            T->naug = na0 + knew;
+        }
+        return;
+    }
+    const double alpha = rz / g;
+    const int slot = na0 + knew;
+    const bool keep = sqrt(rz) >= kTsKeepFloor * T->rn0in && slot < m;
+    double b2 = 0.0;
+    for (int k = t; k < m; k += kTsThreads) {
+        const double p = T->ph[k], gk = T->gh[k];
+        if (keep) {
+            aug[(size_t)slot * kTsCap + k] = p;
+            aug[(size_t)(kTsCap + slot) * kTsCap + k] = gk;
+        }
+        T->muin[k] += alpha * p;
+        const double r = T->rh[k] - alpha * gk;
+        T->rh[k] = r;
+        b2 += r * r;
+    }
+    const double rz_new = ts_sum(b2, red);
+    const bool done = sqrt(rz_new) <= T->tauin || kin + 1 >= T->kinmax;
+    if (t == 0) {
+        if (keep) T->gam_aug[slot] = g;
+        T->rzin = rz_new;
+        T->kin = kin + 1;
+        T->knew = knew + (keep ? 1 : 0);
+        T->donein = done ? 1 : 0;
+        if (done) T->naug = na0 + knew + (keep ? 1 : 0);
+    }
+    if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na0, rz_new / rz, false, cw, nuw, nd);
 }
 
 // ------------------------------------------------------------------ Stage 3
@@ -453,9 +648,23 @@ hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel
     return hipGetLastError();
 }
 
-hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW,
+hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW, double* aug,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_ts_s2_step, dim3(1), dim3(kBlock), 0, s, T, m, sel, w, GinvW);
+    hipLaunchKernelGGL(k_ts_s2_step, dim3(1), dim3(kBlock), 0, s, T, m, sel, w, GinvW, aug);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel, int w, const double* GinvW,
+                             double rel, int kinmax, hipStream_t s) {
+    if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_in_init, dim3(1), dim3(kTsThreads), 0, s, T, aug, m, sel, w, GinvW, rel, kinmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
+                             hipStream_t s) {
+    if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_in_step, dim3(1), dim3(kTsThreads), 0, s, T, aug, m, sel, w, GinvW);
     return hipGetLastError();
 }
 

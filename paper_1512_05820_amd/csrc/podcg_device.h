@@ -531,7 +531,24 @@ struct TsDev {
     int k2, done2, k2max, pad;
     double gam3[kTsCap], alp3[kTsCap];
     double eta_prev[kTsCap], eta_acc[kTsCap];
+    // iterative Stage 3 (phi = 1): the stage-2 increment sum alpha p (reduced),
+    // the current projection solve (right-hand side, solution; its residual
+    // and direction reuse rh / ph and Ghat p reuses gh), and the kept
+    // augmenting directions: naug of them (P and Ghat P in the separate
+    // augmentation block, (Ghat p, p) here), naug0 at the start of the
+    // current solve, knew kept by it so far
+    double xinc[kTsCap], cin[kTsCap], muin[kTsCap];
+    double gam_aug[kTsCap];
+    double rzin, rn0in, tauin, pad5;
+    int kin, donein, kinmax, naug;
+    int naug0, knew, pad6, pad7;
 };
+// Augmentation block of the iterative Stage 3: direction l at P + l kTsCap,
+// Ghat times it at P + (kTsCap + l) kTsCap.
+constexpr size_t kTsAugDoubles = (size_t)2 * kTsCap * kTsCap;
+// Directions formed from a residual below this fraction of their solve's
+// initial residual are not kept (iterative Stage 3).
+constexpr double kTsKeepFloor = 1e-6;
 
 // One-workgroup solve of small systems (k_lds.hip): threads per workgroup,
 // widest slice and largest basis it holds in registers.

@@ -150,7 +150,15 @@ hipError_t launch_gemv_t(int n, size_t ld, const double* Y, int m, const double*
 hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel, int w,
                              const double* GinvW, double tau_rel, double floor_rel, int k2max,
                              hipStream_t s);
-hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW,
+// One Stage-2 step; aug (iterative Stage 3, else NULL) receives the kept directions.
+hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW, double* aug,
+                             hipStream_t s);
+// Projection solves of the iterative Stage 3 (Section 4.3.1), right-hand side
+// in T->cin: start (Galerkin solution over the kept directions, tolerance
+// rel ||c||, step cap kinmax) and one step once T->gh = Ghat T->ph.
+hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel, int w, const double* GinvW,
+                             double rel, int kinmax, hipStream_t s);
+hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
                              hipStream_t s);
 hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
                                     hipStream_t s);

@@ -42,6 +42,7 @@ struct TsHost {
     int* d_info = nullptr;
     double* d_Gbig2 = nullptr;   // second buffer of the Jacobi rounds
     double* d_Gparts = nullptr;  // partial Grams of the row chunks
+    double* d_aug = nullptr;     // iterative Stage 3: kept reduced directions and Ghat times them
     TsDev* d_ts = nullptr;
     double* h_dbl = nullptr;     // pinned, kTsCap + 8
     int* h_int = nullptr;        // pinned, kYMax + 8
@@ -53,7 +54,7 @@ void ts_release(podcg_ctx* ctx) {
     if (!T) return;
     void* dev[] = {T->d_Y, T->d_AZ, T->d_B, T->d_AB, T->d_part, T->d_G, T->d_R, T->d_GinvW, T->d_GinvB,
                    T->d_lamG, T->d_Gbig, T->d_Vbig, T->d_lam, T->d_T, T->d_sel, T->d_info, T->d_ts,
-                   T->d_Gbig2, T->d_Gparts};
+                   T->d_Gbig2, T->d_Gparts, T->d_aug};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (T->h_dbl) (void)hipHostFree(T->h_dbl);
@@ -69,6 +70,9 @@ void ts_release(podcg_ctx* ctx) {
 namespace {
 
 constexpr double kStage2Floor = 1e-6;   // stage-2 tolerance floor, relative to ||Y^T r||
+// Iterative Stage 3 (phi = 1): floor of Stage 2 and of the projection solves,
+// relative to their initial residual (rounding level)
+constexpr double kRoundingFloor = 1e-13;
 constexpr int kJacobiMaxSweeps = 60;
 constexpr int kGramChunks = 64;         // row chunks of the truncation Gram
 
@@ -81,7 +85,9 @@ M* ts_field(TsDev* base, size_t offset) {
 void check_ts_opts(podcg_ctx* ctx, const podcg_ts_options& o) {
     const bool ok = o.cap >= 2 && o.cap <= kTsCap && o.ybar >= 1 && o.ybar < o.cap && o.y_trunc >= 1 &&
                     o.y_trunc <= o.ybar && o.w_max >= 0 && o.w_max <= kYMax && o.w_max <= o.y_trunc &&
-                    o.w_cap >= 0 && o.w_cap <= kYMax && o.stage2_maxit >= 0 && o.stage2_maxit <= kYMax &&
+                    o.w_cap >= 0 && o.w_cap <= kYMax && o.stage2_maxit >= 0 &&
+                    o.stage2_maxit <= (o.phi == 1 ? kTsCap : kYMax) && (o.phi == 0 || o.phi == 1) &&
+                    o.inner_maxit >= 0 && o.inner_rtol < 1.0 &&
                     (o.weights == 0 || o.weights == 1) && (o.stage3_gram == 0 || o.stage3_gram == 1) &&
                     o.energy_y > 0.0 && o.energy_y <= 1.0 && o.energy_w > 0.0 && o.energy_w <= 1.0 &&
                     o.rho >= 0.0 && o.rho <= 1.0 && o.stage2_factor >= 0.0;
@@ -159,6 +165,128 @@ void truncate(podcg_ctx* ctx, TsHost* T, int M, podcg_ts_stats& S) {
     S.truncated = 1;
 }
 
+// Accumulation (Alg. 3): Z = [Y, V Gamma^{-1/2}], weights, truncation or the
+// rho rule; then the timings and the statistics.  Shared by both Stage 3s.
+int ts_finish(podcg_ctx* ctx, TsHost* T, int m, int k3, int code, podcg_ts_stats& S, podcg_ts_stats* out) {
+    hipStream_t s = ctx->stream;
+    const int cap_rec = T->opt.cap - m;
+    if (code >= 0) {
+        const int kr = std::min(k3, cap_rec);
+        HIPCHECK(launch_ts_eta(T->d_ts, m, kr, s));
+        const int M = m + kr;
+        if (M > T->opt.ybar) {
+            truncate(ctx, T, M, S);
+        } else {
+            T->m = M;
+            std::vector<int> pick;
+            if (T->opt.rho >= 1.0) {
+                for (int k = 0; k < kr; ++k) pick.push_back(m + k);
+            } else if (T->opt.rho > 0.0 && kr > 0) {
+                HIPCHECK(hipMemcpyAsync(T->h_dbl, TSF(T, gam3), sizeof(double) * kr, hipMemcpyDeviceToHost, s));
+                HIPCHECK(hipStreamSynchronize(s));
+                double tot = 0.0;
+                for (int k = 0; k < kr; ++k) tot += T->h_dbl[k];
+                for (int k = 0; k < kr; ++k)
+                    if (T->h_dbl[k] / tot > T->opt.rho) pick.push_back(m + k);
+            }
+            for (int c : pick)
+                if ((int)T->sel.size() < T->opt.w_cap) T->sel.push_back(c);
+        }
+    }
+    HIPCHECK(hipEventRecord(T->ev[3], s));
+    HIPCHECK(hipStreamSynchronize(s));
+    float a = 0.f, b3 = 0.f, c = 0.f;
+    HIPCHECK(hipEventElapsedTime(&a, T->ev[0], T->ev[1]));
+    HIPCHECK(hipEventElapsedTime(&b3, T->ev[1], T->ev[2]));
+    HIPCHECK(hipEventElapsedTime(&c, T->ev[2], T->ev[3]));
+    S.stage12_ms = a;
+    S.stage3_ms = b3;
+    S.accum_ms = c;
+    S.m_next = T->m;
+    S.w_next = (int)T->sel.size();
+    if (out) *out = S;
+    return code;
+}
+
+// Stage 3 with phi = 1 (Section 4.3.1): augmented PCG (Alg. 1, Jacobi) from
+// the Stage-2 solution with all of Y as the augmenting basis.  The loop
+// kernels run with no basis (p = z + beta p); each projection
+// Y^T A Y mu = Y^T A z is a projection solve (k_three.hip) whose products
+// with Ghat are Y^T (A (Y ph)), and then p -= Y mu.  The host reads the
+// convergence flag after every iteration and the projection solve's flag
+// after every step of it.
+int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, double rtol, int m, int w, int k2,
+                        podcg_ts_stats& S, podcg_ts_stats* out) {
+    hipStream_t s = ctx->stream;
+    DevBufs D = bufs(ctx);
+    const size_t ld = ctx->ld;
+    const int n = (int)ctx->n;
+    const int maxit = ctx->opt.maxit;
+    // the projection solves' tolerance: inner_rtol, or the solve's own rtol
+    const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : rtol, kRoundingFloor);
+    int* hin = T->h_int + kYMax;    // {steps, done} of the projection solve
+    double* u = T->d_AZ;            // Y ph and A Y ph (the truncation's block is free here)
+    double* au = T->d_AZ + ld;
+    int nproj = 0, kin = 0;
+    // T->muin = Ghat^{-1} Y^T A v, iteratively
+    auto project = [&](const double* v) {
+        HIPCHECK(launch_matvec(D, v, ctx->d_q, s));
+        HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, ctx->d_q, T->d_part, TSF(T, cin), s));
+        HIPCHECK(launch_ts_in_init(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, rel, T->opt.inner_maxit, s));
+        for (;;) {
+            HIPCHECK(hipMemcpyAsync(hin, ts_field<int>(T->d_ts, offsetof(TsDev, kin)), 2 * sizeof(int),
+                                    hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (hin[1]) break;
+            HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, ph), u, 1.0, false, s));
+            HIPCHECK(launch_matvec(D, u, au, s));
+            HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, au, T->d_part, TSF(T, gh), s));
+            HIPCHECK(launch_ts_in_step(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, s));
+        }
+        ++nproj;
+        kin += hin[0];
+    };
+    HIPCHECK(hipEventRecord(T->ev[1], s));
+    HIPCHECK(launch_state_init(ctx->d_st, maxit, rtol * rtol, 0, s));
+    // r = b - A x0 (no projection of x0), z = M^{-1} r, and the test before the loop
+    HIPCHECK(launch_resid(D, 0, 0, b, x, ctx->d_r, nullptr, true, true, s));
+    HIPCHECK(launch_stage1_apply(D, 0, 0, x, ctx->d_r, ctx->d_z, nullptr, nullptr, s));
+    poll(ctx);
+    const int cap_rec = T->opt.cap - m;
+    double* vrec = T->d_Y + (size_t)m * ld;
+    if (ctx->h_poll->done == kRunning) {
+        project(ctx->d_z);
+        HIPCHECK(launch_dir(D, 0, 0, ctx->d_p, x, ctx->d_z, nullptr, true, -1, s));        // p = z
+        HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, muin), ctx->d_p, -1.0, true, s));  // p -= Y mu
+        for (int k = 0; k < maxit; ++k) {
+            HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, s));
+            HIPCHECK(launch_update(D, 0, 0, ctx->d_r, ctx->d_z, ctx->d_q, nullptr, k, s));
+            // x += alpha p, p recorded, p = z + beta p, convergence and cap
+            HIPCHECK(launch_dir_rec(D, 0, 0, ctx->d_p, x, ctx->d_z, nullptr, vrec, ld, cap_rec, TSF(T, gam3),
+                                    TSF(T, alp3), k, s));
+            poll(ctx);
+            if (ctx->h_poll->done != kRunning) break;
+            project(ctx->d_z);
+            HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, muin), ctx->d_p, -1.0, true, s));
+        }
+    }
+    HIPCHECK(launch_resid(D, 0, 0, b, x, nullptr, nullptr, false, false, s));
+    poll(ctx);
+    const PollBlock P = *ctx->h_poll;
+    HIPCHECK(hipEventRecord(T->ev[2], s));
+    const double bn = S.bnorm;
+    const int k3 = P.iter;
+    S.k3 = k3;
+    S.k_in = kin;
+    S.projections = nproj;
+    S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
+    S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
+    S.matvecs = w + 1 + k2 + 1 + k3 + nproj + kin + 1;
+    const int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
+    S.status = code;
+    return ts_finish(ctx, T, m, k3, code, S, out);
+}
+
 int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_ts_stats* out) {
     TsHost* T = ctx->ts;
     if (!T) fail(ctx, PODCG_ERR_INVALID_ARG, "three-stage mode is not enabled");
@@ -205,34 +333,45 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     // ---- Stage 2 (Section 4.2) over Y
     int k2 = 0;
     const int m = T->m;
+    // phi = 1: the stage-2 directions join the reduced augmentation of the
+    // projection solves instead of a [W, X] basis of at most kYMax columns, and
+    // Stage 2 runs to its tolerance with a rounding-level floor only (Alg. 1
+    // over all of Y never corrects the error it leaves in range(Y))
+    const bool iter3 = T->opt.phi == 1 && m > 0;
     if (m > 0) {
-        const int k2max = std::min(T->opt.stage2_maxit, kYMax - w);
+        const int k2max = iter3 ? std::min(T->opt.stage2_maxit, m - w) : std::min(T->opt.stage2_maxit, kYMax - w);
         for (int i = 0; i < w; ++i)
             HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, T->d_AB + i * ld, T->d_part, TSF(T, wtgy) + (size_t)i * m, s));
         HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, ctx->d_r, T->d_part, TSF(T, rh), s));
         HIPCHECK(launch_ts_s2_init(T->d_ts, ctx->d_st, m, T->d_sel, w, T->d_GinvW, T->opt.stage2_factor * rtol,
-                                   kStage2Floor, k2max, s));
+                                   iter3 ? kRoundingFloor : kStage2Floor, k2max, s));
         int* h = T->h_int + kYMax;
         for (int k = 0;; ++k) {
             HIPCHECK(hipMemcpyAsync(h, ts_field<int>(T->d_ts, offsetof(TsDev, k2)), 2 * sizeof(int),
                                     hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
             if (h[1] || k >= k2max) break;   // h = {k2, done2}
-            double* u = T->d_B + (size_t)(w + k) * ld;
-            double* q = T->d_AB + (size_t)(w + k) * ld;
+            // u = Y p and q = A u become columns of [W, X] (phi = 0), or are
+            // scratch (phi = 1: the CG vectors p, q are free before Stage 3)
+            double* u = iter3 ? ctx->d_p : T->d_B + (size_t)(w + k) * ld;
+            double* q = iter3 ? ctx->d_q : T->d_AB + (size_t)(w + k) * ld;
             HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, ph), u, 1.0, false, s));
             HIPCHECK(launch_matvec(D, u, q, s));
             HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, q, T->d_part, TSF(T, gh), s));
-            HIPCHECK(launch_ts_s2_step(T->d_ts, m, T->d_sel, w, T->d_GinvW, s));
+            HIPCHECK(launch_ts_s2_step(T->d_ts, m, T->d_sel, w, T->d_GinvW, iter3 ? T->d_aug : nullptr, s));
         }
         k2 = h[0];
         HIPCHECK(hipMemcpyAsync(T->h_dbl, TSF(T, rn), sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
         S.stage2_relres = bn > 0 ? T->h_dbl[0] / bn : T->h_dbl[0];
         // x = xbar + Y xhat: Stage 1 already added W what, Stage 2 adds sum_k alpha_k Y p_k
-        if (k2 > 0) HIPCHECK(launch_gemv_n(n, ld, T->d_B + (size_t)w * ld, k2, TSF(T, alp2), x, 1.0, true, s));
+        if (k2 > 0) {
+            if (iter3) HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, xinc), x, 1.0, true, s));
+            else HIPCHECK(launch_gemv_n(n, ld, T->d_B + (size_t)w * ld, k2, TSF(T, alp2), x, 1.0, true, s));
+        }
     }
     S.k2 = k2;
+    if (iter3) return ts_stage3_iterative(ctx, T, b, x, rtol, m, w, k2, S, out);
 
     // ---- Stage 3 (Section 4.3): augmented PCG over [W, X] from the Stage-2 solution
     int y = w + k2;
@@ -276,43 +415,7 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
     S.status = code;
 
-    // ---- accumulation (Alg. 3): Z = [Y, V Gamma^{-1/2}], weights, truncation
-    if (code >= 0) {
-        const int kr = std::min(k3, cap_rec);
-        HIPCHECK(launch_ts_eta(T->d_ts, m, kr, s));
-        const int M = m + kr;
-        if (M > T->opt.ybar) {
-            truncate(ctx, T, M, S);
-        } else {
-            T->m = M;
-            std::vector<int> pick;
-            if (T->opt.rho >= 1.0) {
-                for (int k = 0; k < kr; ++k) pick.push_back(m + k);
-            } else if (T->opt.rho > 0.0 && kr > 0) {
-                HIPCHECK(hipMemcpyAsync(T->h_dbl, TSF(T, gam3), sizeof(double) * kr, hipMemcpyDeviceToHost, s));
-                HIPCHECK(hipStreamSynchronize(s));
-                double tot = 0.0;
-                for (int k = 0; k < kr; ++k) tot += T->h_dbl[k];
-                for (int k = 0; k < kr; ++k)
-                    if (T->h_dbl[k] / tot > T->opt.rho) pick.push_back(m + k);
-            }
-            for (int c : pick)
-                if ((int)T->sel.size() < T->opt.w_cap) T->sel.push_back(c);
-        }
-    }
-    HIPCHECK(hipEventRecord(T->ev[3], s));
-    HIPCHECK(hipStreamSynchronize(s));
-    float a = 0.f, b3 = 0.f, c = 0.f;
-    HIPCHECK(hipEventElapsedTime(&a, T->ev[0], T->ev[1]));
-    HIPCHECK(hipEventElapsedTime(&b3, T->ev[1], T->ev[2]));
-    HIPCHECK(hipEventElapsedTime(&c, T->ev[2], T->ev[3]));
-    S.stage12_ms = a;
-    S.stage3_ms = b3;
-    S.accum_ms = c;
-    S.m_next = T->m;
-    S.w_next = (int)T->sel.size();
-    if (out) *out = S;
-    return code;
+    return ts_finish(ctx, T, m, k3, code, S, out);
 }
 
 }  // namespace
@@ -333,6 +436,9 @@ void podcg_ts_default_options(podcg_ts_options* o) {
     o->energy_w = 1.0;
     o->rho = 0.0;
     o->stage2_factor = 1e-4;
+    o->phi = 0;
+    o->inner_maxit = 64;
+    o->inner_rtol = 0.0;
 }
 
 int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
@@ -366,6 +472,7 @@ int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
         dalloc(ctx, &T->d_info, 4);
         dalloc(ctx, &T->d_Gbig2, (size_t)kTsCap * kTsCap);
         dalloc(ctx, &T->d_Gparts, (size_t)(kGramChunks + 1) * kTsCap * kTsCap);
+        if (o.phi == 1) dalloc(ctx, &T->d_aug, kTsAugDoubles);
         dalloc(ctx, &T->d_ts, 1);
         HIPCHECK(hipMemsetAsync(T->d_Y, 0, sizeof(double) * ld * (size_t)o.cap, s));
         HIPCHECK(hipMemsetAsync(T->d_AZ, 0, sizeof(double) * ld * (size_t)o.cap, s));

@@ -1,4 +1,5 @@
-"""The three-stage method (Alg. 3) on the GPU against the three-stage oracle.
+"""The three-stage method (Alg. 3) on the GPU against the three-stage oracle,
+with the non-iterative Stage 3 (phi = 0) and the iterative one (phi = 1).
 
 Lockstep: from identical states (Y, stage-1 columns, weights), matrix and
 right-hand side, with tolerance 0 and the same Stage-3 iteration count,
@@ -54,7 +55,8 @@ def _ctx(P, cfg, maxit=20000, **ts):
 def _opts(**kw):
     o = TS.TSOptions(**kw)
     return o, {f: getattr(o, f) for f in ("ybar", "y_trunc", "w_max", "w_cap", "stage2_maxit", "cap",
-                                          "energy_y", "energy_w", "rho", "stage2_factor")} | {
+                                          "energy_y", "energy_w", "rho", "stage2_factor", "phi",
+                                          "inner_maxit", "inner_rtol")} | {
         "weights": 0 if o.weights == "rbf" else 1,
         "stage3_gram": 0 if o.stage3_gram == "blockdiag" else 1}
 
@@ -170,3 +172,57 @@ def test_record_cap_and_errors(P):
     mixed = P.PodCG(cfg.n, precision="mixed")
     with pytest.raises(P.PodCGError):
         mixed.ts_enable()
+
+
+@pytest.mark.parametrize("case", ["basis", "truncate"])
+def test_lockstep_iterative_stage3(P, case):
+    """phi = 1 from identical states with tolerance 0 and the oracle's Stage-3
+    count: equal Stage-2, Stage-3 and projection-solve step counts, equal
+    truncation decisions, solutions within 1e-10."""
+    cfg = Config4Member(20, 1020, 1021, 3, 5, 4, 1e-10)
+    A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(2))
+    b = cfg.rhs(2)
+    r = np.random.Generator(np.random.PCG64(81))
+    K = 25
+    m = 40 if case == "basis" else 50
+    o, kw = _opts(ybar=100 if case == "basis" else 60, y_trunc=12, w_max=4, stage2_maxit=512, phi=1,
+                  inner_rtol=1e-10)
+    st = TS.TSState(cfg.n)
+    st.Y = _a_orthonormal(oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(1)), r.standard_normal((cfg.n, m)))
+    st.sel = [0, 1, 2, 3]
+    st.eta_acc = r.uniform(0.5, 1.0, m)
+    Y0, sel0, eta0 = st.Y.copy(), list(st.sel), st.eta_acc.copy()
+    xo, So = TS.ts_solve(A, b, np.zeros(cfg.n), st, 0.0, K, o)
+    ctx = _ctx(P, cfg, maxit=K, **kw)
+    ctx.set_matrix(_dev(cfg.matrix_values(2)))
+    ctx.ts_set_state(_dev(Y0), sel0, eta0)
+    x = _dev(np.zeros(cfg.n))
+    Sg = ctx.ts_solve(_dev(b), x, 0.0)
+    e = _relerr(_host(x), xo)
+    print(f"{case}: w {Sg.w}/{So.w} k2 {Sg.k2}/{So.k2} k3 {Sg.k3}/{So.k3} k_in {Sg.k_in}/{So.k_in} "
+          f"trunc {Sg.truncated}/{So.truncated} m_next {Sg.m_next}/{So.m_next} err {e:.2e}")
+    assert (Sg.w, Sg.k2, Sg.k3, Sg.k_in) == (So.w, So.k2, So.k3, So.k_in)
+    assert Sg.k_in > 0 and Sg.projections == K
+    assert bool(Sg.truncated) == So.truncated and Sg.m_next == So.m_next
+    assert e <= 1e-10
+
+
+def test_closed_loop_iterative_stage3_sequence(P):
+    cfg = Config4Member(24, 1022, 1023, 6, 5, 4, 1e-10)
+    o, kw = _opts(ybar=120, y_trunc=30, w_max=5, rho=1e-3, stage2_maxit=512, phi=1)
+    orc = TS.run_three_stage(cfg, o, maxit=20000)
+    ctx = _ctx(P, cfg, **kw)
+    for j, oj in enumerate(orc, start=1):
+        if j > 1:
+            ctx.set_matrix(_dev(cfg.matrix_values(j)))
+        b = cfg.rhs(j)
+        x = _dev(np.zeros(cfg.n))
+        S = ctx.ts_solve(_dev(b), x, cfg.tol)
+        A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(j))
+        tr = np.linalg.norm(b - oracle.matvec(A, _host(x))) / np.linalg.norm(b)
+        print(f"j={j} w {S.w}/{oj['w']} m {S.m}/{oj['m']} k2 {S.k2}/{oj['k2']} k3 {S.k3}/{oj['k3']} "
+              f"k_in {S.k_in}/{oj['k_in']} trunc {S.truncated}/{oj['truncated']} relres {tr:.2e}")
+        assert S.status == 0 and tr <= cfg.tol * 1.01
+        assert (S.w, S.m) == (oj["w"], oj["m"]) and bool(S.truncated) == oj["truncated"]
+        assert abs(S.k2 - oj["k2"]) <= 1 and abs(S.k3 - oj["k3"]) <= 2
+    assert any(o_["truncated"] for o_ in orc) and sum(o_["k_in"] for o_ in orc) > 0
