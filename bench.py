@@ -426,11 +426,12 @@ def bench_config4(args):
 
 
 def bench_three_stage(args):
-    """The paper's full three-stage method (Alg. 3, non-iterative Stage 3) on the
-    3-D diffusion sequence, next to the POD-of-solutions augmented PCG and plain
-    PCG on the same systems.  Variants: ybar 200, POD to 100 vectors, stage-1
-    basis 5, rho 0 (the POD(5,95) family), with the reused block-diagonal factor
-    and with the computed Gram of [W, X] in Stage 3."""
+    """The paper's full three-stage method (Alg. 3) on the 3-D diffusion
+    sequence, next to the POD-of-solutions augmented PCG and plain PCG on the
+    same systems.  Variants: ybar 200, POD to 100 vectors, stage-1 basis 5,
+    rho 0 (the POD(5,95) family), Stage 3 over [W, X] with the reused
+    block-diagonal factor or the computed Gram, and the iterative Stage 3 over
+    all of Y (phi = 1, Stage 2 to its tolerance)."""
     import torch
     import paper_1512_05820_amd as P
     from problems import config2
@@ -459,9 +460,9 @@ def bench_three_stage(args):
         runs["plain_warm"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
         log("plain_warm", runs["plain_warm"])
 
-    def three_stage(gram):
-        ctx.ts_enable(ybar=200, y_trunc=100, w_max=5, w_cap=16, stage2_maxit=24, rho=0.0,
-                      stage2_factor=1e-4, stage3_gram=gram)
+    def three_stage(gram, phi=0):
+        ctx.ts_enable(ybar=200, y_trunc=100, w_max=5, w_cap=16, stage2_maxit=512 if phi else 24, rho=0.0,
+                      stage2_factor=1e-4, stage3_gram=gram, phi=phi)
         src = torch.full((cfg.n,), cfg.source, dtype=torch.float64, device="cuda")
         x_prev = torch.zeros(cfg.n, dtype=torch.float64, device="cuda")
         sts = []
@@ -476,8 +477,8 @@ def bench_three_stage(args):
             x_prev = x
         return sts
 
-    for gram in ("blockdiag", "exact"):
-        ms, sts = timed(lambda: three_stage(gram))
+    for gram, phi in (("blockdiag", 0), ("exact", 0), ("iterative", 1)):
+        ms, sts = timed(lambda: three_stage("blockdiag" if phi else gram, phi))
         runs[f"three_stage_{gram}"] = {
             "ms": round(ms, 1),
             "stage3_iters": sum(s["k3"] for s in sts),
@@ -488,6 +489,7 @@ def bench_three_stage(args):
             "stage3_ms": round(sum(s["stage3_ms"] for s in sts), 1),
             "accumulate_truncate_ms": round(sum(s["accum_ms"] for s in sts), 1),
             "max_jacobi_sweeps": max(s["jacobi_sweeps"] for s in sts),
+            "projection_steps": sum(s["k_in"] for s in sts),
             "max_true_relres": max(s["true_relres"] for s in sts),
             "k3_per_system": [s["k3"] for s in sts],
             "m_per_system": [s["m"] for s in sts],

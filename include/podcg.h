@@ -328,8 +328,9 @@ const char* podcg_batch_last_error(podcg_batch* batch);
  *                          the stage-2 directions and the directions of earlier
  *                          projection solves (block-diagonal factor), started
  *                          from the Galerkin solution over them, to inner_rtol
- *                          (default: the solve's rtol -- the error an inexact
- *                          projection leaves in range(Y) is never corrected);
+ *                          (default: 1e-2 of the solve's rtol -- the error an
+ *                          inexact projection leaves in range(Y) is never
+ *                          corrected);
  *                          Stage 2 then runs to stage2_factor rtol ||b|| (floor
  *                          1e-13 of ||Y^T r||, at most min(stage2_maxit, m - w)
  *                          steps), and directions formed from a residual below
@@ -360,7 +361,8 @@ typedef struct {
                               iterative Stage 3 of Section 4.3.1)                            */
     int32_t inner_maxit;   /* phi = 1: step cap of each projection solve (>= 0)               */
     double inner_rtol;     /* phi = 1: tolerance of each projection solve relative to the norm
-                              of its right-hand side Y^T A z (< 1); <= 0: the solve's rtol    */
+                              of its right-hand side Y^T A z (< 1); <= 0: 1e-2 of the solve's
+                              rtol                                                            */
 } podcg_ts_options;
 
 typedef struct {
@@ -379,7 +381,7 @@ typedef struct {
 
 /* Defaults: ybar 200, y_trunc 100, w_max 5, w_cap 16, stage2_maxit 24, cap 512,
  * RBF weights, reused factor, energies 1, rho 0, stage2_factor 1e-4, phi 0,
- * inner_maxit 64, inner_rtol 0 (the solve's rtol). */
+ * inner_maxit 256, inner_rtol 0 (1e-2 of the solve's rtol). */
 void podcg_ts_default_options(podcg_ts_options* opt);
 
 /* Turns the three-stage mode on (or resets it) with an empty Y; allocates two

@@ -50,16 +50,21 @@ direct block-diagonal solve): Alg. 1 started from zero, as printed, never
 resolves the part of mu in their span, and the outer directions would then not
 be A-orthogonal to them, which the paper states they are.  The projection
 solves stop at inner_rtol times the norm of their right-hand side (the paper
-gives no value) and after inner_maxit steps; by default that tolerance is the
-solve's own relative tolerance (never below the rounding-level floor): the
-error an inexact projection leaves in range(Y) is never corrected by the later
-directions, which are A-orthogonal to Y, and with 1e-8 against an overall
-1e-10 the iteration diverged after reaching 2e-9.  Directions formed after a solve's residual (Stage 2
+gives no value) and after inner_maxit steps; by default that tolerance is
+1e-2 of the solve's own relative tolerance (never below the rounding-level
+floor): the error an inexact projection leaves in range(Y) is never corrected
+by the later directions, which are A-orthogonal to Y.  Measured: with 1e-8
+against an overall 1e-10 the iteration diverged after reaching 2e-9 (2-D,
+24^2); on the 128^3 sequence it diverged with 1e-10 and 1e-8 and converged
+with 1e-12.  Directions formed after a solve's residual (Stage 2
 or a projection solve) has fallen below 1e-6 of its initial value still
-advance that solve but do not join the augmentation: they are orthogonal to
-the earlier ones only to about the rounding error divided by that reduction,
-and the reused block-diagonal factor needs them orthogonal (a late stage-2
-direction made the projection solves diverge).
+advance that solve but do not join the augmentation (for a projection solve
+the measure is the norm of its right-hand side, which its Galerkin start may
+already have cancelled to a small residual): they are orthogonal to the
+earlier ones only to about the rounding error divided by that reduction, and
+the reused block-diagonal factor needs them orthogonal (a late stage-2
+direction made the projection solves diverge, and at 128^3 kept directions
+formed from small post-start residuals made the iteration diverge).
 """
 
 from __future__ import annotations
@@ -74,9 +79,10 @@ BASIS_MAX = 32          # columns of the Stage-1 / Stage-3 augmenting bases
 STAGE2_FLOOR = 1e-6     # stage-2 tolerance floor, relative to the initial reduced residual
 ROUNDING_FLOOR = 1e-13  # phi = 1: floor of Stage 2 and of the projection solves, relative to
                         # their initial residual
+INNER_MARGIN = 1e-2     # phi = 1: default projection-solve tolerance relative to the overall one
 KEEP_FLOOR = 1e-6       # phi = 1: a direction joins the reduced augmentation only if it was
                         # formed from a residual at least this fraction of its solve's
-                        # initial residual
+                        # right-hand side (Stage 2: its initial residual)
 
 
 @dataclass
@@ -97,8 +103,8 @@ class TSOptions:
     cap: int = 512             # columns of the accumulated-vector store
     phi: int = 0               # Stage 3 over [W, X] (0, Section 4.3) or over all of Y (1, Section 4.3.1)
     inner_rtol: float = 0.0    # phi = 1: tolerance of each projection solve, relative to its right-hand
-                               # side; <= 0: the solve's own relative tolerance
-    inner_maxit: int = 64      # phi = 1: step cap of each projection solve
+                               # side; <= 0: INNER_MARGIN times the solve's own relative tolerance
+    inner_maxit: int = 256     # phi = 1: step cap of each projection solve
 
 
 @dataclass
@@ -372,9 +378,10 @@ def projection_solve(c: np.ndarray, aug: ReducedAugmentation, ghat_mv, tol: floa
     """Ghat mu = c by augmented CG (Alg. 1, M = I) against the directions of
     `aug`, from the Galerkin solution over their span.  Its own directions
     join `aug` afterwards, those formed from a residual of at least KEEP_FLOOR
-    of the initial one (later ones are orthogonal to the earlier directions
-    only to about the rounding error divided by that reduction, and the
-    block-diagonal factor needs them orthogonal).  Returns (mu, steps)."""
+    of ||c|| (the residual is computed with cancellation against c, so later
+    directions are orthogonal to the earlier ones only to about the rounding
+    error of c divided by that reduction, and the block-diagonal factor needs
+    them orthogonal).  Returns (mu, steps)."""
     nw, nd = aug.galerkin(c)
     mu = aug.combine(nw, nd)
     r = c - aug.combine_G(nw, nd)
@@ -384,9 +391,9 @@ def projection_solve(c: np.ndarray, aug: ReducedAugmentation, ghat_mv, tol: floa
     rz = r @ z
     newP, newG, newgam = [], [], []
     k = 0
-    rn0 = float(np.linalg.norm(r))
+    cn = float(np.linalg.norm(c))
     while np.linalg.norm(r) > tol and k < maxit:
-        keep = float(np.linalg.norm(r)) >= KEEP_FLOOR * rn0     # p was formed from this residual
+        keep = float(np.linalg.norm(r)) >= KEEP_FLOOR * cn      # p was formed from this residual
         g = ghat_mv(p)
         gam = p @ g
         if not gam > 0:
@@ -538,7 +545,7 @@ def ts_solve(A: CSR, b: np.ndarray, xbar: np.ndarray, st: TSState, rtol: float, 
     aug = None
     if opt.phi == 1 and m:
         aug = ReducedAugmentation(Y, sel, AW, R, red["P"], red["G"], red["gam"])
-        inner_rel = opt.inner_rtol if opt.inner_rtol > 0 else rtol
+        inner_rel = opt.inner_rtol if opt.inner_rtol > 0 else INNER_MARGIN * rtol
         dx, V, gam, alp, k3, rn, kin, mv3 = stage3_iterative(A, rbar, x0, Y, aug, dinv, tol, maxit, rec_max,
                                                              inner_rel, opt.inner_maxit)
         S.k_in = kin

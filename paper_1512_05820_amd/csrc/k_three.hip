@@ -309,6 +309,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_in_init(TsDev* T, const doubl
         T->rzin = rz;
         T->rn0in = rn0;
         T->tauin = tau;
+        T->cnin = cn;
         T->kin = 0;
         T->kinmax = kinmax;
         T->naug0 = na;
@@ -320,8 +321,9 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_in_init(TsDev* T, const doubl
 
 // One step of a projection solve once gh = Ghat ph is in T->gh: mu += alpha
 // ph, rh -= alpha gh; the direction joins the augmentation (after the kept
-// ones) when it was formed from a residual of at least kTsKeepFloor of the
-// solve's initial one; then the next direction, projected against the
+// ones) when it was formed from a residual of at least kTsKeepFloor of ||c||
+// (the residual is computed with cancellation against c); then the next
+// direction, projected against the
 // directions kept before this solve.  The solve's own kept directions count
 // from the moment it ends.
 __global__ __launch_bounds__(kTsThreads) void k_ts_in_step(TsDev* T, double* __restrict__ aug, int m,
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_in_step(TsDev* T, double* __r
     }
     const double alpha = rz / g;
     const int slot = na0 + knew;
-    const bool keep = sqrt(rz) >= kTsKeepFloor * T->rn0in && slot < m;
+    const bool keep = sqrt(rz) >= kTsKeepFloor * T->cnin && slot < m;
     double b2 = 0.0;
     for (int k = t; k < m; k += kTsThreads) {
         const double p = T->ph[k], gk = T->gh[k];

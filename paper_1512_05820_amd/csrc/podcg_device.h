@@ -539,7 +539,7 @@ struct TsDev {
     // current solve, knew kept by it so far
     double xinc[kTsCap], cin[kTsCap], muin[kTsCap];
     double gam_aug[kTsCap];
-    double rzin, rn0in, tauin, pad5;
+    double rzin, rn0in, tauin, cnin;   // cnin = ||c||
     int kin, donein, kinmax, naug;
     int naug0, knew, pad6, pad7;
 };
@@ -547,7 +547,8 @@ struct TsDev {
 // Ghat times it at P + (kTsCap + l) kTsCap.
 constexpr size_t kTsAugDoubles = (size_t)2 * kTsCap * kTsCap;
 // Directions formed from a residual below this fraction of their solve's
-// initial residual are not kept (iterative Stage 3).
+// right-hand side (Stage 2: its initial residual) are not kept (iterative
+// Stage 3).
 constexpr double kTsKeepFloor = 1e-6;
 
 // One-workgroup solve of small systems (k_lds.hip): threads per workgroup,

@@ -73,6 +73,8 @@ constexpr double kStage2Floor = 1e-6;   // stage-2 tolerance floor, relative to 
 // Iterative Stage 3 (phi = 1): floor of Stage 2 and of the projection solves,
 // relative to their initial residual (rounding level)
 constexpr double kRoundingFloor = 1e-13;
+// Iterative Stage 3: default projection-solve tolerance relative to the solve's rtol
+constexpr double kInnerMargin = 1e-2;
 constexpr int kJacobiMaxSweeps = 60;
 constexpr int kGramChunks = 64;         // row chunks of the truncation Gram
 
@@ -222,8 +224,9 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     const size_t ld = ctx->ld;
     const int n = (int)ctx->n;
     const int maxit = ctx->opt.maxit;
-    // the projection solves' tolerance: inner_rtol, or the solve's own rtol
-    const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : rtol, kRoundingFloor);
+    // the projection solves' tolerance: inner_rtol, or a margin below the
+    // solve's own rtol (the error a projection leaves in range(Y) stays)
+    const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : kInnerMargin * rtol, kRoundingFloor);
     int* hin = T->h_int + kYMax;    // {steps, done} of the projection solve
     double* u = T->d_AZ;            // Y ph and A Y ph (the truncation's block is free here)
     double* au = T->d_AZ + ld;
@@ -437,7 +440,7 @@ void podcg_ts_default_options(podcg_ts_options* o) {
     o->rho = 0.0;
     o->stage2_factor = 1e-4;
     o->phi = 0;
-    o->inner_maxit = 64;
+    o->inner_maxit = 256;
     o->inner_rtol = 0.0;
 }
 
