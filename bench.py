@@ -104,7 +104,11 @@ def cpu_baseline(cfg, systems: int) -> dict:
     """The oracle as it stands on the first `systems` systems of the sequence
     (all of them by default), on this process's OpenMP threads."""
     import oracle
-    res = oracle.run_sequence(cfg, "aug", steps=systems)
+
+    def progress(rec):
+        log(f"oracle system {rec['j']}: {rec['iters']} iterations, "
+            f"{rec['solve_s'] + rec['pod_s']:.2f} s")
+    res = oracle.run_sequence(cfg, "aug", steps=systems, on_system=progress)
     t = sum(r["solve_s"] + r["pod_s"] for r in res)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     sample = (f"the whole sequence ({systems} systems)" if systems == cfg.steps else

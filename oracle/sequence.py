@@ -18,11 +18,12 @@ import numpy as np
 
 def run_sequence(cfg, method: str = "aug", steps: int | None = None, warm: bool = False,
                  maxit: int = 100000, rank_rtol: float = 1e-12, keep_x: bool = False,
-                 keep_W: bool = False, aug_xbar: str = "zero"):
+                 keep_W: bool = False, aug_xbar: str = "zero", on_system=None):
     """One pass over the sequence.  aug_xbar chooses the augmented solves'
     initial guess: "zero" (xbar_j = 0, the snapshots are the solutions) or
     "prev" (xbar_j = x_{j-1}, the snapshots are the increments).  keep_W adds
-    to each record the basis W_{j+1} built after system j ((n, y) array)."""
+    to each record the basis W_{j+1} built after system j ((n, y) array).
+    on_system, if given, is called with each system's record as it is done."""
     from . import CSR, aug_pcg, idw_weights, plain_pcg, pod_evd
 
     if aug_xbar not in ("zero", "prev"):
@@ -66,5 +67,7 @@ def run_sequence(cfg, method: str = "aug", steps: int | None = None, warm: bool 
         if keep_W and method == "aug":
             rec["W"] = np.zeros((cfg.n, 0)) if W is None else W
         out.append(rec)
+        if on_system is not None:
+            on_system(rec)
         x_prev = x
     return out
