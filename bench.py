@@ -89,7 +89,7 @@ def run_sequence(torch, ctx, cfg, vals_dev, method: str, warm: bool = False):
             x = torch.zeros(n, dtype=torch.float64, device="cuda")
             st = ctx.solve(b, x, cfg.tol)
             ctx.push_snapshot(x)
-            ctx.build_pod()
+            ctx.build_pod(wait=False)
         else:
             x = x_prev.clone() if warm else torch.zeros(n, dtype=torch.float64, device="cuda")
             st = ctx.solve_plain(b, x, cfg.tol)
@@ -172,7 +172,7 @@ def config1_sequences(torch, P, cfg, reps: int) -> dict:
                     if method == "aug":
                         st = ctx.solve(rhs[j], x, cfg.tol)
                         ctx.push_snapshot(x)
-                        ctx.build_pod()
+                        ctx.build_pod(wait=False)
                     else:
                         st = ctx.solve_plain(rhs[j], x, cfg.tol)
                     if st.status not in (0, 2):
@@ -276,7 +276,7 @@ def bench_config3(args):
                         st = (ctx.solve if method == "aug" else ctx.solve_plain)(rhs[j], x, cfg.tol)
                         if method == "aug":
                             ctx.push_snapshot(x)
-                            ctx.build_pod()
+                            ctx.build_pod(wait=False)
                         if st.status not in (0, 2):
                             raise RuntimeError(f"{variant}/{precision}/{method} system {j + 1}: {st.status}")
                         sts.append(st.as_dict())
@@ -364,7 +364,7 @@ def bench_config4(args):
             if not plain:
                 for k, x in zip(ctxs, xs):
                     k.push_snapshot(x)
-                    k.build_pod()
+                    k.build_pod(wait=False)
             sts.append([s.as_dict() for s in st])
         return sts
 
@@ -379,7 +379,7 @@ def bench_config4(args):
                 if st.status not in (0, 2):
                     raise RuntimeError(f"member {i} system {j + 1}: {st.status}")
                 k.push_snapshot(x)
-                k.build_pod()
+                k.build_pod(wait=False)
                 sts[j][i] = st.as_dict()
         return sts
 

@@ -156,8 +156,12 @@ int podcg_reset_snapshots(podcg_ctx* ctx);
  * symmetric eigen-decomposition, dimension y = #{lam_i > rank_rtol lam_1}
  * capped by rank_max and the energy criterion, W = S diag(w) V_y Sigma_y^{-1}
  * (so W^T A W = I for the current A).  *rank_out (host, may be NULL)
- * receives y.  With no snapshots the basis becomes empty.
- * Errors: NO_MATRIX, HIP. */
+ * receives y, which makes the call wait for the GPU.  With rank_out NULL the
+ * call only enqueues the work on the context's stream (the basis is formed
+ * with the rank chosen on the device) and returns; the next call that needs
+ * the rank on the host (a solve, the basis or spectrum getters, set_basis,
+ * another build) waits for it then.  With no snapshots the basis becomes
+ * empty.  Errors: NO_MATRIX, HIP. */
 int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out);
 
 /* Replace the augmenting basis with W (device, n x y, column-major with

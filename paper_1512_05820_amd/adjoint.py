@@ -64,7 +64,7 @@ class RecycledSequence(torch.autograd.Function):
                 if st.status not in (0, 2):
                     raise RuntimeError(f"forward solve {j} failed with status {st.status}")
                 solver.push_snapshot(x)
-                solver.build_pod()
+                solver.build_pod(wait=False)
                 xs.append(x)
                 qs.append(spec.output(j, x))
                 stats.append(st.as_dict())
@@ -139,7 +139,7 @@ class RecycledSequence(torch.autograd.Function):
                         if mode == "adjoint":
                             # metric A_j for the basis of system j-1
                             adj.push_snapshot(lam)
-                            adj.build_pod()
+                            adj.build_pod(wait=False)
                     vbar = adj.pattern_outer(lam, xj, -1.0, torch.empty_like(vals))
                 with torch.enable_grad():
                     p_req = [p for p in params if p.requires_grad]

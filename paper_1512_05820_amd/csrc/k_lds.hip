@@ -12,8 +12,12 @@
 // product A p gathers across rows, is shared through LDS.  Reductions are
 // wavefront butterflies followed by a fixed-order sum of the 16 wave
 // partials, so results are bitwise repeatable.  Per iteration: one gathered
-// product, two reductions and four workgroup barriers, and no memory round
-// trip at all (the matrix rows stay in registers).
+// product, two reductions and three workgroup barriers, and no memory round
+// trip at all (the matrix rows stay in registers).  Wave sums use DPP row
+// operations (VALU lane moves) rather than LDS permutes, and every wavefront
+// finishes each reduction itself from the 16 wave partials (same values in
+// the same order, so every wave reaches the same decisions) instead of waiting
+// behind a barrier for one wave to do it.
 //
 // The basis products (A W, W^T A W and its factor, Alg. 2) come from the
 // setup kernels of the multi-kernel path, launched ahead of this kernel on the
@@ -25,13 +29,43 @@ namespace podcg {
 
 constexpr int kLdsWaves = kLdsThreads / kWave;   // 16
 
-// Wave sums of NV values, stored by lane 0 of each wave at red[wave * NV + k].
+// One DPP lane move of a double (two 32-bit moves); lanes the row and bank
+// masks leave out, or whose source lane does not exist, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order; the total lands in lane
+// 63.  Within each row of 16 lanes: swap neighbours, swap pairs, rotate by 4
+// and by 8 (every lane then holds its row's sum); then lane 15 of rows 0 and 2
+// is added into rows 1 and 3, and lane 31 into rows 2 and 3.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+    v += dpp_move<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x124, 0xf>(v);   // row_ror 4
+    v += dpp_move<0x128, 0xf>(v);   // row_ror 8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast 15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast 31 into rows 2 and 3
+    return v;
+}
+
+// Lane `l` (wave-uniform) of v, as a scalar.
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave sums of NV values, stored by lane 63 of each wave at red[wave * NV + k].
 template <int NV>
 __device__ __forceinline__ void lds_wave_partials(double (&v)[NV], double* red) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0) {
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum_to_last(v[k]);
+    if (lane == kWave - 1) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
     }
@@ -170,8 +204,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
     }
     const double tol2 = sh.tol2;
     int iters = 0;
-    double rr_last = 0.0, alpha = 0.0, gamma = 0.0;
-    if (sh.state == kRunning) {
+    double rr_last = 0.0, alpha = 0.0, gamma = 0.0, rho_last = 0.0, beta_last = 0.0;
+    int state = sh.state, status = sh.status;
+    if (state == kRunning) {
         // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r,
         // sums (r, z), (r, r), c = (A W)^T z; mu = G^{-1} c
         {
@@ -225,8 +260,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
             for (int k = 0; k < YB; ++k) s -= wr[k] * (k < y ? smu[k] : 0.0);
             pi = s;
         }
-        // ---- the loop of Alg. 1
-        while (sh.state == kRunning) {
+        state = sh.state;
+        status = sh.status;
+        // ---- the loop of Alg. 1; every thread keeps the same state, so no
+        // barrier is needed to share the decisions
+        while (state == kRunning) {
             sp[row] = pi;
             __syncthreads();
             // q = A p, gamma = (A p, p)
@@ -237,11 +275,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
             gamma = redg[0];
 #pragma unroll
             for (int w = 1; w < kLdsWaves; ++w) gamma += redg[w];
-            if (!(gamma > 0.0 && is_finite(gamma))) {   // gamma is the same in every thread
-                if (threadIdx.x == 0) {
-                    sh.state = kFailed;
-                    sh.status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
-                }
+            if (!(gamma > 0.0 && is_finite(gamma))) {
+                state = kFailed;
+                status = is_finite(gamma) ? kStNotSpd : kStNonfinite;
                 break;
             }
             alpha = rho / gamma;
@@ -259,36 +295,46 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
             }
             __syncthreads();
             ++iters;
-            if (wid == 0) {
-                const double tot = lds_total<NV>(red);
-                lds_project<YB>(tot, sginv, y, smu);   // mu = G^{-1} (A W)^T z
-                const double rz = __shfl(tot, 0, kWave), rr = __shfl(tot, 1, kWave);
-                if (lane == 0) {
-                    sh.rz = rz;
-                    sh.rr = rr;
-                    if (!is_finite(rr) || !is_finite(rz)) {
-                        sh.state = kFailed;
-                        sh.status = kStNonfinite;
-                    } else if (rr <= tol2 || iters >= maxit) {
-                        sh.state = kFinished;
-                        sh.status = rr <= tol2 ? kStOk : kStNotConverged;
-                    }
+            // every wave sums the 16 wave partials itself: lane t < NV holds
+            // total t, read back as scalars
+            double tot = 0.0;
+            if (lane < NV) {
+                tot = red[lane];
+#pragma unroll
+                for (int w = 1; w < kLdsWaves; ++w) tot += red[w * NV + lane];
+            }
+            const double rz = lane_value(tot, 0), rr = lane_value(tot, 1);
+            rr_last = rr;
+            if (!is_finite(rr) || !is_finite(rz)) {
+                state = kFailed;
+                status = kStNonfinite;
+                break;
+            }
+            if (rr <= tol2 || iters >= maxit) {
+                state = kFinished;
+                status = rr <= tol2 ? kStOk : kStNotConverged;
+                break;
+            }
+            // mu = G^{-1} (A W)^T z: lane k < y forms mu_k
+            double muk = 0.0;
+            {
+                const int kl = lane < YB ? lane : 0;
+#pragma unroll
+                for (int j = 0; j < YB; ++j) {
+                    const double cj = lane_value(tot, 2 + j);
+                    if (lane < y && j < y) muk += sginv[kl * YB + j] * cj;
                 }
             }
-            __syncthreads();
-            rr_last = sh.rr;
-            if (sh.state != kRunning) break;
             // p = z + beta p - W mu, beta = (r', z') / (r, z)
-            const double rz = sh.rz;
             const double beta = rz / rho;
             rho = rz;
+            beta_last = beta;
             double s = zi + beta * pi;
 #pragma unroll
-            for (int k = 0; k < YB; ++k) s -= wr[k] * (k < y ? smu[k] : 0.0);
+            for (int k = 0; k < YB; ++k) s -= wr[k] * (k < y ? lane_value(muk, k) : 0.0);
             pi = s;
-            if (threadIdx.x == 0) sh.beta = beta;
         }
-        if (threadIdx.x == 0) sh.rho = rho;
+        rho_last = rho;
     }
     // ---- the true residual ||b - A x|| and the solution
     __syncthreads();
@@ -308,13 +354,13 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
         st->true_rr = trr;
         st->iter = iters;
         st->rr = rr_last;
-        st->status = sh.status;
-        st->done = sh.state == kFailed ? kFailed : kFinished;
+        st->status = status;
+        st->done = state == kFailed ? kFailed : kFinished;
         st->stop = iters;
         st->y = y;
-        st->rho = sh.rho;
+        st->rho = rho_last;
         st->alpha = alpha;
-        st->beta = sh.beta;
+        st->beta = beta_last;
         st->gamma = gamma;
     }
 }

@@ -611,12 +611,15 @@ __global__ __launch_bounds__(kBlock) void k_implicit_finish(DevBufs B, int y, do
 }
 
 // W(:, i) = sum_k S(:, k) T(k, i) for i < y, k < count (Eq. (podAlgebraicDefinition)
-// with T = diag(w) V_y Sigma_y^{-1}).
+// with T = diag(w) V_y Sigma_y^{-1}).  y is the rank the eigen-solve wrote to
+// *ydev, at most ymax.
 template <int KB>
 __global__ __launch_bounds__(kBlock) void k_pod_form(int n, size_t ld, const double* __restrict__ S,
-                                                     int count, const double* __restrict__ T, int y,
-                                                     double* __restrict__ W) {
+                                                     int count, const double* __restrict__ T, int ymax,
+                                                     const int* __restrict__ ydev, double* __restrict__ W) {
     __shared__ double t[kYMax * kYMax];
+    const int yd = *ydev;
+    const int y = yd < 0 ? 0 : (yd < ymax ? yd : ymax);
     for (int e = threadIdx.x; e < count * y; e += kBlock) t[e] = T[e];
     __syncthreads();
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -885,12 +888,12 @@ hipError_t launch_stage1_apply(const DevBufs& B, int yb, int y, double* x, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
-                           double* W, hipStream_t s) {
-    if (y < 1) return hipSuccess;
+hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int ymax,
+                           const int* ydev, double* W, hipStream_t s) {
+    if (ymax < 1) return hipSuccess;
     dim3 g(vec_grid(n)), t(kBlock);
     switch (basis_tier(count)) {
-#define CASE(K) case K: hipLaunchKernelGGL((k_pod_form<K>), g, t, 0, s, n, ld, S, count, T, y, W); break;
+#define CASE(K) case K: hipLaunchKernelGGL((k_pod_form<K>), g, t, 0, s, n, ld, S, count, T, ymax, ydev, W); break;
         PODCG_POS_TIERS(CASE)
 #undef CASE
         default: return hipErrorInvalidValue;

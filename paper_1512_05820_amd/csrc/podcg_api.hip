@@ -52,6 +52,13 @@ DevBufs bufs(podcg_ctx* ctx) {
 
 void sync(podcg_ctx* ctx) { HIPCHECK(hipStreamSynchronize(ctx->stream)); }
 
+void pod_resolve(podcg_ctx* ctx) {
+    if (!ctx->y_pending) return;
+    HIPCHECK(hipEventSynchronize(ctx->ev_pod));
+    ctx->y = *ctx->h_rank;
+    ctx->y_pending = false;
+}
+
 void poll(podcg_ctx* ctx) {
     HIPCHECK(hipMemcpyAsync(ctx->h_poll, ctx->d_st, sizeof(PollBlock), hipMemcpyDeviceToHost,
                             ctx->stream));
@@ -253,6 +260,7 @@ int solve_lds(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_sta
 
 int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_stats* st, bool plain) {
     if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+    pod_resolve(ctx);
     if (!b || !x || !(rtol >= 0.0)) fail(ctx, PODCG_ERR_INVALID_ARG, "bad solve arguments");
     podcg_stats S{};
     float ms = 0.f;
@@ -355,6 +363,8 @@ void release(podcg_ctx* ctx) {
     if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
     if (ctx->h_int) (void)hipHostFree(ctx->h_int);
     if (ctx->h_dbl) (void)hipHostFree(ctx->h_dbl);
+    if (ctx->h_rank) (void)hipHostFree(ctx->h_rank);
+    if (ctx->ev_pod) (void)hipEventDestroy(ctx->ev_pod);
     hipEvent_t evs[] = {ctx->ev_a, ctx->ev_b, ctx->ev_c, ctx->ev_d};
     for (hipEvent_t e : evs)
         if (e) (void)hipEventDestroy(e);
@@ -478,6 +488,8 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         HIPCHECK(hipHostMalloc((void**)&ctx->h_poll, sizeof(PollBlock), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_int, 64 * sizeof(int), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_dbl, 64 * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_rank, sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipEventCreateWithFlags(&ctx->ev_pod, hipEventDisableTiming));
         HIPCHECK(hipEventCreate(&ctx->ev_a));
         HIPCHECK(hipEventCreate(&ctx->ev_b));
         HIPCHECK(hipEventCreate(&ctx->ev_c));
@@ -608,6 +620,7 @@ int podcg_reset_snapshots(podcg_ctx* ctx) {
 int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out) {
     return guarded(ctx, [&]() {
         if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
+        pod_resolve(ctx);
         const int count = ctx->count;
         if (count == 0 || ctx->opt.rank_max == 0) {
             ctx->y = 0;
@@ -627,20 +640,25 @@ int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out) {
         HIPCHECK(launch_spmm_gram(B, count, ctx->d_S, nullptr, false, ctx->d_Gs, s));
         HIPCHECK(launch_pod_coeffs(ctx->d_Gs, count, w, ctx->opt.rank_max, ctx->opt.rank_rtol,
                                    ctx->opt.energy, ctx->d_T, ctx->d_lamS, ctx->d_yout, s));
-        HIPCHECK(hipMemcpyAsync(ctx->h_int, ctx->d_yout, sizeof(int), hipMemcpyDeviceToHost, s));
-        sync(ctx);
-        const int y = ctx->h_int[0];
-        HIPCHECK(launch_pod_form((int)ctx->n, ctx->ld, ctx->d_S, count, ctx->d_T, y, ctx->d_W, s));
-        ctx->y = y;
+        // W = S T with the rank the eigen-solve chose, read on the device
+        HIPCHECK(launch_pod_form((int)ctx->n, ctx->ld, ctx->d_S, count, ctx->d_T, std::min(count, ctx->opt.rank_max),
+                                 ctx->d_yout, ctx->d_W, s));
+        HIPCHECK(hipMemcpyAsync(ctx->h_rank, ctx->d_yout, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipEventRecord(ctx->ev_pod, s));
+        ctx->y_pending = true;
         ctx->pod_count = count;
         ctx->setup_valid = false;
-        if (rank_out) *rank_out = y;
+        if (rank_out) {
+            pod_resolve(ctx);
+            *rank_out = ctx->y;
+        }
         return PODCG_OK;
     });
 }
 
 int podcg_set_basis(podcg_ctx* ctx, const double* W, int32_t y) {
     return guarded(ctx, [&]() {
+        pod_resolve(ctx);
         if (y < 0 || y > ctx->opt.rank_max || (y > 0 && !W))
             fail(ctx, PODCG_ERR_INVALID_ARG, "basis dimension out of range");
         for (int k = 0; k < y; ++k)
@@ -654,6 +672,7 @@ int podcg_set_basis(podcg_ctx* ctx, const double* W, int32_t y) {
 
 int podcg_get_basis(podcg_ctx* ctx, double* W, int32_t* rank) {
     return guarded(ctx, [&]() {
+        pod_resolve(ctx);
         if (rank) *rank = ctx->y;
         if (ctx->y > 0 && !W) fail(ctx, PODCG_ERR_INVALID_ARG, "null output");
         for (int k = 0; k < ctx->y; ++k)
@@ -666,6 +685,7 @@ int podcg_get_basis(podcg_ctx* ctx, double* W, int32_t* rank) {
 
 int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank) {
     return guarded(ctx, [&]() {
+        pod_resolve(ctx);
         if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
         if (!ctx->setup_valid) setup_basis(ctx);
         const int y = ctx->y_kept;
@@ -687,6 +707,7 @@ int podcg_get_reduced(podcg_ctx* ctx, double* G, double* Ginv, int32_t* rank) {
 
 int podcg_get_pod_spectrum(podcg_ctx* ctx, double* lam, int32_t* count) {
     return guarded(ctx, [&]() {
+        pod_resolve(ctx);
         if (count) *count = ctx->pod_count;
         if (lam && ctx->pod_count > 0) {
             HIPCHECK(hipMemcpyAsync(lam, ctx->d_lamS, sizeof(double) * ctx->pod_count, hipMemcpyDeviceToHost,

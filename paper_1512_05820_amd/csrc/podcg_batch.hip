@@ -238,6 +238,7 @@ int batch_yb(podcg_batch* ctx, bool plain) {
 int batch_solve_impl(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
                      bool plain, podcg_stats* stats) {
     check_solve_args(ctx, b, x, rtol);
+    for (podcg_ctx* c : ctx->members) pod_resolve(c);
     if (!rtol) fail(ctx, PODCG_ERR_INVALID_ARG, "null tolerance array");
     const int count = (int)ctx->members.size();
     hipStream_t s = ctx->stream;
@@ -448,6 +449,7 @@ int podcg_batch_tune(podcg_batch* ctx, const double* const* b, double* const* x,
     return guarded(ctx, [&]() {
         check_solve_args(ctx, b, x, nullptr);
         if (iters < 1 || iters > 100000) fail(ctx, PODCG_ERR_INVALID_ARG, "bad tuning length");
+        for (podcg_ctx* c : ctx->members) pod_resolve(c);
         const int count = (int)ctx->members.size();
         std::vector<double> zero(count, 0.0);
         std::vector<int> maxit(count, iters);

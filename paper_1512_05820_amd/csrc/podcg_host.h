@@ -68,6 +68,11 @@ struct podcg_ctx {
     double *d_S = nullptr, *d_Gs = nullptr, *d_T = nullptr, *d_lamS = nullptr;
     int head = 0, count = 0, pod_count = 0;
     int* d_yout = nullptr;
+    // a POD built without waiting: its rank arrives in h_rank (pinned) when
+    // ev_pod completes; calls that need the rank on the host wait for it first
+    bool y_pending = false;
+    int* h_rank = nullptr;
+    hipEvent_t ev_pod = nullptr;
 
     // scalar state and scratch
     podcg::DevState* d_st = nullptr;
@@ -137,6 +142,8 @@ void sync(podcg_ctx* ctx);
 void poll(podcg_ctx* ctx);
 // A W, G = W^T A W, its factor and inverse, the kept rank (synchronises).
 void setup_basis(podcg_ctx* ctx);
+// Takes the rank of a POD built without waiting (no-op when none is pending).
+void pod_resolve(podcg_ctx* ctx);
 int fail_code(podcg_ctx* ctx, const podcg::PollBlock& P);
 void record(podcg_ctx* ctx, hipEvent_t e);
 // Launch loop iterations in batches until the device reports that the solve

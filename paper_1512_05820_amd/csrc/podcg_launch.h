@@ -116,8 +116,8 @@ hipError_t launch_stage1_mixed(const DevBufs& B, int yb, int y, double* x64, con
                                float* r32, float* z32, const double* W, const double* AW,
                                const float* AW32, double inner_rtol, hipStream_t s);
 hipError_t launch_to_float(const double* src, float* dst, size_t n, hipStream_t s);
-hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int y,
-                           double* W, hipStream_t s);
+hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const double* T, int ymax,
+                           const int* ydev, double* W, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, double sc,
                         hipStream_t s);

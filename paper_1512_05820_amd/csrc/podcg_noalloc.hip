@@ -99,6 +99,7 @@ extern "C" int podcg_solve_noalloc(podcg_ctx* ctx, const double* b, double* x, d
     return guarded(ctx, [&]() {
         if (!ctx->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "no matrix set");
         if (!b || !x || !(rtol >= 0.0)) fail(ctx, PODCG_ERR_INVALID_ARG, "bad solve arguments");
+        pod_resolve(ctx);
         const int y = ctx->y;
         if (ctx->opt.precision != 0 || ctx->max_width < 0 || ctx->max_width > kLdsWidth ||
             lds_tier((int)ctx->n, y) < 0)

@@ -89,7 +89,12 @@ class PodCG:
     def push_snapshot(self, s: torch.Tensor):
         self._check(self._L.podcg_push_snapshot(self._h, _ptr(s, torch.float64)))
 
-    def build_pod(self) -> int:
+    def build_pod(self, wait: bool = True) -> int | None:
+        """Build the next basis; returns its rank, or None with wait=False (the
+        call then returns without waiting for the GPU)."""
+        if not wait:
+            self._check(self._L.podcg_build_pod(self._h, None))
+            return None
         y = C.c_int32()
         self._check(self._L.podcg_build_pod(self._h, C.byref(y)))
         return y.value

@@ -375,7 +375,7 @@ def test_lockstep_config2_small(P, N, projection):
     assert _relerr(xg, xo) <= 1e-10
 
 
-def _gpu_sequence(P, cfg, steps, method="aug", warm=False, projection="implicit"):
+def _gpu_sequence(P, cfg, steps, method="aug", warm=False, projection="implicit", wait=True):
     ctx = _ctx(P, cfg.n, omega=cfg.omega, rank_max=cfg.rank, projection=projection)
     rowptr, colind = _dev(cfg.rowptr, torch.int32), _dev(cfg.colind, torch.int32)
     out = []
@@ -396,10 +396,25 @@ def _gpu_sequence(P, cfg, steps, method="aug", warm=False, projection="implicit"
         xh = _host(x)
         if method == "aug":
             ctx.push_snapshot(_dev(xh - xbar))
-            ctx.build_pod()
+            ctx.build_pod(wait=wait)
         out.append((st.as_dict(), xh, b, vals))
         x_prev = xh
     return out
+
+
+@pytest.mark.parametrize("which", ["c1", "c2_small"])
+def test_pod_build_without_waiting_matches(P, which):
+    """build_pod with no rank output returns without waiting for the GPU; the
+    next solve takes the rank then.  Same kernels in the same order, so the
+    sequence must match the waiting build bit for bit (config 1 runs the
+    one-workgroup solve, the 26^3 family the multi-kernel loop)."""
+    cfg = config1() if which == "c1" else config2(N=26, steps=6)
+    a = _gpu_sequence(P, cfg, cfg.steps, wait=True)
+    b = _gpu_sequence(P, cfg, cfg.steps, wait=False)
+    for (sa, xa, _, _), (sb, xb, _, _) in zip(a, b):
+        assert sa["iters"] == sb["iters"] and sa["rank"] == sb["rank"]
+        assert np.array_equal(xa, xb)
+    assert max(s["rank"] for s, _, _, _ in b) > 0
 
 
 @pytest.mark.parametrize("which,projection", [("c1", "implicit"), ("c1_r2", "implicit"),
