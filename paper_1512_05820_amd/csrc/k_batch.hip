@@ -378,6 +378,281 @@ hipError_t launch_batch_dir(int yb, const BatchMember* mem, const BatchItem* ite
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ batched Stage 1
+// The single-sequence Stage 1 (k_resid, k_stage1_apply and the first
+// direction) for all members in three launches over the work lists; each
+// member's sums are reduced by its last item, as in the loop kernels.
+
+// rbar = b - A xbar with (b, b), (rbar, rbar), W^T rbar per member; the last
+// item sets ||b||^2, the absolute tolerance and what = G^{-1} W^T rbar (Alg. 2).
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_resid(const BatchMember* __restrict__ mem,
+                                                        const BatchSetup* __restrict__ su,
+                                                        const BatchItem* __restrict__ items, int nitems) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        DevState* st = M.B.st;
+        if (st->done != kRunning) continue;
+        const double* __restrict__ b = su[it.member].b;
+        const double* __restrict__ W = M.W;
+        const size_t ld = M.B.ld;
+        const int y = M.y;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+        for (int s = it.begin + wid; s < it.end; s += kWavesPerBlock) {
+            const double ax = sell_row<double>(M.B, M.B.vals, s, lane, M.x);
+            const int row = s * kSlice + lane;
+            if (row < M.B.n) {
+                const double bi = b[row];
+                const double ri = bi - ax;
+                M.r[row] = ri;
+                v[0] += bi * bi;
+                v[1] += ri * ri;
+                if (YB > 0 && y > 0) {
+#pragma unroll
+                    for (int k = 0; k < YB; ++k) {
+                        const double wk = W[(size_t)bcol(k, y) * ld + row];
+                        if (k < y) v[2 + k] += wk * ri;
+                    }
+                }
+            }
+        }
+        if (member_sum_last<NV>(v, M.B.part, M.B.counter, M.spmv_items, it.local, lds)) {
+            if (threadIdx.x == 0) {
+                const double bb = lds[0];
+                st->bnorm2 = bb;
+                st->true_rr = lds[1];
+                st->tol2 = st->tol2 * bb;
+                if (!is_finite(bb) || !is_finite(lds[1])) {
+                    st->status = kStNonfinite;
+                    st->done = kFailed;
+                    st->stop = 0;
+                }
+            }
+            if ((int)threadIdx.x < y) {
+                double sum = 0.0;
+                for (int j = 0; j < y; ++j) sum += M.B.Ginv[threadIdx.x * y + j] * lds[2 + j];
+                st->what[threadIdx.x] = sum;
+            }
+        }
+        __syncthreads();   // lds is reused by the next item
+    }
+}
+
+// x <- xbar + W what, r <- rbar - (A W) what, z = M^{-1} r, with (r, z),
+// (r, r), c = (A W)^T z per member; the last item sets mu = G^{-1} c, tests
+// the Stage-1 residual, and for the implicit form starts nu = mu, a = c,
+// xi = 0.  A member in the implicit form gets its first direction pt = z here.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_stage1(const BatchMember* __restrict__ mem,
+                                                         const BatchItem* __restrict__ items, int nitems) {
+    constexpr int NV = 2 + YB;
+    __shared__ double lds[kWavesPerBlock * NV + NV + 1];
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        DevState* st = M.B.st;
+        if (st->done != kRunning) continue;
+        const int y = M.y;
+        const bool imp = M.implicit != 0;
+        const size_t ld = M.B.ld;
+        double what[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int k = 0; k < YB; ++k) what[k] = k < y ? st->what[k] : 0.0;
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
+            double ri = M.r[i];
+            if (YB > 0 && y > 0) {
+                double wx = 0.0, awx = 0.0;
+#pragma unroll
+                for (int k = 0; k < YB; ++k) {
+                    const int kc = bcol(k, y);
+                    wx += M.W[(size_t)kc * ld + i] * what[k];
+                    awx += M.AW[(size_t)kc * ld + i] * what[k];
+                }
+                M.x[i] += wx;
+                ri -= awx;
+                M.r[i] = ri;
+            }
+            const double zi = M.B.dinv[i] * ri;
+            M.z[i] = zi;
+            if (imp) M.p[i] = zi;
+            v[0] += ri * zi;
+            v[1] += ri * ri;
+            if (YB > 0 && y > 0) {
+#pragma unroll
+                for (int k = 0; k < YB; ++k) {
+                    const double a = M.AW[(size_t)bcol(k, y) * ld + i];
+                    if (k < y) v[2 + k] += a * zi;
+                }
+            }
+        }
+        if (member_sum_last<NV>(v, M.B.part, M.B.counter, M.vec_items, it.local, lds)) {
+            if (threadIdx.x == 0) {
+                const double rz = lds[0], rr = lds[1];
+                st->rho = rz;
+                st->lrho[0] = rz;
+                st->rr = rr;
+                st->rr0 = rr;
+                if (!is_finite(rr) || !is_finite(rz)) {
+                    st->status = kStNonfinite;
+                    st->done = kFailed;
+                    st->stop = 0;
+                } else if (rr <= st->tol2) {
+                    st->status = kStOk;
+                    st->done = kFinished;
+                    st->stop = 0;
+                } else if (st->maxit <= 0) {
+                    st->status = kStNotConverged;
+                    st->done = kFinished;
+                    st->stop = 0;
+                }
+            }
+            if ((int)threadIdx.x < kWave) {
+                const int k = threadIdx.x;
+                double prod = 0.0;
+                if (k < y) {
+                    double sum = 0.0;
+                    for (int j = 0; j < y; ++j) sum += M.B.Ginv[k * y + j] * lds[2 + j];
+                    st->mu[k] = sum;
+                    if (imp) {
+                        st->lnu[0][k] = sum;
+                        st->lacc[0][k] = lds[2 + k];
+                        st->xi[k] = 0.0;
+                        prod = sum * lds[2 + k];
+                    }
+                }
+                if (imp) {
+                    prod = wave_sum(prod);
+                    if (k == 0) st->lgcorr[0] = prod;
+                }
+            }
+        }
+        __syncthreads();   // lds is reused by the next item
+    }
+}
+
+// First direction of the members in the explicit form: p = z - W mu.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_dir_init(const BatchMember* __restrict__ mem,
+                                                           const BatchItem* __restrict__ items, int nitems) {
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        const DevState* st = M.B.st;
+        if (M.implicit || st->stop <= 0 || st->done != kRunning) continue;
+        const int y = M.y;
+        const size_t ld = M.B.ld;
+        double mu[YB > 0 ? YB : 1];
+#pragma unroll
+        for (int k = 0; k < YB; ++k) mu[k] = k < y ? st->mu[k] : 0.0;
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
+            double sum = M.z[i];
+            if (YB > 0 && y > 0) {
+#pragma unroll
+                for (int k = 0; k < YB; ++k) sum -= M.W[(size_t)bcol(k, y) * ld + i] * mu[k];
+            }
+            M.p[i] = sum;
+        }
+    }
+}
+
+// The tiled copy of A W (element (i, j) at (i / 64) 64 y + 64 j + i mod 64)
+// that the single-sequence implicit update reads, for the members whose basis
+// products were just formed; the member's last item also covers the padding
+// rows up to the leading dimension.
+template <int YB>
+__global__ __launch_bounds__(kBlock) void k_batch_tile_aw(const BatchMember* __restrict__ mem,
+                                                          const BatchSetup* __restrict__ su,
+                                                          const BatchItem* __restrict__ items, int nitems) {
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchSetup& S = su[it.member];
+        const BatchMember& M = mem[it.member];
+        const int y = M.y;
+        if (!S.setup || !S.AWt || y < 1) continue;
+        const size_t ld = M.B.ld;
+        const int end = it.end == M.B.n ? (int)ld : it.end;
+        for (int i = it.begin + (int)threadIdx.x; i < end; i += kBlock) {
+            const size_t tb = (size_t)(i / kSlice) * kSlice * y + (i % kSlice);
+#pragma unroll
+            for (int k = 0; k < YB; ++k)
+                if (k < y) S.AWt[tb + (size_t)k * kSlice] = M.AW[(size_t)k * ld + i];
+        }
+    }
+}
+
+hipError_t launch_batch_resid(int yb, const BatchMember* mem, const BatchSetup* su, const BatchItem* items,
+                              int nitems, int grid, hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    const dim3 g(grid < nitems ? grid : nitems), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_resid<T>), g, t, 0, s, mem, su, items, nitems); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage1(int yb, const BatchMember* mem, const BatchItem* items, int nitems, int grid,
+                               hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    const dim3 g(grid < nitems ? grid : nitems), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_stage1<T>), g, t, 0, s, mem, items, nitems); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_dir_init(int yb, const BatchMember* mem, const BatchItem* items, int nitems, int grid,
+                                 hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    const dim3 g(grid < nitems ? grid : nitems), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_dir_init<T>), g, t, 0, s, mem, items, nitems); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile_aw(int yb, const BatchMember* mem, const BatchSetup* su, const BatchItem* items,
+                                int nitems, int grid, hipStream_t s) {
+    if (nitems < 1 || yb < 1) return hipSuccess;
+    const dim3 g(grid < nitems ? grid : nitems), t(kBlock);
+    switch (yb) {
+#define CASE(T) case T: hipLaunchKernelGGL((k_batch_tile_aw<T>), g, t, 0, s, mem, su, items, nitems); break;
+        PODCG_BATCH_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_gather(const BatchMember* mem, int count, PollBlock* out, hipStream_t s) {
     if (count < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_gather, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, mem,

@@ -173,8 +173,10 @@ __device__ void block_jacobi(double* a, double* V, double* lam, int m) {
 // <= 1e-14 max_i G_ii, and form Ginv = R^{-1} R^{-T} on the kept leading
 // block (row-major, stride = kept rank).  st->y receives the kept rank and
 // lam the eigenvalues of the kept block (for its condition number).
-__global__ __launch_bounds__(kBlock) void k_reduced_factor(double* G, int m, double* R, double* Ginv,
-                                                          double* lam, DevState* st) {
+// The body, for one workgroup; `report` (if not null) receives the kept rank
+// and the largest and smallest kept eigenvalue.
+__device__ void reduced_factor(double* G, int m, double* R, double* Ginv, double* lam, DevState* st,
+                               double* report) {
     __shared__ double g[kYMax * kLd], rr[kYMax * kLd], ri[kYMax * kLd], v[kYMax * kLd];
     __shared__ double lm[kYMax];
     __shared__ int kept_s;
@@ -230,7 +232,19 @@ __global__ __launch_bounds__(kBlock) void k_reduced_factor(double* G, int m, dou
     __syncthreads();
     if (y > 0) block_jacobi(v, ri, lm, y);
     if (tid < y) lam[tid] = lm[tid];
-    if (tid == 0) st->y = y;
+    if (tid == 0) {
+        st->y = y;
+        if (report) {
+            report[0] = (double)y;
+            report[1] = y > 0 ? lm[0] : 0.0;
+            report[2] = y > 0 ? lm[y - 1] : 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduced_factor(double* G, int m, double* R, double* Ginv,
+                                                          double* lam, DevState* st) {
+    reduced_factor(G, m, R, Ginv, lam, st, nullptr);
 }
 
 struct Weights {
@@ -283,6 +297,22 @@ __global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int cou
         T[e] = wt.w[k] * V[k * kLd + i] / sqrt(lam[i]);
     }
     if (tid < m) lam_out[tid] = lam[tid];
+}
+
+// Batched: workgroup b factors member list[b] (its G of ynom columns).
+__global__ __launch_bounds__(kBlock) void k_batch_reduced_factor(const BatchMember* __restrict__ mem,
+                                                                const BatchSetup* __restrict__ su,
+                                                                const int* __restrict__ list) {
+    const int m = list[blockIdx.x];
+    const BatchSetup& S = su[m];
+    reduced_factor(S.G, S.ynom, S.R, S.Ginv, S.lamG, mem[m].B.st, S.report);
+}
+
+hipError_t launch_batch_reduced_factor(const BatchMember* mem, const BatchSetup* su, const int* list, int nlist,
+                                       hipStream_t s) {
+    if (nlist < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_reduced_factor, dim3(nlist), dim3(kBlock), 0, s, mem, su, list);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduced_factor(double* G, int m, double* R, double* Ginv, double* lam,

@@ -673,8 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) c[n - 1] = a[n - 1] + s * b[n - 1];
 }
 
-__global__ void k_state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
-    if (threadIdx.x != 0) return;
+__device__ void state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
     st->implicit = implicit;
     st->stop = maxit;
     for (int h = 0; h < 2; ++h) {
@@ -691,6 +690,17 @@ __global__ void k_state_init(DevState* st, int maxit, double tol2, int y, int im
     st->tol2 = tol2;
     st->rho = st->alpha = st->beta = st->gamma = 0.0;
     for (int k = 0; k < kYMax; ++k) st->mu[k] = st->what[k] = 0.0;
+}
+
+__global__ void k_state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
+    if (threadIdx.x == 0) state_init(st, maxit, tol2, y, implicit);
+}
+
+// Batched: thread m initialises member m.
+__global__ void k_batch_state_init(const BatchMember* __restrict__ mem, const BatchSetup* __restrict__ su,
+                                   int count) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < count) state_init(mem[m].B.st, su[m].maxit, su[m].tol2, mem[m].y, mem[m].implicit);
 }
 
 // Stage 1 of one refinement step of the mixed-precision solve.  In FP64:
@@ -925,6 +935,11 @@ hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, d
     if (g > 512) g = 512;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_triad, dim3((int)g), dim3(kBlock), 0, s, a, b, c, n, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_state_init(const BatchMember* mem, const BatchSetup* su, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_state_init, dim3((count + 63) / 64), dim3(64), 0, s, mem, su, count);
     return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
 // Batched solves of many independent sequences (the podcg_batch_* calls of
 // include/podcg.h).
 //
-// A batch groups existing contexts (its members).  Per solve, every member
-// gets its own basis setup and Stage 1 (Alg. 2) with the single-sequence
-// kernels; then the loop of augmented PCG (Alg. 1) runs for all members
+// A batch groups existing contexts (its members).  Per solve, the basis
+// setup of the members whose basis changed and Stage 1 (Alg. 2) of every
+// member run as work-list launches over all members (one synchronisation for
+// the kept ranks); then the loop of augmented PCG (Alg. 1) runs for all members
 // together: per iteration one launch of each batched loop kernel over a work
 // list of row ranges of all members still running.  Blocks of iterations are
 // captured once into a HIP graph (list compaction + graph_iters iterations)
@@ -43,6 +44,15 @@ struct podcg_batch {
     PollBlock* d_gather = nullptr;
     PollBlock* h_gather = nullptr;          // pinned
     int* h_active = nullptr;                // pinned
+    int n_spmv_full = 0, n_vec_full = 0;    // lengths of the full work lists
+    // batched basis setup and Stage 1: per-member inputs, factor reports, and
+    // the list of members whose basis products are formed in this solve
+    BatchSetup* d_su = nullptr;
+    BatchSetup* h_su = nullptr;             // pinned
+    double* d_report = nullptr;
+    double* h_report = nullptr;             // pinned
+    int* d_list = nullptr;
+    int* h_list = nullptr;                  // pinned
 
     struct Graph {
         int yb, grid, iters;
@@ -93,6 +103,8 @@ void build_lists(podcg_batch* ctx) {
     }
     if (s.size() > ctx->cap_spmv || v.size() > ctx->cap_vec)
         fail(ctx, PODCG_ERR_INVALID_ARG, "work list exceeds its capacity");
+    ctx->n_spmv_full = (int)s.size();
+    ctx->n_vec_full = (int)v.size();
     // ordered on the batch stream; the host lists must outlive the copies
     HIPCHECK(hipMemcpyAsync(ctx->d_spmv_full, s.data(), s.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
                             ctx->stream));
@@ -192,31 +204,82 @@ int run_batch_loop(podcg_batch* ctx, int yb, int cap, int first) {
     return polls;
 }
 
-// Setup (where the basis changed) and Stage 1 of every member, all on the
-// batch stream after the members' own streams.
+int batch_yb(podcg_batch* ctx, bool plain);
+
+// Basis setup (where the basis changed) and Stage 1 (Alg. 2) of every
+// member, on the batch stream after the members' own streams: the products
+// A W and W^T A W of all such members in one work-list launch, their factors
+// in one launch of one workgroup per member, one synchronisation for the kept
+// ranks, then the tiled copies of A W, the state, the residual with W^T rbar,
+// Stage 1 and the first direction, each one launch for all members.  Records
+// ev_b between the setup and Stage 1.
 void stage1_all(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
                 const int* maxit, bool plain) {
     const int count = (int)ctx->members.size();
-    for (int m = 0; m < count; ++m) {
-        podcg_ctx* c = ctx->members[m];
-        if (!plain && !c->setup_valid) setup_basis(c);
-        HIPCHECK(hipEventRecord(ctx->member_ev[m], c->stream));
-        HIPCHECK(hipStreamWaitEvent(ctx->stream, ctx->member_ev[m], 0));
-    }
-    HIPCHECK(hipEventRecord(ctx->ev_b, ctx->stream));
     hipStream_t s = ctx->stream;
+    const int grid = ctx->opt.grid;
     for (int m = 0; m < count; ++m) {
         podcg_ctx* c = ctx->members[m];
-        const int y = plain ? 0 : c->y_kept;
-        const int yb = basis_tier(y);
-        DevBufs B = bufs(c);
-        const bool imp = member_implicit(c, plain);
-        HIPCHECK(launch_state_init(c->d_st, maxit[m], rtol[m] * rtol[m], y, s, imp));
-        HIPCHECK(launch_resid(B, yb, y, b[m], x[m], c->d_r, c->d_W, true, true, s));
-        HIPCHECK(launch_stage1_apply(B, yb, y, x[m], c->d_r, c->d_z, c->d_W, c->d_AW, s));
-        // p = z - W mu (explicit), pt = z (implicit)
-        HIPCHECK(launch_dir(B, imp ? 0 : yb, imp ? 0 : y, c->d_p, x[m], c->d_z, c->d_W, true, -1, s));
+        HIPCHECK(hipEventRecord(ctx->member_ev[m], c->stream));
+        HIPCHECK(hipStreamWaitEvent(s, ctx->member_ev[m], 0));
     }
+    int nlist = 0, ks = 0;
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        BatchSetup& S = ctx->h_su[m];
+        S = BatchSetup{};
+        S.b = b[m];
+        S.tol2 = rtol[m] * rtol[m];
+        S.maxit = maxit[m];
+        S.G = c->d_G;
+        S.R = c->d_R;
+        S.Ginv = c->d_Ginv;
+        S.lamG = c->d_lamG;
+        S.AWt = c->opt.projection == 1 ? c->d_AWt : nullptr;
+        S.report = ctx->d_report + 3 * (size_t)m;
+        S.ynom = c->y;
+        if (plain || c->setup_valid) continue;
+        if (c->y == 0 || (size_t)c->y * c->y * ctx->spmv_items[m] > (size_t)kPartials) {
+            setup_basis(c);   // an empty basis, or more partial Grams than the member's slots hold
+            continue;
+        }
+        S.setup = 1;
+        ctx->h_list[nlist++] = m;
+        ks = std::max(ks, c->y);
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->d_su, ctx->h_su, count * sizeof(BatchSetup), hipMemcpyHostToDevice, s));
+    if (nlist > 0) {
+        upload_members(ctx, x, plain);   // matrix, basis and work-item fields; ranks follow below
+        HIPCHECK(hipMemcpyAsync(ctx->d_list, ctx->h_list, nlist * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHECK(launch_batch_spmm_gram(ks, ctx->d_mem, ctx->d_su, ctx->d_spmv_full, ctx->n_spmv_full, grid, s));
+        HIPCHECK(launch_batch_reduced_factor(ctx->d_mem, ctx->d_su, ctx->d_list, nlist, s));
+        HIPCHECK(hipMemcpyAsync(ctx->h_report, ctx->d_report, 3 * (size_t)count * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (int q = 0; q < nlist; ++q) {
+            const int m = ctx->h_list[q];
+            podcg_ctx* c = ctx->members[m];
+            const double* rep = ctx->h_report + 3 * (size_t)m;
+            const int kept = (int)rep[0];
+            c->y_kept = kept;
+            c->rank_reduced = kept < c->y;
+            c->cond_G = kept > 0 ? (rep[2] > 0.0 ? rep[1] / rep[2] : INFINITY) : 1.0;
+            c->setup_valid = true;
+        }
+    }
+    HIPCHECK(hipEventRecord(ctx->ev_b, s));
+    upload_members(ctx, x, plain);
+    const int yb = batch_yb(ctx, plain);
+    if (nlist > 0) {
+        int kmax = 0;
+        for (int q = 0; q < nlist; ++q) kmax = std::max(kmax, ctx->members[ctx->h_list[q]]->y_kept);
+        HIPCHECK(launch_batch_tile_aw(batch_tier(kmax), ctx->d_mem, ctx->d_su, ctx->d_vec_full, ctx->n_vec_full,
+                                      grid, s));
+    }
+    HIPCHECK(launch_batch_state_init(ctx->d_mem, ctx->d_su, count, s));
+    HIPCHECK(launch_batch_resid(yb, ctx->d_mem, ctx->d_su, ctx->d_spmv_full, ctx->n_spmv_full, grid, s));
+    HIPCHECK(launch_batch_stage1(yb, ctx->d_mem, ctx->d_vec_full, ctx->n_vec_full, grid, s));
+    HIPCHECK(launch_batch_dir_init(yb, ctx->d_mem, ctx->d_vec_full, ctx->n_vec_full, grid, s));
 }
 
 void check_solve_args(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol) {
@@ -253,8 +316,7 @@ int batch_solve_impl(podcg_batch* ctx, const double* const* b, double* const* x,
     for (int m = 0; m < count; ++m)
         did_setup[m] = !plain && !ctx->members[m]->setup_valid && ctx->members[m]->y > 0;
     stage1_all(ctx, b, x, rtol, maxit.data(), plain);
-    const int yb = batch_yb(ctx, plain);
-    upload_members(ctx, x, plain);
+    const int yb = batch_yb(ctx, plain);   // stage1_all uploaded the member table
     const int slot = plain ? 1 : 0;
     const int first = (int)(0.85 * ctx->prev_iters[slot]);
     const int polls = run_batch_loop(ctx, yb, cap + 1, first);
@@ -316,9 +378,12 @@ void release_batch(podcg_batch* ctx) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     void* dev[] = {ctx->d_mem, ctx->d_spmv_full, ctx->d_vec_full, ctx->d_spmv, ctx->d_vec,
-                   ctx->d_counts, ctx->d_active, ctx->d_gather};
+                   ctx->d_counts, ctx->d_active, ctx->d_gather, ctx->d_su, ctx->d_report, ctx->d_list};
     for (void* p : dev)
         if (p) (void)hipFree(p);
+    void* host[] = {ctx->h_su, ctx->h_report, ctx->h_list};
+    for (void* p : host)
+        if (p) (void)hipHostFree(p);
     if (ctx->h_mem) (void)hipHostFree(ctx->h_mem);
     if (ctx->h_gather) (void)hipHostFree(ctx->h_gather);
     if (ctx->h_active) (void)hipHostFree(ctx->h_active);
@@ -386,6 +451,12 @@ int podcg_batch_create(podcg_batch** out, int32_t count, podcg_ctx* const* membe
         dalloc(ctx, &ctx->d_counts, 2);
         dalloc(ctx, &ctx->d_active, 1);
         dalloc(ctx, &ctx->d_gather, count);
+        dalloc(ctx, &ctx->d_su, count);
+        dalloc(ctx, &ctx->d_report, 3 * (size_t)count);
+        dalloc(ctx, &ctx->d_list, count);
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_su, count * sizeof(BatchSetup), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_report, 3 * count * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_list, count * sizeof(int), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_mem, count * sizeof(BatchMember), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_gather, count * sizeof(PollBlock), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_active, sizeof(int), hipHostMallocDefault));
@@ -458,7 +529,6 @@ int podcg_batch_tune(podcg_batch* ctx, const double* const* b, double* const* x,
         auto measure = [&]() -> double {
             stage1_all(ctx, b, x, zero.data(), maxit.data(), false);
             const int yb = batch_yb(ctx, false);
-            upload_members(ctx, x, false);
             (void)block_graph(ctx, yb);   // capture outside the timed region
             HIPCHECK(hipEventRecord(ctx->ev_a, ctx->stream));
             (void)run_batch_loop(ctx, yb, iters + 1, iters + 1);

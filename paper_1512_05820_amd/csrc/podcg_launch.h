@@ -139,6 +139,42 @@ hipError_t launch_batch_dir(int yb, const BatchMember* mem, const BatchItem* ite
                             int grid, hipStream_t s);
 hipError_t launch_batch_gather(const BatchMember* mem, int count, PollBlock* out, hipStream_t s);
 
+// Per-member inputs of the batched basis setup and Stage 1 (index = member,
+// parallel to the BatchMember table).
+struct BatchSetup {
+    const double* b;     // right-hand side of this solve
+    double tol2;         // rtol^2 (the Stage-1 kernel scales it by ||b||^2)
+    double* G;           // W^T A W (ynom x ynom), its Cholesky factor R, inverse, eigenvalues
+    double* R;
+    double* Ginv;
+    double* lamG;
+    double* AWt;         // A W in 64-row tiles for the implicit update, or null
+    double* report;      // kept rank, largest and smallest kept eigenvalue (3 doubles)
+    int maxit;
+    int setup;           // 1: A W, W^T A W and its factor are formed in this solve
+    int ynom;            // columns of W before the factor's pivot cut
+    int pad;
+};
+
+// Batched basis setup (k_gram.hip, k_small.hip, k_batch.hip): A W and
+// W^T A W over the SpMV items of the members with `setup` set (ks >= their
+// ynom), then one workgroup per listed member for the factor, inverse and
+// eigenvalues, then the tiled copy of A W over the vector items.
+hipError_t launch_batch_spmm_gram(int ks, const BatchMember* mem, const BatchSetup* su, const BatchItem* items,
+                                  int nitems, int grid, hipStream_t s);
+hipError_t launch_batch_reduced_factor(const BatchMember* mem, const BatchSetup* su, const int* list, int nlist,
+                                       hipStream_t s);
+hipError_t launch_batch_tile_aw(int yb, const BatchMember* mem, const BatchSetup* su, const BatchItem* items,
+                                int nitems, int grid, hipStream_t s);
+// Batched Stage 1 (Alg. 2) and the first direction of every member (k_batch.hip).
+hipError_t launch_batch_state_init(const BatchMember* mem, const BatchSetup* su, int count, hipStream_t s);
+hipError_t launch_batch_resid(int yb, const BatchMember* mem, const BatchSetup* su, const BatchItem* items,
+                              int nitems, int grid, hipStream_t s);
+hipError_t launch_batch_stage1(int yb, const BatchMember* mem, const BatchItem* items, int nitems, int grid,
+                               hipStream_t s);
+hipError_t launch_batch_dir_init(int yb, const BatchMember* mem, const BatchItem* items, int nitems, int grid,
+                                 hipStream_t s);
+
 hipError_t launch_dir_rec(const DevBufs& B, int yb, int y, double* p, double* x, const double* z,
                           const double* W, double* V, size_t ldv, int cap, double* gamma,
                           double* alpha, int k, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -1,7 +1,9 @@
 """Batched solves of independent sequences (podcg_batch_*) against the oracle.
 
 Members of uneven sizes (n = 25 .. 10,000, ragged slices, members of one and
-of many work items) are solved together.  Bars: lockstep (the oracle's
+of many work items; and members at the config-4 sizes up to 512 x 512) are
+solved together; their basis setup and Stage 1 run as batched work-list
+launches.  Bars: lockstep (the oracle's
 iteration count from identical A, b, W) to 1e-10 relative for every member;
 closed-loop config-4-type sequences meeting the tolerance by the oracle's
 own residual with the oracle's ranks and iteration counts within one; graph
@@ -110,6 +112,85 @@ def test_lockstep_every_member_matches_oracle(P, items):
         assert st[i].iters == so.iters
         assert st[i].rank == (0 if Ws[i] is None else Ws[i].shape[1])
         assert e <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def large_refs():
+    """Members at the config-4 sizes (sides 64 .. 512, n up to 262,144) with
+    ranks 0 .. 6 and the oracle's solves of system 2 to 1e-10."""
+    cfgs = _members([64, 200, 384, 512], rank=6)
+    r = np.random.Generator(np.random.PCG64(41))
+    out = []
+    for c, y in zip(cfgs, [6, 0, 3, 6]):
+        W = r.standard_normal((c.n, y)) if y else None
+        A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(2))
+        xo, so = oracle.aug_pcg(A, c.rhs(2), np.zeros(c.n), W, tol=1e-10, maxit=20000)
+        assert so.status == 0
+        out.append((c, W, xo, so))
+    return out
+
+
+@pytest.mark.parametrize("items", ["default", "finest"])
+def test_lockstep_members_up_to_512_squared(P, large_refs, items):
+    """Batched basis setup, Stage 1 and loop at the config-4 member sizes: every
+    member runs exactly the oracle's iteration count (tolerance 0) and matches
+    the oracle's solution to 1e-10."""
+    ctxs = []
+    for c, W, xo, so in large_refs:
+        k = P.PodCG(c.n, rank_max=6, maxit=so.iters)
+        k.set_matrix(_dev(c.matrix_values(2)), _dev(c.rowptr, torch.int32), _dev(c.colind, torch.int32))
+        k.set_basis(None if W is None else _dev(W))
+        ctxs.append(k)
+    kw = {} if items == "default" else {"slices_per_item": 1, "rows_per_item": 256}
+    batch = P.PodCGBatch(ctxs, **kw)
+    xs = [_dev(np.zeros(c.n)) for c, _, _, _ in large_refs]
+    rc, st = batch.solve([_dev(c.rhs(2)) for c, _, _, _ in large_refs], xs, [0.0] * len(large_refs))
+    assert rc == 1
+    for i, (c, W, xo, so) in enumerate(large_refs):
+        e = _relerr(_host(xs[i]), xo)
+        print(f"member n={c.n} rank {st[i].rank} iters {st[i].iters} (oracle {so.iters}) err {e:.2e}")
+        assert st[i].iters == so.iters
+        assert st[i].rank == (0 if W is None else W.shape[1])
+        assert e <= 1e-10
+    # the batched setup left each member ready for a single-sequence solve:
+    # its reduced matrix is W^T A W
+    for k, (c, W, _, _) in zip(ctxs, large_refs):
+        if W is None:
+            continue
+        G, _ = k.get_reduced()
+        A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(2))
+        AW = np.stack([oracle.matvec(A, W[:, j]) for j in range(W.shape[1])], axis=1)
+        Gref = W.T @ AW
+        assert np.abs(G - Gref).max() <= 1e-11 * np.abs(Gref).max()
+    batch.close()
+
+
+def test_batched_setup_leaves_single_solves_consistent(P):
+    """After a batched solve formed a member's basis products, a single-sequence
+    solve of that member (which reads the tiled copy of A W in the implicit
+    form) agrees with a fresh context's solve: the two factors differ only by
+    the summation order of W^T A W."""
+    cfgs = _members([40, 64], rank=3)
+    r = np.random.Generator(np.random.PCG64(42))
+    Ws = [r.standard_normal((c.n, 3)) for c in cfgs]
+    ctxs = _contexts(P, cfgs)
+    for k, W in zip(ctxs, Ws):
+        k.set_basis(_dev(W))
+    batch = P.PodCGBatch(ctxs)
+    xs = [_dev(np.zeros(c.n)) for c in cfgs]
+    rc, _ = batch.solve([_dev(c.rhs(1)) for c in cfgs], xs, [c.tol for c in cfgs])
+    assert rc == 0
+    for c, k, W in zip(cfgs, ctxs, Ws):
+        x1 = _dev(np.zeros(c.n))
+        s1 = k.solve(_dev(c.rhs(1)), x1, c.tol)
+        fresh = _contexts(P, [c])[0]
+        fresh.set_basis(_dev(W))
+        x2 = _dev(np.zeros(c.n))
+        s2 = fresh.solve(_dev(c.rhs(1)), x2, c.tol)
+        assert s1.status == 0 and s1.true_relres <= c.tol * 1.01
+        assert abs(s1.iters - s2.iters) <= 1
+        assert _relerr(_host(x1), _host(x2)) <= 1e-8
+    batch.close()
 
 
 def test_closed_loop_batch_matches_oracle_sequences(P):
