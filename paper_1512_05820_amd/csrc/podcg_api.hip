@@ -437,7 +437,12 @@ int podcg_create(podcg_ctx** out, int64_t n, const podcg_options* opt, void* hip
         return PODCG_ERR_HIP;
     }
     ctx->nslices = (int)((n + kSlice - 1) / kSlice);
-    ctx->ld = (size_t)ctx->nslices * kSlice;
+    // leading dimension of the vectors and column blocks: the slices, plus one
+    // padding slice for large systems with an even slice count, so that the
+    // stride between columns of W, A W, S and Y is an odd multiple of 512
+    // bytes -- at a multiple of 8 KB (n = 2^21, say) every column's rows map
+    // to the same L1 set and the multi-column gathers stall on tag conflicts
+    ctx->ld = (size_t)(ctx->nslices + (ctx->nslices >= 1024 && ctx->nslices % 2 == 0 ? 1 : 0)) * kSlice;
     int rc = guarded(ctx, [&]() {
         const int src = noalloc_init(ctx->device, &ctx->last_error);
         if (src != PODCG_OK) throw Fail{src};
