@@ -1,23 +1,23 @@
 // One-workgroup solve of a small system: Stage 1 (Alg. 2) and augmented PCG
 // (Alg. 1 with the Jacobi preconditioner and the explicit direction
-// recurrence p = z + beta p - W mu) in a single launch of 1024 threads.
+// recurrence p = z + beta p - W mu) in a single launch of 512 threads.
 //
 // For a few thousand unknowns the multi-kernel loop is bound by launch and
 // synchronisation latency (three dependent launches per iteration, each
-// finishing a grid reduction).  Here one workgroup of 16 wavefronts keeps the
-// whole solve on one compute unit: each thread owns R rows (row 64 s + lane
-// of slice s = wave + 16 r, the SELL layout's own mapping) and holds that
-// row's matrix entries, x, r, z, p, the Jacobi inverse and the rows of W and
+// finishing a grid reduction).  Here one workgroup of 8 wavefronts keeps the
+// whole solve on one compute unit: each thread owns two rows (row 64 s + lane
+// of slices s = wave and wave + 8, the SELL layout's own mapping) and holds
+// their matrix entries, x, r, z, p, the Jacobi inverse and the rows of W and
 // A W in registers for the whole solve; only the search direction, which the
-// product A p gathers across rows, is shared through LDS.  Reductions are
-// wavefront butterflies followed by a fixed-order sum of the 16 wave
-// partials, so results are bitwise repeatable.  Per iteration: one gathered
-// product, two reductions and three workgroup barriers, and no memory round
-// trip at all (the matrix rows stay in registers).  Wave sums use DPP row
-// operations (VALU lane moves) rather than LDS permutes, and every wavefront
-// finishes each reduction itself from the 16 wave partials (same values in
-// the same order, so every wave reaches the same decisions) instead of waiting
-// behind a barrier for one wave to do it.
+// product A p gathers across rows, is shared through LDS.  Per iteration: one
+// gathered product, two reductions and three workgroup barriers, and no
+// memory round trip at all (the matrix rows stay in registers).  A reduction
+// adds the thread's two rows, sums each wave with DPP row operations (VALU
+// lane moves rather than LDS permutes), and then every wavefront sums the 8
+// wave partials itself (same values in the same order, so every wave reaches
+// the same decisions) instead of waiting behind a barrier for one wave to do
+// it; results are bitwise repeatable.  Two rows a thread halve the reduction
+// work each SIMD issues per iteration (two wavefronts a SIMD instead of four).
 //
 // The basis products (A W, W^T A W and its factor, Alg. 2) come from the
 // setup kernels of the multi-kernel path, launched ahead of this kernel on the
@@ -27,7 +27,9 @@
 
 namespace podcg {
 
-constexpr int kLdsWaves = kLdsThreads / kWave;   // 16
+constexpr int kLdsRows = 2;                       // rows per thread
+constexpr int kLdsBlock = kLdsThreads / kLdsRows; // 512 threads
+constexpr int kLdsWaves = kLdsBlock / kWave;      // 8
 
 // One DPP lane move of a double (two 32-bit moves); lanes the row and bank
 // masks leave out, or whose source lane does not exist, receive 0.
@@ -71,7 +73,7 @@ __device__ __forceinline__ void lds_wave_partials(double (&v)[NV], double* red) 
     }
 }
 
-// Lane t of the calling wave: the total of value t (t < NV), the 16 wave
+// Lane t of the calling wave: the total of value t (t < NV), the wave
 // partials added in wave order.
 template <int NV>
 __device__ __forceinline__ double lds_total(const double* red) {
@@ -107,16 +109,17 @@ struct LdsShared {
 };
 
 template <int YB>
-__global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const double* __restrict__ b,
-                                                           double* __restrict__ x,
-                                                           const double* __restrict__ W,
-                                                           const double* __restrict__ AW) {
+__global__ __launch_bounds__(kLdsBlock) void k_lds_solve(DevBufs B, const double* __restrict__ b,
+                                                         double* __restrict__ x,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ AW) {
     constexpr int NV = 2 + YB;
+    constexpr int R = kLdsRows;
     __shared__ double sp[kLdsThreads];            // the vector the product gathers from
     __shared__ double red[kLdsWaves * NV];        // wave partials of the vector sums
     __shared__ double redg[kLdsWaves];            // wave partials of (A p, p) and of ||b - A x||^2
     __shared__ double sginv[YB > 0 ? YB * YB : 1];
-    __shared__ double smu[YB > 0 ? YB : 1];       // what in Stage 1, then mu
+    __shared__ double smu[YB > 0 ? YB : 1];       // what in Stage 1
     __shared__ LdsShared sh;
     DevState* st = B.st;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -124,66 +127,88 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
     const int y = YB > 0 ? min(st->y, YB) : 0;
     const int maxit = st->maxit;
 
-    // ---- this thread's row (row 64 s + lane of slice s = wave): matrix
-    // entries, vectors, basis rows
-    const int row = wid * kSlice + lane;
-    const bool in = row < n;
-    int mw = 0;
-    double av[kLdsWidth];
-    int ac[kLdsWidth];
-    if (wid < B.nslices) {
-        // slice bounds, width and column storage are wave-uniform
-        const int s = __builtin_amdgcn_readfirstlane(wid);
-        const int64_t base = B.sptr[s];
-        mw = (int)((B.sptr[s + 1] - base) / kSlice);
-        const int flag = B.sflag[s];
-        const int rb = in ? row : 0;
+    // ---- this thread's rows (row 64 s + lane of slices s = wave + 8 q):
+    // matrix entries, vectors, basis rows
+    int row[R], mw[R];
+    bool in[R];
+    double av[R][kLdsWidth];
+    int ac[R][kLdsWidth];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int sl = wid + kLdsWaves * q;
+        row[q] = sl * kSlice + lane;
+        in[q] = row[q] < n;
+        mw[q] = 0;
+        const int rb = in[q] ? row[q] : 0;
 #pragma unroll
         for (int j = 0; j < kLdsWidth; ++j) {
-            av[j] = 0.0;
-            ac[j] = rb;
-            if (j < mw) {
-                const size_t e = (size_t)base + (size_t)j * kSlice + lane;
-                int c;
-                if (flag == 2) c = row + B.soff[(size_t)s * kTabMax + j];
-                else if (flag == 1) c = rb + (int)B.cols16[e];
-                else c = B.cols[e];
-                ac[j] = c < 0 ? 0 : (c < n ? c : n - 1);
-                av[j] = B.vals[e];
+            av[q][j] = 0.0;
+            ac[q][j] = rb;
+        }
+        if (sl < B.nslices) {
+            // slice bounds, width and column storage are wave-uniform
+            const int s = __builtin_amdgcn_readfirstlane(sl);
+            const int64_t base = B.sptr[s];
+            mw[q] = (int)((B.sptr[s + 1] - base) / kSlice);
+            const int flag = B.sflag[s];
+#pragma unroll
+            for (int j = 0; j < kLdsWidth; ++j) {
+                if (j < mw[q]) {
+                    const size_t e = (size_t)base + (size_t)j * kSlice + lane;
+                    int c;
+                    if (flag == 2) c = row[q] + B.soff[(size_t)s * kTabMax + j];
+                    else if (flag == 1) c = rb + (int)B.cols16[e];
+                    else c = B.cols[e];
+                    ac[q][j] = c < 0 ? 0 : (c < n ? c : n - 1);
+                    av[q][j] = B.vals[e];
+                }
             }
         }
     }
-    const double bi = in ? b[row] : 0.0;
-    double xi = in ? x[row] : 0.0;
-    const double di = in ? B.dinv[row] : 0.0;
-    double ri, zi = 0.0, pi = 0.0;
-    double wr[YB > 0 ? YB : 1], awr[YB > 0 ? YB : 1];
+    double bi[R], xi[R], di[R], ri[R], zi[R], pi[R];
+    double wr[R][YB > 0 ? YB : 1], awr[R][YB > 0 ? YB : 1];
 #pragma unroll
-    for (int k = 0; k < YB; ++k) {
-        wr[k] = in && k < y ? W[(size_t)k * B.ld + row] : 0.0;
-        awr[k] = in && k < y ? AW[(size_t)k * B.ld + row] : 0.0;
+    for (int q = 0; q < R; ++q) {
+        bi[q] = in[q] ? b[row[q]] : 0.0;
+        xi[q] = in[q] ? x[row[q]] : 0.0;
+        di[q] = in[q] ? B.dinv[row[q]] : 0.0;
+        ri[q] = zi[q] = pi[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < YB; ++k) {
+            wr[q][k] = in[q] && k < y ? W[(size_t)k * B.ld + row[q]] : 0.0;
+            awr[q][k] = in[q] && k < y ? AW[(size_t)k * B.ld + row[q]] : 0.0;
+        }
     }
     if (YB > 0)
-        for (int e = threadIdx.x; e < y * y; e += kLdsThreads) sginv[(e / y) * YB + e % y] = B.Ginv[e];
-    // (A v)_row, v gathered from sp
-    auto product = [&]() {
+        for (int e = threadIdx.x; e < y * y; e += kLdsBlock) sginv[(e / y) * YB + e % y] = B.Ginv[e];
+    // (A v) of row q, v gathered from sp
+    auto product = [&](int q) {
         double acc = 0.0;
 #pragma unroll
         for (int j = 0; j < kLdsWidth; ++j)
-            if (j < mw) acc = fma(av[j], sp[ac[j]], acc);
+            if (j < mw[q]) acc = fma(av[q][j], sp[ac[q][j]], acc);
         return acc;
+    };
+    auto share = [&](const double (&v)[R]) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) sp[row[q]] = v[q];
     };
 
     // ---- Stage 1 (Alg. 2): rbar = b - A xbar, (b, b), (rbar, rbar), W^T rbar
-    sp[row] = xi;
+    share(xi);
     __syncthreads();
     {
-        ri = in ? bi - product() : 0.0;
         double v[NV];
-        v[0] = bi * bi;
-        v[1] = ri * ri;
 #pragma unroll
-        for (int k = 0; k < YB; ++k) v[2 + k] = wr[k] * ri;
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            ri[q] = in[q] ? bi[q] - product(q) : 0.0;
+            v[0] += bi[q] * bi[q];
+            v[1] += ri[q] * ri[q];
+#pragma unroll
+            for (int k = 0; k < YB; ++k) v[2 + k] += wr[q][k] * ri[q];
+        }
         lds_wave_partials<NV>(v, red);
         __syncthreads();
         if (wid == 0) {
@@ -206,27 +231,39 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
     int iters = 0;
     double rr_last = 0.0, alpha = 0.0, gamma = 0.0, rho_last = 0.0, beta_last = 0.0;
     int state = sh.state, status = sh.status;
+    // this lane's row of G^{-1} (lane k < y), for mu = G^{-1} c in the loop
+    double ginv_row[YB > 0 ? YB : 1];
+    {
+        const int kl = lane < YB ? lane : 0;
+#pragma unroll
+        for (int j = 0; j < YB; ++j) ginv_row[j] = (lane < y && j < y) ? sginv[kl * YB + j] : 0.0;
+    }
     if (state == kRunning) {
         // x = xbar + W what, r = rbar - (A W) what, z = M^{-1} r,
         // sums (r, z), (r, r), c = (A W)^T z; mu = G^{-1} c
         {
-            if (YB > 0) {
-                double wx = 0.0, awx = 0.0;
-#pragma unroll
-                for (int k = 0; k < YB; ++k) {
-                    const double wh = k < y ? smu[k] : 0.0;
-                    wx += wr[k] * wh;
-                    awx += awr[k] * wh;
-                }
-                xi += wx;
-                ri -= awx;
-            }
-            zi = di * ri;
             double v[NV];
-            v[0] = ri * zi;
-            v[1] = ri * ri;
 #pragma unroll
-            for (int k = 0; k < YB; ++k) v[2 + k] = awr[k] * zi;
+            for (int k = 0; k < NV; ++k) v[k] = 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (YB > 0) {
+                    double wx = 0.0, awx = 0.0;
+#pragma unroll
+                    for (int k = 0; k < YB; ++k) {
+                        const double wh = k < y ? smu[k] : 0.0;
+                        wx += wr[q][k] * wh;
+                        awx += awr[q][k] * wh;
+                    }
+                    xi[q] += wx;
+                    ri[q] -= awx;
+                }
+                zi[q] = di[q] * ri[q];
+                v[0] += ri[q] * zi[q];
+                v[1] += ri[q] * ri[q];
+#pragma unroll
+                for (int k = 0; k < YB; ++k) v[2 + k] += awr[q][k] * zi[q];
+            }
             lds_wave_partials<NV>(v, red);
         }
         __syncthreads();
@@ -254,22 +291,28 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
         rr_last = sh.rr;
         double rho = sh.rho;
         // the first direction p = z - W mu
-        {
-            double s = zi;
 #pragma unroll
-            for (int k = 0; k < YB; ++k) s -= wr[k] * (k < y ? smu[k] : 0.0);
-            pi = s;
+        for (int q = 0; q < R; ++q) {
+            double s = zi[q];
+#pragma unroll
+            for (int k = 0; k < YB; ++k) s -= wr[q][k] * (k < y ? smu[k] : 0.0);
+            pi[q] = s;
         }
         state = sh.state;
         status = sh.status;
         // ---- the loop of Alg. 1; every thread keeps the same state, so no
         // barrier is needed to share the decisions
         while (state == kRunning) {
-            sp[row] = pi;
+            share(pi);
             __syncthreads();
             // q = A p, gamma = (A p, p)
-            const double q = in ? product() : 0.0;
-            double g[1] = {q * pi};
+            double qv[R];
+            double g[1] = {0.0};
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                qv[q] = in[q] ? product(q) : 0.0;
+                g[0] += qv[q] * pi[q];
+            }
             lds_wave_partials<1>(g, redg);
             __syncthreads();
             gamma = redg[0];
@@ -282,20 +325,25 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
             }
             alpha = rho / gamma;
             // x += alpha p, r -= alpha q, z = M^{-1} r; (r, z), (r, r), (A W)^T z
-            xi = xi + alpha * pi;
-            ri = ri - alpha * q;
-            zi = di * ri;
             {
                 double v[NV];
-                v[0] = ri * zi;
-                v[1] = ri * ri;
 #pragma unroll
-                for (int k = 0; k < YB; ++k) v[2 + k] = awr[k] * zi;
+                for (int k = 0; k < NV; ++k) v[k] = 0.0;
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    xi[q] = xi[q] + alpha * pi[q];
+                    ri[q] = ri[q] - alpha * qv[q];
+                    zi[q] = di[q] * ri[q];
+                    v[0] += ri[q] * zi[q];
+                    v[1] += ri[q] * ri[q];
+#pragma unroll
+                    for (int k = 0; k < YB; ++k) v[2 + k] += awr[q][k] * zi[q];
+                }
                 lds_wave_partials<NV>(v, red);
             }
             __syncthreads();
             ++iters;
-            // every wave sums the 16 wave partials itself: lane t < NV holds
+            // every wave sums the wave partials itself: lane t < NV holds
             // total t, read back as scalars
             double tot = 0.0;
             if (lane < NV) {
@@ -317,34 +365,37 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
             }
             // mu = G^{-1} (A W)^T z: lane k < y forms mu_k
             double muk = 0.0;
-            {
-                const int kl = lane < YB ? lane : 0;
 #pragma unroll
-                for (int j = 0; j < YB; ++j) {
-                    const double cj = lane_value(tot, 2 + j);
-                    if (lane < y && j < y) muk += sginv[kl * YB + j] * cj;
-                }
-            }
+            for (int j = 0; j < YB; ++j) muk += ginv_row[j] * lane_value(tot, 2 + j);
             // p = z + beta p - W mu, beta = (r', z') / (r, z)
             const double beta = rz / rho;
             rho = rz;
             beta_last = beta;
-            double s = zi + beta * pi;
+            double mu[YB > 0 ? YB : 1];
 #pragma unroll
-            for (int k = 0; k < YB; ++k) s -= wr[k] * (k < y ? lane_value(muk, k) : 0.0);
-            pi = s;
+            for (int k = 0; k < YB; ++k) mu[k] = k < y ? lane_value(muk, k) : 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                double s = zi[q] + beta * pi[q];
+#pragma unroll
+                for (int k = 0; k < YB; ++k) s -= wr[q][k] * mu[k];
+                pi[q] = s;
+            }
         }
         rho_last = rho;
     }
     // ---- the true residual ||b - A x|| and the solution
     __syncthreads();
-    sp[row] = xi;
+    share(xi);
     __syncthreads();
     double t[1] = {0.0};
-    if (in) {
-        const double rt = bi - product();
-        t[0] = rt * rt;
-        x[row] = xi;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (in[q]) {
+            const double rt = bi[q] - product(q);
+            t[0] += rt * rt;
+            x[row[q]] = xi[q];
+        }
     }
     lds_wave_partials<1>(t, redg);
     __syncthreads();
@@ -365,15 +416,13 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_solve(DevBufs B, const doub
     }
 }
 
-// Basis dimensions of the one-workgroup solve: up to kLdsYMax, where the
-// registers of 16 wavefronts per compute unit (128 per lane) still hold the
-// rows of W and A W without spilling.
+// Basis dimensions of the one-workgroup solve: up to kLdsYMax.
 int lds_tier(int n, int y) { return n >= 1 && n <= kLdsThreads && y >= 0 && y <= kLdsYMax ? y : -1; }
 
 hipError_t launch_lds_solve(const DevBufs& B, int yb, const double* b, double* x, const double* W,
                             const double* AW, hipStream_t s) {
-    if (lds_tier(B.n, yb) != yb || B.nslices > kLdsWaves) return hipErrorInvalidValue;
-    const dim3 g(1), t(kLdsThreads);
+    if (lds_tier(B.n, yb) != yb || B.nslices > kLdsWaves * kLdsRows) return hipErrorInvalidValue;
+    const dim3 g(1), t(kLdsBlock);
     switch (yb) {
 #define CASE(T) case T: hipLaunchKernelGGL((k_lds_solve<T>), g, t, 0, s, B, b, x, W, AW); break;
         CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(5)
