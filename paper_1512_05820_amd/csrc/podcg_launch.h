@@ -196,6 +196,11 @@ hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel,
                              double rel, int kinmax, hipStream_t s);
 hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
                              hipStream_t s);
+// A whole projection solve (Galerkin start and steps) in one launch, with
+// Ghat = Y^T A Y (row-major m x m) formed beforehand; acc[0] += steps,
+// acc[1] += 1.
+hipError_t launch_ts_in_solve(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
+                              const double* Ghat, double rel, int kinmax, int* acc, hipStream_t s);
 hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
                                     hipStream_t s);
 hipError_t launch_ts_eta(TsDev* T, int m, int kr, hipStream_t s);

@@ -43,6 +43,7 @@ struct TsHost {
     double* d_Gbig2 = nullptr;   // second buffer of the Jacobi rounds
     double* d_Gparts = nullptr;  // partial Grams of the row chunks
     double* d_aug = nullptr;     // iterative Stage 3: kept reduced directions and Ghat times them
+    int* d_acc = nullptr;        // iterative Stage 3: projection steps and solves of the current system
     TsDev* d_ts = nullptr;
     double* h_dbl = nullptr;     // pinned, kTsCap + 8
     int* h_int = nullptr;        // pinned, kYMax + 8
@@ -54,7 +55,7 @@ void ts_release(podcg_ctx* ctx) {
     if (!T) return;
     void* dev[] = {T->d_Y, T->d_AZ, T->d_B, T->d_AB, T->d_part, T->d_G, T->d_R, T->d_GinvW, T->d_GinvB,
                    T->d_lamG, T->d_Gbig, T->d_Vbig, T->d_lam, T->d_T, T->d_sel, T->d_info, T->d_ts,
-                   T->d_Gbig2, T->d_Gparts, T->d_aug};
+                   T->d_Gbig2, T->d_Gparts, T->d_aug, T->d_acc};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (T->h_dbl) (void)hipHostFree(T->h_dbl);
@@ -227,27 +228,25 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     // the projection solves' tolerance: inner_rtol, or a margin below the
     // solve's own rtol (the error a projection leaves in range(Y) stays)
     const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : kInnerMargin * rtol, kRoundingFloor);
-    int* hin = T->h_int + kYMax;    // {steps, done} of the projection solve
-    double* u = T->d_AZ;            // Y ph and A Y ph (the truncation's block is free here)
-    double* au = T->d_AZ + ld;
-    int nproj = 0, kin = 0;
+    // Ghat = Y^T A Y, formed once for the system: A Y in blocks of up to
+    // kYMax columns (into the truncation's block, free here), then the MFMA
+    // Gram of the row chunks.  The projection solves then need Ghat p only,
+    // an m x m product inside their own launch, instead of two passes over
+    // the tall Y and a matvec per step.
+    for (int c0 = 0; c0 < m; c0 += kYMax) {
+        const int kc = std::min(kYMax, m - c0);
+        HIPCHECK(launch_spmm(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, s));
+    }
+    const size_t pstride = (size_t)kTsCap * kTsCap;
+    HIPCHECK(launch_gemm_tn_parts(n, ld, T->d_Y, m, T->d_AZ, m, kGramChunks, true, T->d_Gparts, pstride, m, s));
+    HIPCHECK(launch_gram_sum(T->d_Gparts, gemm_tn_chunks(n, kGramChunks), pstride, m, m, m, true, T->d_Gbig2, m, s));
+    HIPCHECK(hipMemsetAsync(T->d_acc, 0, 2 * sizeof(int), s));
     // T->muin = Ghat^{-1} Y^T A v, iteratively
     auto project = [&](const double* v) {
         HIPCHECK(launch_matvec(D, v, ctx->d_q, s));
         HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, ctx->d_q, T->d_part, TSF(T, cin), s));
-        HIPCHECK(launch_ts_in_init(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, rel, T->opt.inner_maxit, s));
-        for (;;) {
-            HIPCHECK(hipMemcpyAsync(hin, ts_field<int>(T->d_ts, offsetof(TsDev, kin)), 2 * sizeof(int),
-                                    hipMemcpyDeviceToHost, s));
-            HIPCHECK(hipStreamSynchronize(s));
-            if (hin[1]) break;
-            HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, ph), u, 1.0, false, s));
-            HIPCHECK(launch_matvec(D, u, au, s));
-            HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, au, T->d_part, TSF(T, gh), s));
-            HIPCHECK(launch_ts_in_step(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, s));
-        }
-        ++nproj;
-        kin += hin[0];
+        HIPCHECK(launch_ts_in_solve(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, T->d_Gbig2, rel,
+                                    T->opt.inner_maxit, T->d_acc, s));
     };
     HIPCHECK(hipEventRecord(T->ev[1], s));
     HIPCHECK(launch_state_init(ctx->d_st, maxit, rtol * rtol, 0, s));
@@ -274,7 +273,10 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
         }
     }
     HIPCHECK(launch_resid(D, 0, 0, b, x, nullptr, nullptr, false, false, s));
+    int* hacc = T->h_int + kYMax;
+    HIPCHECK(hipMemcpyAsync(hacc, T->d_acc, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     poll(ctx);
+    const int kin = hacc[0], nproj = hacc[1];
     const PollBlock P = *ctx->h_poll;
     HIPCHECK(hipEventRecord(T->ev[2], s));
     const double bn = S.bnorm;
@@ -284,7 +286,8 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     S.projections = nproj;
     S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
     S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
-    S.matvecs = w + 1 + k2 + 1 + k3 + nproj + kin + 1;
+    // products with A: Stage 1 and 2, r0, the loop, A v per projection, A Y for Ghat, the true residual
+    S.matvecs = w + 1 + k2 + 1 + k3 + nproj + m + 1;
     const int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
     S.status = code;
     return ts_finish(ctx, T, m, k3, code, S, out);
@@ -474,6 +477,7 @@ int podcg_ts_enable(podcg_ctx* ctx, const podcg_ts_options* opt) {
         dalloc(ctx, &T->d_sel, kYMax);
         dalloc(ctx, &T->d_info, 4);
         dalloc(ctx, &T->d_Gbig2, (size_t)kTsCap * kTsCap);
+        dalloc(ctx, &T->d_acc, 2);
         dalloc(ctx, &T->d_Gparts, (size_t)(kGramChunks + 1) * kTsCap * kTsCap);
         if (o.phi == 1) dalloc(ctx, &T->d_aug, kTsAugDoubles);
         dalloc(ctx, &T->d_ts, 1);
