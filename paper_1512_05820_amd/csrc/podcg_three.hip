@@ -229,10 +229,10 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     // solve's own rtol (the error a projection leaves in range(Y) stays)
     const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : kInnerMargin * rtol, kRoundingFloor);
     // Ghat = Y^T A Y, formed once for the system: A Y in blocks of up to
-    // kYMax columns (into the truncation's block, free here), then the MFMA
-    // Gram of the row chunks.  The projection solves then need Ghat p only,
-    // an m x m product inside their own launch, instead of two passes over
-    // the tall Y and a matvec per step.
+    // kYMax columns (into the truncation's block, free here, and kept for the
+    // right-hand sides below), then the MFMA Gram of the row chunks.  The
+    // projection solves then need Ghat p only, an m x m product inside their
+    // own launch, instead of two passes over the tall Y and a matvec per step.
     for (int c0 = 0; c0 < m; c0 += kYMax) {
         const int kc = std::min(kYMax, m - c0);
         HIPCHECK(launch_spmm(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, s));
@@ -241,10 +241,10 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     HIPCHECK(launch_gemm_tn_parts(n, ld, T->d_Y, m, T->d_AZ, m, kGramChunks, true, T->d_Gparts, pstride, m, s));
     HIPCHECK(launch_gram_sum(T->d_Gparts, gemm_tn_chunks(n, kGramChunks), pstride, m, m, m, true, T->d_Gbig2, m, s));
     HIPCHECK(hipMemsetAsync(T->d_acc, 0, 2 * sizeof(int), s));
-    // T->muin = Ghat^{-1} Y^T A v, iteratively
+    // T->muin = Ghat^{-1} Y^T A v, iteratively; Y^T A v = (A Y)^T v from the
+    // block A Y formed above (A symmetric), with no product with A
     auto project = [&](const double* v) {
-        HIPCHECK(launch_matvec(D, v, ctx->d_q, s));
-        HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, ctx->d_q, T->d_part, TSF(T, cin), s));
+        HIPCHECK(launch_gemv_t(n, ld, T->d_AZ, m, v, T->d_part, TSF(T, cin), s));
         HIPCHECK(launch_ts_in_solve(T->d_ts, T->d_aug, m, T->d_sel, w, T->d_GinvW, T->d_Gbig2, rel,
                                     T->opt.inner_maxit, T->d_acc, s));
     };
@@ -286,8 +286,8 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     S.projections = nproj;
     S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
     S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
-    // products with A: Stage 1 and 2, r0, the loop, A v per projection, A Y for Ghat, the true residual
-    S.matvecs = w + 1 + k2 + 1 + k3 + nproj + m + 1;
+    // products with A: Stage 1 and 2, r0, the loop, A Y for Ghat, the true residual
+    S.matvecs = w + 1 + k2 + 1 + k3 + m + 1;
     const int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
     S.status = code;
     return ts_finish(ctx, T, m, k3, code, S, out);
