@@ -377,6 +377,17 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_in_step(TsDev* T, double* __r
     if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na0, rz_new / rz, false, cw, nuw, nd);
 }
 
+// gh = Ghat ph for Stage 2 when Ghat = Y^T A Y has been formed (one
+// workgroup; Ghat row-major m x m).
+__global__ __launch_bounds__(kTsThreads) void k_ts_ghat_mv(TsDev* T, const double* __restrict__ Ghat, int m) {
+    for (int k = threadIdx.x; k < m; k += kTsThreads) {
+        const double* __restrict__ g = Ghat + (size_t)k * m;
+        double s = 0.0;
+        for (int l = 0; l < m; ++l) s += g[l] * T->ph[l];
+        T->gh[k] = s;
+    }
+}
+
 // A whole projection solve in one launch, with the reduced matrix Ghat =
 // Y^T A Y formed beforehand (row-major m x m): the Galerkin start of
 // k_ts_in_init, then steps as k_ts_in_step with gh = Ghat ph computed here
@@ -776,6 +787,12 @@ hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w
                              hipStream_t s) {
     if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ts_in_step, dim3(1), dim3(kTsThreads), 0, s, T, aug, m, sel, w, GinvW);
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_ghat_mv(TsDev* T, const double* Ghat, int m, hipStream_t s) {
+    if (m < 1 || m > kTsCap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ts_ghat_mv, dim3(1), dim3(kTsThreads), 0, s, T, Ghat, m);
     return hipGetLastError();
 }
 

@@ -196,6 +196,8 @@ hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel,
                              double rel, int kinmax, hipStream_t s);
 hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
                              hipStream_t s);
+// T->gh = Ghat T->ph with Ghat = Y^T A Y formed (row-major m x m).
+hipError_t launch_ts_ghat_mv(TsDev* T, const double* Ghat, int m, hipStream_t s);
 // A whole projection solve (Galerkin start and steps) in one launch, with
 // Ghat = Y^T A Y (row-major m x m) formed beforehand; acc[0] += steps,
 // acc[1] += 1.

@@ -228,18 +228,7 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     // the projection solves' tolerance: inner_rtol, or a margin below the
     // solve's own rtol (the error a projection leaves in range(Y) stays)
     const double rel = std::max(T->opt.inner_rtol > 0.0 ? T->opt.inner_rtol : kInnerMargin * rtol, kRoundingFloor);
-    // Ghat = Y^T A Y, formed once for the system: A Y in blocks of up to
-    // kYMax columns (into the truncation's block, free here, and kept for the
-    // right-hand sides below), then the MFMA Gram of the row chunks.  The
-    // projection solves then need Ghat p only, an m x m product inside their
-    // own launch, instead of two passes over the tall Y and a matvec per step.
-    for (int c0 = 0; c0 < m; c0 += kYMax) {
-        const int kc = std::min(kYMax, m - c0);
-        HIPCHECK(launch_spmm(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, s));
-    }
-    const size_t pstride = (size_t)kTsCap * kTsCap;
-    HIPCHECK(launch_gemm_tn_parts(n, ld, T->d_Y, m, T->d_AZ, m, kGramChunks, true, T->d_Gparts, pstride, m, s));
-    HIPCHECK(launch_gram_sum(T->d_Gparts, gemm_tn_chunks(n, kGramChunks), pstride, m, m, m, true, T->d_Gbig2, m, s));
+    // Ghat = Y^T A Y and A Y (in T->d_Gbig2 and T->d_AZ) were formed before Stage 2
     HIPCHECK(hipMemsetAsync(T->d_acc, 0, 2 * sizeof(int), s));
     // T->muin = Ghat^{-1} Y^T A v, iteratively; Y^T A v = (A Y)^T v from the
     // block A Y formed above (A symmetric), with no product with A
@@ -286,8 +275,9 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
     S.projections = nproj;
     S.relres = bn > 0 ? std::sqrt(P.rr) / bn : std::sqrt(P.rr);
     S.true_relres = bn > 0 ? std::sqrt(P.true_rr) / bn : std::sqrt(P.true_rr);
-    // products with A: Stage 1 and 2, r0, the loop, A Y for Ghat, the true residual
-    S.matvecs = w + 1 + k2 + 1 + k3 + m + 1;
+    // products with A: Stage 1, r0, the loop, A Y for Ghat, the true residual
+    // (Stage 2 and the projection solves apply Ghat)
+    S.matvecs = w + 1 + 1 + k3 + m + 1;
     const int code = P.done == kFailed ? fail_code(ctx, P) : P.status;
     S.status = code;
     return ts_finish(ctx, T, m, k3, code, S, out);
@@ -344,6 +334,22 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     // Stage 2 runs to its tolerance with a rounding-level floor only (Alg. 1
     // over all of Y never corrects the error it leaves in range(Y))
     const bool iter3 = T->opt.phi == 1 && m > 0;
+    if (iter3) {
+        // Ghat = Y^T A Y, formed once for the system: A Y in blocks of up to
+        // kYMax columns (into the truncation's block, free until the
+        // truncation, and kept for the right-hand sides of the projection
+        // solves), then the MFMA Gram of the row chunks.  Stage 2 and the
+        // projection solves then need Ghat p only, an m x m product, instead
+        // of two passes over the tall Y and a matvec per step.
+        for (int c0 = 0; c0 < m; c0 += kYMax) {
+            const int kc = std::min(kYMax, m - c0);
+            HIPCHECK(launch_spmm(D, kc, T->d_Y + c0 * ld, T->d_AZ + c0 * ld, s));
+        }
+        const size_t pstride = (size_t)kTsCap * kTsCap;
+        HIPCHECK(launch_gemm_tn_parts(n, ld, T->d_Y, m, T->d_AZ, m, kGramChunks, true, T->d_Gparts, pstride, m, s));
+        HIPCHECK(launch_gram_sum(T->d_Gparts, gemm_tn_chunks(n, kGramChunks), pstride, m, m, m, true, T->d_Gbig2, m,
+                                 s));
+    }
     if (m > 0) {
         const int k2max = iter3 ? std::min(T->opt.stage2_maxit, m - w) : std::min(T->opt.stage2_maxit, kYMax - w);
         for (int i = 0; i < w; ++i)
@@ -357,13 +363,17 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
                                     hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
             if (h[1] || k >= k2max) break;   // h = {k2, done2}
-            // u = Y p and q = A u become columns of [W, X] (phi = 0), or are
-            // scratch (phi = 1: the CG vectors p, q are free before Stage 3)
-            double* u = iter3 ? ctx->d_p : T->d_B + (size_t)(w + k) * ld;
-            double* q = iter3 ? ctx->d_q : T->d_AB + (size_t)(w + k) * ld;
-            HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, ph), u, 1.0, false, s));
-            HIPCHECK(launch_matvec(D, u, q, s));
-            HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, q, T->d_part, TSF(T, gh), s));
+            // u = Y p and q = A u become columns of [W, X] (phi = 0); with
+            // phi = 1 the step needs Ghat p only
+            if (iter3) {
+                HIPCHECK(launch_ts_ghat_mv(T->d_ts, T->d_Gbig2, m, s));
+            } else {
+                double* u = T->d_B + (size_t)(w + k) * ld;
+                double* q = T->d_AB + (size_t)(w + k) * ld;
+                HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, ph), u, 1.0, false, s));
+                HIPCHECK(launch_matvec(D, u, q, s));
+                HIPCHECK(launch_gemv_t(n, ld, T->d_Y, m, q, T->d_part, TSF(T, gh), s));
+            }
             HIPCHECK(launch_ts_s2_step(T->d_ts, m, T->d_sel, w, T->d_GinvW, iter3 ? T->d_aug : nullptr, s));
         }
         k2 = h[0];
