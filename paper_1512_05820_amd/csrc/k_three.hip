@@ -261,122 +261,6 @@ __device__ void ts_in_direction(TsDev* T, const double* __restrict__ aug, int m,
     __syncthreads();
 }
 
-// Start of a projection solve with its right-hand side c in T->cin: the
-// Galerkin solution over the kept directions (mu = B nu, nu = blockdiag(...)
-// B^T c, B^T c = (c[sel], P_l^T c)), its residual rh = c - Ghat B nu, the
-// tolerance rel ||c||, and the first direction.
-__global__ __launch_bounds__(kTsThreads) void k_ts_in_init(TsDev* T, const double* __restrict__ aug, int m,
-                                                           const int* __restrict__ sel, int w,
-                                                           const double* __restrict__ GinvW, double rel,
-                                                           int kinmax) {
-    __shared__ double red[kTsWaves];
-    __shared__ double cw[kYMax], nuw[kYMax], nd[kTsCap];
-    const int t = threadIdx.x;
-    const int na = T->naug;
-    const double* __restrict__ G = aug + (size_t)kTsCap * kTsCap;
-    if (t < w) cw[t] = T->cin[sel[t]];
-    for (int l = t; l < na; l += kTsThreads) {
-        double s = 0.0;
-        for (int k = 0; k < m; ++k) s += aug[(size_t)l * kTsCap + k] * T->cin[k];
-        nd[l] = s / T->gam_aug[l];
-    }
-    __syncthreads();
-    if (t < w) {
-        double s = 0.0;
-        for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * cw[j];
-        nuw[t] = s;
-    }
-    __syncthreads();
-    double rr = 0.0, cc = 0.0;
-    for (int k = t; k < m; k += kTsThreads) {
-        const double c = T->cin[k];
-        double mu = 0.0, r = c;
-        for (int i = 0; i < w; ++i) {
-            mu += sel[i] == k ? nuw[i] : 0.0;
-            r -= T->wtgy[(size_t)i * m + k] * nuw[i];
-        }
-        for (int l = 0; l < na; ++l) {
-            mu += aug[(size_t)l * kTsCap + k] * nd[l];
-            r -= G[(size_t)l * kTsCap + k] * nd[l];
-        }
-        T->muin[k] = mu;
-        T->rh[k] = r;
-        rr += r * r;
-        cc += c * c;
-    }
-    const double rz = ts_sum(rr, red);
-    const double cn = sqrt(ts_sum(cc, red));
-    const double rn0 = sqrt(rz);
-    const double tau = rel * cn;
-    const bool done = rn0 <= tau || kinmax <= 0;
-    if (t == 0) {
-        T->rzin = rz;
-        T->rn0in = rn0;
-        T->tauin = tau;
-        T->cnin = cn;
-        T->kin = 0;
-        T->kinmax = kinmax;
-        T->naug0 = na;
-        T->knew = 0;
-        T->donein = done ? 1 : 0;
-    }
-    if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, 0.0, true, cw, nuw, nd);
-}
-
-// One step of a projection solve once gh = Ghat ph is in T->gh: mu += alpha
-// ph, rh -= alpha gh; the direction joins the augmentation (after the kept
-// ones) when it was formed from a residual of at least kTsKeepFloor of ||c||
-// (the residual is computed with cancellation against c); then the next
-// direction, projected against the
-// directions kept before this solve.  The solve's own kept directions count
-// from the moment it ends.
-__global__ __launch_bounds__(kTsThreads) void k_ts_in_step(TsDev* T, double* __restrict__ aug, int m,
-                                                           const int* __restrict__ sel, int w,
-                                                           const double* __restrict__ GinvW) {
-    __shared__ double red[kTsWaves];
-    __shared__ double cw[kYMax], nuw[kYMax], nd[kTsCap];
-    const int t = threadIdx.x;
-    if (T->donein) return;
-    double a = 0.0;
-    for (int k = t; k < m; k += kTsThreads) a += T->ph[k] * T->gh[k];
-    const double g = ts_sum(a, red);
-    const double rz = T->rzin;
-    const int na0 = T->naug0, knew = T->knew, kin = T->kin;
-    if (!(g > 0.0)) {
-        if (t == 0) {
-            T->donein = 1;
-            T->naug = na0 + knew;
-        }
-        return;
-    }
-    const double alpha = rz / g;
-    const int slot = na0 + knew;
-    const bool keep = sqrt(rz) >= kTsKeepFloor * T->cnin && slot < m;
-    double b2 = 0.0;
-    for (int k = t; k < m; k += kTsThreads) {
-        const double p = T->ph[k], gk = T->gh[k];
-        if (keep) {
-            aug[(size_t)slot * kTsCap + k] = p;
-            aug[(size_t)(kTsCap + slot) * kTsCap + k] = gk;
-        }
-        T->muin[k] += alpha * p;
-        const double r = T->rh[k] - alpha * gk;
-        T->rh[k] = r;
-        b2 += r * r;
-    }
-    const double rz_new = ts_sum(b2, red);
-    const bool done = sqrt(rz_new) <= T->tauin || kin + 1 >= T->kinmax;
-    if (t == 0) {
-        if (keep) T->gam_aug[slot] = g;
-        T->rzin = rz_new;
-        T->kin = kin + 1;
-        T->knew = knew + (keep ? 1 : 0);
-        T->donein = done ? 1 : 0;
-        if (done) T->naug = na0 + knew + (keep ? 1 : 0);
-    }
-    if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na0, rz_new / rz, false, cw, nuw, nd);
-}
-
 // gh = Ghat ph for Stage 2 when Ghat = Y^T A Y has been formed (one
 // workgroup; Ghat row-major m x m).
 __global__ __launch_bounds__(kTsThreads) void k_ts_ghat_mv(TsDev* T, const double* __restrict__ Ghat, int m) {
@@ -388,12 +272,18 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_ghat_mv(TsDev* T, const doubl
     }
 }
 
-// A whole projection solve in one launch, with the reduced matrix Ghat =
-// Y^T A Y formed beforehand (row-major m x m): the Galerkin start of
-// k_ts_in_init, then steps as k_ts_in_step with gh = Ghat ph computed here
-// instead of Y^T (A (Y ph)) from the tall products and the SpMV.  The
-// solve's scalars stay in registers (the same in every thread); acc[0]
-// accumulates the steps and acc[1] the solves.
+// A whole projection solve Ghat mu = c (c in T->cin) in one launch, with the
+// reduced matrix Ghat = Y^T A Y formed beforehand (row-major m x m).  Start:
+// the Galerkin solution over the kept directions (mu = B nu, nu =
+// blockdiag(G_W^{-1}, 1 / gam_aug) B^T c, B^T c = (c[sel], P_l^T c)), its
+// residual rh = c - Ghat B nu, the tolerance rel ||c|| and the first
+// direction.  Steps: gh = Ghat ph, mu += alpha ph, rh -= alpha gh; a
+// direction joins the augmentation (after the kept ones) when it was formed
+// from a residual of at least kTsKeepFloor of ||c|| (the residual is computed
+// with cancellation against c), then the next direction, projected against
+// the directions kept before this solve.  The solve's scalars stay in
+// registers (the same in every thread); acc[0] accumulates the steps and
+// acc[1] the solves.
 __global__ __launch_bounds__(kTsThreads) void k_ts_in_solve(TsDev* T, double* __restrict__ aug, int m,
                                                             const int* __restrict__ sel, int w,
                                                             const double* __restrict__ GinvW,
@@ -773,20 +663,6 @@ hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel
 hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW, double* aug,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_ts_s2_step, dim3(1), dim3(kBlock), 0, s, T, m, sel, w, GinvW, aug);
-    return hipGetLastError();
-}
-
-hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel, int w, const double* GinvW,
-                             double rel, int kinmax, hipStream_t s) {
-    if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ts_in_init, dim3(1), dim3(kTsThreads), 0, s, T, aug, m, sel, w, GinvW, rel, kinmax);
-    return hipGetLastError();
-}
-
-hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
-                             hipStream_t s) {
-    if (m < 1 || m > kTsCap || w < 0 || w > kYMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ts_in_step, dim3(1), dim3(kTsThreads), 0, s, T, aug, m, sel, w, GinvW);
     return hipGetLastError();
 }
 

@@ -189,18 +189,12 @@ hipError_t launch_ts_s2_init(TsDev* T, const DevState* st, int m, const int* sel
 // One Stage-2 step; aug (iterative Stage 3, else NULL) receives the kept directions.
 hipError_t launch_ts_s2_step(TsDev* T, int m, const int* sel, int w, const double* GinvW, double* aug,
                              hipStream_t s);
-// Projection solves of the iterative Stage 3 (Section 4.3.1), right-hand side
-// in T->cin: start (Galerkin solution over the kept directions, tolerance
-// rel ||c||, step cap kinmax) and one step once T->gh = Ghat T->ph.
-hipError_t launch_ts_in_init(TsDev* T, const double* aug, int m, const int* sel, int w, const double* GinvW,
-                             double rel, int kinmax, hipStream_t s);
-hipError_t launch_ts_in_step(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
-                             hipStream_t s);
 // T->gh = Ghat T->ph with Ghat = Y^T A Y formed (row-major m x m).
 hipError_t launch_ts_ghat_mv(TsDev* T, const double* Ghat, int m, hipStream_t s);
-// A whole projection solve (Galerkin start and steps) in one launch, with
-// Ghat = Y^T A Y (row-major m x m) formed beforehand; acc[0] += steps,
-// acc[1] += 1.
+// A projection solve of the iterative Stage 3 (Section 4.3.1), right-hand side
+// in T->cin, in one launch: the Galerkin start over the kept directions, then
+// steps with Ghat = Y^T A Y (row-major m x m, formed beforehand) to the
+// tolerance rel ||c|| or kinmax steps; acc[0] += steps, acc[1] += 1.
 hipError_t launch_ts_in_solve(TsDev* T, double* aug, int m, const int* sel, int w, const double* GinvW,
                               const double* Ghat, double rel, int kinmax, int* acc, hipStream_t s);
 hipError_t launch_ts_ginv_blockdiag(const double* GinvW, int w, const TsDev* T, int k2, double* GinvB,
