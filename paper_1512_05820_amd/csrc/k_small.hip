@@ -8,23 +8,63 @@ namespace podcg {
 
 constexpr int kLd = kYMax + 1;   // padded LDS row stride
 
+// Pair t of round `step` of the round-robin (tournament) ordering of me
+// players: position 0 is fixed, positions 1..me-1 rotate.  p < q; q = -1 for
+// the bye (a player index >= m, when m is odd).
+__device__ __forceinline__ void tournament_pair(int t, int step, int me, int m, int& p, int& q) {
+    int p0 = 0, p1 = me - 2 - t + step;
+    if (t > 0) {
+        p0 = t - 1 + step;
+        if (p0 >= me - 1) p0 -= me - 1;
+        ++p0;
+    }
+    if (p1 >= me - 1) p1 -= me - 1;
+    ++p1;
+    p = p0 < p1 ? p0 : p1;
+    q = p0 < p1 ? p1 : p0;
+    if (q >= m) q = -1;
+}
+
+// Rotation (c, s) that annihilates a_pq: the symmetric Schur decomposition
+// of the 2 x 2 block {p, q} (Golub & Van Loan), t = tan(theta) the root of
+// t^2 + 2 tau t - 1 = 0 of smaller magnitude, tau = (a_qq - a_pp) / (2 a_pq).
+// Written without divisions: with x = a_qq - a_pp, y = 2 a_pq (both scaled
+// by the same power of two so that the larger has magnitude in [1/2, 1)),
+// r = sqrt(x^2 + y^2), u = |x| + r and v = sign(x) y, t = v / u, so
+// c = u / sqrt(u^2 + v^2) and s = v / sqrt(u^2 + v^2).  The identity for the
+// bye or a zero a_pq.
+__device__ __forceinline__ void schur2(const double* a, int p, int q, double& c, double& sn) {
+    const int qq = q < 0 ? p : q;
+    const double apq = a[p * kLd + qq], app = a[p * kLd + p], aqq = a[qq * kLd + qq];
+    const double x0 = aqq - app, y0 = 2.0 * apq;
+    const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(x0), fabs(y0)));
+    const double x = __builtin_amdgcn_ldexp(x0, -e), y = __builtin_amdgcn_ldexp(y0, -e);
+    const double r = sqrt(x * x + y * y);
+    const double u = fabs(x) + r, v = x >= 0.0 ? y : -y;
+    const double h = rsqrt(u * u + v * v);
+    const bool rot = q >= 0 && apq != 0.0;
+    c = rot ? u * h : 1.0;
+    sn = rot ? v * h : 0.0;
+}
+
 // Jacobi eigen-decomposition of the symmetric m x m matrix a (LDS, stride
-// kLd) by one workgroup of kBlock threads; V (LDS) receives the eigenvectors
-// as columns.  Each rotation is the symmetric Schur decomposition of a 2 x 2
-// block (Golub & Van Loan).  The rotations of one sweep are grouped by the
-// round-robin (tournament) ordering: each step holds m/2 disjoint pairs, so
-// the step's whole similarity transform splits into independent 2 x 2 blocks,
-// one per thread, and the eigenvector update into independent column pairs.
-// Sweeps stop when the off-diagonal Frobenius norm drops below 1e-15 of the
-// full norm.  On exit lam[0..m) holds the eigenvalues in decreasing order, V
-// is permuted to match, and each eigenvector is signed so that its entry of
-// largest magnitude (first such index) is positive.
-__device__ void block_jacobi(double* a, double* V, double* lam, int m) {
-    __shared__ double cs[2 * (kYMax / 2 + 1)];
-    __shared__ int pq[2 * (kYMax / 2 + 1)];
+// kLd) by one workgroup of kBlock threads; b is LDS scratch of the same
+// shape; V (LDS, may be null) receives the eigenvectors as columns.  The
+// rotations of one sweep are grouped by the round-robin ordering: each step
+// holds m/2 disjoint pairs, so the step's whole similarity transform splits
+// into independent 2 x 2 blocks, one per thread, and the eigenvector update
+// into independent column pairs.  Every thread forms the rotations it applies
+// from the step's input matrix itself, and writes its block into the other
+// buffer, so a step costs one barrier.  Sweeps stop when the off-diagonal
+// Frobenius norm drops below 1e-15 of the full norm.  On exit lam[0..m) holds
+// the eigenvalues in decreasing order, V is permuted to match, and each
+// eigenvector is signed so that its entry of largest magnitude (first such
+// index) is positive.
+__device__ void block_jacobi(double* a, double* b, double* V, double* lam, int m) {
     __shared__ double red[kWavesPerBlock + 1];
     const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += kBlock) V[(e / m) * kLd + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+    if (V)
+        for (int e = tid; e < m * m; e += kBlock) V[(e / m) * kLd + e % m] = (e / m == e % m) ? 1.0 : 0.0;
     double f[1] = {0.0};
     for (int e = tid; e < m * m; e += kBlock) {
         const double v = a[(e / m) * kLd + e % m];
@@ -34,106 +74,59 @@ __device__ void block_jacobi(double* a, double* V, double* lam, int m) {
     const double fro = red[0];
     const int me = m + (m & 1);          // players, with a bye when m is odd
     const int npair = me / 2;
-    // this thread's 2 x 2 block of pairs (t, u) (npair^2 <= kBlock), and its
-    // entry kq of the V columns of pairs u0 and u0 + 8 (m <= 32)
+    // this thread's 2 x 2 block of pairs (t, u) (npair^2 <= kBlock)
     const bool has_blk = tid < npair * npair;
     const int bt = tid / npair, bu = tid % npair;
-    const int kq = tid & 31, u0 = tid >> 5;
     __syncthreads();
     for (int sweep = 0; sweep < 100 && m > 1; ++sweep) {
         double o[1] = {0.0};
-        if (kq < m)
-            for (int i = u0; i < m; i += kBlock / 32)
-                if (i != kq) o[0] += a[i * kLd + kq] * a[i * kLd + kq];
+        for (int e = tid; e < m * m; e += kBlock) {
+            const int i = e / m, j = e % m;
+            if (i != j) o[0] += a[i * kLd + j] * a[i * kLd + j];
+        }
         block_sum<1>(o, red);
         const double off = red[0];
         __syncthreads();
         if (off <= 1.0e-30 * fro) break;
         for (int step = 0; step < me - 1; ++step) {
-            // pairs of this round: position 0 is fixed, the others rotate
-            if (tid < npair) {
-                int p0 = 0, p1 = me - 2 - tid + step;
-                if (tid > 0) {
-                    p0 = tid - 1 + step;
-                    if (p0 >= me - 1) p0 -= me - 1;
-                    ++p0;
-                }
-                if (p1 >= me - 1) p1 -= me - 1;
-                ++p1;
-                const int p = p0 < p1 ? p0 : p1;
-                int q = p0 < p1 ? p1 : p0;
-                double c = 1.0, sn = 0.0;
-                if (q < m) {
-                    const double apq = a[p * kLd + q];
-                    if (apq != 0.0) {
-                        const double tau = (a[q * kLd + q] - a[p * kLd + p]) / (2.0 * apq);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * c;
-                    }
-                } else {
-                    q = -1;                      // bye: index p keeps the identity
-                }
-                pq[2 * tid] = p;
-                pq[2 * tid + 1] = q;
-                cs[2 * tid] = c;
-                cs[2 * tid + 1] = sn;
-            }
-            __syncthreads();
-            // A <- J^T A J with J the direct sum of the pairs' rotations: the
+            // b <- J^T a J with J the direct sum of the pairs' rotations: the
             // 2 x 2 block of rows {p_t, q_t} and columns {p_u, q_u} becomes
-            // J_t^T A_tu J_u (rows first, then columns).  The blocks partition
-            // A, and V's column pairs are disjoint, so every thread loads all
-            // of its entries before it stores any.
-            double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
-            int pt = 0, qt = -1, pu = 0, qu = -1;
+            // J_t^T a_tu J_u (rows first, then columns); V <- V J in place,
+            // rows t and t + npair of the column pair u (each entry one owner)
             if (has_blk) {
-                pt = pq[2 * bt];
-                qt = pq[2 * bt + 1];
-                pu = pq[2 * bu];
-                qu = pq[2 * bu + 1];
-                b0 = a[pt * kLd + pu];
-                if (qu >= 0) b1 = a[pt * kLd + qu];
-                if (qt >= 0) b2 = a[qt * kLd + pu];
-                if (qt >= 0 && qu >= 0) b3 = a[qt * kLd + qu];
-            }
-            double vp[2] = {0.0, 0.0}, vq[2] = {0.0, 0.0};
-            int vpu[2] = {0, 0}, vqu[2] = {-1, -1};
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int u = u0 + 8 * r;
-                if (kq < m && u < npair) {
-                    vpu[r] = pq[2 * u];
-                    vqu[r] = pq[2 * u + 1];
-                    vp[r] = V[kq * kLd + vpu[r]];
-                    if (vqu[r] >= 0) vq[r] = V[kq * kLd + vqu[r]];
-                }
-            }
-            if (has_blk) {
-                const double ct = cs[2 * bt], st = cs[2 * bt + 1];
-                const double cu = cs[2 * bu], su = cs[2 * bu + 1];
+                int pt, qt, pu, qu;
+                tournament_pair(bt, step, me, m, pt, qt);
+                tournament_pair(bu, step, me, m, pu, qu);
+                double ct, st, cu, su;
+                schur2(a, pt, qt, ct, st);
+                schur2(a, pu, qu, cu, su);
+                const double b0 = a[pt * kLd + pu];
+                const double b1 = qu >= 0 ? a[pt * kLd + qu] : 0.0;
+                const double b2 = qt >= 0 ? a[qt * kLd + pu] : 0.0;
+                const double b3 = (qt >= 0 && qu >= 0) ? a[qt * kLd + qu] : 0.0;
                 const double rp0 = ct * b0 - st * b2;
                 const double rp1 = ct * b1 - st * b3;
                 const double rq0 = st * b0 + ct * b2;
                 const double rq1 = st * b1 + ct * b3;
                 const bool zero = bt == bu && st != 0.0;   // the pair's own a_pq
-                a[pt * kLd + pu] = cu * rp0 - su * rp1;
-                if (qu >= 0) a[pt * kLd + qu] = zero ? 0.0 : su * rp0 + cu * rp1;
+                b[pt * kLd + pu] = cu * rp0 - su * rp1;
+                if (qu >= 0) b[pt * kLd + qu] = zero ? 0.0 : su * rp0 + cu * rp1;
                 if (qt >= 0) {
-                    a[qt * kLd + pu] = zero ? 0.0 : cu * rq0 - su * rq1;
-                    if (qu >= 0) a[qt * kLd + qu] = su * rq0 + cu * rq1;
+                    b[qt * kLd + pu] = zero ? 0.0 : cu * rq0 - su * rq1;
+                    if (qu >= 0) b[qt * kLd + qu] = su * rq0 + cu * rq1;
                 }
-            }
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int u = u0 + 8 * r;
-                if (kq < m && u < npair) {
-                    const double c = cs[2 * u], sn = cs[2 * u + 1];
-                    V[kq * kLd + vpu[r]] = c * vp[r] - sn * vq[r];
-                    if (vqu[r] >= 0) V[kq * kLd + vqu[r]] = sn * vp[r] + c * vq[r];
-                }
+                if (V)
+                    for (int kq = bt; kq < m; kq += npair) {
+                        const double xp = V[kq * kLd + pu];
+                        const double xq = qu >= 0 ? V[kq * kLd + qu] : 0.0;
+                        V[kq * kLd + pu] = cu * xp - su * xq;
+                        if (qu >= 0) V[kq * kLd + qu] = su * xp + cu * xq;
+                    }
             }
             __syncthreads();
+            double* t = a;
+            a = b;
+            b = t;
         }
     }
     if (tid < m) lam[tid] = a[tid * kLd + tid];
@@ -145,7 +138,7 @@ __device__ void block_jacobi(double* a, double* V, double* lam, int m) {
             if (lam[j] > lam[best]) best = j;
         __syncthreads();
         if (best != i) {
-            if (tid < m) {
+            if (V && tid < m) {
                 const double t = V[tid * kLd + i];
                 V[tid * kLd + i] = V[tid * kLd + best];
                 V[tid * kLd + best] = t;
@@ -158,7 +151,7 @@ __device__ void block_jacobi(double* a, double* V, double* lam, int m) {
         }
         __syncthreads();
     }
-    if (tid < m) {
+    if (V && tid < m) {
         int big = 0;
         for (int k = 1; k < m; ++k)
             if (fabs(V[k * kLd + tid]) > fabs(V[big * kLd + tid])) big = k;
@@ -177,7 +170,7 @@ __device__ void block_jacobi(double* a, double* V, double* lam, int m) {
 // and the largest and smallest kept eigenvalue.
 __device__ void reduced_factor(double* G, int m, double* R, double* Ginv, double* lam, DevState* st,
                                double* report) {
-    __shared__ double g[kYMax * kLd], rr[kYMax * kLd], ri[kYMax * kLd], v[kYMax * kLd];
+    __shared__ double g[kYMax * kLd], rr[kYMax * kLd], ri[kYMax * kLd], v[kYMax * kLd], vb[kYMax * kLd];
     __shared__ double lm[kYMax];
     __shared__ int kept_s;
     const int tid = threadIdx.x;
@@ -230,7 +223,7 @@ __device__ void reduced_factor(double* G, int m, double* R, double* Ginv, double
     __syncthreads();
     for (int e = tid; e < y * y; e += kBlock) v[(e / y) * kLd + e % y] = g[(e / y) * kLd + e % y];
     __syncthreads();
-    if (y > 0) block_jacobi(v, ri, lm, y);
+    if (y > 0) block_jacobi(v, vb, nullptr, lm, y);   // eigenvalues only
     if (tid < y) lam[tid] = lm[tid];
     if (tid == 0) {
         st->y = y;
@@ -258,7 +251,7 @@ struct Weights {
 __global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int count, Weights wt,
                                                       int rank_max, double rank_rtol, double energy,
                                                       double* T, double* lam_out, int* y_out) {
-    __shared__ double a[kYMax * kLd], V[kYMax * kLd];
+    __shared__ double a[kYMax * kLd], b[kYMax * kLd], V[kYMax * kLd];
     __shared__ double lam[kYMax];
     __shared__ int y_s;
     const int tid = threadIdx.x;
@@ -270,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int cou
         a[i * kLd + j] = 0.5 * (gij + gji);
     }
     __syncthreads();
-    block_jacobi(a, V, lam, m);
+    block_jacobi(a, b, V, lam, m);
     if (tid == 0) {
         int y = 0;
         if (lam[0] > 0.0)
