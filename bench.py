@@ -12,7 +12,11 @@ The same sequence is then solved with plain Jacobi PCG from the library
 (warm start x_{j-1} and cold start 0, median of five sequences each) for the
 wall-time comparison, and the config-1 sequence (32 x 32, 10 systems) is
 timed through the one-workgroup solve and the multi-kernel loop.  The
-oracle's baseline covers the whole config-2 sequence.
+oracle's baseline covers the whole config-2 sequence.  Last, one short pass
+of each other workload (the three-stage method on the same sequence, mixed
+precision on the config-3 elasticity sequence, the config-4 batch, the
+config-5 adjoint gradient) goes into `other_workloads`; --no-workloads skips
+them, and --workload NAME gives each its own full line.
 
 Prints one JSON line.  The value is milliseconds per sequence (lower is
 better).  The roofline object covers the loop kernel with the largest share
@@ -237,23 +241,23 @@ def bench_config1(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_config3(args):
+def run_config3(args, quick=False):
     """Mixed precision at the stated size: Q1 elasticity 64^3 x 3 dof, 30 systems.
 
     Times whole sequences of augmented PCG (and plain PCG, warm start) in FP64
     and in mixed precision (FP32 inner solve, FP64 refinement), for the stated
     load (scaled, collinear) and for the moving-load variant, and states the
-    error of system 1 against the FP64 oracle."""
+    error of system 1 against the FP64 oracle.  quick: the moving-load
+    augmented sequences only, one pass each, no oracle."""
     import torch
     import paper_1512_05820_amd as P
-    import oracle
     from problems import config3
 
     torch.cuda.set_device(0)
     out = {"metric": METRIC, "unit": "ms/sequence", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "f32 inner / f64 refinement", "vs_baseline": None}
     results = {}
-    for variant in ("scale", "moving"):
+    for variant in (("moving",) if quick else ("scale", "moving")):
         cfg = config3(variant=variant, steps=args.systems if args.systems != 50 else 30)
         vals = torch.from_numpy(cfg.matrix_values(1)).cuda()
         rowptr, colind = torch.from_numpy(cfg.rowptr).cuda(), torch.from_numpy(cfg.colind).cuda()
@@ -261,8 +265,8 @@ def bench_config3(args):
         for precision in ("mixed", "fp64"):
             ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000, precision=precision)
             ctx.set_matrix(vals, rowptr, colind)
-            for method in ("aug", "plain"):
-                for rep in range(1 + args.warmup):
+            for method in (("aug",) if quick else ("aug", "plain")):
+                for rep in range(1 if quick else 1 + args.warmup):
                     ctx.reset_snapshots()
                     ctx.set_basis(None)
                     torch.cuda.synchronize()
@@ -294,6 +298,13 @@ def bench_config3(args):
                     results[key]["x1"] = x1.cpu().numpy()
                 log(key, {k: v for k, v in results[key].items() if k != "x1"})
             ctx.close()
+    if quick:
+        cfg = config3(variant="moving", steps=args.systems if args.systems != 50 else 30)
+        return {"workload": cfg.name + "_moving", "unit": "ms/sequence", "n": cfg.n, "nnz": cfg.nnz,
+                "systems": cfg.steps, "omega": cfg.omega, "rank_max": cfg.rank, "rel_tol": cfg.tol,
+                "value_is": "moving-load variant, mixed precision, augmented", "value": results["moving/mixed/aug"]["ms"],
+                "runs": results}
+    import oracle
     # error of system 1 against the FP64 oracle (solved to 1e-12)
     cfg = config3()
     A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(1))
@@ -315,15 +326,20 @@ def bench_config3(args):
                 "rel_error_vs_fp64_oracle_system1": errs,
                 "oracle_system1": {"iters": so.iters, "seconds": round(cpu_s, 2),
                                    "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}})
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_config4(args):
+def bench_config3(args):
+    print(json.dumps(run_config3(args)), flush=True)
+
+
+def run_config4(args, quick=False):
     """Batched: 64 independent 2-D diffusion sequences (sides 64..512), 20 systems
     each, advanced together by the batched loop (podcg_batch_solve) after the
     autotuner has picked work-item sizes and grid.  Compared with the same
     batch solved by plain Jacobi PCG and with the 64 sequences solved one
-    context at a time (single-sequence path)."""
+    context at a time (single-sequence path).  quick: the batched augmented
+    sequences only (one warm-up pass, one timed)."""
     import torch
     import paper_1512_05820_amd as P
     from problems import config4
@@ -393,10 +409,19 @@ def bench_config4(args):
             ms.append(1e3 * (time.perf_counter() - t1))
         return min(ms), sts
 
-    for _ in range(args.warmup):
+    for _ in range(1 if quick else args.warmup):
         batched(False)
-    aug_ms, aug = timed(lambda: batched(False), max(1, args.steps))
+    aug_ms, aug = timed(lambda: batched(False), 1 if quick else max(1, args.steps))
     log(f"batched augmented: {aug_ms:.1f} ms")
+    if quick:
+        worst = max(s["true_relres"] for sts in aug for s in sts)
+        batch.close()
+        for k in ctxs:
+            k.close()
+        return {"workload": "config4_batched", "unit": "ms per batch of sequences", **cfg.describe(),
+                "value": round(aug_ms, 1), "iters_aug": sum(s["iters"] for sts in aug for s in sts),
+                "batched_solve_ms": round(sum(sts[0]["solve_ms"] for sts in aug), 1),
+                "max_true_relres": worst, "tuned_options": tuned}
     plain_ms, plain = timed(lambda: batched(True), 1)
     log(f"batched plain: {plain_ms:.1f} ms")
     seq_ms, seq = (None, None) if args.no_plain else timed(sequential, 1)
@@ -426,25 +451,34 @@ def bench_config4(args):
            "batched_solve_ms": round(solve_ms, 1),
            "loop_GBps_lower_bound": round(loop_bytes / (solve_ms * 1e-3) / 1e9, 1),
            "tuned_options": tuned, "tune_ms_per_32_iters": round(tune_ms, 3)}
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_three_stage(args):
+def bench_config4(args):
+    print(json.dumps(run_config4(args)), flush=True)
+
+
+def run_three_stage(args, quick=False, inputs=None):
     """The paper's full three-stage method (Alg. 3) on the 3-D diffusion
     sequence, next to the POD-of-solutions augmented PCG and plain PCG on the
     same systems.  Variants: ybar 200, POD to 100 vectors, stage-1 basis 5,
     rho 0 (the POD(5,95) family), Stage 3 over [W, X] with the reused
     block-diagonal factor or the computed Gram, and the iterative Stage 3 over
-    all of Y (phi = 1, Stage 2 to its tolerance)."""
+    all of Y (phi = 1, Stage 2 to its tolerance).  quick: the reused factor
+    and the iterative Stage 3 only.  inputs: (cfg, matrices on the device,
+    rowptr, colind) already resident."""
     import torch
     import paper_1512_05820_amd as P
     from problems import config2
 
     torch.cuda.set_device(0)
-    cfg = config2(N=args.N, steps=args.systems)
-    vals_dev = [torch.from_numpy(cfg.matrix_values(j)).cuda() for j in range(1, cfg.steps + 1)]
-    rowptr = torch.from_numpy(cfg.rowptr).cuda()
-    colind = torch.from_numpy(cfg.colind).cuda()
+    if inputs is None:
+        cfg = config2(N=args.N, steps=args.systems)
+        vals_dev = [torch.from_numpy(cfg.matrix_values(j)).cuda() for j in range(1, cfg.steps + 1)]
+        rowptr = torch.from_numpy(cfg.rowptr).cuda()
+        colind = torch.from_numpy(cfg.colind).cuda()
+    else:
+        cfg, vals_dev, rowptr, colind = inputs
     ctx = P.PodCG(cfg.n, omega=cfg.omega, rank_max=cfg.rank, maxit=20000)
     ctx.set_matrix(vals_dev[0], rowptr, colind)
     runs = {}
@@ -456,10 +490,11 @@ def bench_three_stage(args):
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t1), out
 
-    ms, st = timed(lambda: run_sequence(torch, ctx, cfg, vals_dev, "aug"))
-    runs["pod_of_solutions"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
-    log("pod_of_solutions", runs["pod_of_solutions"])
-    if not args.no_plain:
+    if not quick:
+        ms, st = timed(lambda: run_sequence(torch, ctx, cfg, vals_dev, "aug"))
+        runs["pod_of_solutions"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
+        log("pod_of_solutions", runs["pod_of_solutions"])
+    if not args.no_plain and not quick:
         ms, st = timed(lambda: run_sequence(torch, ctx, cfg, vals_dev, "plain", warm=True))
         runs["plain_warm"] = {"ms": round(ms, 1), "iters": sum(s["iters"] for s in st)}
         log("plain_warm", runs["plain_warm"])
@@ -481,7 +516,8 @@ def bench_three_stage(args):
             x_prev = x
         return sts
 
-    for gram, phi in (("blockdiag", 0), ("exact", 0), ("iterative", 1)):
+    for gram, phi in ((("blockdiag", 0), ("iterative", 1)) if quick else
+                      (("blockdiag", 0), ("exact", 0), ("iterative", 1))):
         ms, sts = timed(lambda: three_stage("blockdiag" if phi else gram, phi))
         runs[f"three_stage_{gram}"] = {
             "ms": round(ms, 1),
@@ -500,7 +536,14 @@ def bench_three_stage(args):
         }
         log(f"three_stage_{gram}", {k: v for k, v in runs[f"three_stage_{gram}"].items()
                                     if not k.endswith("per_system")})
+    ctx.close()
     v = runs["three_stage_blockdiag"]["ms"]
+    if quick:
+        return {"workload": "three_stage_" + cfg.name, "unit": "ms/sequence", "n": cfg.n, "nnz": cfg.nnz,
+                "systems": cfg.steps, "rel_tol": cfg.tol, "ybar": 200, "y_trunc": 100, "w_max": 5,
+                "value_is": "Stage 3 with the reused block-diagonal factor", "value": v,
+                "runs": {k: {kk: vv for kk, vv in r.items() if not kk.endswith("per_system")}
+                         for k, r in runs.items()}}
     out = {"metric": METRIC, "value": v, "unit": "ms/sequence", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": v, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
@@ -508,13 +551,18 @@ def bench_three_stage(args):
                       "systems": cfg.steps, "rel_tol": cfg.tol, "ybar": 200, "y_trunc": 100, "w_max": 5,
                       "rho": 0.0, "stage2_factor": 1e-4},
            "runs": runs}
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_config5(args):
+def bench_three_stage(args):
+    print(json.dumps(run_three_stage(args)), flush=True)
+
+
+def run_config5(args, quick=False):
     """Differentiation at the stated size: 96^3 diffusion, 200 systems, outputs at
     256 dofs, gradients of J = sum_j w_j . q_j with respect to log kappa and the
-    source, adjoint solves reusing the recycled bases, checkpoints every 20."""
+    source, adjoint solves reusing the recycled bases, checkpoints every 20.
+    quick: one pass, no warm-up."""
     import torch
     import paper_1512_05820_amd as P
     from paper_1512_05820_amd.adjoint import RecycledSequence, SequenceSpec
@@ -545,7 +593,7 @@ def bench_config5(args):
     w = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).standard_normal(
         (cfg.steps, cfg.outputs.size))).cuda()
     rec = {}
-    for rep in range(1 + args.warmup):
+    for rep in range(1 if quick else 1 + args.warmup):
         th = theta.clone().requires_grad_(True)
         s = torch.full((cfg.n,), cfg.source, dtype=torch.float64, device="cuda", requires_grad=True)
         torch.cuda.synchronize()
@@ -575,7 +623,17 @@ def bench_config5(args):
            "data": "synthetic", "config": {**cfg.describe(), "adjoint_basis": args.adjoint_basis},
            **rec,
            "forward_iters": fwd_it, "adjoint_iters": adj_it}
-    print(json.dumps(out), flush=True)
+    solver.close()
+    adj.close()
+    if quick:
+        return {"workload": "config5_adjoint", "unit": "ms per forward+backward sequence",
+                **{k: out[k] for k in ("value", "config", "forward_ms", "backward_ms", "forward_iters",
+                                       "adjoint_iters", "grad_theta_norm", "grad_s_norm")}}
+    return out
+
+
+def bench_config5(args):
+    print(json.dumps(run_config5(args)), flush=True)
 
 
 def main():
@@ -591,6 +649,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=5, help="plain-PCG sequences timed (median reported)")
     ap.add_argument("--no-config1", action="store_true", help="skip the config-1 sequences of the default run")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the short runs of configs 3-5 and the three-stage method in the default run")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the context run of the other direction form")
     ap.add_argument("--projection", default="implicit", choices=["implicit", "explicit"],
@@ -737,6 +797,24 @@ def main():
               **{k: {"ms": v["ms"], "iters": v["iters"], "us_per_iteration_gpu": v["us_per_iteration_gpu"]}
                  for k, v in r1.items()}}
 
+    # the other workloads, one short pass each, so that the default line
+    # records them too (their own lines: --workload config3 / config4 /
+    # config5 / three_stage)
+    others = None
+    if not args.no_workloads and cfg.N == 128 and cfg.steps == 50:
+        ctx.close()
+        others = {}
+        for name, fn in (("three_stage", lambda: run_three_stage(args, quick=True,
+                                                                 inputs=(cfg, vals_dev, rowptr, colind))),
+                         ("config3", lambda: run_config3(args, quick=True)),
+                         ("config4", lambda: run_config4(args, quick=True)),
+                         ("config5", lambda: run_config5(args, quick=True))):
+            t1 = time.perf_counter()
+            others[name] = fn()
+            others[name]["wall_s"] = round(time.perf_counter() - t1, 1)
+            log(f"{name}: {others[name]['value']} {others[name]['unit']} ({others[name]['wall_s']} s)")
+            torch.cuda.empty_cache()
+
     aug_iters = sum(s["iters"] for s in aug_stats)
     rec = {
         "metric": METRIC,
@@ -779,6 +857,7 @@ def main():
                      "timed_launches": launches},
         "cpu_baseline": cpu,
         "config1_sequence": c1,
+        "other_workloads": others,
     }
     print(json.dumps(rec), flush=True)
 
