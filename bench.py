@@ -335,8 +335,9 @@ def bench_config3(args):
 
 def run_config4(args, quick=False):
     """Batched: 64 independent 2-D diffusion sequences (sides 64..512), 20 systems
-    each, advanced together by the batched loop (podcg_batch_solve) after the
-    autotuner has picked work-item sizes and grid.  Compared with the same
+    each, advanced together (podcg_batch_set_values, podcg_batch_solve,
+    podcg_batch_push_build per system) after the autotuner has picked
+    work-item sizes and grid.  Compared with the same
     batch solved by plain Jacobi PCG and with the 64 sequences solved one
     context at a time (single-sequence path).  quick: the batched augmented
     sequences only (one warm-up pass, one timed)."""
@@ -368,19 +369,17 @@ def run_config4(args, quick=False):
             k.set_basis(None)
 
     def batched(plain):
+        # every step of the sequence batched: values, solve, snapshot push + POD build
         reset()
         sts = []
         for j in range(steps):
-            for k, v in zip(ctxs, vals):
-                k.set_matrix(v[j])
+            batch.set_values([v[j] for v in vals])
             xs = [torch.zeros(m.n, dtype=torch.float64, device="cuda") for m in mem]
             rc, st = batch.solve([r[j] for r in rhs], xs, [m.tol for m in mem], plain=plain)
             if rc not in (0, 2):
                 raise RuntimeError(f"batched system {j + 1}: {rc}")
             if not plain:
-                for k, x in zip(ctxs, xs):
-                    k.push_snapshot(x)
-                    k.build_pod(wait=False)
+                batch.push_build(xs)
             sts.append([s.as_dict() for s in st])
         return sts
 

@@ -253,7 +253,8 @@ int podcg_stream_triad(podcg_ctx* ctx, const double* a, const double* b, double*
  * contexts (its members, each with its own matrix, snapshots and basis, all on
  * one device, precision 0); every member still follows the sequence
  * semantics above (set_matrix / solve / push_snapshot / build_pod on the
- * member itself).  podcg_batch_solve replaces the members' podcg_solve calls
+ * member itself, or podcg_batch_set_values / podcg_batch_push_build for all
+ * members at once).  podcg_batch_solve replaces the members' podcg_solve calls
  * for one system each: every member gets its basis setup and Stage 1
  * (Alg. 2), then the loop of augmented PCG (Alg. 1) runs for all members at
  * once -- per iteration one launch of each loop kernel over a work list of row
@@ -296,6 +297,26 @@ int podcg_batch_get_options(podcg_batch* batch, podcg_batch_options* opt);
  * code (an error, else NOT_CONVERGED, else RANK_REDUCED, else OK). */
 int podcg_batch_solve(podcg_batch* batch, const double* const* b, double* const* x,
                       const double* rtol, int32_t plain, podcg_stats* stats);
+
+/* New matrix values for every member, with each member's cached pattern:
+ * the values-only podcg_set_matrix of all members at once (one ingest launch
+ * over all members, one synchronisation).  nnz: host array of `count` entry
+ * counts; vals: host array of `count` device pointers (member m's CSR values,
+ * nnz[m] float64).  Returns OK, or the first of NONFINITE / NOT_SPD found
+ * (that member keeps no matrix and names the cause in its own last error; the
+ * others take their values), or INVALID_ARG (a null pointer), NO_MATRIX (a
+ * member without a pattern), SIZE (nnz[m] differs from the member's pattern);
+ * after INVALID_ARG, NO_MATRIX or SIZE no member changed. */
+int podcg_batch_set_values(podcg_batch* batch, const int64_t* nnz, const double* const* vals);
+
+/* After a solve of every member (Section 3.3, Alg. pod_evd): push s[m]
+ * (device, n_m float64) as member m's newest snapshot and build its next basis,
+ * as podcg_push_snapshot + podcg_build_pod(rank_out = NULL) on each member,
+ * with the copies, the Grams S^T A S, the eigen-solves and the bases W = S T
+ * each one launch over all members.  Returns without waiting; a member's rank
+ * is taken when a later call needs it.  Errors: INVALID_ARG (a null pointer),
+ * NO_MATRIX, HIP. */
+int podcg_batch_push_build(podcg_batch* batch, const double* const* s);
 
 /* Autotuner: times `iters` loop iterations of all members (Stage 1 first,
  * tolerance 0 so that no member stops early) for candidate work-item sizes and

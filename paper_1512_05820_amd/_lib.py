@@ -21,7 +21,7 @@ EXPORTED = [
     "podcg_strerror", "podcg_last_error",
     "podcg_batch_default_options", "podcg_batch_create", "podcg_batch_destroy",
     "podcg_batch_set_options", "podcg_batch_get_options", "podcg_batch_solve", "podcg_batch_tune",
-    "podcg_batch_last_error",
+    "podcg_batch_set_values", "podcg_batch_push_build", "podcg_batch_last_error",
     "podcg_ts_default_options", "podcg_ts_enable", "podcg_ts_solve", "podcg_ts_get_state",
     "podcg_ts_set_state",
 ]
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
                               C.c_int),
         "podcg_batch_tune": ([P, C.POINTER(P), C.POINTER(P), I32, C.POINTER(BatchOptions),
                              C.POINTER(D)], C.c_int),
+        "podcg_batch_set_values": ([P, C.POINTER(C.c_int64), C.POINTER(P)], C.c_int),
+        "podcg_batch_push_build": ([P, C.POINTER(P)], C.c_int),
         "podcg_batch_last_error": ([P], C.c_char_p),
         "podcg_ts_default_options": ([C.POINTER(TsOptions)], None),
         "podcg_ts_enable": ([P, C.POINTER(TsOptions)], C.c_int),

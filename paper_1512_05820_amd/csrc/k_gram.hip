@@ -223,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_gram(DevBufs B, int k, const do
 // Batched basis setup: A W and G = W^T A W of every member with `setup` set,
 // over the SpMV work list (items are slice ranges of one member).  Each item
 // leaves its partial Gram in the member's partial slots; the member's last
-// item to arrive sums them in item order into the member's G.
+// item to arrive sums them in item order into the member's G.  A member table
+// with AW null forms the Gram only (the POD Gram S^T A S, with W = S).
 template <int KS>
 __global__ __launch_bounds__(kBlock) void k_batch_spmm_gram(const BatchMember* __restrict__ mem,
                                                             const BatchSetup* __restrict__ su,
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmm_gram(const BatchMember* _
         const int nsl = it.end - it.begin;
         for (int q = 0; q < nsl; q += kWavesPerBlock) {
             const int s = __builtin_amdgcn_readfirstlane(q + wid < nsl ? it.begin + q + wid : M.B.nslices);
-            gram_slice<KS>(M.B, k, M.W, const_cast<double*>(M.AW), 1, s, d, tw);
+            gram_slice<KS>(M.B, k, M.W, const_cast<double*>(M.AW), M.AW != nullptr, s, d, tw);
         }
         const int nit = M.spmv_items;
         double* part = M.B.part;

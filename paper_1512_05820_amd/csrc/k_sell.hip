@@ -215,20 +215,16 @@ __global__ __launch_bounds__(kBlock) void k_fill_offsets16(int n, int nslices, c
     }
 }
 
-// SELL values from CSR values, and dinv = 1 / (sum of the diagonal entries).
-// flag |= 4: a diagonal entry missing or not positive; |= 8: non-finite value.
-__global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
-                                                        const int64_t* __restrict__ sptr,
-                                                        const int* __restrict__ cols,
-                                                        const int* __restrict__ map,
-                                                        const uint8_t* __restrict__ sflag,
-                                                        const int* __restrict__ soff,
-                                                        const double* __restrict__ csr_vals,
-                                                        double* __restrict__ vals,
-                                                        double* __restrict__ dinv, int* flag) {
-    const int total = nslices * kSlice;
+// SELL values of one stored row (row < nslices * 64) from the CSR values, and
+// dinv[row] = 1 / (sum of its diagonal entries).  Returns the flags: 4 a
+// diagonal entry missing or not positive, 8 a non-finite value.
+__device__ __forceinline__ int fill_values_row(int row, int n, const int64_t* __restrict__ sptr,
+                                               const int* __restrict__ cols, const int* __restrict__ map,
+                                               const uint8_t* __restrict__ sflag, const int* __restrict__ soff,
+                                               const double* __restrict__ csr_vals, double* __restrict__ vals,
+                                               double* __restrict__ dinv) {
     int bad = 0;
-    for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock) {
+    {
         const int s = row / kSlice, lane = row % kSlice;   // s is wave-uniform
         const int64_t base = sptr[s];
         const int w = (int)((sptr[s + 1] - base) / kSlice);
@@ -273,7 +269,45 @@ __global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
             dinv[row] = 0.0;
         }
     }
+    return bad;
+}
+
+// SELL values from CSR values, and dinv = 1 / (sum of the diagonal entries).
+// flag |= 4: a diagonal entry missing or not positive; |= 8: non-finite value.
+__global__ __launch_bounds__(kBlock) void k_fill_values(int n, int nslices,
+                                                        const int64_t* __restrict__ sptr,
+                                                        const int* __restrict__ cols,
+                                                        const int* __restrict__ map,
+                                                        const uint8_t* __restrict__ sflag,
+                                                        const int* __restrict__ soff,
+                                                        const double* __restrict__ csr_vals,
+                                                        double* __restrict__ vals,
+                                                        double* __restrict__ dinv, int* flag) {
+    const int total = nslices * kSlice;
+    int bad = 0;
+    for (int row = blockIdx.x * kBlock + threadIdx.x; row < total; row += gridDim.x * kBlock)
+        bad |= fill_values_row(row, n, sptr, cols, map, sflag, soff, csr_vals, vals, dinv);
     if (bad) atomicOr(flag, bad);
+}
+
+// Batched value ingest: every member's SELL values and dinv from its CSR
+// values (aux.src), over the SpMV work list (slice ranges of one member).
+__global__ __launch_bounds__(kBlock) void k_batch_fill_values(const BatchMember* __restrict__ mem,
+                                                              const BatchAux* __restrict__ aux,
+                                                              const BatchItem* __restrict__ items, int nitems) {
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchMember& M = mem[it.member];
+        const BatchAux& A = aux[it.member];
+        int bad = 0;
+        for (int row = it.begin * kSlice + (int)threadIdx.x; row < it.end * kSlice; row += kBlock)
+            bad |= fill_values_row(row, M.B.n, M.B.sptr, M.B.cols, A.map, M.B.sflag, M.B.soff, A.src, A.vals,
+                                   A.dinv);
+        if (bad) atomicOr(A.flag, bad);
+    }
 }
 
 // out[e] = scale * u[row(e)] * v[col(e)] for every stored CSR entry e, in CSR
@@ -517,6 +551,14 @@ hipError_t launch_fill_values(int n, int nslices, const int64_t* sptr, const int
                               double* vals, double* dinv, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_values, dim3(grid_for((int64_t)nslices * kSlice, 8192)), dim3(kBlock),
                        0, s, n, nslices, sptr, cols, map, sflag, soff, csr_vals, vals, dinv, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fill_values(const BatchMember* mem, const BatchAux* aux, const BatchItem* items,
+                                    int nitems, int grid, hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_fill_values, dim3(grid < nitems ? grid : nitems), dim3(kBlock), 0, s, mem, aux,
+                       items, nitems);
     return hipGetLastError();
 }
 

@@ -247,10 +247,10 @@ struct Weights {
 // POD coefficients (Alg. pod_evd): Gbar = diag(w) Gs diag(w), symmetrised;
 // Gbar = V diag(lam) V^T; y = #{lam_i > rank_rtol lam_1}, capped by rank_max
 // and the energy criterion; T = diag(w) V_y diag(lam_y)^{-1/2} (count x y,
-// row-major).  Writes lam[0..count) and *y_out.
-__global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int count, Weights wt,
-                                                      int rank_max, double rank_rtol, double energy,
-                                                      double* T, double* lam_out, int* y_out) {
+// row-major).  Writes lam[0..count), *y_out and, if not null, *y_copy.  The
+// body, for one workgroup.
+__device__ void pod_coeffs(const double* Gs, int count, const double* w, int rank_max, double rank_rtol,
+                           double energy, double* T, double* lam_out, int* y_out, int* y_copy) {
     __shared__ double a[kYMax * kLd], b[kYMax * kLd], V[kYMax * kLd];
     __shared__ double lam[kYMax];
     __shared__ int y_s;
@@ -258,8 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int cou
     const int m = count;
     for (int e = tid; e < m * m; e += kBlock) {
         const int i = e / m, j = e % m;
-        const double gij = wt.w[i] * Gs[i * m + j] * wt.w[j];
-        const double gji = wt.w[j] * Gs[j * m + i] * wt.w[i];
+        const double gij = w[i] * Gs[i * m + j] * w[j];
+        const double gji = w[j] * Gs[j * m + i] * w[i];
         a[i * kLd + j] = 0.5 * (gij + gji);
     }
     __syncthreads();
@@ -282,14 +282,34 @@ __global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int cou
         }
         y_s = y;
         *y_out = y;
+        if (y_copy) *y_copy = y;
     }
     __syncthreads();
     const int y = y_s;
     for (int e = tid; e < m * y; e += kBlock) {
         const int k = e / y, i = e % y;
-        T[e] = wt.w[k] * V[k * kLd + i] / sqrt(lam[i]);
+        T[e] = w[k] * V[k * kLd + i] / sqrt(lam[i]);
     }
     if (tid < m) lam_out[tid] = lam[tid];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pod_coeffs(const double* Gs, int count, Weights wt,
+                                                      int rank_max, double rank_rtol, double energy,
+                                                      double* T, double* lam_out, int* y_out) {
+    pod_coeffs(Gs, count, wt.w, rank_max, rank_rtol, energy, T, lam_out, y_out, nullptr);
+}
+
+// Batched: workgroup b solves the POD eigen-problem of member list[b].
+__global__ __launch_bounds__(kBlock) void k_batch_pod_coeffs(const BatchAux* __restrict__ aux,
+                                                            const int* __restrict__ list) {
+    const BatchAux& A = aux[list[blockIdx.x]];
+    pod_coeffs(A.Gs, A.count, A.w, A.rank_max, A.rank_rtol, A.energy, A.T, A.lam, A.yout, A.rank);
+}
+
+hipError_t launch_batch_pod_coeffs(const BatchAux* aux, const int* list, int nlist, hipStream_t s) {
+    if (nlist < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_pod_coeffs, dim3(nlist), dim3(kBlock), 0, s, aux, list);
+    return hipGetLastError();
 }
 
 // Batched: workgroup b factors member list[b] (its G of ynom columns).

@@ -639,6 +639,63 @@ __global__ __launch_bounds__(kBlock) void k_pod_form(int n, size_t ld, const dou
     }
 }
 
+// Batched POD form: W = S T for every member with a POD (aux.count > 0), over
+// the vector work list (row ranges of one member); the member's rank is read
+// on the device, as in k_pod_form.
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_batch_pod_form(const BatchMember* __restrict__ mem,
+                                                           const BatchAux* __restrict__ aux,
+                                                           const BatchItem* __restrict__ items, int nitems) {
+    __shared__ double t[kYMax * kYMax];
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchAux& A = aux[it.member];
+        const int count = A.count;
+        if (count < 1) continue;
+        const size_t ld = mem[it.member].B.ld;
+        const int ymax = count < A.rank_max ? count : A.rank_max;
+        const int yd = *A.yout;
+        const int y = yd < 0 ? 0 : (yd < ymax ? yd : ymax);
+        __syncthreads();   // the previous item's reads of t are done
+        for (int e = threadIdx.x; e < count * y; e += kBlock) t[e] = A.T[e];
+        __syncthreads();
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) {
+            double sv[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const double v = A.S[(size_t)(k < count ? k : count - 1) * ld + i];
+                sv[k] = k < count ? v : 0.0;
+            }
+            for (int c = 0; c < y; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    if (k < count) acc += sv[k] * t[k * y + c];
+                A.W[(size_t)c * ld + i] = acc;
+            }
+        }
+    }
+}
+
+// Batched snapshot push: column aux.slot of every member's ring = aux.src,
+// over the vector work list.
+__global__ __launch_bounds__(kBlock) void k_batch_push(const BatchMember* __restrict__ mem,
+                                                       const BatchAux* __restrict__ aux,
+                                                       const BatchItem* __restrict__ items, int nitems) {
+    const int G = gridDim.x;
+    for (int base = 0; base < nitems; base += G) {
+        const int m = min(G, nitems - base);
+        if ((int)blockIdx.x >= m) break;
+        const BatchItem it = items[base + xcd_block(blockIdx.x, m)];
+        const BatchAux& A = aux[it.member];
+        double* dst = A.S + (size_t)A.slot * mem[it.member].B.ld;
+        for (int i = it.begin + (int)threadIdx.x; i < it.end; i += kBlock) dst[i] = A.src[i];
+    }
+}
+
 // dst[(i / 64) 64 y + 64 j + i mod 64] = src[j ld + i] for i < ld, j < y.
 __global__ __launch_bounds__(kBlock) void k_tile_columns(const double* __restrict__ src, size_t ld, int y,
                                                          double* __restrict__ dst) {
@@ -908,6 +965,27 @@ hipError_t launch_pod_form(int n, size_t ld, const double* S, int count, const d
 #undef CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pod_form(int kb, const BatchMember* mem, const BatchAux* aux, const BatchItem* items,
+                                 int nitems, int grid, hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    const dim3 g(grid < nitems ? grid : nitems), t(kBlock);
+    switch (basis_tier(kb)) {
+#define CASE(K) case K: hipLaunchKernelGGL((k_batch_pod_form<K>), g, t, 0, s, mem, aux, items, nitems); break;
+        PODCG_POS_TIERS(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_push(const BatchMember* mem, const BatchAux* aux, const BatchItem* items, int nitems,
+                             int grid, hipStream_t s) {
+    if (nitems < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_push, dim3(grid < nitems ? grid : nitems), dim3(kBlock), 0, s, mem, aux, items,
+                       nitems);
     return hipGetLastError();
 }
 

@@ -54,9 +54,18 @@ void sync(podcg_ctx* ctx) { HIPCHECK(hipStreamSynchronize(ctx->stream)); }
 
 void pod_resolve(podcg_ctx* ctx) {
     if (!ctx->y_pending) return;
-    HIPCHECK(hipEventSynchronize(ctx->ev_pod));
-    ctx->y = *ctx->h_rank;
+    HIPCHECK(hipEventSynchronize(ctx->ev_ext ? ctx->ev_ext : ctx->ev_pod));
+    ctx->y = ctx->rank_ext ? *ctx->rank_ext : *ctx->h_rank;
     ctx->y_pending = false;
+    ctx->rank_ext = nullptr;
+    ctx->ev_ext = nullptr;
+}
+
+void pod_slot_weights(const podcg_ctx* ctx, double* w) {
+    for (int slot = 0; slot < ctx->count; ++slot) {
+        const int age = (ctx->head - 1 - slot + ctx->opt.omega) % ctx->opt.omega;   // 0 = newest
+        w[slot] = ctx->opt.weights == 0 ? std::ldexp(1.0, -age) : 1.0;
+    }
 }
 
 void poll(podcg_ctx* ctx) {
@@ -638,10 +647,7 @@ int podcg_build_pod(podcg_ctx* ctx, int32_t* rank_out) {
         DevBufs B = bufs(ctx);
         // the used snapshots are ring slots 0..count-1; weight by age
         double w[kYMax];
-        for (int slot = 0; slot < count; ++slot) {
-            const int age = (ctx->head - 1 - slot + ctx->opt.omega) % ctx->opt.omega;   // 0 = newest
-            w[slot] = ctx->opt.weights == 0 ? std::ldexp(1.0, -age) : 1.0;
-        }
+        pod_slot_weights(ctx, w);
         HIPCHECK(launch_spmm_gram(B, count, ctx->d_S, nullptr, false, ctx->d_Gs, s));
         HIPCHECK(launch_pod_coeffs(ctx->d_Gs, count, w, ctx->opt.rank_max, ctx->opt.rank_rtol,
                                    ctx->opt.energy, ctx->d_T, ctx->d_lamS, ctx->d_yout, s));

@@ -53,6 +53,22 @@ struct podcg_batch {
     double* h_report = nullptr;             // pinned
     int* d_list = nullptr;
     int* h_list = nullptr;                  // pinned
+    // batched value ingest and POD build: their own member table, setup
+    // table, per-member inputs, ingest flags and POD ranks; the staging
+    // buffers are rewritten only after ev_aux (their last upload) completed
+    BatchMember* d_mem_aux = nullptr;
+    BatchMember* h_mem_aux = nullptr;       // pinned
+    BatchSetup* d_su_aux = nullptr;
+    BatchSetup* h_su_aux = nullptr;         // pinned
+    BatchAux* d_aux = nullptr;
+    BatchAux* h_aux = nullptr;              // pinned
+    int* d_flags = nullptr;
+    int* h_flags = nullptr;                 // pinned
+    int* d_ranks = nullptr;
+    int* h_ranks = nullptr;                 // pinned; members' pending POD ranks point here
+    int* d_list_aux = nullptr;
+    int* h_list_aux = nullptr;              // pinned
+    hipEvent_t ev_aux = nullptr, ev_pod = nullptr;
 
     struct Graph {
         int yb, grid, iters;
@@ -282,6 +298,177 @@ void stage1_all(podcg_batch* ctx, const double* const* b, double* const* x, cons
     HIPCHECK(launch_batch_dir_init(yb, ctx->d_mem, ctx->d_vec_full, ctx->n_vec_full, grid, s));
 }
 
+// The batch stream waits for every member's stream.
+void after_members(podcg_batch* ctx) {
+    for (size_t m = 0; m < ctx->members.size(); ++m) {
+        HIPCHECK(hipEventRecord(ctx->member_ev[m], ctx->members[m]->stream));
+        HIPCHECK(hipStreamWaitEvent(ctx->stream, ctx->member_ev[m], 0));
+    }
+}
+
+// Member table of the batched ingest and POD build: each member's matrix
+// buffers and work items, W = its snapshot ring (the POD Gram's operand),
+// no A W (the Gram kernel then stores nothing).
+void upload_aux_members(podcg_batch* ctx) {
+    const int count = (int)ctx->members.size();
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        BatchMember M{};
+        M.B = bufs(c);
+        M.W = c->d_S;
+        M.AW = nullptr;
+        M.spmv_items = ctx->spmv_items[m];
+        M.vec_items = ctx->vec_items[m];
+        M.spmv_first = ctx->spmv_first[m];
+        M.vec_first = ctx->vec_first[m];
+        ctx->h_mem_aux[m] = M;
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->d_mem_aux, ctx->h_mem_aux, count * sizeof(BatchMember), hipMemcpyHostToDevice,
+                            ctx->stream));
+}
+
+// New matrix values for every member (values-only podcg_set_matrix): one
+// ingest launch over all members' slices, one synchronisation for the flags.
+int batch_set_values(podcg_batch* ctx, const int64_t* nnz, const double* const* vals) {
+    if (!vals || !nnz) fail(ctx, PODCG_ERR_INVALID_ARG, "null value or size array");
+    const int count = (int)ctx->members.size();
+    for (int m = 0; m < count; ++m) {
+        if (!vals[m]) fail(ctx, PODCG_ERR_INVALID_ARG, "null member values");
+        if (!ctx->members[m]->has_pattern) fail(ctx, PODCG_ERR_NO_MATRIX, "values-only update before any pattern");
+        if (nnz[m] != ctx->members[m]->nnz) fail(ctx, PODCG_ERR_SIZE, "nnz differs from a member's pattern");
+    }
+    HIPCHECK(hipEventSynchronize(ctx->ev_aux));
+    after_members(ctx);
+    hipStream_t s = ctx->stream;
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        BatchAux A{};
+        A.src = vals[m];
+        A.map = c->d_map;
+        A.vals = c->d_vals;
+        A.dinv = c->d_dinv;
+        A.flag = ctx->d_flags + m;
+        ctx->h_aux[m] = A;
+    }
+    upload_aux_members(ctx);
+    HIPCHECK(hipMemcpyAsync(ctx->d_aux, ctx->h_aux, count * sizeof(BatchAux), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipEventRecord(ctx->ev_aux, s));
+    HIPCHECK(hipMemsetAsync(ctx->d_flags, 0, count * sizeof(int), s));
+    HIPCHECK(launch_batch_fill_values(ctx->d_mem_aux, ctx->d_aux, ctx->d_spmv_full, ctx->n_spmv_full,
+                                      ctx->opt.grid, s));
+    HIPCHECK(hipMemcpyAsync(ctx->h_flags, ctx->d_flags, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    int worst = PODCG_OK;
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        c->setup_valid = false;
+        const int f = ctx->h_flags[m];
+        c->has_values = f == 0;
+        if (f & 8) {
+            c->last_error = "non-finite matrix value";
+            if (worst == PODCG_OK) worst = PODCG_ERR_NONFINITE;
+        } else if (f & 4) {
+            c->last_error = "missing or non-positive diagonal entry";
+            if (worst == PODCG_OK) worst = PODCG_ERR_NOT_SPD;
+        }
+    }
+    if (worst != PODCG_OK) ctx->last_error = "a member's values were rejected; see its last error";
+    return worst;
+}
+
+// Push s[m] into every member's snapshot ring and build every member's next
+// basis (podcg_push_snapshot + podcg_build_pod with no rank output, per
+// member): the copies, the POD Grams S^T A S, the eigen-solves (one workgroup
+// per member) and W = S T, one launch each for all members.  Returns without
+// waiting; the ranks arrive in h_ranks when ev_pod completes.
+int batch_push_build(podcg_batch* ctx, const double* const* snap) {
+    if (!snap) fail(ctx, PODCG_ERR_INVALID_ARG, "null snapshot array");
+    const int count = (int)ctx->members.size();
+    for (int m = 0; m < count; ++m) {
+        if (!snap[m]) fail(ctx, PODCG_ERR_INVALID_ARG, "null member snapshot");
+        if (!ctx->members[m]->has_values) fail(ctx, PODCG_ERR_NO_MATRIX, "member without a matrix");
+    }
+    for (podcg_ctx* c : ctx->members) pod_resolve(c);
+    HIPCHECK(hipEventSynchronize(ctx->ev_aux));
+    after_members(ctx);
+    hipStream_t s = ctx->stream;
+    int nlist = 0, ks = 0;
+    std::vector<int> own_gram;   // members whose partial Grams exceed their slots
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        BatchAux A{};
+        A.src = snap[m];
+        A.S = c->d_S;
+        A.slot = c->head;
+        c->head = (c->head + 1) % c->opt.omega;
+        c->count = std::min(c->count + 1, c->opt.omega);
+        BatchSetup& G = ctx->h_su_aux[m];
+        G = BatchSetup{};
+        if (c->opt.rank_max > 0) {
+            A.Gs = c->d_Gs;
+            A.T = c->d_T;
+            A.lam = c->d_lamS;
+            A.yout = c->d_yout;
+            A.rank = ctx->d_ranks + m;
+            A.W = c->d_W;
+            A.count = c->count;
+            A.rank_max = c->opt.rank_max;
+            A.rank_rtol = c->opt.rank_rtol;
+            A.energy = c->opt.energy;
+            pod_slot_weights(c, A.w);
+            ctx->h_list_aux[nlist++] = m;
+            G.ynom = c->count;
+            G.G = c->d_Gs;
+            if ((size_t)c->count * c->count * ctx->spmv_items[m] > (size_t)kPartials) {
+                own_gram.push_back(m);
+            } else {
+                G.setup = 1;
+                ks = std::max(ks, c->count);
+            }
+        }
+        ctx->h_aux[m] = A;
+    }
+    upload_aux_members(ctx);
+    HIPCHECK(hipMemcpyAsync(ctx->d_aux, ctx->h_aux, count * sizeof(BatchAux), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ctx->d_su_aux, ctx->h_su_aux, count * sizeof(BatchSetup), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(ctx->d_list_aux, ctx->h_list_aux, std::max(nlist, 1) * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    HIPCHECK(hipEventRecord(ctx->ev_aux, s));
+    const int grid = ctx->opt.grid;
+    HIPCHECK(launch_batch_push(ctx->d_mem_aux, ctx->d_aux, ctx->d_vec_full, ctx->n_vec_full, grid, s));
+    if (nlist > 0) {
+        if (ks > 0)
+            HIPCHECK(launch_batch_spmm_gram(ks, ctx->d_mem_aux, ctx->d_su_aux, ctx->d_spmv_full, ctx->n_spmv_full,
+                                            grid, s));
+        for (int m : own_gram) {
+            podcg_ctx* c = ctx->members[m];
+            HIPCHECK(launch_spmm_gram(bufs(c), c->count, c->d_S, nullptr, false, c->d_Gs, s));
+        }
+        HIPCHECK(launch_batch_pod_coeffs(ctx->d_aux, ctx->d_list_aux, nlist, s));
+        int kb = 0;
+        for (int q = 0; q < nlist; ++q) kb = std::max(kb, ctx->members[ctx->h_list_aux[q]]->count);
+        HIPCHECK(launch_batch_pod_form(kb, ctx->d_mem_aux, ctx->d_aux, ctx->d_vec_full, ctx->n_vec_full, grid, s));
+        HIPCHECK(hipMemcpyAsync(ctx->h_ranks, ctx->d_ranks, count * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHECK(hipEventRecord(ctx->ev_pod, s));
+    for (int m = 0; m < count; ++m) {
+        podcg_ctx* c = ctx->members[m];
+        c->setup_valid = false;
+        if (c->opt.rank_max > 0) {
+            c->y_pending = true;
+            c->rank_ext = ctx->h_ranks + m;
+            c->ev_ext = ctx->ev_pod;
+            c->pod_count = c->count;
+        } else {
+            c->y = 0;
+            c->pod_count = 0;
+        }
+        // the member's own later work follows the batched build
+        HIPCHECK(hipStreamWaitEvent(c->stream, ctx->ev_pod, 0));
+    }
+    return PODCG_OK;
+}
+
 void check_solve_args(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol) {
     if (!b || !x) fail(ctx, PODCG_ERR_INVALID_ARG, "null b or x array");
     for (size_t m = 0; m < ctx->members.size(); ++m) {
@@ -374,14 +561,27 @@ int batch_solve_impl(podcg_batch* ctx, const double* const* b, double* const* x,
 }
 
 void release_batch(podcg_batch* ctx) {
+    // members whose rank still points at this batch take it now
+    for (podcg_ctx* c : ctx->members)
+        if (c->y_pending && c->ev_ext && c->ev_ext == ctx->ev_pod) {
+            try {
+                pod_resolve(c);
+            } catch (...) {
+                c->y_pending = false;
+                c->rank_ext = nullptr;
+                c->ev_ext = nullptr;
+            }
+        }
     for (auto& g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     ctx->graphs.clear();
     void* dev[] = {ctx->d_mem, ctx->d_spmv_full, ctx->d_vec_full, ctx->d_spmv, ctx->d_vec,
-                   ctx->d_counts, ctx->d_active, ctx->d_gather, ctx->d_su, ctx->d_report, ctx->d_list};
+                   ctx->d_counts, ctx->d_active, ctx->d_gather, ctx->d_su, ctx->d_report, ctx->d_list,
+                   ctx->d_mem_aux, ctx->d_su_aux, ctx->d_aux, ctx->d_flags, ctx->d_ranks, ctx->d_list_aux};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {ctx->h_su, ctx->h_report, ctx->h_list};
+    void* host[] = {ctx->h_su, ctx->h_report, ctx->h_list, ctx->h_mem_aux, ctx->h_su_aux, ctx->h_aux,
+                    ctx->h_flags, ctx->h_ranks, ctx->h_list_aux};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (ctx->h_mem) (void)hipHostFree(ctx->h_mem);
@@ -389,7 +589,7 @@ void release_batch(podcg_batch* ctx) {
     if (ctx->h_active) (void)hipHostFree(ctx->h_active);
     for (hipEvent_t e : ctx->member_ev)
         if (e) (void)hipEventDestroy(e);
-    hipEvent_t evs[] = {ctx->ev_a, ctx->ev_b, ctx->ev_c};
+    hipEvent_t evs[] = {ctx->ev_a, ctx->ev_b, ctx->ev_c, ctx->ev_aux, ctx->ev_pod};
     for (hipEvent_t e : evs)
         if (e) (void)hipEventDestroy(e);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -460,6 +660,21 @@ int podcg_batch_create(podcg_batch** out, int32_t count, podcg_ctx* const* membe
         HIPCHECK(hipHostMalloc((void**)&ctx->h_mem, count * sizeof(BatchMember), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_gather, count * sizeof(PollBlock), hipHostMallocDefault));
         HIPCHECK(hipHostMalloc((void**)&ctx->h_active, sizeof(int), hipHostMallocDefault));
+        dalloc(ctx, &ctx->d_mem_aux, count);
+        dalloc(ctx, &ctx->d_su_aux, count);
+        dalloc(ctx, &ctx->d_aux, count);
+        dalloc(ctx, &ctx->d_flags, count);
+        dalloc(ctx, &ctx->d_ranks, count);
+        dalloc(ctx, &ctx->d_list_aux, count);
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_mem_aux, count * sizeof(BatchMember), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_su_aux, count * sizeof(BatchSetup), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_aux, count * sizeof(BatchAux), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_flags, count * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_ranks, count * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void**)&ctx->h_list_aux, count * sizeof(int), hipHostMallocDefault));
+        HIPCHECK(hipEventCreateWithFlags(&ctx->ev_aux, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&ctx->ev_pod, hipEventDisableTiming));
+        HIPCHECK(hipEventRecord(ctx->ev_aux, ctx->stream));
         ctx->member_ev.assign(count, nullptr);
         for (auto& e : ctx->member_ev) HIPCHECK(hipEventCreate(&e));
         HIPCHECK(hipEventCreate(&ctx->ev_a));
@@ -513,6 +728,14 @@ int podcg_batch_get_options(podcg_batch* ctx, podcg_batch_options* opt) {
 int podcg_batch_solve(podcg_batch* ctx, const double* const* b, double* const* x, const double* rtol,
                       int32_t plain, podcg_stats* stats) {
     return guarded(ctx, [&]() { return batch_solve_impl(ctx, b, x, rtol, plain != 0, stats); });
+}
+
+int podcg_batch_set_values(podcg_batch* ctx, const int64_t* nnz, const double* const* vals) {
+    return guarded(ctx, [&]() { return batch_set_values(ctx, nnz, vals); });
+}
+
+int podcg_batch_push_build(podcg_batch* ctx, const double* const* s) {
+    return guarded(ctx, [&]() { return batch_push_build(ctx, s); });
 }
 
 int podcg_batch_tune(podcg_batch* ctx, const double* const* b, double* const* x, int32_t iters,

@@ -69,10 +69,13 @@ struct podcg_ctx {
     int head = 0, count = 0, pod_count = 0;
     int* d_yout = nullptr;
     // a POD built without waiting: its rank arrives in h_rank (pinned) when
-    // ev_pod completes; calls that need the rank on the host wait for it first
+    // ev_pod completes; calls that need the rank on the host wait for it first.
+    // A batched build points rank_ext / ev_ext at the batch's copy instead.
     bool y_pending = false;
     int* h_rank = nullptr;
     hipEvent_t ev_pod = nullptr;
+    const int* rank_ext = nullptr;
+    hipEvent_t ev_ext = nullptr;
 
     // scalar state and scratch
     podcg::DevState* d_st = nullptr;
@@ -144,6 +147,9 @@ void poll(podcg_ctx* ctx);
 void setup_basis(podcg_ctx* ctx);
 // Takes the rank of a POD built without waiting (no-op when none is pending).
 void pod_resolve(podcg_ctx* ctx);
+// POD weight of each ring slot (inverse distance 2^{-age}, newest 1, or all
+// ones), slots 0..count-1.
+void pod_slot_weights(const podcg_ctx* ctx, double* w);
 int fail_code(podcg_ctx* ctx, const podcg::PollBlock& P);
 void record(podcg_ctx* ctx, hipEvent_t e);
 // Launch loop iterations in batches until the device reports that the solve

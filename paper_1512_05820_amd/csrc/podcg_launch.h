@@ -156,6 +156,40 @@ struct BatchSetup {
     int pad;
 };
 
+// Per-member inputs of the batched value ingest and POD build.
+struct BatchAux {
+    const double* src;     // CSR values (ingest) or the new snapshot (POD build)
+    const int* map;        // SELL slot -> CSR entry
+    double* vals;          // SELL values and 1 / diag, written by the ingest
+    double* dinv;
+    int* flag;             // ingest flags: 4 diagonal missing or not positive, 8 non-finite value
+    double* S;             // snapshot ring, column-major, leading dimension ld
+    double* Gs;            // S^T A S (count x count)
+    double* T;             // POD coefficients (count x y)
+    double* lam;           // POD spectrum
+    int* yout;             // POD rank (the member's)
+    int* rank;             // the batch's copy of it
+    double* W;             // the member's basis
+    int slot;              // ring slot of the new snapshot
+    int count;             // snapshots in the POD (0: no POD built)
+    int rank_max;
+    int pad;
+    double rank_rtol, energy;
+    double w[kYMax];       // weight of each ring slot
+};
+
+// Batched value ingest over the SpMV items (k_sell.hip); batched snapshot
+// copy and POD form over the vector items (k_vec.hip); the POD eigen-solves,
+// one workgroup per listed member (k_small.hip).  The POD Gram S^T A S runs
+// through launch_batch_spmm_gram with W = S and no A X store.
+hipError_t launch_batch_fill_values(const BatchMember* mem, const BatchAux* aux, const BatchItem* items,
+                                    int nitems, int grid, hipStream_t s);
+hipError_t launch_batch_push(const BatchMember* mem, const BatchAux* aux, const BatchItem* items, int nitems,
+                             int grid, hipStream_t s);
+hipError_t launch_batch_pod_coeffs(const BatchAux* aux, const int* list, int nlist, hipStream_t s);
+hipError_t launch_batch_pod_form(int kb, const BatchMember* mem, const BatchAux* aux, const BatchItem* items,
+                                 int nitems, int grid, hipStream_t s);
+
 // Batched basis setup (k_gram.hip, k_small.hip, k_batch.hip): A W and
 // W^T A W over the SpMV items of the members with `setup` set (ks >= their
 // ynom), then one workgroup per listed member for the factor, inverse and

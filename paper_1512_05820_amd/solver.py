@@ -230,8 +230,9 @@ class PodCGBatch:
     """Independent sequences advanced together (podcg_batch_* of include/podcg.h).
 
     `members` are PodCG contexts (FP64); each keeps its own matrix, snapshots
-    and basis and is still driven with set_matrix / push_snapshot / build_pod.
-    solve() runs one system of every member in one batched loop."""
+    and basis and is still driven with set_matrix / push_snapshot / build_pod,
+    or all at once with set_values / push_build.  solve() runs one system of
+    every member in one batched loop."""
 
     def __init__(self, members, slices_per_item: int | None = None, rows_per_item: int | None = None,
                  grid: int | None = None, graph_iters: int | None = None,
@@ -298,6 +299,25 @@ class PodCGBatch:
         stats = (L.Stats * len(self.members))()
         rc = self._check(self._L.podcg_batch_solve(self._h, pb, px, ptol, 1 if plain else 0, stats))
         return rc, list(stats)
+
+    def set_values(self, vals):
+        """New CSR values for every member (same patterns), one batched ingest."""
+        if len(vals) != len(self.members):
+            raise ValueError("one value array per member")
+        pv = (C.c_void_p * len(vals))(*[_ptr(v, torch.float64).value for v in vals])
+        nz = (C.c_int64 * len(vals))(*[v.numel() for v in vals])
+        return self._check(self._L.podcg_batch_set_values(self._h, nz, pv))
+
+    def push_build(self, xs):
+        """Push xs[m] as member m's newest snapshot and build every member's next
+        basis, batched (returns without waiting for the GPU)."""
+        if len(xs) != len(self.members):
+            raise ValueError("one snapshot per member")
+        for m, x in zip(self.members, xs):
+            if x.numel() != m.n:
+                raise ValueError("snapshot length differs from the member size")
+        px = (C.c_void_p * len(xs))(*[_ptr(x, torch.float64).value for x in xs])
+        return self._check(self._L.podcg_batch_push_build(self._h, px))
 
     def tune(self, bs, xs, iters: int = 32):
         """Autotune work-item sizes and grid; x is overwritten.  Returns (options, ms)."""

@@ -3,7 +3,8 @@
 Members of uneven sizes (n = 25 .. 10,000, ragged slices, members of one and
 of many work items; and members at the config-4 sizes up to 512 x 512) are
 solved together; their basis setup and Stage 1 run as batched work-list
-launches.  Bars: lockstep (the oracle's
+launches, and so, optionally, do their value updates, snapshot pushes and
+POD builds.  Bars: lockstep (the oracle's
 iteration count from identical A, b, W) to 1e-10 relative for every member;
 closed-loop config-4-type sequences meeting the tolerance by the oracle's
 own residual with the oracle's ranks and iteration counts within one; graph
@@ -62,22 +63,34 @@ def _contexts(P, cfgs, **kw):
     return ctxs
 
 
-def _batched_sequence(P, cfgs, steps, plain=False, **bopt):
+def _batched_sequence(P, cfgs, steps, plain=False, batched_steps=False, spectra=None, **bopt):
+    """batched_steps: new values and the snapshot push + POD build of all
+    members through podcg_batch_set_values / podcg_batch_push_build instead of
+    each member's own calls.  spectra (a list) receives each member's POD
+    spectrum after the last build."""
     ctxs = _contexts(P, cfgs)
     batch = P.PodCGBatch(ctxs, **bopt)
     out = []
     for j in range(1, steps + 1):
         if j > 1:
-            for c, k in zip(cfgs, ctxs):
-                k.set_matrix(_dev(c.matrix_values(j)))
+            if batched_steps:
+                batch.set_values([_dev(c.matrix_values(j)) for c in cfgs])
+            else:
+                for c, k in zip(cfgs, ctxs):
+                    k.set_matrix(_dev(c.matrix_values(j)))
         bs = [_dev(c.rhs(j)) for c in cfgs]
         xs = [_dev(np.zeros(c.n)) for c in cfgs]
         rc, st = batch.solve(bs, xs, [c.tol for c in cfgs], plain=plain)
         if not plain:
-            for k, x in zip(ctxs, xs):
-                k.push_snapshot(x)
-                k.build_pod()
+            if batched_steps:
+                batch.push_build(xs)
+            else:
+                for k, x in zip(ctxs, xs):
+                    k.push_snapshot(x)
+                    k.build_pod()
         out.append((rc, [s.as_dict() for s in st], [_host(x) for x in xs]))
+    if spectra is not None:
+        spectra.extend(k.pod_spectrum() for k in ctxs)
     batch.close()
     return out
 
@@ -207,6 +220,72 @@ def test_closed_loop_batch_matches_oracle_sequences(P):
             assert tr <= c.tol * 1.01, (c.n, j + 1, tr)
             assert st[i]["rank"] == o["rank"], (c.n, j + 1)
             assert abs(st[i]["iters"] - o["iters"]) <= 1, (c.n, j + 1, st[i]["iters"], o["iters"])
+
+
+def test_batched_sequence_steps_match_oracle_sequences(P):
+    # values, snapshot pushes and POD builds of all members in batched calls;
+    # one member without a basis (rank 0), snapshot rings that evict
+    cfgs = _members(SIZES, steps=5)
+    cfgs.append(Config4Member(30, 1100, 1101, 5, 3, 0, 1e-10))
+    gpu = _batched_sequence(P, cfgs, 5, batched_steps=True)
+    for i, c in enumerate(cfgs):
+        orc = oracle.run_sequence(c, "aug", keep_x=True)
+        for j, o in enumerate(orc):
+            rc, st, xs = gpu[j]
+            A = oracle.CSR(c.rowptr, c.colind, c.matrix_values(j + 1))
+            b = o["b"]
+            tr = np.linalg.norm(b - oracle.matvec(A, xs[i])) / np.linalg.norm(b)
+            assert st[i]["status"] in (0, 2)
+            assert tr <= c.tol * 1.01, (c.n, j + 1, tr)
+            assert st[i]["rank"] == o["rank"], (c.n, j + 1)
+            assert abs(st[i]["iters"] - o["iters"]) <= 1, (c.n, j + 1, st[i]["iters"], o["iters"])
+
+
+def test_batched_sequence_steps_equal_member_calls(P):
+    # the batched ingest and POD build against each member's own calls: the
+    # ingest is elementwise (same values), the POD Grams sum their partials
+    # in another grouping, so spectra agree to rounding
+    cfgs = _members(SIZES, steps=4, omega=3, rank=3)
+    sa, sb = [], []
+    a = _batched_sequence(P, cfgs, 4, batched_steps=False, spectra=sa)
+    b = _batched_sequence(P, cfgs, 4, batched_steps=True, spectra=sb)
+    for (_, st_a, xa), (_, st_b, xb) in zip(a, b):
+        for i in range(len(cfgs)):
+            assert st_a[i]["rank"] == st_b[i]["rank"]
+            assert abs(st_a[i]["iters"] - st_b[i]["iters"]) <= 1
+            assert _relerr(xa[i], xb[i]) <= 1e-8
+    for la, lb in zip(sa, sb):
+        la, lb = np.asarray(la), np.asarray(lb)
+        assert la.shape == lb.shape
+        assert np.all(np.abs(la - lb) <= 1e-9 * np.abs(la).max())
+
+
+def test_batched_set_values_errors(P):
+    from paper_1512_05820_amd import _lib
+    cfgs = _members(SIZES[:3], steps=2)
+    ctxs = _contexts(P, cfgs)
+    batch = P.PodCGBatch(ctxs)
+    good = [_dev(c.matrix_values(2)) for c in cfgs]
+    # a wrong entry count changes no member
+    with pytest.raises(P.PodCGError) as e:
+        batch.set_values([good[0], good[1][:-1], good[2]])
+    assert e.value.code == _lib.ERR_SIZE
+    # a non-finite value: that member keeps no matrix, the others take theirs
+    bad = good[1].clone()
+    bad[3] = float("nan")
+    with pytest.raises(P.PodCGError) as e:
+        batch.set_values([good[0], bad, good[2]])
+    assert e.value.code == _lib.ERR_NONFINITE
+    x = _dev(np.zeros(cfgs[1].n))
+    with pytest.raises(P.PodCGError):
+        ctxs[1].solve(_dev(cfgs[1].rhs(2)), x, 1e-10)
+    for i in (0, 2):
+        x = _dev(np.zeros(cfgs[i].n))
+        st = ctxs[i].solve(_dev(cfgs[i].rhs(2)), x, cfgs[i].tol)
+        A = oracle.CSR(cfgs[i].rowptr, cfgs[i].colind, cfgs[i].matrix_values(2))
+        b = cfgs[i].rhs(2)
+        assert np.linalg.norm(b - oracle.matvec(A, _host(x))) / np.linalg.norm(b) <= cfgs[i].tol * 1.01
+    batch.close()
 
 
 def test_plain_batch_matches_oracle_plain(P):
