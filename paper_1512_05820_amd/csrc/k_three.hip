@@ -528,16 +528,6 @@ __global__ __launch_bounds__(kBlock) void k_jac_init(double* __restrict__ V, int
         V[e] = (e / M == e % M) ? 1.0 : 0.0;
 }
 
-// Gbar = sum over the row chunks of the partial Grams, in chunk order.
-__global__ __launch_bounds__(kBlock) void k_ts_sum_parts(const double* __restrict__ parts, int nparts,
-                                                         size_t stride, int count, double* __restrict__ G) {
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < count; e += gridDim.x * kBlock) {
-        double s = 0.0;
-        for (int c = 0; c < nparts; ++c) s += parts[(size_t)c * stride + e];
-        G[e] = s;
-    }
-}
-
 // off = sum of squared off-diagonal entries, fro = all; flag = off <= 1e-30 fro
 // (off-diagonal norm <= 1e-15 of the Frobenius norm).  One workgroup.
 __global__ __launch_bounds__(kJacobiThreads) void k_jac_offnorm(const double* __restrict__ A, int M,
@@ -729,12 +719,6 @@ hipError_t launch_ts_jacobi_sweep(double** A, double** A2, double* V, int M, int
         *A2 = t;
     }
     hipLaunchKernelGGL(k_jac_offnorm, dim3(1), dim3(kJacobiThreads), 0, s, (const double*)*A, M, flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_ts_sum_parts(const double* parts, int nparts, size_t stride, int count, double* G,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_ts_sum_parts, dim3(rows_grid(count)), dim3(kBlock), 0, s, parts, nparts, stride, count, G);
     return hipGetLastError();
 }
 

@@ -243,9 +243,6 @@ hipError_t launch_ts_weight_sym(double* G, int M, const double* eta, hipStream_t
 // the current buffer).
 hipError_t launch_ts_jacobi_init(double* V, int M, hipStream_t s);
 hipError_t launch_ts_jacobi_sweep(double** A, double** A2, double* V, int M, int* flag, hipStream_t s);
-// G = sum of nparts partial Grams (stride apart), in order.
-hipError_t launch_ts_sum_parts(const double* parts, int nparts, size_t stride, int count, double* G,
-                               hipStream_t s);
 hipError_t launch_ts_jacobi_offnorm(const double* A, int M, int* flag, hipStream_t s);
 hipError_t launch_ts_jacobi_finish(double* A, int M, double* V, double* lam, hipStream_t s);
 hipError_t launch_ts_pod_coeffs(const double* Vs, int M, const double* lam, const double* eta, int y,
