@@ -58,7 +58,7 @@ def kernel_bytes(n: int, nnz: int, y: int, implicit: bool = True) -> dict:
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_gamma_config2_128_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_gamma2_config2_128_traffic.md")
 
 
 def measured_traffic():
