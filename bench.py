@@ -512,6 +512,8 @@ def run_three_stage(args, quick=False, inputs=None):
             if S.status != 0:
                 raise RuntimeError(f"three-stage system {j}: status {S.status}")
             sts.append(S.as_dict())
+            log(f"three-stage ({gram}, phi {phi}) system {j}: stage-2 steps {S.k2}, stage-3 iterations {S.k3}, "
+                f"projection steps {S.k_in}, relres {S.true_relres:.2e}")
             x_prev = x
         return sts
 

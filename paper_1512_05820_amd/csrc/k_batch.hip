@@ -89,14 +89,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __rest
         const double* __restrict__ p = M.p;
         double* __restrict__ q = M.q;
         double g[1] = {0.0};
-        for (int s = it.begin + wid; s < it.end; s += kWavesPerBlock) {
-            const double acc = sell_row<double>(M.B, M.B.vals, s, lane, p);
-            const int row = s * kSlice + lane;
-            if (row < M.B.n) {
-                q[row] = acc;
-                g[0] += acc * p[row];
-            }
-        }
+        // two slices a wave, two rows a lane (spmv_slice_pair)
+        for (int s = it.begin + 2 * wid; s < it.end; s += 2 * kWavesPerBlock)
+            spmv_slice_pair(M.B, s, s + 1 < it.end, lane, p, q, g[0]);
         if (member_sum_last<1>(g, M.B.part, M.B.counter, M.spmv_items, it.local, lds) &&
             threadIdx.x == 0) {
             // implicit form: p = pt - W nu and (A p, p) = (A pt, pt) - nu^T a (slot 0 of the state)

@@ -281,9 +281,13 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_ghat_mv(TsDev* T, const doubl
 // direction joins the augmentation (after the kept ones) when it was formed
 // from a residual of at least kTsKeepFloor of ||c|| (the residual is computed
 // with cancellation against c), then the next direction, projected against
-// the directions kept before this solve.  The solve's scalars stay in
-// registers (the same in every thread); acc[0] accumulates the steps and
-// acc[1] the solves.
+// the directions kept before this solve.  The start and the projections
+// assume the kept directions Ghat-orthogonal; kept from many solves they can
+// lose that in rounding, and a solve can then stall.  A solve that ends
+// above its tolerance after kinmax steps is therefore done once more with
+// none kept (the stage-1 columns only), and the directions of that second
+// solve replace the kept set.  The solve's scalars stay in registers (the
+// same in every thread); acc[0] accumulates the steps and acc[1] the solves.
 __global__ __launch_bounds__(kTsThreads) void k_ts_in_solve(TsDev* T, double* __restrict__ aug, int m,
                                                             const int* __restrict__ sel, int w,
                                                             const double* __restrict__ GinvW,
@@ -292,93 +296,105 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_in_solve(TsDev* T, double* __
     __shared__ double red[kTsWaves];
     __shared__ double cw[kYMax], nuw[kYMax], nd[kTsCap];
     const int t = threadIdx.x;
-    const int na = T->naug;
     const double* __restrict__ G = aug + (size_t)kTsCap * kTsCap;
-    if (t < w) cw[t] = T->cin[sel[t]];
-    for (int l = t; l < na; l += kTsThreads) {
-        double s = 0.0;
-        for (int k = 0; k < m; ++k) s += aug[(size_t)l * kTsCap + k] * T->cin[k];
-        nd[l] = s / T->gam_aug[l];
-    }
-    __syncthreads();
-    if (t < w) {
-        double s = 0.0;
-        for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * cw[j];
-        nuw[t] = s;
-    }
-    __syncthreads();
-    double rr = 0.0, cc = 0.0;
-    for (int k = t; k < m; k += kTsThreads) {
-        const double c = T->cin[k];
-        double mu = 0.0, r = c;
-        for (int i = 0; i < w; ++i) {
-            mu += sel[i] == k ? nuw[i] : 0.0;
-            r -= T->wtgy[(size_t)i * m + k] * nuw[i];
-        }
-        for (int l = 0; l < na; ++l) {
-            mu += aug[(size_t)l * kTsCap + k] * nd[l];
-            r -= G[(size_t)l * kTsCap + k] * nd[l];
-        }
-        T->muin[k] = mu;
-        T->rh[k] = r;
-        rr += r * r;
-        cc += c * c;
-    }
-    double rz = ts_sum(rr, red);
-    const double cn = sqrt(ts_sum(cc, red));
-    const double rn0 = sqrt(rz);
-    const double tau = rel * cn;
-    bool done = rn0 <= tau || kinmax <= 0;
-    int kin = 0, knew = 0;
-    if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, 0.0, true, cw, nuw, nd);
-    while (!done) {
-        // gh = Ghat ph
-        for (int k = t; k < m; k += kTsThreads) {
-            const double* __restrict__ g = Ghat + (size_t)k * m;
+    int na = T->naug;
+    int kin = 0, knew = 0, kall = 0;
+    double rz = 0.0, rn0 = 0.0, cn = 0.0, tau = 0.0;
+    bool conv = false;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (t < w) cw[t] = T->cin[sel[t]];
+        for (int l = t; l < na; l += kTsThreads) {
             double s = 0.0;
-            for (int l = 0; l < m; ++l) s += g[l] * T->ph[l];
-            T->gh[k] = s;
+            for (int k = 0; k < m; ++k) s += aug[(size_t)l * kTsCap + k] * T->cin[k];
+            nd[l] = s / T->gam_aug[l];
         }
         __syncthreads();
-        double a = 0.0;
-        for (int k = t; k < m; k += kTsThreads) a += T->ph[k] * T->gh[k];
-        const double g = ts_sum(a, red);
-        if (!(g > 0.0)) break;
-        const double alpha = rz / g;
-        const int slot = na + knew;
-        const bool keep = sqrt(rz) >= kTsKeepFloor * cn && slot < m;
-        double b2 = 0.0;
-        for (int k = t; k < m; k += kTsThreads) {
-            const double p = T->ph[k], gk = T->gh[k];
-            if (keep) {
-                aug[(size_t)slot * kTsCap + k] = p;
-                aug[(size_t)(kTsCap + slot) * kTsCap + k] = gk;
-            }
-            T->muin[k] += alpha * p;
-            const double r = T->rh[k] - alpha * gk;
-            T->rh[k] = r;
-            b2 += r * r;
+        if (t < w) {
+            double s = 0.0;
+            for (int j = 0; j < w; ++j) s += GinvW[t * w + j] * cw[j];
+            nuw[t] = s;
         }
-        const double rz_new = ts_sum(b2, red);
-        if (keep && t == 0) T->gam_aug[slot] = g;
-        ++kin;
-        if (keep) ++knew;
-        done = sqrt(rz_new) <= tau || kin >= kinmax;
-        if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, rz_new / rz, false, cw, nuw, nd);
-        rz = rz_new;
+        __syncthreads();
+        double rr = 0.0, cc = 0.0;
+        for (int k = t; k < m; k += kTsThreads) {
+            const double c = T->cin[k];
+            double mu = 0.0, r = c;
+            for (int i = 0; i < w; ++i) {
+                mu += sel[i] == k ? nuw[i] : 0.0;
+                r -= T->wtgy[(size_t)i * m + k] * nuw[i];
+            }
+            for (int l = 0; l < na; ++l) {
+                mu += aug[(size_t)l * kTsCap + k] * nd[l];
+                r -= G[(size_t)l * kTsCap + k] * nd[l];
+            }
+            T->muin[k] = mu;
+            T->rh[k] = r;
+            rr += r * r;
+            cc += c * c;
+        }
+        rz = ts_sum(rr, red);
+        cn = sqrt(ts_sum(cc, red));
+        rn0 = sqrt(rz);
+        tau = rel * cn;
+        conv = rn0 <= tau;
+        bool done = conv || kinmax <= 0;
+        kin = 0;
+        knew = 0;
+        if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, 0.0, true, cw, nuw, nd);
+        while (!done) {
+            // gh = Ghat ph
+            for (int k = t; k < m; k += kTsThreads) {
+                const double* __restrict__ g = Ghat + (size_t)k * m;
+                double s = 0.0;
+                for (int l = 0; l < m; ++l) s += g[l] * T->ph[l];
+                T->gh[k] = s;
+            }
+            __syncthreads();
+            double a = 0.0;
+            for (int k = t; k < m; k += kTsThreads) a += T->ph[k] * T->gh[k];
+            const double g = ts_sum(a, red);
+            if (!(g > 0.0)) break;
+            const double alpha = rz / g;
+            const int slot = na + knew;
+            const bool keep = sqrt(rz) >= kTsKeepFloor * cn && slot < m;
+            double b2 = 0.0;
+            for (int k = t; k < m; k += kTsThreads) {
+                const double p = T->ph[k], gk = T->gh[k];
+                if (keep) {
+                    aug[(size_t)slot * kTsCap + k] = p;
+                    aug[(size_t)(kTsCap + slot) * kTsCap + k] = gk;
+                }
+                T->muin[k] += alpha * p;
+                const double r = T->rh[k] - alpha * gk;
+                T->rh[k] = r;
+                b2 += r * r;
+            }
+            const double rz_new = ts_sum(b2, red);
+            if (keep && t == 0) T->gam_aug[slot] = g;
+            ++kin;
+            if (keep) ++knew;
+            conv = sqrt(rz_new) <= tau;
+            done = conv || kin >= kinmax;
+            if (!done) ts_in_direction(T, aug, m, sel, w, GinvW, na, rz_new / rz, false, cw, nuw, nd);
+            rz = rz_new;
+        }
+        kall += kin;
+        if (conv || na == 0) break;
+        na = 0;   // stalled with kept directions: once more with none
+        __syncthreads();
     }
     if (t == 0) {
         T->rzin = rz;
         T->rn0in = rn0;
         T->tauin = tau;
         T->cnin = cn;
-        T->kin = kin;
+        T->kin = kall;
         T->kinmax = kinmax;
         T->naug0 = na;
         T->knew = knew;
         T->donein = 1;
         T->naug = na + knew;
-        acc[0] += kin;
+        acc[0] += kall;
         acc[1] += 1;
     }
 }

@@ -457,6 +457,127 @@ __device__ __forceinline__ double sell_row_meta(const DevBufs& B, const SliceMet
     return sell_row_cols<T, int>(B.cols + m.base + lane, v, w, 0, x);
 }
 
+// q = A p on two consecutive slices s0, s0 + 1 by one wave, two rows per
+// lane: lane l holds rows r = 64 s0 + 2 l and r + 1 (lanes 0..31 in slice
+// s0, 32..63 in slice s0 + 1) and loads their values, the even-offset entries
+// of p and the products as 16-byte pairs; the +-1 offsets of the table come
+// from the neighbouring lanes' own pairs (lane moves), so a 7-point row needs
+// 5 instead of 7 gathers.  Row sums run over the table in order, as in
+// sell_row_tab.  p and q must be 16-byte aligned.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ dbl2 ld2(const double* __restrict__ a) {
+    return *reinterpret_cast<const dbl2*>(a);
+}
+// entries c, c + 1 of p, each clamped into [0, n) (padding slots multiply a
+// clamped entry by a zero value); one 16-byte load when c is even and in range
+__device__ __forceinline__ dbl2 gather2(const double* __restrict__ p, int c, int n) {
+    if (c >= 0 && c + 1 < n) {
+        if ((c & 1) == 0) return ld2(p + c);
+        return dbl2{p[c], p[c + 1]};
+    }
+    const int c0 = c < 0 ? 0 : (c < n ? c : n - 1);
+    const int c1 = c + 1 < 0 ? 0 : (c + 1 < n ? c + 1 : n - 1);
+    return dbl2{p[c0], p[c1]};
+}
+template <int WN>
+__device__ __forceinline__ void pair_rows(const DevBufs& B, const SliceMeta& m0, const SliceMeta& m1, int s0,
+                                          int lane, const double* __restrict__ p, double* __restrict__ q,
+                                          double& g) {
+    const int r = s0 * kSlice + 2 * lane;
+    const int64_t base = lane < 32 ? m0.base : m1.base;
+    const double* v = B.vals + base + 2 * (lane & 31);
+    dbl2 vv[WN];
+#pragma unroll
+    for (int u = 0; u < WN; ++u) vv[u] = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(v + u * kSlice));
+    const dbl2 own = gather2(p, r, B.n);
+    // neighbours' pairs for the +-1 offsets; the wave's ends load theirs
+    const double left = __shfl_up(own.y, 1, kWave);
+    const double right = __shfl_down(own.x, 1, kWave);
+    const int rl = s0 * kSlice - 1, rr = s0 * kSlice + 2 * kSlice;
+    const double pl = lane == 0 ? p[rl < 0 ? 0 : (rl < B.n ? rl : B.n - 1)] : left;
+    const double pr = lane == kWave - 1 ? p[rr < B.n ? rr : B.n - 1] : right;
+    dbl2 xi[WN];
+#pragma unroll
+    for (int u = 0; u < WN; ++u) {
+        const int off = m0.tab[u];
+        if (off == 0) xi[u] = own;
+        else if (off == -1) xi[u] = dbl2{pl, own.x};
+        else if (off == 1) xi[u] = dbl2{own.y, pr};
+        else xi[u] = gather2(p, r + off, B.n);
+    }
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < WN; ++u) {
+        a0 = fma(vv[u].x, xi[u].x, a0);
+        a1 = fma(vv[u].y, xi[u].y, a1);
+    }
+    if (r + 1 < B.n) {
+        *reinterpret_cast<dbl2*>(q + r) = dbl2{a0, a1};
+        g += a0 * own.x;
+        g += a1 * own.y;
+    } else if (r < B.n) {
+        q[r] = a0;
+        g += a0 * own.x;
+    }
+}
+
+// Slices s0 and (when has1) s0 + 1 of q = A p, with the (q, p) partial added
+// to g: the two-rows-per-lane path of pair_rows when both are offset-table
+// slices with one table, else one slice at a time with lane = row.
+__device__ __forceinline__ void spmv_slice_pair(const DevBufs& B, int s0, bool has1, int lane,
+                                                const double* __restrict__ p, double* __restrict__ q, double& g) {
+    const int s1 = has1 ? s0 + 1 : s0;
+    const int mw = B.smeta[(size_t)(lane < kMetaWords ? s0 : s1) * kMetaWords + (lane & (kMetaWords - 1))];
+    SliceMeta m0, m1;
+    m0.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mw, 1) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane(mw, 0));
+    m0.w = __builtin_amdgcn_readlane(mw, 2);
+    m0.flag = __builtin_amdgcn_readlane(mw, 3);
+    m1.base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mw, 17) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane(mw, 16));
+    m1.w = __builtin_amdgcn_readlane(mw, 18);
+    m1.flag = __builtin_amdgcn_readlane(mw, 19);
+#pragma unroll
+    for (int u = 0; u < kTabMax; ++u) {
+        m0.tab[u] = __builtin_amdgcn_readlane(mw, 4 + u);
+        m1.tab[u] = __builtin_amdgcn_readlane(mw, 20 + u);
+    }
+    bool uni = has1 && m0.flag == 2 && m1.flag == 2 && m0.w == m1.w && m0.w >= 1 && m0.w <= kTabMax;
+#pragma unroll
+    for (int u = 0; u < kTabMax; ++u) uni = uni && (u >= m0.w || m0.tab[u] == m1.tab[u]);
+    if (uni) {
+        switch (m0.w) {
+#define PODCG_PAIR_CASE(WN) case WN: pair_rows<WN>(B, m0, m1, s0, lane, p, q, g); break;
+            PODCG_TAB_WIDTHS(PODCG_PAIR_CASE)
+#undef PODCG_PAIR_CASE
+            default: break;
+        }
+        return;
+    }
+    for (int h = 0; h < (has1 ? 2 : 1); ++h) {
+        const int s = s0 + h;
+        const SliceMeta m = h == 0 ? m0 : m1;
+        const int row = s * kSlice + lane;
+        RowDiag<double> o{0.0, 0.0, false};
+        if (m.flag == 2 && m.w >= 1 && m.w <= kTabMax) {
+            const auto tab = [&](int u) { return m.tab[u]; };
+            const double* v = B.vals + m.base + lane;
+            switch (m.w) {
+#define PODCG_TAB_CASE(WN) case WN: o = sell_row_tab_diag<double, WN>(B, tab, v, row, p); break;
+                PODCG_TAB_WIDTHS(PODCG_TAB_CASE)
+#undef PODCG_TAB_CASE
+                default: break;
+            }
+        } else {
+            o.acc = sell_row_meta<double>(B, m, B.vals, s, lane, p);
+        }
+        if (row < B.n) {
+            q[row] = o.acc;
+            g += o.acc * (o.has ? o.xd : p[row]);
+        }
+    }
+}
+
 // Matrix values and Jacobi inverse in the storage type T of a kernel.
 template <typename T> __device__ __forceinline__ const T* mat_vals(const DevBufs& B);
 template <> __device__ __forceinline__ const double* mat_vals<double>(const DevBufs& B) { return B.vals; }

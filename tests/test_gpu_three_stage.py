@@ -226,3 +226,31 @@ def test_closed_loop_iterative_stage3_sequence(P):
         assert (S.w, S.m) == (oj["w"], oj["m"]) and bool(S.truncated) == oj["truncated"]
         assert abs(S.k2 - oj["k2"]) <= 1 and abs(S.k3 - oj["k3"]) <= 2
     assert any(o_["truncated"] for o_ in orc) and sum(o_["k_in"] for o_ in orc) > 0
+
+
+def test_iterative_stage3_with_capped_projection_solves(P):
+    # projection solves capped at one step: a solve seeded with kept
+    # directions that stays above its tolerance is redone once with none kept
+    # (its step then counts twice in k_in).  Over the first systems of this
+    # sequence that happens and the solves still meet the tolerance by the
+    # oracle's own residual; with one step per projection the outer iteration
+    # is not guaranteed to converge in general (here it diverges at system 4)
+    cfg = Config4Member(24, 1022, 1023, 3, 5, 4, 1e-10)
+    o, kw = _opts(ybar=120, y_trunc=30, w_max=5, rho=1e-3, stage2_maxit=512, phi=1)
+    kw["inner_maxit"] = 1
+    kw["inner_rtol"] = 1e-13
+    ctx = _ctx(P, cfg, maxit=400, **kw)
+    restarts = 0
+    for j in range(1, cfg.steps + 1):
+        if j > 1:
+            ctx.set_matrix(_dev(cfg.matrix_values(j)))
+        b = cfg.rhs(j)
+        x = _dev(np.zeros(cfg.n))
+        S = ctx.ts_solve(_dev(b), x, cfg.tol)
+        A = oracle.CSR(cfg.rowptr, cfg.colind, cfg.matrix_values(j))
+        tr = np.linalg.norm(b - oracle.matvec(A, _host(x))) / np.linalg.norm(b)
+        print(f"j={j} status {S.status} k3 {S.k3} k_in {S.k_in} projections {S.projections} relres {tr:.2e}")
+        assert S.status == 0 and tr <= cfg.tol * 1.01, (j, S.status, tr)
+        assert S.k_in <= 2 * S.projections
+        restarts += S.k_in - S.projections
+    assert restarts > 0
