@@ -59,23 +59,45 @@ def kernel_bytes(n: int, nnz: int, y: int, implicit: bool = True) -> dict:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_gamma2_config2_128_traffic.md")
+LOOP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loop_update_dir_config2_128_traffic.md")
 
 
-def measured_traffic():
-    """HBM bytes per SpMV launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernel sources changed since it was taken."""
+def _summary_fields(path: str, source: str):
+    """Machine-readable lines of a committed traffic summary, or None when the
+    kernel source or the device header changed since the counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and " " not in line.split(": ", 1)[0])
     csrc = os.path.join(ROOT, "paper_1512_05820_amd", "csrc")
-    h1 = hashlib.sha256(open(os.path.join(csrc, "k_sell.hip"), "rb").read()).hexdigest()[:16]
+    h1 = hashlib.sha256(open(os.path.join(csrc, source), "rb").read()).hexdigest()[:16]
     h2 = hashlib.sha256(open(os.path.join(csrc, "podcg_device.h"), "rb").read()).hexdigest()[:16]
     if fields.get("kernel_source_sha256_16") != h1 or fields.get("device_header_sha256_16") != h2:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def measured_traffic(kernel: str = "spmv", launches_by_rank: dict | None = None):
+    """HBM bytes per launch of a loop kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summaries (for the update and direction kernels the
+    launch-weighted mean over the basis ranks of the timed launches), or None
+    when the kernel sources changed since they were taken."""
+    if kernel == "spmv":
+        f = _summary_fields(TRAFFIC_FILE, "k_sell.hip")
+        return None if f is None else float(f["traffic_bytes_per_launch"])
+    f = _summary_fields(LOOP_TRAFFIC_FILE, "k_vec.hip")
+    if f is None or not launches_by_rank:
+        return None
+    tot = cnt = 0.0
+    for y, c in launches_by_rank.items():
+        key = f"traffic_{kernel}_rank_{y}"
+        if key not in f:
+            return None
+        tot += c * float(f[key])
+        cnt += c
+    return tot / cnt if cnt else None
 
 
 def run_sequence(torch, ctx, cfg, vals_dev, method: str, warm: bool = False):
@@ -745,6 +767,10 @@ def main():
                 tot[key][0] += s["timed_iters"] * kb[key]
                 tot[key][1] += s[ms_key]
     launches = sum(s["timed_iters"] for _, sts in per_step for s in sts)
+    by_rank = {}
+    for _, sts in per_step:
+        for s in sts:
+            by_rank[s["rank"]] = by_rank.get(s["rank"], 0) + s["timed_iters"]
     dom = max(tot, key=lambda k: tot[k][1])
     gbps = {k: (v[0] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else 0.0) for k, v in tot.items()}
     loop_bytes = sum(v[0] for v in tot.values())
@@ -849,9 +875,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(gbps[dom], 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(gbps[dom] / HBM_PEAK_GBPS, 4),
-                     "traffic": (measured_traffic() if dom == "spmv" and cfg.N == 128 else None),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
-                     "algorithmic_bytes": kernel_bytes(cfg.n, cfg.nnz, 0)[dom] if dom == "spmv" else None,
+                     "traffic": (measured_traffic(dom, by_rank) if cfg.N == 128 else None),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated; "
+                                     "update and direction: mean over the timed launches' basis ranks)",
+                     "algorithmic_bytes": round(tot[dom][0] / max(launches, 1)),
                      "format_bytes": (8 * fmt["slots"] + fmt["column_bytes"] + 16 * cfg.n + 9 * ((cfg.n + 63) // 64)
                                       if dom == "spmv" else None),
                      "avg_launch_us": round(1e3 * tot[dom][1] / max(launches, 1), 2),
