@@ -53,7 +53,7 @@ def kernel_bytes(n: int, nnz: int, y: int, implicit: bool = True) -> dict:
     reads no basis column."""
     return {
         "spmv": 12 * nnz + 4 * (n + 1) + 16 * n,   # CSR values + int32 columns + row offsets, read p, write q
-        "update": (5 + y) * 8 * n,             # read r, q, dinv, A W; write r, z
+        "update": (4 + y) * 8 * n,             # read z, q, dinv, A W; write z (r = z / dinv is not stored)
         "dir": (5 + (0 if implicit else y)) * 8 * n,   # read z, p, x (, W); write p, x
     }
 

@@ -78,7 +78,11 @@ __device__ __forceinline__ bool loop_alpha(const DevBufs& B, int k, int nsp, con
 // SpMV's partials,
 //   r <- r - alpha q,  z <- M^{-1} r  (Jacobi),
 // and the sums (r, z), (r, r), c = (A W)^T z, reduced per group of
-// workgroups; the direction kernel finishes the sums.
+// workgroups; the direction kernel finishes the sums.  In FP64 only z is
+// stored: with the Jacobi preconditioner r = M z, so the kernel reads z,
+// recovers r = z / dinv and writes z alone (one vector of traffic less; r
+// then carries one more rounding per iteration).  The FP32 inner solve of
+// mixed precision keeps r and z.
 // T: storage and arithmetic type of the vectors and of A W (FP64, or FP32
 // for the inner solve of mixed precision); all sums are accumulated in FP64.
 template <typename T, int YB, bool NTB = false>
@@ -99,6 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
     // workgroup sums the SpMV partials (fewer for wide bases, to bound the
     // registers)
     constexpr int kPrefetch = YB <= 7 ? 4 : (YB <= 10 ? 3 : (YB <= 14 ? 2 : 1));
+    constexpr bool kZOnly = sizeof(T) == 8;
     const int i0 = blockIdx.x * kBlock + threadIdx.x;
     T rf[kPrefetch], qf[kPrefetch], df[kPrefetch], af[kPrefetch][YB > 0 ? YB : 1];
     // elements base, base + stride, ... (kPrefetch of them): all loads first
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 #pragma unroll
         for (int u = 0; u < kPrefetch; ++u) {
             const int ic = base + u * stride < n ? base + u * stride : 0;
-            rf[u] = r[ic];
+            rf[u] = kZOnly ? z[ic] : r[ic];
             qf[u] = q[ic];
             df[u] = dinv[ic];
 #pragma unroll
@@ -121,9 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = 0.0;
     auto step = [&](int i, T rold, T qi, T di, const T* a) {
+        if (kZOnly) rold = rold / di;   // r = M z (Jacobi): only z is stored
         const T ri = rold - alpha * qi;
         const T zi = di * ri;
-        r[i] = ri;
+        if (!kZOnly) r[i] = ri;
         z[i] = zi;
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
@@ -144,7 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_update(DevBufs B, int y, T* __restri
 
 // Loop kernel 2 in the implicit form of the direction, p = pt - W nu.  The
 // SpMV has produced qt = A pt, and
-//   A p = A pt - (A W) nu,  r <- r - alpha A p,  z <- M^{-1} r,
+//   A p = A pt - (A W) nu,  r <- r - alpha A p,  z <- M^{-1} r
+// (only z is stored, r = z / dinv recovered, as in k_update),
 // with the sums (r, z), (r, r), c = (A W)^T z: each column of A W is loaded
 // once and serves both A p and c.  gamma = (A p, p) = (A pt, pt) - nu^T a with
 // a = (A W)^T pt (this uses (A W)^T p = 0, the property Alg. 1's projection
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
         for (int u = 0; u < kPrefetch; ++u) {
             const int i = base + u * stride;
             const int ic = i < n ? i : 0;
-            rf[u] = r[ic];
+            rf[u] = z[ic];
             qf[u] = qt[ic];
             df[u] = B.dinv[ic];
             const double* t0 = AWt + (size_t)(ic / kSlice) * (kSlice * y) + (ic % kSlice);
@@ -198,9 +205,9 @@ __global__ __launch_bounds__(kBlock) void k_update_imp(DevBufs B, int y, double*
 #pragma unroll
         for (int j = 0; j < YB; ++j)
             if (tier_live<YB>(j, y)) qi -= a[j] * nu[j];
+        rold = rold / di;   // r = M z (Jacobi): only z is stored
         const double ri = rold - alpha * qi;
         const double zi = di * ri;
-        r[i] = ri;
         z[i] = zi;
         v[0] += ri * zi;
         v[1] += ri * ri;
