@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpodcg.so")
 SOURCES = ["podcg_api.hip", "podcg_batch.hip", "podcg_three.hip", "k_sell.hip", "k_vec.hip", "k_small.hip",
-           "k_batch.hip", "k_three.hip", "k_lds.hip", "k_gram.hip", "k_gemm.hip", "podcg_noalloc.hip"]
+           "k_batch.hip", "k_three.hip", "k_lds.hip", "k_gram.hip", "k_gemm.hip", "podcg_noalloc.hip",
+           "k_probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

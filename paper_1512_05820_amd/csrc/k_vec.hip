@@ -721,25 +721,6 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ a, d
         c[i] = a[i];
 }
 
-// Stream triad c = a + s b, 16 bytes per lane and nontemporal loads (the
-// fastest form measured on MI355X with three 134 MB arrays: 7.1 TB/s at 512
-// workgroups, against 5.8 TB/s with plain loads and 5.0-5.6 TB/s with 8-byte
-// lanes).  An odd last element is handled by one thread.
-typedef double dbl2_t __attribute__((ext_vector_type(2)));
-__global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
-                                                  const double* __restrict__ b,
-                                                  double* __restrict__ c, size_t n, double s) {
-    const size_t n2 = n / 2;
-    const dbl2_t* __restrict__ a2 = (const dbl2_t*)a;
-    const dbl2_t* __restrict__ b2 = (const dbl2_t*)b;
-    dbl2_t* __restrict__ c2 = (dbl2_t*)c;
-    // nontemporal loads: the probe's arrays are larger than the last-level
-    // cache and read once, the case in which such loads stream fastest
-    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock)
-        c2[i] = __builtin_nontemporal_load(a2 + i) + s * __builtin_nontemporal_load(b2 + i);
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) c[n - 1] = a[n - 1] + s * b[n - 1];
-}
-
 __device__ void state_init(DevState* st, int maxit, double tol2, int y, int implicit) {
     st->implicit = implicit;
     st->stop = maxit;
@@ -1012,17 +993,6 @@ hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) 
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_copy, dim3((int)g), dim3(kBlock), 0, s, src, dst, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_triad(const double* a, const double* b, double* c, size_t n, double sc,
-                        hipStream_t s) {
-    // 16-byte lanes need 16-byte aligned arrays
-    if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return hipErrorInvalidValue;
-    int64_t g = ((int64_t)n / 2 + kBlock - 1) / kBlock;
-    if (g > 512) g = 512;
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_triad, dim3((int)g), dim3(kBlock), 0, s, a, b, c, n, sc);
     return hipGetLastError();
 }
 
