@@ -5,10 +5,11 @@
 namespace podcg {
 
 // Stream triad c = a + s b: 16 bytes per lane, two elements of each thread in
-// flight, nontemporal loads (the fastest form measured on MI355X with three
-// 134 MB arrays: 7.1 TB/s at 512 workgroups, against 5.8 TB/s with plain
-// loads and 5.0-5.6 TB/s with 8-byte lanes).  An odd last element is handled
-// by one thread.
+// flight, nontemporal loads.  Measured on MI355X at 512 workgroups: with three
+// 1 GB arrays (what the bench uses) 5.8 TB/s; with three 134 MB arrays, which
+// the 256 MB last-level cache partly holds from one launch to the next,
+// 7.1 TB/s with these loads against 5.8 TB/s with plain ones (and 5.0-5.6 TB/s
+// with 8-byte lanes).  An odd last element is handled by one thread.
 typedef double dbl2_t __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(kBlock) void k_triad(const double* __restrict__ a,
                                                   const double* __restrict__ b,
