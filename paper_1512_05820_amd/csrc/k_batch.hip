@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_spmv(const BatchMember* __rest
 }
 
 // r -= alpha q, z = M^{-1} r, sums (r, z), (r, r), (A W)^T z; the last item of
-// a member forms beta, mu = G^{-1} (A W)^T z and tests convergence.  For a
+// a member forms beta, mu = G^{-1} (A W)^T z and tests convergence.  Only z is
+// stored: with Jacobi r = M z is recovered as z / dinv, as in k_update.  For a
 // member in the implicit form the SpMV multiplied pt, so A p = q - (A W) nu is
 // formed from the A W columns loaded for the sums, and the last item advances
 // xi += alpha nu, nu = mu + beta nu, a = c + beta a and nu^T a (state slot 0).
@@ -132,7 +133,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
         if (st->done != kRunning) continue;   // only this kernel's last item changes it
         const double alpha = st->alpha;
         const int y = M.y;
-        double* __restrict__ r = M.r;
         double* __restrict__ z = M.z;
         const double* __restrict__ q = M.q;
         const double* __restrict__ dinv = M.B.dinv;
@@ -155,9 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(const BatchMember* __re
                     if (imp && k < y) qi -= a[k] * nu[k];
                 }
             }
-            const double ri = r[i] - alpha * qi;
-            const double zi = dinv[i] * ri;
-            r[i] = ri;
+            // r = M z (Jacobi): only z is stored, r recovered
+            const double di = dinv[i];
+            const double ri = z[i] / di - alpha * qi;
+            const double zi = di * ri;
             z[i] = zi;
             v[0] += ri * zi;
             v[1] += ri * ri;
