@@ -300,11 +300,13 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         // implicit form: d_p holds pt and the direction kernel carries no basis
         const bool imp = y > 0 && ctx->opt.projection == 1;
         const int dyb = imp ? 0 : yb, dy = imp ? 0 : y;
-        // the implicit update by default: about eight rows a thread (one
-        // workgroup per 2048 rows, a multiple of 256, between 512 and 1024)
+        // the implicit update by default: about sixteen rows a thread (one
+        // workgroup per 4096 rows, a multiple of 256, between 512 and 1024;
+        // 512 at 128^3, where it took 27.8 against 29.6 us at 1024 once the
+        // update stored z alone)
         if (imp && ctx->opt.update_grid == 0)
             B.update_grid = (int)std::min<int64_t>(kUpdateGridImplicit,
-                std::max<int64_t>(kUpdateGrid, ((ctx->n + 2047) / 2048 + 255) / 256 * 256));
+                std::max<int64_t>(kUpdateGrid, ((ctx->n + 4095) / 4096 + 255) / 256 * 256));
         HIPCHECK(launch_state_init(ctx->d_st, ctx->opt.maxit, rtol * rtol, y, s, imp));
         // Stage 1: rbar = b - A xbar, what = G^{-1} W^T rbar
         HIPCHECK(launch_resid(B, yb, y, b, x, ctx->d_r, ctx->d_W, true, true, s));
