@@ -590,10 +590,11 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, hipStream_t s, hipEvent_t e0,
-                             hipEvent_t e1) {
-    // the pair kernel's 16-byte accesses need 16-byte aligned vectors
-    if ((((uintptr_t)p | (uintptr_t)q) & 15) == 0)
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, bool pairs, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+    // the pair kernel's 16-byte accesses need 16-byte aligned vectors; its
+    // fallback for slices without a table has no metadata prefetch
+    if (pairs && (((uintptr_t)p | (uintptr_t)q) & 15) == 0)
         PODCG_LAUNCH(k_spmv_gamma2, dim3(spmv_blocks(B)), dim3(kBlock), s, e0, e1, B, p, q, k);
     else
         PODCG_LAUNCH((k_spmv_gamma<double>), dim3(spmv_blocks(B)), dim3(kBlock), s, e0, e1, B, p, q, k);

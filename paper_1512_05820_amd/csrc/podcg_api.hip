@@ -318,7 +318,7 @@ int solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg_st
         std::vector<int> timed = run_loop(ctx, plain ? 1 : 0, &polls, [&](bool t, hipEvent_t* ev, int k) {
             hipEvent_t none[6] = {};
             hipEvent_t* e = t ? ev : none;
-            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, k, s, e[0], e[1]));
+            HIPCHECK(launch_spmv_gamma(B, ctx->d_p, ctx->d_q, k, ctx->spmv_pairs, s, e[0], e[1]));
             if (imp) {
                 HIPCHECK(launch_update_implicit(B, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, ctx->d_AWt, k, s, e[2], e[3]));
                 HIPCHECK(launch_dir_implicit(B, yb, y, ctx->d_p, x, ctx->d_z, k, s, e[4], e[5]));
@@ -586,6 +586,15 @@ int podcg_set_matrix(podcg_ctx* ctx, int64_t nnz, const int32_t* rowptr, const i
             HIPCHECK(launch_fill_offsets16(n, ctx->nslices, ctx->d_sptr, ctx->d_cols, ctx->d_cols16,
                                            ctx->d_sflag, s));
             HIPCHECK(launch_fill_meta(ctx->nslices, ctx->d_sptr, ctx->d_sflag, ctx->d_soff, ctx->d_smeta, s));
+            // the loop SpMV takes two rows a lane where the slices have tables
+            {
+                std::vector<uint8_t> f((size_t)ctx->nslices);
+                HIPCHECK(hipMemcpyAsync(f.data(), ctx->d_sflag, f.size(), hipMemcpyDeviceToHost, s));
+                sync(ctx);
+                int64_t tabled = 0;
+                for (uint8_t v : f) tabled += v == 2;
+                ctx->spmv_pairs = tabled * 10 >= (int64_t)ctx->nslices * 9;
+            }
             ctx->has_pattern = true;
             ctx->nnz = nnz;
         } else {

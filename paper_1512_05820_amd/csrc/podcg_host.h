@@ -35,6 +35,7 @@ struct podcg_ctx {
 
     // matrix
     bool has_pattern = false, has_values = false;
+    bool spmv_pairs = false;   // at least 90% of the slices are offset-table slices
     int64_t nnz = 0, nsell = 0, sell_cap = 0;
     int max_width = -1;                     // widest slice when n <= kLdsThreads (else -1)
     int64_t* d_sptr = nullptr;

@@ -34,7 +34,9 @@ hipError_t launch_pattern_outer(int n, int nslices, const int64_t* sptr, const i
                                 hipStream_t s);
 // The loop launchers take optional start/stop events that the dispatch itself
 // records (hipExtLaunchKernel): the kernel time without event-marker overhead.
-hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, hipStream_t s,
+// pairs: use the two-rows-a-lane kernel (matrices stored mostly as offset-table
+// slices); otherwise, and for vectors not 16-byte aligned, one row a lane.
+hipError_t launch_spmv_gamma(const DevBufs& B, const double* p, double* q, int k, bool pairs, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_spmv_gamma32(const DevBufs& B, const float* p, float* q, int k, hipStream_t s,
                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

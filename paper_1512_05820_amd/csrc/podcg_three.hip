@@ -250,7 +250,7 @@ int ts_stage3_iterative(podcg_ctx* ctx, TsHost* T, const double* b, double* x, d
         HIPCHECK(launch_dir(D, 0, 0, ctx->d_p, x, ctx->d_z, nullptr, true, -1, s));        // p = z
         HIPCHECK(launch_gemv_n(n, ld, T->d_Y, m, TSF(T, muin), ctx->d_p, -1.0, true, s));  // p -= Y mu
         for (int k = 0; k < maxit; ++k) {
-            HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, s));
+            HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, ctx->spmv_pairs, s));
             HIPCHECK(launch_update(D, 0, 0, ctx->d_r, ctx->d_z, ctx->d_q, nullptr, k, s));
             // x += alpha p, p recorded, p = z + beta p, convergence and cap
             HIPCHECK(launch_dir_rec(D, 0, 0, ctx->d_p, x, ctx->d_z, nullptr, vrec, ld, cap_rec, TSF(T, gam3),
@@ -413,7 +413,7 @@ int ts_solve_impl(podcg_ctx* ctx, const double* b, double* x, double rtol, podcg
     double* vrec = T->d_Y + (size_t)m * ld;
     int polls = 0;
     (void)run_loop(ctx, 0, &polls, [&](bool, hipEvent_t*, int k) {
-        HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, s));
+        HIPCHECK(launch_spmv_gamma(D, ctx->d_p, ctx->d_q, k, ctx->spmv_pairs, s));
         HIPCHECK(launch_update(D, yb, y, ctx->d_r, ctx->d_z, ctx->d_q, T->d_AB, k, s));
         HIPCHECK(launch_dir_rec(D, yb, y, ctx->d_p, x, ctx->d_z, T->d_B, vrec, ld, cap_rec, TSF(T, gam3),
                                 TSF(T, alp3), k, s));
