@@ -322,7 +322,9 @@ int podcg_batch_push_build(podcg_batch* batch, const double* const* s);
  * tolerance 0 so that no member stops early) for candidate work-item sizes and
  * grids, by coordinate descent (SpMV item, vector item, grid), keeps the
  * fastest options in the batch and returns them in *chosen (host, may be
- * NULL) with the time of `iters` iterations in *best_ms.  x[m] is used as
+ * NULL) with the time of `iters` iterations in *best_ms.  Each candidate is
+ * timed three times (the fastest run counts) and replaces the current choice
+ * only when it is at least 1% faster.  x[m] is used as
  * scratch and overwritten.  Errors as podcg_batch_solve. */
 int podcg_batch_tune(podcg_batch* batch, const double* const* b, double* const* x, int32_t iters,
                      podcg_batch_options* chosen, double* best_ms);
